@@ -1,0 +1,426 @@
+"""Krylov solvers with and without subspace recycling (oracle; test infrastructure).
+
+All solvers are right-preconditioned: they work with the operator
+A~ = A M^-1 (`op`) on the iterate y and return x = M^-1 y (`minv`).  This is
+the reading under which the recycle space built by rGCROT is valid for
+rBiCGStab (Sec. 2.4 reuses range(U), range(C) of rGCROT in rBiCGStab, so both
+must see the same operator); Sec. 2.2 notes that the operator and right-hand
+side of Alg. 1 may be taken as the preconditioned ones.
+
+The initial guess is always zero, so r_0 = b (Sec. 2.2).  The stopping test
+is ||r|| <= tol * ||b|| (Alg. 1-4, line 3).
+
+Recycle space convention: U, C with A~ U = C and C^T C = I, i.e. the factor R
+of Alg. 3 line 1a is absorbed into U (U R^-1 is stored as U).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.linalg
+
+CONVERGED, NOT_CONVERGED, BREAKDOWN, DIVERGED = 0, 1, 2, 3
+
+
+@dataclasses.dataclass
+class Recycle:
+    """Recycle space: columns of U (N x kc) and C (N x kc) with A~ U = C."""
+    U: np.ndarray
+    C: np.ndarray
+
+    @classmethod
+    def empty(cls, n):
+        return cls(np.zeros((n, 0)), np.zeros((n, 0)))
+
+    @property
+    def dim(self):
+        return self.U.shape[1]
+
+
+@dataclasses.dataclass
+class Result:
+    x: np.ndarray
+    y: np.ndarray
+    status: int
+    history: list
+    iterations: int          # Arnoldi steps (GMRES type) or while-loop passes
+    matvecs: int             # applications of A~ inside the iteration
+    cycles: int = 0
+    rel_res_true: float = float("nan")
+    eig_ties: int = 0
+    fallback: bool = False
+    events: list = dataclasses.field(default_factory=list)
+
+
+def _norm(v):
+    return float(np.sqrt(np.dot(v, v)))
+
+
+def _ls(Hbar, rho):
+    """Line 12 of Alg. 1/3: y = argmin || e1 rho - Hbar y ||, and that minimum."""
+    rhs = np.zeros(Hbar.shape[0])
+    rhs[0] = rho
+    y = np.linalg.lstsq(Hbar, rhs, rcond=None)[0]
+    return y, _norm(rhs - Hbar @ y)
+
+
+def _orthogonalize(w, blocks, orth):
+    """Orthogonalise w against the columns of each matrix in `blocks` (in order).
+
+    'mgs': one column at a time, as in the loops of Alg. 1 lines 7-9 and
+    Alg. 3 lines 6a-9.  'cgs2': classical Gram-Schmidt against all columns at
+    once, applied twice, coefficients summed.  Both give the same coefficients
+    in exact arithmetic.  Returns (w, list of coefficient vectors per block)."""
+    coefs = [np.zeros(Q.shape[1]) for Q in blocks]
+    if orth == "mgs":
+        for Q, c in zip(blocks, coefs):
+            for l in range(Q.shape[1]):
+                c[l] = Q[:, l] @ w
+                w = w - Q[:, l] * c[l]
+        return w, coefs
+    if orth != "cgs2":
+        raise ValueError(orth)
+    Qall = np.hstack(blocks)
+    tot = np.zeros(Qall.shape[1])
+    for _ in range(2):
+        c = Qall.T @ w
+        w = w - Qall @ c
+        tot += c
+    off = 0
+    for Q, c in zip(blocks, coefs):
+        c[:] = tot[off:off + Q.shape[1]]
+        off += Q.shape[1]
+    return w, coefs
+
+
+# ---------------------------------------------------------------------------
+# Alg. 1: GMRES(m)
+# ---------------------------------------------------------------------------
+
+def gmres(op, minv, b, m, tol, max_its=2000, orth="cgs2"):
+    """Restarted GMRES, Alg. 1, right-preconditioned, x_0 = 0.
+
+    Convergence is tested inside the cycle on the least-squares residual
+    (the estimate mentioned in the note to Alg. 1) and confirmed at the end of
+    the cycle with the true residual b - A~ y (line 14); if the confirmation
+    fails the next cycle starts."""
+    b = np.asarray(b, dtype=np.float64)
+    n = b.size
+    nb = _norm(b)
+    y_acc = np.zeros(n)
+    r = b.copy()
+    rho = _norm(r)
+    hist, its, mv, cycles = [], 0, 0, 0
+    status = NOT_CONVERGED
+    while rho > tol * nb and its < max_its:
+        V = np.zeros((n, m + 1))
+        H = np.zeros((m + 1, m))
+        V[:, 0] = r / rho
+        jj = 0
+        for j in range(m):
+            w = op(V[:, j])
+            its += 1
+            mv += 1
+            w, (h,) = _orthogonalize(w, [V[:, :j + 1]], orth)
+            H[:j + 1, j] = h
+            H[j + 1, j] = _norm(w)
+            jj = j + 1
+            _, est = _ls(H[:j + 2, :j + 1], rho)
+            hist.append(est / nb)
+            if H[j + 1, j] != 0.0:
+                V[:, j + 1] = w / H[j + 1, j]
+            if est <= tol * nb or H[j + 1, j] == 0.0 or its >= max_its:
+                break
+        y, _ = _ls(H[:jj + 1, :jj], rho)
+        y_acc = y_acc + V[:, :jj] @ y                     # line 13
+        r = b - op(y_acc)                                 # line 14
+        mv += 1
+        rho = _norm(r)
+        cycles += 1
+        if not np.isfinite(rho):
+            status = DIVERGED
+            break
+    if rho <= tol * nb:
+        status = CONVERGED
+    return Result(minv(y_acc), y_acc, status, hist, its, mv, cycles, rho / nb)
+
+
+# ---------------------------------------------------------------------------
+# Alg. 3: rGCROT(m,k) / GCRODR(m,k) with the harmonic-Ritz update (line 14a)
+# ---------------------------------------------------------------------------
+
+def harmonic_ritz_pairs(G, F):
+    """Harmonic Ritz pairs of the GCRODR rule: G^T G z = theta G^T F z, with
+    F = W^T V^ (QZ via scipy.linalg.eig)."""
+    return scipy.linalg.eig(G.T @ G, G.T @ F)
+
+
+def harmonic_ritz_update(rec: Recycle, V, Hbar, B, k):
+    """Line 14a of Alg. 3, by the GCRODR rule (the recycle space is spanned
+    by harmonic Ritz vectors of the search space range(U) + range(V_j)).
+
+    V: N x (j+1) Arnoldi basis, Hbar: (j+1) x j, B = C^T A~ V_j: kc x j.
+    With D = diag(1/||u_i||), W^ = [C, V_{j+1}], V^ = [U D, V_j] and
+    G = [[D, B], [0, Hbar]] one has A~ V^ = W^ G (augmented Arnoldi
+    relation).  If kc + j <= k the whole search space is kept; otherwise the
+    harmonic Ritz problem G^T G z = theta G^T W^T V^ z is solved and the k
+    vectors with the smallest |theta| are kept (a complex pair is never
+    split).  With G P = Q R: C <- W^ Q, U <- V^ P R^-1, so A~ U = C and
+    C^T C = I.  Returns the number of near-ties at the cut."""
+    kc = rec.dim
+    j = Hbar.shape[1]
+    if j == 0:
+        return 0
+    d = 1.0 / np.sqrt(np.sum(rec.U * rec.U, axis=0)) if kc else np.zeros(0)
+    D = np.diag(d)
+    G = np.zeros((kc + j + 1, kc + j))
+    G[:kc, :kc] = D
+    G[:kc, kc:] = B
+    G[kc:, kc:] = Hbar
+    What = np.hstack([rec.C, V[:, :j + 1]])
+    Vhat = np.hstack([rec.U * d[None, :], V[:, :j]])
+    ties = 0
+    if kc + j <= k:
+        P = np.eye(kc + j)
+    else:
+        theta, Z = harmonic_ritz_pairs(G, What.T @ Vhat)
+        mag = np.where(np.isfinite(theta), np.abs(theta), np.inf)
+        order = np.argsort(mag, kind="stable")
+        sel = list(order[:k])
+        if k < len(order) and np.isfinite(mag[order[k]]) and mag[order[k - 1]] > 0:
+            if (mag[order[k]] - mag[order[k - 1]]) / mag[order[k - 1]] < 1e-8:
+                ties += 1
+        # do not split a complex-conjugate pair
+        chosen = []
+        for i in sel:
+            if abs(theta[i].imag) > 0:
+                partner = [q for q in sel if q != i and np.isclose(theta[q], np.conj(theta[i]),
+                                                                 rtol=1e-10, atol=0)]
+                if not partner:
+                    continue
+            chosen.append(i)
+        cols = []
+        done = set()
+        for i in chosen:
+            if i in done:
+                continue
+            z = Z[:, i]
+            if abs(theta[i].imag) > 0:
+                cols.append(z.real)
+                cols.append(z.imag)
+                for q in chosen:
+                    if q != i and np.isclose(theta[q], np.conj(theta[i]), rtol=1e-10, atol=0):
+                        done.add(q)
+            else:
+                cols.append(z.real)
+            done.add(i)
+        P = np.array(cols).T
+    Q, R = np.linalg.qr(G @ P)
+    s = np.sign(np.diag(R))
+    s[s == 0] = 1.0
+    Q = Q * s[None, :]
+    R = R * s[:, None]
+    rec.C = What @ Q
+    rec.U = scipy.linalg.solve_triangular(R, (Vhat @ P).T, trans="T", lower=False).T
+    return ties
+
+
+def recycle_setup(op, rec: Recycle):
+    """Alg. 3 line 1a: C~ = A~ U, thin QR C~ = C R, U <- U R^-1."""
+    if rec.dim == 0:
+        return
+    Ct = np.column_stack([op(rec.U[:, i]) for i in range(rec.dim)])
+    Q, R = np.linalg.qr(Ct)
+    s = np.sign(np.diag(R))
+    s[s == 0] = 1.0
+    Q = Q * s[None, :]
+    R = R * s[:, None]
+    rec.C = Q
+    rec.U = scipy.linalg.solve_triangular(R, rec.U.T, trans="T", lower=False).T
+
+
+def rgcrot(op, minv, b, m, k, tol, rec: Recycle, update=True, max_its=2000, orth="cgs2",
+           trace=None):
+    """rGCROT(m,k), Alg. 3, right-preconditioned, x^ = 0, R absorbed in U.
+
+    Line 1b projects b against C; lines 6a-6c orthogonalise each new Arnoldi
+    vector against C before V; line 12a takes z = -B y, and the update of the
+    solution uses V y + U z = V y - U B y (the form that minimises the
+    residual over range(U) + range(V_m), eq. for x_m and its argmin; the sign
+    printed in line 13a would add +U B y instead).  Line 14 takes the true
+    residual, line 14a updates (U, C) when `update`, and the residual is then
+    re-projected against the new C so that the next cycle starts with
+    r, v_1 orthogonal to C.  `rec` is updated in place."""
+    b = np.asarray(b, dtype=np.float64)
+    n = b.size
+    nb = _norm(b)
+    hist, its, mv, cycles, ties = [], 0, 0, 0, 0
+    status = NOT_CONVERGED
+    if rec.dim:
+        xi = rec.C.T @ b                                  # line 1b
+        r = b - rec.C @ xi
+        y_acc = rec.U @ xi
+    else:
+        r = b.copy()
+        y_acc = np.zeros(n)
+    rho = _norm(r)
+    while rho > tol * nb and its < max_its:
+        kc = rec.dim
+        V = np.zeros((n, m + 1))
+        H = np.zeros((m + 1, m))
+        Bm = np.zeros((kc, m))
+        V[:, 0] = r / rho                                 # line 4
+        jj = 0
+        for j in range(m):
+            w = op(V[:, j])                               # line 6
+            its += 1
+            mv += 1
+            w, (bcol, h) = _orthogonalize(w, [rec.C, V[:, :j + 1]], orth)  # 6a-9
+            Bm[:, j] = bcol
+            H[:j + 1, j] = h
+            H[j + 1, j] = _norm(w)                        # line 10
+            jj = j + 1
+            _, est = _ls(H[:j + 2, :j + 1], rho)
+            hist.append(est / nb)
+            if H[j + 1, j] != 0.0:
+                V[:, j + 1] = w / H[j + 1, j]
+            if est <= tol * nb or H[j + 1, j] == 0.0 or its >= max_its:
+                break
+        y, _ = _ls(H[:jj + 1, :jj], rho)                  # line 12
+        z = -Bm[:, :jj] @ y                               # line 12a
+        y_acc = y_acc + V[:, :jj] @ y + rec.U @ z         # lines 13, 13a
+        r = b - op(y_acc)                                 # line 14
+        mv += 1
+        cycles += 1
+        if trace is not None:
+            trace(dict(V=V[:, :jj + 1].copy(), H=H[:jj + 1, :jj].copy(), B=Bm[:, :jj].copy(),
+                       U=rec.U.copy(), C=rec.C.copy(), y_acc=y_acc.copy(), r=r.copy()))
+        if update:                                        # line 14a
+            ties += harmonic_ritz_update(rec, V[:, :jj + 1], H[:jj + 1, :jj], Bm[:, :jj], k)
+        if rec.dim:
+            xi = rec.C.T @ r
+            r = r - rec.C @ xi
+            y_acc = y_acc + rec.U @ xi
+        rho = _norm(r)
+        if not np.isfinite(rho):
+            status = DIVERGED
+            break
+    if rho <= tol * nb:
+        status = CONVERGED
+    res = Result(minv(y_acc), y_acc, status, hist, its, mv, cycles, rho / nb)
+    res.eig_ties = ties
+    return res
+
+
+# ---------------------------------------------------------------------------
+# Alg. 2 / Alg. 4: BiCGStab and rBiCGStab with one recycle space
+# ---------------------------------------------------------------------------
+
+def rbicgstab(op, minv, b, tol, rec: Recycle | None = None, max_matvecs=2000,
+              div_factor=1e2, trace=None):
+    """rBiCGStab with one recycle space, Alg. 4 (Alg. 2 when the space is empty).
+
+    Runs BiCGStab on A~_C = (I - C C^T) A~ from r_0 = (I - C C^T) b
+    (lines 1c, 7a, 12a) with r~ = r_0; the U-parts of the solution updates are
+    accumulated in xi (lines 1c, 10a, 13a) and applied once at the end
+    (line 17a: y <- y - U xi).  The while test and line 9 use the updated
+    residual.  Breakdown (rho = 0, r~^T v = 0 or t^T t = 0) ends the
+    iteration; so does a non-finite residual or one above div_factor*||b||
+    (divergence guard for the hybrid solver)."""
+    b = np.asarray(b, dtype=np.float64)
+    n = b.size
+    nb = _norm(b)
+    if rec is None:
+        rec = Recycle.empty(n)
+    C, U = rec.C, rec.U
+    eta1 = C.T @ b                                        # line 1c
+    r = b - C @ eta1
+    xi = -eta1
+    rt = r.copy()                                         # line 2: r~ = r_0
+    y = np.zeros(n)
+    p = np.zeros(n)
+    v = np.zeros(n)
+    hist, its, mv = [], 0, 0
+    status = NOT_CONVERGED
+    rho_old = alpha = omega = 0.0
+    rnorm = _norm(r)
+    while rnorm > tol * nb and mv < max_matvecs:
+        rho = rt @ r                                      # line 4
+        if rho == 0.0:
+            status = BREAKDOWN
+            break
+        if its == 0:
+            p = r.copy()
+        else:
+            beta = (rho / rho_old) * (alpha / omega)
+            p = r + beta * (p - omega * v)                # line 6
+        v = op(p)                                         # line 7
+        mv += 1
+        eta1 = C.T @ v                                    # line 7a
+        v = v - C @ eta1
+        rtv = rt @ v
+        if rtv == 0.0:
+            status = BREAKDOWN
+            break
+        alpha = rho / rtv                                 # line 8
+        s = r - alpha * v
+        snorm = _norm(s)
+        hist.append(snorm / nb)
+        its += 1
+        if snorm <= tol * nb:                             # lines 9-10a
+            y = y + alpha * p
+            r = s
+            xi = xi + alpha * eta1
+            rnorm = snorm
+            break
+        t = op(s)                                         # line 12
+        mv += 1
+        eta2 = C.T @ t                                    # line 12a
+        t = t - C @ eta2
+        tt = t @ t
+        if tt == 0.0:
+            status = BREAKDOWN
+            y = y + alpha * p
+            xi = xi + alpha * eta1
+            r = s
+            rnorm = snorm
+            break
+        omega = (t @ s) / tt                              # line 13
+        xi = xi + alpha * eta1 + omega * eta2             # line 13a
+        y = y + alpha * p + omega * s                     # line 14
+        r = s - omega * t                                 # line 15
+        rho_old = rho                                     # line 16
+        rnorm = _norm(r)
+        hist.append(rnorm / nb)
+        if trace is not None:
+            trace(dict(r=r.copy(), s=s.copy(), t=t.copy(), v=v.copy(), xi=xi.copy(), y=y.copy()))
+        if not np.isfinite(rnorm) or rnorm > div_factor * nb:
+            status = DIVERGED
+            break
+    y = y - U @ xi                                        # line 17a
+    if status == NOT_CONVERGED and rnorm <= tol * nb:
+        status = CONVERGED
+    true = _norm(b - op(y)) / nb
+    return Result(minv(y), y, status, hist, its, mv, 0, true)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.4: hybrid rGCROT -> rBiCGStab over a sequence of systems
+# ---------------------------------------------------------------------------
+
+def hybrid_step(step, n_switch, op, minv, b, m, k, tol, rec: Recycle,
+                max_its=2000, orth="cgs2", div_factor=1e2):
+    """One system of the hybrid sequence: the first n_switch systems are solved
+    by rGCROT(m,k), which builds (U, C); later systems by rBiCGStab with that
+    space held fixed.  If rBiCGStab diverges, breaks down or fails to
+    converge, the system is solved again by rGCROT (switch back, Sec. 2.4)."""
+    if step < n_switch:
+        return rgcrot(op, minv, b, m, k, tol, rec, True, max_its, orth)
+    res = rbicgstab(op, minv, b, tol, rec, max_its, div_factor)
+    if res.status == CONVERGED:
+        return res
+    again = rgcrot(op, minv, b, m, k, tol, rec, True, max_its, orth)
+    again.fallback = True
+    again.events = [("rbicgstab_status", res.status)]
+    return again
