@@ -1,0 +1,243 @@
+/*
+ * krs -- recycling Krylov solvers for sequences of structured-grid pressure
+ * Poisson systems A x_t = b_t on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Amritkar, de Sturler, Swirydowicz, Tafti, Ahuja, "Recycling Krylov
+ * subspaces for CFD applications and a new hybrid recycling solver".
+ *   GMRES(m) ............................ Alg. 1 (Sec. 2.2)
+ *   BiCGStab ............................ Alg. 2 (Sec. 2.2)
+ *   rGCROT(m,k)/GCRODR(m,k) ............. Alg. 3 (Sec. 2.3)
+ *   rBiCGStab with one recycle space .... Alg. 4 (Sec. 2.3)
+ *   hybrid rGCROT -> rBiCGStab .......... Sec. 2.4
+ *   banded 7-point storage .............. Sec. 2.1, "Data Layout"
+ *   Schwarz-Jacobi preconditioner ....... Sec. 2.1, "Preconditioners"
+ *
+ * Conventions (all entry points)
+ * ------------------------------
+ * Grid (nx, ny, nz); unknown i = x + nx*(y + ny*z), x fastest; N = nx*ny*nz.
+ * Bands: one device array of 7*N values, band-major ([7][N]) in the order
+ *   C, W (x-1), E (x+1), S (y-1), N (y+1), B (z-1), T (z+1):
+ *   (A u)_i = C_i u_i + W_i u_{i-1} + E_i u_{i+1} + S_i u_{i-nx} + ...
+ * A periodic axis wraps; across a non-periodic boundary the neighbour term is
+ * dropped (the band there must be 0 or folded into C).
+ * Vectors: device arrays of N values of the handle's dtype (FP64 or FP32),
+ *   except where an argument says otherwise.
+ * Multi-vectors (U, C): column-major, column c at base + c*ld, ld >= N.
+ * Solvers are right-preconditioned: they iterate on A~ = A M^-1 and return
+ *   x = M^-1 y; the initial guess is always x = 0 (Sec. 2.2), the stopping
+ *   test is ||b - A x|| <= tol ||b|| (Alg. 1-4, line 3).
+ * Recycle space: (U, C) with A~ U = C and C^T C = I (the R factor of
+ *   Alg. 3 line 1a is absorbed into U).
+ *
+ * Ownership: every device pointer belongs to the caller and must stay valid
+ *   while a handle that borrowed it is alive.  The library never allocates
+ *   device memory: solver scratch is a caller-provided workspace of the size
+ *   returned by krs_workspace_size.  A context owns a small pinned host
+ *   buffer and its HIP events.
+ * Streams: every call enqueues on the context's stream.  krs_stencil_apply
+ *   and krs_precond_apply are asynchronous; solver calls synchronise the
+ *   stream (for convergence tests) and return when done; statistics are
+ *   valid on return.
+ * Threads: a context and the handles created from it are used by one host
+ *   thread at a time; distinct contexts are independent.
+ * Errors: functions return an int status; no exception crosses the ABI.
+ *   0 = KRS_OK; > 0 = solver outcome (x holds the final iterate, stats are
+ *   filled); < 0 = error (outputs unspecified); krs_last_error() describes
+ *   the most recent error of a context.
+ */
+#ifndef KRS_H
+#define KRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define KRS_OK 0
+#define KRS_NOT_CONVERGED 1   /* max_matvecs reached before tol */
+#define KRS_BREAKDOWN 2       /* rho = 0, r~^T v = 0 or t^T t = 0 (Alg. 2/4 line 5) */
+#define KRS_DIVERGED 3        /* non-finite residual or growth above div_factor */
+#define KRS_ERR_ARG (-1)      /* invalid argument or unsupported shape */
+#define KRS_ERR_HIP (-2)      /* HIP runtime error */
+#define KRS_ERR_WORKSPACE (-3)/* workspace missing or too small */
+#define KRS_ERR_STATE (-4)    /* handles do not match (size, dtype) */
+#define KRS_ERR_EIG (-5)      /* host eigen-solver of the recycle update failed */
+
+typedef enum krs_dtype { KRS_F64 = 0, KRS_F32 = 1 } krs_dtype;
+
+typedef enum krs_solver {
+  KRS_SOLVER_GMRES = 0,     /* Alg. 1 */
+  KRS_SOLVER_RGCROT = 1,    /* Alg. 3 */
+  KRS_SOLVER_RBICGSTAB = 2, /* Alg. 4 (Alg. 2 with an empty recycle space) */
+  KRS_SOLVER_IR = 3         /* FP32 inner solver inside FP64 refinement: extra FP64/FP32 vectors */
+} krs_solver;
+
+typedef enum krs_pc_type {
+  KRS_PC_NONE = 0,
+  KRS_PC_JACOBI = 1,          /* point Jacobi, M = diag(A) */
+  KRS_PC_SCHWARZ_JACOBI = 2   /* overlapping tiles, damped Jacobi sweeps, global Jacobi sweep */
+} krs_pc_type;
+
+typedef struct krs_ctx krs_ctx;
+typedef struct krs_matrix krs_matrix;
+typedef struct krs_precond krs_precond;
+typedef struct krs_recycle krs_recycle;
+
+typedef struct krs_grid {
+  int64_t nx, ny, nz;
+  int32_t periodic[3];   /* nonzero: axis x / y / z wraps */
+} krs_grid;
+
+/* Preconditioner (Sec. 2.1, "Preconditioners in GenIDLEST"): cubic tiles of
+ * `tile` owned cells per axis (4 or 8; grid sizes must be multiples; a
+ * periodic axis must be longer than tile + 2*overlap), extended by `overlap`
+ * (= 1) cells; `local_sweeps` damped Jacobi sweeps (factor omega_local) from
+ * zero on each extended tile with zero values outside it; every cell keeps
+ * the value of the tile owning it; then `global_sweeps` damped point-Jacobi
+ * sweeps (factor omega_global) on the whole grid. */
+typedef struct krs_precond_desc {
+  int32_t type;            /* krs_pc_type */
+  int32_t tile;
+  int32_t overlap;
+  int32_t local_sweeps;
+  int32_t global_sweeps;
+  int32_t reserved;
+  double omega_local;
+  double omega_global;
+} krs_precond_desc;
+
+typedef struct krs_opts {
+  int32_t m;               /* Arnoldi steps per cycle (GMRES, rGCROT), 1..64 */
+  int32_t k;               /* maximum recycle dimension (rGCROT update), <= recycle kmax */
+  int32_t update_recycle;  /* rGCROT: update (U, C) at every cycle end (Alg. 3 line 14a) */
+  int32_t inner_solver;    /* IR only: KRS_SOLVER_RGCROT or KRS_SOLVER_RBICGSTAB */
+  double tol;              /* relative tolerance on ||b - A x|| / ||b|| */
+  int64_t max_matvecs;     /* cap on applications of A~ in the iteration */
+  double div_factor;       /* rBiCGStab: ||r|| > div_factor ||b|| => KRS_DIVERGED (<= 0: off) */
+  double inner_tol;        /* IR only: relative tolerance of each inner solve */
+  int32_t max_outer;       /* IR only: cap on refinement steps */
+  int32_t reserved;
+  double* history;         /* optional host buffer: residual history (relative) */
+  int64_t history_cap;
+} krs_opts;
+
+typedef struct krs_stats {
+  int32_t status;
+  int32_t eig_ties;        /* recycle updates whose k-th/(k+1)-th |theta| nearly tie */
+  int64_t matvecs;         /* applications of A~ (iteration + residual checks) */
+  int64_t iterations;      /* Arnoldi steps / BiCGStab while-loop passes */
+  int64_t cycles;          /* GMRES-type cycles */
+  int64_t outer;           /* IR refinement steps */
+  int64_t history_len;
+  double rel_res_true;     /* ||b - A x|| / ||b|| at exit, FP64 where applicable */
+  double rel_res_est;      /* last recurrence/least-squares estimate */
+  double time_ms;          /* wall time of the call */
+  double host_eig_ms;      /* time in the host eigen step of the recycle update */
+  double bytes_model;      /* algorithmic HBM bytes of the call (byte model) */
+} krs_stats;
+
+/* ---------------- context ---------------- */
+
+/* Creates a context enqueuing on `hip_stream` (a hipStream_t; NULL = the
+ * default stream) of the current device. */
+int krs_create(krs_ctx** out, void* hip_stream);
+void krs_destroy(krs_ctx* ctx);
+const char* krs_last_error(const krs_ctx* ctx);
+int krs_set_stream(krs_ctx* ctx, void* hip_stream);
+
+/* ---------------- handles ---------------- */
+
+/* Matrix: borrows `bands` (7*N device values of `dt`). */
+int krs_matrix_create(krs_ctx* ctx, const krs_grid* g, krs_dtype dt, const void* bands,
+                      krs_matrix** out);
+void krs_matrix_destroy(krs_matrix* A);
+
+/* Preconditioner for A; `ws` is a device buffer of at least
+ * krs_precond_workspace_size() bytes (one temporary vector), owned by the
+ * caller; may be NULL when global_sweeps == 0 or type != SCHWARZ_JACOBI. */
+int krs_precond_create(krs_ctx* ctx, const krs_matrix* A, const krs_precond_desc* d,
+                       void* ws, size_t ws_bytes, krs_precond** out);
+size_t krs_precond_workspace_size(const krs_matrix* A);
+void krs_precond_destroy(krs_precond* M);
+
+/* Recycle space: borrows U and C (each kmax columns of ld >= N values of
+ * `dt`); starts with dimension 0 (no recycling). */
+int krs_recycle_create(krs_ctx* ctx, int64_t N, int kmax, krs_dtype dt, void* U, void* C,
+                       int64_t ld, krs_recycle** out);
+void krs_recycle_destroy(krs_recycle* rec);
+int krs_recycle_dim(const krs_recycle* rec);
+/* Sets the dimension (0..kmax), e.g. after U was filled by the caller; call
+ * krs_recycle_update before solving if C does not hold A~ U. */
+int krs_recycle_set_dim(krs_recycle* rec, int k);
+
+/* Workspace (bytes) for `solver` on N unknowns with parameters m, k. */
+int krs_workspace_size(krs_solver solver, int64_t N, int m, int k, krs_dtype dt, size_t* bytes);
+
+/* ---------------- operations ---------------- */
+
+/* y = alpha * A x + beta * (b if b != NULL else y); y may not alias x.
+ * The stencil of Sec. 2.1 in banded storage. Asynchronous. */
+int krs_stencil_apply(krs_ctx* ctx, const krs_matrix* A, const void* x, void* y, double alpha,
+                      double beta, const void* b);
+
+/* z = M^-1 r (Sec. 2.1, "Preconditioners"); z may not alias r. Asynchronous. */
+int krs_precond_apply(krs_ctx* ctx, const krs_precond* M, const void* r, void* z);
+
+/* GMRES(m), Alg. 1, right-preconditioned (M may be NULL: no preconditioner).
+ * b, x: N values of A's dtype. Uses opts.m, tol, max_matvecs. */
+int krs_gmres(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const void* b, void* x,
+              const krs_opts* opts, void* ws, size_t ws_bytes, krs_stats* stats);
+
+/* rGCROT(m,k)/GCRODR(m,k), Alg. 3.  Projects b against C (line 1b), runs
+ * augmented Arnoldi cycles (lines 4-11, 6a-6c), updates x with V y - U B y
+ * (lines 12-13a; the sign minimising the residual over range(U)+range(V)),
+ * and, when opts.update_recycle, replaces (U, C) at every cycle end by the
+ * k harmonic Ritz vectors of smallest |theta| of range(U)+range(V_j) (line 14a,
+ * GCRODR rule; eigenproblem in FP64 on the host).  With an empty recycle
+ * space and no update this is GMRES(m). */
+int krs_rgcrot_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
+                     const void* b, void* x, const krs_opts* opts, void* ws, size_t ws_bytes,
+                     krs_stats* stats);
+
+/* rBiCGStab with one recycle space, Alg. 4 (rec may be NULL or of dimension
+ * 0: BiCGStab, Alg. 2).  r~ = r_0 after projection; U-updates postponed to
+ * the end (line 17a); rec is read only. */
+int krs_rbicgstab_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M,
+                        const krs_recycle* rec, const void* b, void* x, const krs_opts* opts,
+                        void* ws, size_t ws_bytes, krs_stats* stats);
+
+/* Alg. 3 line 1a / Alg. 4 line 1b: C~ = A~ U, thin QR C~ = C R (Cholesky QR,
+ * twice), U <- U R^-1.  Call when A changed or U was set by the caller. */
+int krs_recycle_update(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
+                       void* ws, size_t ws_bytes);
+
+/* Hybrid solver step (Sec. 2.4): systems with step < n_switch are solved by
+ * rGCROT(m,k) with recycle updates, later ones by rBiCGStab with (U, C)
+ * fixed; when rBiCGStab diverges, breaks down or does not converge, the
+ * system is solved again by rGCROT (switch back).  stats->cycles > 0 tells
+ * which solver produced x.  ws: krs_workspace_size(KRS_SOLVER_RGCROT). */
+int krs_hybrid_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
+                     int step, int n_switch, const void* b, void* x, const krs_opts* opts,
+                     void* ws, size_t ws_bytes, krs_stats* stats);
+
+/* Mixed precision: FP64 iterative refinement around an FP32 inner solver.
+ * A64/b/x are FP64 (true residual b - A64 x, update x += d in FP64);
+ * A32, M32, rec32 are the FP32 operator, preconditioner and recycle space
+ * used by the inner solver opts.inner_solver (RGCROT: with recycle updates
+ * when opts.update_recycle; RBICGSTAB: rec32 read only) to the relative
+ * tolerance opts.inner_tol.  Stops when ||b - A64 x|| <= tol ||b||.
+ * ws: krs_workspace_size(KRS_SOLVER_IR, N, m, k, KRS_F32). */
+int krs_ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32,
+                 const krs_precond* M32, krs_recycle* rec32, const void* b, void* x,
+                 const krs_opts* opts, void* ws, size_t ws_bytes, krs_stats* stats);
+
+/* Library version string. */
+const char* krs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KRS_H */

@@ -1,0 +1,300 @@
+// C-ABI of the krs library: argument checking and dispatch to the drivers.
+#include <climits>
+#include <new>
+
+#include "internal.hpp"
+
+using krs::set_err;
+
+namespace {
+
+size_t dsize(krs_dtype dt) { return dt == KRS_F64 ? sizeof(double) : sizeof(float); }
+
+bool valid_dtype(int dt) { return dt == KRS_F64 || dt == KRS_F32; }
+
+int check_opts(krs_ctx* ctx, const krs_opts* o, bool needs_m) {
+  if (!o) return set_err(ctx, KRS_ERR_ARG, "opts is NULL");
+  if (needs_m && (o->m < 1 || o->m > krs::kMaxM))
+    return set_err(ctx, KRS_ERR_ARG, "opts.m must be in 1..64");
+  if (!(o->tol >= 0)) return set_err(ctx, KRS_ERR_ARG, "opts.tol must be >= 0");
+  if (o->history_cap < 0 || (o->history_cap > 0 && !o->history))
+    return set_err(ctx, KRS_ERR_ARG, "history buffer inconsistent");
+  return KRS_OK;
+}
+
+int check_rec(krs_ctx* ctx, const krs_matrix* A, const krs_recycle* rec, const krs_opts* o,
+              bool updating) {
+  if (!rec) return KRS_OK;
+  if (rec->n != A->n) return set_err(ctx, KRS_ERR_STATE, "recycle space size differs from matrix");
+  if (rec->dt != A->dt) return set_err(ctx, KRS_ERR_STATE, "recycle space dtype differs from matrix");
+  if (o && updating) {
+    if (o->k < 1 || o->k > rec->kmax)
+      return set_err(ctx, KRS_ERR_ARG, "opts.k must be in 1..kmax of the recycle space");
+    if (o->k + o->m + 1 > 64)
+      return set_err(ctx, KRS_ERR_ARG, "opts.k + opts.m + 1 must not exceed 64");
+  }
+  if (o && rec->dim + o->m + 1 > 64)
+    return set_err(ctx, KRS_ERR_ARG, "recycle dimension + opts.m + 1 must not exceed 64");
+  return KRS_OK;
+}
+
+int check_precond(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M) {
+  if (M && M->A != A) {
+    const krs_matrix* B = M->A;
+    if (B->n != A->n || B->dt != A->dt)
+      return set_err(ctx, KRS_ERR_STATE, "preconditioner built for another matrix");
+  }
+  return KRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* krs_version(void) { return "krs 0.1 (gfx950)"; }
+
+int krs_create(krs_ctx** out, void* hip_stream) {
+  if (!out) return KRS_ERR_ARG;
+  *out = nullptr;
+  krs_ctx* c = new (std::nothrow) krs_ctx();
+  if (!c) return KRS_ERR_ARG;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return KRS_ERR_HIP;
+  }
+  if (hipHostMalloc((void**)&c->pin, sizeof(double) * krs::kPinDoubles, hipHostMallocDefault) !=
+      hipSuccess) {
+    delete c;
+    return KRS_ERR_HIP;
+  }
+  *out = c;
+  return KRS_OK;
+}
+
+void krs_destroy(krs_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
+  delete ctx;
+}
+
+const char* krs_last_error(const krs_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int krs_set_stream(krs_ctx* ctx, void* hip_stream) {
+  if (!ctx) return KRS_ERR_ARG;
+  ctx->stream = (hipStream_t)hip_stream;
+  return KRS_OK;
+}
+
+int krs_matrix_create(krs_ctx* ctx, const krs_grid* g, krs_dtype dt, const void* bands,
+                      krs_matrix** out) {
+  if (!ctx || !g || !out) return KRS_ERR_ARG;
+  *out = nullptr;
+  if (!valid_dtype(dt)) return set_err(ctx, KRS_ERR_ARG, "unknown dtype");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return set_err(ctx, KRS_ERR_ARG, "grid sizes must be >= 1");
+  const int64_t n = g->nx * g->ny * g->nz;
+  if (g->nx > INT_MAX || g->ny > INT_MAX || g->nz > INT_MAX || n > (int64_t)INT_MAX)
+    return set_err(ctx, KRS_ERR_ARG, "grid too large (N must fit in 31 bits)");
+  const int64_t dims[3] = {g->nx, g->ny, g->nz};
+  for (int a = 0; a < 3; ++a)
+    if (g->periodic[a] && dims[a] < 3)
+      return set_err(ctx, KRS_ERR_ARG, "a periodic axis needs at least 3 cells");
+  if (!bands) return set_err(ctx, KRS_ERR_ARG, "bands is NULL");
+  krs_matrix* A = new (std::nothrow) krs_matrix();
+  if (!A) return KRS_ERR_ARG;
+  A->ctx = ctx;
+  A->g = *g;
+  A->dt = dt;
+  A->bands = bands;
+  A->n = n;
+  *out = A;
+  return KRS_OK;
+}
+
+void krs_matrix_destroy(krs_matrix* A) { delete A; }
+
+size_t krs_precond_workspace_size(const krs_matrix* A) {
+  return A ? (size_t)krs::vec_ld(A->n) * dsize(A->dt) : 0;
+}
+
+int krs_precond_create(krs_ctx* ctx, const krs_matrix* A, const krs_precond_desc* d, void* ws,
+                       size_t ws_bytes, krs_precond** out) {
+  if (!ctx || !A || !d || !out) return KRS_ERR_ARG;
+  *out = nullptr;
+  if (d->type != KRS_PC_NONE && d->type != KRS_PC_JACOBI && d->type != KRS_PC_SCHWARZ_JACOBI)
+    return set_err(ctx, KRS_ERR_ARG, "unknown preconditioner type");
+  if (d->type == KRS_PC_SCHWARZ_JACOBI) {
+    if (d->tile != 4 && d->tile != 8) return set_err(ctx, KRS_ERR_ARG, "tile must be 4 or 8");
+    if (d->overlap != 1) return set_err(ctx, KRS_ERR_ARG, "overlap must be 1");
+    if (d->local_sweeps < 0 || d->global_sweeps < 0)
+      return set_err(ctx, KRS_ERR_ARG, "sweep counts must be >= 0");
+    const int64_t dims[3] = {A->g.nx, A->g.ny, A->g.nz};
+    for (int a = 0; a < 3; ++a) {
+      if (dims[a] % d->tile)
+        return set_err(ctx, KRS_ERR_ARG, "grid sizes must be multiples of the tile size");
+      if (A->g.periodic[a] && dims[a] <= d->tile + 2 * d->overlap)
+        return set_err(ctx, KRS_ERR_ARG, "a periodic axis must be longer than an extended tile");
+    }
+    if (d->global_sweeps > 0 && (!ws || ws_bytes < krs_precond_workspace_size(A)))
+      return set_err(ctx, KRS_ERR_WORKSPACE, "preconditioner workspace too small");
+  }
+  krs_precond* M = new (std::nothrow) krs_precond();
+  if (!M) return KRS_ERR_ARG;
+  M->ctx = ctx;
+  M->A = A;
+  M->d = *d;
+  M->tmp = ws;
+  *out = M;
+  return KRS_OK;
+}
+
+void krs_precond_destroy(krs_precond* M) { delete M; }
+
+int krs_recycle_create(krs_ctx* ctx, int64_t N, int kmax, krs_dtype dt, void* U, void* C,
+                       int64_t ld, krs_recycle** out) {
+  if (!ctx || !out) return KRS_ERR_ARG;
+  *out = nullptr;
+  if (!valid_dtype(dt)) return set_err(ctx, KRS_ERR_ARG, "unknown dtype");
+  if (N < 1 || kmax < 1 || kmax > krs::kMaxK)
+    return set_err(ctx, KRS_ERR_ARG, "recycle space: need N >= 1 and 1 <= kmax <= 32");
+  if (ld < N || !U || !C) return set_err(ctx, KRS_ERR_ARG, "recycle space: bad U, C or ld");
+  krs_recycle* r = new (std::nothrow) krs_recycle();
+  if (!r) return KRS_ERR_ARG;
+  r->ctx = ctx;
+  r->n = N;
+  r->kmax = kmax;
+  r->dt = dt;
+  r->U = U;
+  r->C = C;
+  r->ld = ld;
+  r->dim = 0;
+  *out = r;
+  return KRS_OK;
+}
+
+void krs_recycle_destroy(krs_recycle* rec) { delete rec; }
+
+int krs_recycle_dim(const krs_recycle* rec) { return rec ? rec->dim : KRS_ERR_ARG; }
+
+int krs_recycle_set_dim(krs_recycle* rec, int k) {
+  if (!rec || k < 0 || k > rec->kmax) return KRS_ERR_ARG;
+  rec->dim = k;
+  return KRS_OK;
+}
+
+int krs_workspace_size(krs_solver solver, int64_t N, int m, int k, krs_dtype dt, size_t* bytes) {
+  if (!bytes || N < 1 || m < 0 || m > krs::kMaxM || !valid_dtype(dt)) return KRS_ERR_ARG;
+  return krs::workspace_bytes(solver, N, m, k, dt, bytes);
+}
+
+int krs_stencil_apply(krs_ctx* ctx, const krs_matrix* A, const void* x, void* y, double alpha,
+                      double beta, const void* b) {
+  if (!ctx || !A || !x || !y) return KRS_ERR_ARG;
+  if (x == y) return set_err(ctx, KRS_ERR_ARG, "y must not alias x");
+  const krs::Grid3 g = krs::grid3(A);
+  const int mode = b ? 1 : (beta != 0.0 ? 2 : 0);
+  hipError_t e;
+  if (A->dt == KRS_F64)
+    e = krs::stencil<double>(ctx->stream, g, (const double*)A->bands, (const double*)x, (double*)y,
+                             alpha, beta, (const double*)b, mode);
+  else
+    e = krs::stencil<float>(ctx->stream, g, (const float*)A->bands, (const float*)x, (float*)y,
+                            alpha, beta, (const float*)b, mode);
+  if (e != hipSuccess) return set_err(ctx, KRS_ERR_HIP, hipGetErrorString(e));
+  return KRS_OK;
+}
+
+int krs_precond_apply(krs_ctx* ctx, const krs_precond* M, const void* r, void* z) {
+  if (!ctx || !M || !r || !z) return KRS_ERR_ARG;
+  if (r == z) return set_err(ctx, KRS_ERR_ARG, "z must not alias r");
+  return krs::precond_apply(ctx, M, r, z, M->tmp);
+}
+
+int krs_gmres(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const void* b, void* x,
+              const krs_opts* opts, void* ws, size_t ws_bytes, krs_stats* stats) {
+  if (!ctx || !A || !b || !x) return KRS_ERR_ARG;
+  int rc = check_opts(ctx, opts, true);
+  if (rc) return rc;
+  if ((rc = check_precond(ctx, A, M))) return rc;
+  return krs::gmres_rgcrot(ctx, A, M, nullptr, false, b, x, opts, ws, ws_bytes, stats);
+}
+
+int krs_rgcrot_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
+                     const void* b, void* x, const krs_opts* opts, void* ws, size_t ws_bytes,
+                     krs_stats* stats) {
+  if (!ctx || !A || !b || !x) return KRS_ERR_ARG;
+  int rc = check_opts(ctx, opts, true);
+  if (rc) return rc;
+  if ((rc = check_precond(ctx, A, M))) return rc;
+  const bool upd = rec && opts->update_recycle;
+  if ((rc = check_rec(ctx, A, rec, opts, upd))) return rc;
+  return krs::gmres_rgcrot(ctx, A, M, rec, upd, b, x, opts, ws, ws_bytes, stats);
+}
+
+int krs_rbicgstab_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M,
+                        const krs_recycle* rec, const void* b, void* x, const krs_opts* opts,
+                        void* ws, size_t ws_bytes, krs_stats* stats) {
+  if (!ctx || !A || !b || !x) return KRS_ERR_ARG;
+  int rc = check_opts(ctx, opts, false);
+  if (rc) return rc;
+  if ((rc = check_precond(ctx, A, M))) return rc;
+  if (rec) {
+    if (rec->n != A->n || rec->dt != A->dt)
+      return set_err(ctx, KRS_ERR_STATE, "recycle space does not match the matrix");
+  }
+  return krs::rbicgstab(ctx, A, M, rec, b, x, opts, ws, ws_bytes, stats);
+}
+
+int krs_recycle_update(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
+                       void* ws, size_t ws_bytes) {
+  if (!ctx || !A || !rec) return KRS_ERR_ARG;
+  int rc = check_precond(ctx, A, M);
+  if (rc) return rc;
+  if ((rc = check_rec(ctx, A, rec, nullptr, false))) return rc;
+  return krs::recycle_setup(ctx, A, M, rec, ws, ws_bytes);
+}
+
+int krs_hybrid_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
+                     int step, int n_switch, const void* b, void* x, const krs_opts* opts,
+                     void* ws, size_t ws_bytes, krs_stats* stats) {
+  if (!ctx || !A || !b || !x || !rec) return KRS_ERR_ARG;
+  int rc = check_opts(ctx, opts, true);
+  if (rc) return rc;
+  if ((rc = check_precond(ctx, A, M))) return rc;
+  if ((rc = check_rec(ctx, A, rec, opts, true))) return rc;
+  if (step < n_switch)
+    return krs::gmres_rgcrot(ctx, A, M, rec, true, b, x, opts, ws, ws_bytes, stats);
+  krs_stats first;
+  rc = krs::rbicgstab(ctx, A, M, rec, b, x, opts, ws, ws_bytes, &first);
+  if (rc <= 0) {
+    if (stats) *stats = first;
+    return rc;
+  }
+  // rBiCGStab failed: solve this system again with rGCROT (switch back)
+  rc = krs::gmres_rgcrot(ctx, A, M, rec, true, b, x, opts, ws, ws_bytes, stats);
+  if (stats) {
+    stats->matvecs += first.matvecs;
+    stats->time_ms += first.time_ms;
+    stats->bytes_model += first.bytes_model;
+  }
+  return rc;
+}
+
+int krs_ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32,
+                 const krs_precond* M32, krs_recycle* rec32, const void* b, void* x,
+                 const krs_opts* opts, void* ws, size_t ws_bytes, krs_stats* stats) {
+  if (!ctx || !A64 || !A32 || !b || !x) return KRS_ERR_ARG;
+  int rc = check_opts(ctx, opts, true);
+  if (rc) return rc;
+  if (A64->dt != KRS_F64 || A32->dt != KRS_F32)
+    return set_err(ctx, KRS_ERR_STATE, "IR needs an FP64 and an FP32 matrix");
+  if (A64->n != A32->n) return set_err(ctx, KRS_ERR_STATE, "IR matrices differ in size");
+  if ((rc = check_precond(ctx, A32, M32))) return rc;
+  if (opts->inner_solver != KRS_SOLVER_RGCROT && opts->inner_solver != KRS_SOLVER_RBICGSTAB)
+    return set_err(ctx, KRS_ERR_ARG, "inner solver must be RGCROT or RBICGSTAB");
+  const bool upd = rec32 && (opts->update_recycle || opts->inner_solver == KRS_SOLVER_RBICGSTAB);
+  if ((rc = check_rec(ctx, A32, rec32, opts, upd))) return rc;
+  return krs::ir_solve(ctx, A64, A32, M32, rec32, b, x, opts, ws, ws_bytes, stats);
+}
+
+}  // extern "C"

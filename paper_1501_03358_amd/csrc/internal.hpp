@@ -1,0 +1,133 @@
+// Internal state of the krs library (contexts, handles, workspace carving).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/krs.h"
+#include "kernels.hpp"
+
+struct krs_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  double* pin = nullptr;         // pinned host staging (kPinDoubles)
+  double bytes = 0;              // byte-model accumulator of the current call
+};
+
+struct krs_matrix {
+  krs_ctx* ctx = nullptr;
+  krs_grid g{};
+  krs_dtype dt = KRS_F64;
+  const void* bands = nullptr;
+  int64_t n = 0;
+};
+
+struct krs_precond {
+  krs_ctx* ctx = nullptr;
+  const krs_matrix* A = nullptr;
+  krs_precond_desc d{};
+  void* tmp = nullptr;           // one vector, needed when global sweeps > 0
+};
+
+struct krs_recycle {
+  krs_ctx* ctx = nullptr;
+  int64_t n = 0;
+  int kmax = 0;
+  krs_dtype dt = KRS_F64;
+  void* U = nullptr;
+  void* C = nullptr;
+  int64_t ld = 0;
+  int dim = 0;
+};
+
+namespace krs {
+
+constexpr int kPinDoubles = 1 << 16;       // 512 KiB pinned staging
+constexpr int kMaxM = 64;                  // Arnoldi steps per cycle
+constexpr int kMaxK = 32;                  // recycle dimension
+constexpr int kScalarDoubles = 1 << 14;    // device scalar area (128 KiB)
+constexpr int kGramBlocks = 256;
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+inline int64_t vec_ld(int64_t n) { return (n + 63) / 64 * 64; }
+
+// Bump allocator over a caller workspace; with base == nullptr it only sizes.
+struct Carver {
+  char* base;
+  size_t cap;
+  size_t off = 0;
+  bool ok = true;
+  Carver(void* b, size_t c) : base((char*)b), cap(c) {}
+  void* take(size_t bytes) {
+    off = align_up(off);
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    if (base && off > cap) ok = false;
+    return p;
+  }
+  template <class T>
+  T* vec(int64_t count) { return (T*)take(sizeof(T) * (size_t)count); }
+};
+
+inline size_t partials_bytes(size_t elem) {
+  const size_t red = (size_t)kMaxRedBlocks * (kMaxM + kMaxK + 4);
+  const size_t gram = (size_t)kGramBlocks * kThreads * 8;
+  return elem * (red > gram ? red : gram);
+}
+
+inline Grid3 grid3(const krs_matrix* A) {
+  Grid3 g;
+  g.nx = (int)A->g.nx;
+  g.ny = (int)A->g.ny;
+  g.nz = (int)A->g.nz;
+  g.px = A->g.periodic[0] ? 1 : 0;
+  g.py = A->g.periodic[1] ? 1 : 0;
+  g.pz = A->g.periodic[2] ? 1 : 0;
+  g.n = A->n;
+  return g;
+}
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+        .count();
+  }
+};
+
+inline int set_err(krs_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+}  // namespace krs
+
+#define KRS_CHECK_HIP(ctx, expr)                                                        \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return krs::set_err((ctx), KRS_ERR_HIP,                                          \
+                          std::string(#expr) + ": " + hipGetErrorString(_e));          \
+  } while (0)
+
+// solver entry points implemented in solvers.cpp (dtype dispatched)
+namespace krs {
+int workspace_bytes(krs_solver solver, int64_t n, int m, int k, krs_dtype dt, size_t* bytes);
+int precond_apply(krs_ctx* ctx, const krs_precond* M, const void* r, void* z, void* tmp);
+int gmres_rgcrot(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
+                 bool update, const void* b, void* x, const krs_opts* o, void* ws, size_t wsb,
+                 krs_stats* st);
+int rbicgstab(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const krs_recycle* rec,
+              const void* b, void* x, const krs_opts* o, void* ws, size_t wsb, krs_stats* st);
+int recycle_setup(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
+                  void* ws, size_t wsb);
+int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const krs_precond* M32,
+             krs_recycle* rec32, const void* b, void* x, const krs_opts* o, void* ws, size_t wsb,
+             krs_stats* st);
+}  // namespace krs

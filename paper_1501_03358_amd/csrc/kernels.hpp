@@ -1,0 +1,140 @@
+// Device kernel launchers for the recycling Krylov solvers (gfx950).
+//
+// All launchers enqueue on the given stream and return hipGetLastError().
+// Reductions are deterministic: a fixed number of blocks (a function of the
+// row count only) writes per-block partial sums, and a finishing kernel adds
+// them in a fixed order.  Per-thread and per-block sums use the working
+// precision T; the cross-block sum and every scalar recurrence use FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace krs {
+
+constexpr int kThreads = 256;      // threads per block (4 wave64)
+constexpr int kMaxRedBlocks = 1024;
+
+struct Grid3 {
+  int nx, ny, nz;
+  int px, py, pz;
+  int64_t n;
+};
+
+// A column set [P1 (n1 columns, ld1) | P2 (n2 columns, ld2)].
+template <class T>
+struct Cols {
+  const T* p1 = nullptr;
+  int64_t ld1 = 0;
+  int n1 = 0;
+  const T* p2 = nullptr;
+  int64_t ld2 = 0;
+  int n2 = 0;
+  int count() const { return n1 + n2; }
+};
+
+inline int red_blocks(int64_t n) {
+  int64_t b = (n + kThreads * 4 - 1) / (kThreads * 4);
+  if (b < 1) b = 1;
+  if (b > kMaxRedBlocks) b = kMaxRedBlocks;
+  return (int)b;
+}
+
+// y = alpha*A x (+ beta*b | + beta*y): mode 0 / 1 / 2.
+template <class T>
+hipError_t stencil(hipStream_t s, const Grid3& g, const T* bands, const T* x, T* y, double alpha,
+                   double beta, const T* b, int mode);
+// y = b - A x and per-block partial sums of y^2 (reduction grid red_blocks(n)).
+template <class T>
+hipError_t residual_norm(hipStream_t s, const Grid3& g, const T* bands, const T* x, const T* b,
+                         T* y, T* partials);
+// z_out = z_in + omega * (r - A z_in) / diag(A)
+template <class T>
+hipError_t jacobi_sweep(hipStream_t s, const Grid3& g, const T* bands, const T* r, const T* zin,
+                        T* zout, double omega);
+// z = r / diag(A)
+template <class T>
+hipError_t point_jacobi(hipStream_t s, const Grid3& g, const T* bands, const T* r, T* z);
+// Local Schwarz-Jacobi on every (tile+2)^3 extended tile; writes owned cells.
+template <class T>
+hipError_t schwarz_local(hipStream_t s, const Grid3& g, int tile, const T* bands, const T* r, T* z,
+                         double omega, int sweeps);
+
+// partials[c*nblk + blk] = sum_rows Q_c * w  (c < ncols), then w.w if self_dot
+template <class T>
+hipError_t block_dot(hipStream_t s, const Cols<T>& Q, const T* w, int64_t n, int self_dot,
+                     T* partials, int nblk);
+// w_out = (w_in + sgn * Q coef) * (scale ? *scale : 1); w_in may be null (0).
+// dots: 0 none; 1 partial |w_out|^2; 2 partial Q^T w_out and |w_out|^2.
+template <class T>
+hipError_t block_update(hipStream_t s, const Cols<T>& Q, const double* coef, double sgn,
+                        const T* w_in, T* w_out, int64_t n, const double* scale, int dots,
+                        T* partials, int nblk);
+// partials of Q^T (w - Q coef) and |w - Q coef|^2 without writing anything.
+template <class T>
+hipError_t block_dot_after_update(hipStream_t s, const Cols<T>& Q, const double* coef,
+                                  const T* w, int64_t n, T* partials, int nblk);
+// Gram: partials[(a*nb + b)*nblk + blk] = sum_rows X_a * Y_b
+template <class T>
+hipError_t gram(hipStream_t s, const Cols<T>& X, const Cols<T>& Y, int64_t n, T* partials,
+                int nblk);
+// out[:, o] = sum_c In_c * M[c + nin*o]   (o < nout; in place over In1 allowed)
+template <class T>
+hipError_t row_transform(hipStream_t s, const Cols<T>& In, const double* M, int nout, T* out,
+                         int64_t ldo, int64_t n);
+
+// out[c] = sum_blk partials[c*nblk + blk]   (fixed order, FP64)
+template <class T>
+hipError_t finish_sum(hipStream_t s, const T* partials, int nblk, int ncols, double* out);
+// CGS2 end: h2 = sum(partials[0..ncols)), nrm2 = sum(partials[ncols]);
+// hcol[c] = h1[c] + h2[c]; hcol[ncols] = sqrt(nrm2 - |h2|^2) (flag = 1 when the
+// Pythagorean form is unreliable and an explicit norm is needed); inv = 1/hcol[ncols].
+template <class T>
+hipError_t finish_cgs2(hipStream_t s, const T* partials, int nblk, int ncols, const double* h1,
+                       double* h2, double* hcol, double* inv, int* flag);
+
+// ---- BiCGStab fused passes (all scalars in the FP64 array `sc`) ----
+// scalar slots
+enum BicgSlot {
+  kRho = 0, kRhoOld, kAlpha, kOmega, kBeta, kRtv, kSnorm2, kRnorm2, kTs, kTt, kFlag,
+  kSlots
+};
+// BiCGStab pieces; `sums` are finished FP64 dot products.
+template <class T>
+hipError_t bicg_p(hipStream_t s, const T* r, T* p, const T* v, const double* sc, int64_t n);
+// eta1 = sums[0..kc), alpha = rho / (sums[kc] - ctrt . eta1)
+hipError_t bicg_alpha(hipStream_t s, const double* sums, int kc, double* sc, int off_eta1,
+                      int off_ctrt);
+// v -= C eta1 ; s = r - alpha v ; partial |s|^2
+template <class T>
+hipError_t bicg_sv(hipStream_t s, const Cols<T>& C, const T* r, T* v, T* sv, const double* sc,
+                   int off_eta1, int64_t n, T* partials, int nblk);
+// eta2 = sums[0..kc), omega = sums[kc] / (sums[kc+1] - |eta2|^2), xi += alpha eta1 + omega eta2
+hipError_t bicg_omega(hipStream_t s, const double* sums, int kc, double* sc, int off_eta1,
+                      int off_eta2, int off_xi);
+// y += alpha p + omega s ; r = s - omega (t - C eta2) ; partials r~.r, |r|^2
+template <class T>
+hipError_t bicg_yr(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, const T* p, T* y,
+                   T* r, const T* rt, const double* sc, int off_eta2, int64_t n, T* partials,
+                   int nblk);
+// rho_old = rho, rho = sums[0], rnorm2 = sums[1], beta = (rho/rho_old)(alpha/omega)
+hipError_t bicg_rho(hipStream_t s, const double* sums, double* sc);
+// line 10/10a early exit: y += alpha p ; r = s ; xi += alpha eta1
+template <class T>
+hipError_t bicg_exit_s(hipStream_t s, const T* p, T* y, const T* sv, T* r, double* sc,
+                       int off_eta1, int off_xi, int kc, int64_t n);
+// hcol_last = sqrt(*nrm2), inv = 1/hcol_last
+hipError_t set_norm_from_sum(hipStream_t s, const double* nrm2, double* hcol_last, double* inv);
+
+// misc
+template <class T>
+hipError_t fill(hipStream_t s, T* x, int64_t n, double v);
+template <class T>
+hipError_t copy(hipStream_t s, const T* x, T* y, int64_t n);
+// x32 = (float)(x64 * (*scale))
+hipError_t cast_scale_f64_f32(hipStream_t s, const double* x, float* y, int64_t n,
+                              const double* scale);
+// x64 += (*scale) * (double)d32
+hipError_t axpy_f32_into_f64(hipStream_t s, const float* d, double* x, int64_t n,
+                             const double* scale);
+
+}  // namespace krs

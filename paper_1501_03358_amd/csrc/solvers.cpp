@@ -1,0 +1,898 @@
+// Host drivers of the Krylov solvers: GMRES(m) (Alg. 1), rGCROT(m,k)/GCRODR
+// (Alg. 3) with the harmonic-Ritz recycle update, the thin-QR recycle setup
+// (Alg. 3 line 1a), rBiCGStab with one recycle space (Alg. 4) and FP64
+// iterative refinement around an FP32 inner solver.
+//
+// All vector work runs in the device kernels of kernels.hip; the host keeps
+// the small FP64 matrices (Hessenberg columns, Givens rotations, B = C^T A~ V,
+// the harmonic-Ritz eigenproblem) and reads a few scalars per step to drive
+// convergence tests.  Every solver is right-preconditioned and works on the
+// iterate y of A~ y = b with A~ = A M^-1, x = M^-1 y.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "dense.hpp"
+#include "internal.hpp"
+
+namespace krs {
+namespace {
+
+template <class T>
+struct Ws {
+  // scalar area layout (doubles)
+  static constexpr int kH1 = 0, kH2 = 128, kHcol = 256, kInv = 384, kFlagOff = 392;
+  static constexpr int kCoef = 512, kXi = 768, kNrm = 832, kAux = 840, kM = 1024;
+  static constexpr int kGram1 = 4096, kGram2 = 8192;
+};
+
+// y-space operator A~ = A M^-1 and its pieces
+template <class T>
+struct Op {
+  krs_ctx* ctx;
+  const krs_matrix* A;
+  const krs_precond* M;
+  Grid3 g;
+  T* z;     // M^-1 v
+  T* tmp;   // preconditioner temporary
+  const T* bands() const { return (const T*)A->bands; }
+
+  int minv(const T* r, T* out) {
+    hipStream_t s = ctx->stream;
+    const double NW = (double)g.n * sizeof(T);
+    if (!M || M->d.type == KRS_PC_NONE) {
+      KRS_CHECK_HIP(ctx, copy<T>(s, r, out, g.n));
+      ctx->bytes += 2 * NW;
+      return 0;
+    }
+    if (M->d.type == KRS_PC_JACOBI) {
+      KRS_CHECK_HIP(ctx, point_jacobi<T>(s, g, bands(), r, out));
+      ctx->bytes += 3 * NW;
+      return 0;
+    }
+    const int gs = M->d.global_sweeps;
+    T* first = (gs % 2 == 0) ? out : tmp;
+    if (M->d.local_sweeps > 0) {
+      KRS_CHECK_HIP(ctx, schwarz_local<T>(s, g, M->d.tile, bands(), r, first, M->d.omega_local,
+                                          M->d.local_sweeps));
+      ctx->bytes += 9 * NW;
+    } else {
+      KRS_CHECK_HIP(ctx, fill<T>(s, first, g.n, 0.0));
+      ctx->bytes += NW;
+    }
+    T* cur = first;
+    for (int i = 0; i < gs; ++i) {
+      T* nxt = (cur == out) ? tmp : out;
+      KRS_CHECK_HIP(ctx, jacobi_sweep<T>(s, g, bands(), r, cur, nxt, M->d.omega_global));
+      ctx->bytes += 10 * NW;
+      cur = nxt;
+    }
+    return 0;
+  }
+  // w = A M^-1 v
+  int apply(const T* v, T* w) {
+    int rc = minv(v, z);
+    if (rc) return rc;
+    KRS_CHECK_HIP(ctx, stencil<T>(ctx->stream, g, bands(), z, w, 1.0, 0.0, nullptr, 0));
+    ctx->bytes += 9.0 * g.n * sizeof(T);
+    return 0;
+  }
+};
+
+int read_dev(krs_ctx* ctx, const double* src, int count) {
+  KRS_CHECK_HIP(ctx, hipMemcpyAsync(ctx->pin, src, sizeof(double) * count, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+  KRS_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return 0;
+}
+
+int upload(krs_ctx* ctx, double* dst, const double* src, int count) {
+  double* stage = ctx->pin + kPinDoubles / 2;
+  KRS_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  std::memcpy(stage, src, sizeof(double) * count);
+  KRS_CHECK_HIP(ctx, hipMemcpyAsync(dst, stage, sizeof(double) * count, hipMemcpyHostToDevice,
+                                    ctx->stream));
+  KRS_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return 0;
+}
+
+template <class T>
+Cols<T> cols(const T* p1, int64_t ld1, int n1, const T* p2 = nullptr, int64_t ld2 = 0, int n2 = 0) {
+  Cols<T> c;
+  c.p1 = p1;
+  c.ld1 = ld1;
+  c.n1 = n1;
+  c.p2 = p2;
+  c.ld2 = ld2;
+  c.n2 = n2;
+  return c;
+}
+
+// ||w||^2 -> host
+template <class T>
+int norm2(krs_ctx* ctx, const T* w, int64_t n, T* part, double* d_out, double& out) {
+  const int nblk = red_blocks(n);
+  KRS_CHECK_HIP(ctx, block_dot<T>(ctx->stream, Cols<T>{}, w, n, 1, part, nblk));
+  KRS_CHECK_HIP(ctx, finish_sum<T>(ctx->stream, part, nblk, 1, d_out));
+  ctx->bytes += (double)n * sizeof(T);
+  int rc = read_dev(ctx, d_out, 1);
+  if (rc) return rc;
+  out = ctx->pin[0];
+  return 0;
+}
+
+void init_stats(krs_stats* st) {
+  if (!st) return;
+  std::memset(st, 0, sizeof(*st));
+  st->rel_res_true = NAN;
+  st->rel_res_est = NAN;
+}
+
+template <class T>
+size_t ws_gmres(int64_t n, int m) {
+  Carver c(nullptr, 0);
+  const int64_t ld = vec_ld(n);
+  c.vec<T>(ld * (m + 1));
+  c.vec<T>(ld);
+  c.vec<T>(ld);
+  c.take(partials_bytes(sizeof(T)));
+  c.vec<double>(kScalarDoubles);
+  return c.off;
+}
+
+template <class T>
+size_t ws_bicg(int64_t n) {
+  Carver c(nullptr, 0);
+  const int64_t ld = vec_ld(n);
+  for (int i = 0; i < 8; ++i) c.vec<T>(ld);
+  c.take(partials_bytes(sizeof(T)));
+  c.vec<double>(kScalarDoubles);
+  return c.off;
+}
+
+size_t ws_ir(int64_t n, int m) {
+  Carver c(nullptr, 0);
+  const int64_t ld = vec_ld(n);
+  c.take(std::max(ws_gmres<float>(n, m), ws_bicg<float>(n)));
+  c.vec<double>(ld);
+  c.vec<float>(ld);
+  c.vec<float>(ld);
+  c.take(partials_bytes(sizeof(double)));
+  c.vec<double>(kScalarDoubles);
+  return c.off;
+}
+
+// ---------------------------------------------------------------------------
+// recycle-space update, Alg. 3 line 14a (harmonic Ritz, GCRODR rule)
+// ---------------------------------------------------------------------------
+template <class T>
+int harmonic_update(krs_ctx* ctx, krs_recycle* rec, const T* V, int64_t ld, int jj,
+                    const std::vector<double>& Hbar, int ldh, const std::vector<double>& Bm,
+                    int ldb, int k, T* part, double* sc, krs_stats* st) {
+  hipStream_t s = ctx->stream;
+  const int64_t n = rec->n;
+  const int kc = rec->dim;
+  const int ng = kc + jj, mg = ng + 1;
+  if (jj == 0) return 0;
+  T* U = (T*)rec->U;
+  T* C = (T*)rec->C;
+  const int64_t ldr = rec->ld;
+  std::vector<double> dvec(kc), CtU((size_t)kc * kc), VtU((size_t)(jj + 1) * kc);
+  if (kc > 0) {
+    const int na = kc + jj + 1;
+    KRS_CHECK_HIP(ctx, gram<T>(s, cols<T>(C, ldr, kc, V, ld, jj + 1), cols<T>(U, ldr, kc), n, part,
+                               kGramBlocks));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, kGramBlocks, na * kc, sc + Ws<T>::kGram1));
+    KRS_CHECK_HIP(ctx, gram<T>(s, cols<T>(U, ldr, kc), cols<T>(U, ldr, kc), n, part, kGramBlocks));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, kGramBlocks, kc * kc, sc + Ws<T>::kGram2));
+    ctx->bytes += (double)n * sizeof(T) * (2 * kc + jj + 1 + kc);
+    int rc = read_dev(ctx, sc + Ws<T>::kGram1, na * kc);
+    if (rc) return rc;
+    for (int a = 0; a < kc; ++a)
+      for (int b = 0; b < kc; ++b) CtU[a + (size_t)kc * b] = ctx->pin[a * kc + b];
+    for (int r = 0; r <= jj; ++r)
+      for (int b = 0; b < kc; ++b) VtU[r + (size_t)(jj + 1) * b] = ctx->pin[(kc + r) * kc + b];
+    rc = read_dev(ctx, sc + Ws<T>::kGram2, kc * kc);
+    if (rc) return rc;
+    for (int i = 0; i < kc; ++i) dvec[i] = 1.0 / std::sqrt(ctx->pin[i * kc + i]);
+  }
+  Timer te;
+  // G = [[D, B], [0, Hbar]]
+  std::vector<double> G((size_t)mg * ng, 0.0);
+  auto gref = [&](int i, int j) -> double& { return G[i + (size_t)mg * j]; };
+  for (int i = 0; i < kc; ++i) gref(i, i) = dvec[i];
+  for (int j = 0; j < jj; ++j)
+    for (int i = 0; i < kc; ++i) gref(i, kc + j) = Bm[i + (size_t)ldb * j];
+  for (int j = 0; j < jj; ++j)
+    for (int i = 0; i <= jj; ++i) gref(kc + i, kc + j) = Hbar[i + (size_t)ldh * j];
+  std::vector<double> P;
+  int kk = 0, ties = 0;
+  if (ng <= k) {
+    kk = ng;
+    P.assign((size_t)ng * ng, 0.0);
+    for (int i = 0; i < ng; ++i) P[i + (size_t)ng * i] = 1.0;
+  } else {
+    // F = W^T V^ = [[C^T U D, 0], [V_{j+1}^T U D, I~]]
+    std::vector<double> F((size_t)mg * ng, 0.0);
+    for (int b = 0; b < kc; ++b) {
+      for (int a = 0; a < kc; ++a) F[a + (size_t)mg * b] = CtU[a + (size_t)kc * b] * dvec[b];
+      for (int r = 0; r <= jj; ++r)
+        F[kc + r + (size_t)mg * b] = VtU[r + (size_t)(jj + 1) * b] * dvec[b];
+    }
+    for (int c = 0; c < jj; ++c) F[kc + c + (size_t)mg * (kc + c)] = 1.0;
+    if (!dense::harmonic_ritz_select(mg, ng, G.data(), F.data(), k, P, kk, ties)) {
+      if (st) st->host_eig_ms += te.ms();
+      return set_err(ctx, KRS_ERR_EIG, "harmonic Ritz eigen-solver failed");
+    }
+  }
+  // [Q, R] = qr(G P);  U <- V^ P R^-1 (D folded in), C <- W^ Q
+  std::vector<double> GP((size_t)mg * kk, 0.0);
+  for (int c = 0; c < kk; ++c)
+    for (int j = 0; j < ng; ++j) {
+      const double pj = P[j + (size_t)ng * c];
+      if (pj == 0) continue;
+      for (int i = 0; i < mg; ++i) GP[i + (size_t)mg * c] += G[i + (size_t)mg * j] * pj;
+    }
+  std::vector<double> Q((size_t)mg * kk), R((size_t)kk * kk), Ri((size_t)kk * kk);
+  dense::qr_thin(mg, kk, GP.data(), Q.data(), R.data());
+  if (!dense::upper_inverse(kk, R.data(), Ri.data())) {
+    if (st) st->host_eig_ms += te.ms();
+    return set_err(ctx, KRS_ERR_EIG, "recycle update: singular R");
+  }
+  std::vector<double> Mu((size_t)ng * kk, 0.0);
+  for (int c = 0; c < kk; ++c)
+    for (int i = 0; i < ng; ++i) {
+      double sum = 0;
+      for (int q = 0; q <= c; ++q) sum += P[i + (size_t)ng * q] * Ri[q + (size_t)kk * c];
+      Mu[i + (size_t)ng * c] = (i < kc ? dvec[i] : 1.0) * sum;
+    }
+  if (st) {
+    st->host_eig_ms += te.ms();
+    st->eig_ties += ties;
+  }
+  std::vector<double> both(Mu);
+  both.insert(both.end(), Q.begin(), Q.end());
+  int rc = upload(ctx, sc + Ws<T>::kM, both.data(), (int)both.size());
+  if (rc) return rc;
+  KRS_CHECK_HIP(ctx, row_transform<T>(s, cols<T>(U, ldr, kc, V, ld, jj), sc + Ws<T>::kM, kk, U, ldr,
+                                      n));
+  KRS_CHECK_HIP(ctx, row_transform<T>(s, cols<T>(C, ldr, kc, V, ld, jj + 1),
+                                      sc + Ws<T>::kM + (size_t)ng * kk, kk, C, ldr, n));
+  ctx->bytes += (double)n * sizeof(T) * ((kc + jj + kk) + (kc + jj + 1 + kk));
+  rec->dim = kk;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES(m) and rGCROT(m,k)
+// ---------------------------------------------------------------------------
+template <class T>
+int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
+                   bool update, const T* b, T* x, const krs_opts* o, void* ws, size_t wsb,
+                   krs_stats* st) {
+  Timer tm;
+  const double bytes0 = ctx->bytes;
+  hipStream_t s = ctx->stream;
+  const int64_t n = A->n;
+  const int64_t ld = vec_ld(n);
+  const int m = o->m;
+  const double tol = o->tol;
+  const int64_t maxit = o->max_matvecs > 0 ? o->max_matvecs : 2000;
+  Carver cv(ws, wsb);
+  T* V = cv.vec<T>(ld * (m + 1));
+  T* z = cv.vec<T>(ld);
+  T* w = cv.vec<T>(ld);  // A~ v_j; doubles as the preconditioner temporary
+  T* part = (T*)cv.take(partials_bytes(sizeof(T)));
+  double* sc = cv.vec<double>(kScalarDoubles);
+  if (!ws || !cv.ok) return set_err(ctx, KRS_ERR_WORKSPACE, "workspace missing or too small");
+  double* d_h1 = sc + Ws<T>::kH1;
+  double* d_h2 = sc + Ws<T>::kH2;
+  double* d_hcol = sc + Ws<T>::kHcol;
+  double* d_inv = sc + Ws<T>::kInv;
+  int* d_flag = (int*)(sc + Ws<T>::kFlagOff);
+  double* d_coef = sc + Ws<T>::kCoef;
+  double* d_xi = sc + Ws<T>::kXi;
+  double* d_nrm = sc + Ws<T>::kNrm;
+  const int nblk = red_blocks(n);
+  Op<T> op{ctx, A, M, grid3(A), z, w};
+  const double NW = (double)n * sizeof(T);
+
+  init_stats(st);
+  double nb2 = 0;
+  int rc = norm2<T>(ctx, b, n, part, d_nrm, nb2);
+  if (rc) return rc;
+  const double nb = std::sqrt(nb2);
+  if (nb == 0 || !std::isfinite(nb)) {
+    KRS_CHECK_HIP(ctx, fill<T>(s, x, n, 0.0));
+    KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
+    if (st) {
+      st->status = std::isfinite(nb) ? KRS_OK : KRS_DIVERGED;
+      st->rel_res_true = 0;
+      st->time_ms = tm.ms();
+    }
+    return std::isfinite(nb) ? KRS_OK : KRS_DIVERGED;
+  }
+  T* U = rec ? (T*)rec->U : nullptr;
+  T* C = rec ? (T*)rec->C : nullptr;
+  const int64_t ldr = rec ? rec->ld : 0;
+  int kc = rec ? rec->dim : 0;
+  T* r0 = V;  // the residual lives in the first basis column
+  double rho2 = 0;
+  // Alg. 3 line 1b: xi = C^T b, r = b - C xi, y = U xi
+  if (kc > 0) {
+    KRS_CHECK_HIP(ctx, block_dot<T>(s, cols<T>(C, ldr, kc), b, n, 0, part, nblk));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, kc, d_xi));
+    KRS_CHECK_HIP(ctx, block_update<T>(s, cols<T>(C, ldr, kc), d_xi, -1.0, b, r0, n, nullptr, 1,
+                                       part, nblk));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, d_nrm));
+    KRS_CHECK_HIP(ctx, block_update<T>(s, cols<T>(U, ldr, kc), d_xi, 1.0, nullptr, x, n, nullptr, 0,
+                                       part, nblk));
+    ctx->bytes += NW * ((kc + 1) + (kc + 2) + (kc + 1));
+    rc = read_dev(ctx, d_nrm, 1);
+    if (rc) return rc;
+    rho2 = ctx->pin[0];
+  } else {
+    KRS_CHECK_HIP(ctx, copy<T>(s, b, r0, n));
+    KRS_CHECK_HIP(ctx, fill<T>(s, x, n, 0.0));
+    ctx->bytes += 3 * NW;
+    rho2 = nb2;
+  }
+  double rho = std::sqrt(rho2);
+
+  const int ldh = m + 1;
+  const int ldb = kMaxK;
+  std::vector<double> Hbar((size_t)ldh * m), Rr((size_t)ldh * m), Bm((size_t)ldb * m);
+  std::vector<double> cs(m), sn(m), gv(m + 1), hc(m + 1), yv(m), coef(m + kMaxK);
+  int64_t its = 0, mv = 0, cycles = 0, hlen = 0;
+  int status = KRS_NOT_CONVERGED;
+  double est = rho;
+  while (rho > tol * nb && its < maxit) {
+    kc = rec ? rec->dim : 0;
+    // v_1 = r / rho
+    const double inv_rho = 1.0 / rho;
+    rc = upload(ctx, d_inv, &inv_rho, 1);
+    if (rc) return rc;
+    KRS_CHECK_HIP(ctx, block_update<T>(s, Cols<T>{}, nullptr, 0.0, r0, V, n, d_inv, 0, part, nblk));
+    ctx->bytes += 2 * NW;
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = rho;
+    std::fill(Hbar.begin(), Hbar.end(), 0.0);
+    std::fill(Bm.begin(), Bm.end(), 0.0);
+    int jj = 0;
+    for (int j = 0; j < m; ++j) {
+      T* vj = V + (int64_t)j * ld;
+      T* vn = V + (int64_t)(j + 1) * ld;
+      rc = op.apply(vj, w);                              // line 6
+      if (rc) return rc;
+      ++its;
+      ++mv;
+      const int ncols = kc + j + 1;
+      const Cols<T> Q = cols<T>(C, ldr, kc, V, ld, j + 1);
+      // lines 6a-9 as two classical Gram-Schmidt passes against [C, V_j]
+      KRS_CHECK_HIP(ctx, block_dot<T>(s, Q, w, n, 0, part, nblk));
+      KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, ncols, d_h1));
+      KRS_CHECK_HIP(ctx, block_dot_after_update<T>(s, Q, d_h1, w, n, part, nblk));
+      KRS_CHECK_HIP(ctx, finish_cgs2<T>(s, part, nblk, ncols, d_h1, d_h2, d_hcol, d_inv, d_flag));
+      // line 10: v_{j+1} = (w - Q h) / h_{j+1,j}
+      KRS_CHECK_HIP(ctx, block_update<T>(s, Q, d_hcol, -1.0, w, vn, n, d_inv, 0, part, nblk));
+      ctx->bytes += NW * ((ncols + 1) + (ncols + 1) + (ncols + 2));
+      rc = read_dev(ctx, sc, Ws<T>::kFlagOff + 1);
+      if (rc) return rc;
+      std::vector<double> hv(ctx->pin + Ws<T>::kHcol, ctx->pin + Ws<T>::kHcol + ncols + 1);
+      int flag = *(int*)(ctx->pin + Ws<T>::kFlagOff);
+      if (flag) {
+        // norm from the Pythagorean identity unreliable: recompute explicitly
+        KRS_CHECK_HIP(ctx, block_update<T>(s, Q, d_hcol, -1.0, w, vn, n, nullptr, 1, part, nblk));
+        KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, d_nrm));
+        KRS_CHECK_HIP(ctx, set_norm_from_sum(s, d_nrm, d_hcol + ncols, d_inv));
+        KRS_CHECK_HIP(ctx, block_update<T>(s, Cols<T>{}, nullptr, 0.0, vn, vn, n, d_inv, 0, part,
+                                           nblk));
+        ctx->bytes += NW * (ncols + 2 + 2);
+        rc = read_dev(ctx, d_hcol + ncols, 1);
+        if (rc) return rc;
+        hv[ncols] = ctx->pin[0];
+      }
+      for (int i = 0; i < kc; ++i) Bm[i + (size_t)ldb * j] = hv[i];
+      for (int i = 0; i <= j; ++i) Hbar[i + (size_t)ldh * j] = hv[kc + i];
+      Hbar[(j + 1) + (size_t)ldh * j] = hv[ncols];
+      // Givens rotations for the least-squares problem of line 12
+      for (int i = 0; i <= j + 1; ++i) hc[i] = Hbar[i + (size_t)ldh * j];
+      for (int i = 0; i < j; ++i) {
+        const double a = hc[i], bb = hc[i + 1];
+        hc[i] = cs[i] * a + sn[i] * bb;
+        hc[i + 1] = -sn[i] * a + cs[i] * bb;
+      }
+      const double a = hc[j], bb = hc[j + 1];
+      const double rr = std::hypot(a, bb);
+      cs[j] = rr > 0 ? a / rr : 1.0;
+      sn[j] = rr > 0 ? bb / rr : 0.0;
+      hc[j] = rr;
+      hc[j + 1] = 0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      for (int i = 0; i <= j + 1; ++i) Rr[i + (size_t)ldh * j] = hc[i];
+      est = std::fabs(gv[j + 1]);
+      if (o->history && hlen < o->history_cap) o->history[hlen] = est / nb;
+      ++hlen;
+      jj = j + 1;
+      if (!std::isfinite(est)) break;
+      if (est <= tol * nb || hv[ncols] == 0.0 || its >= maxit) break;
+    }
+    // line 12: y = R^-1 g ; line 12a: z = -B y ; lines 13-13a: y_acc += V y + U z
+    dense::upper_solve(jj, Rr.data(), ldh, gv.data(), yv.data());
+    for (int i = 0; i < jj; ++i) coef[i] = yv[i];
+    for (int c = 0; c < kc; ++c) {
+      double sum = 0;
+      for (int j = 0; j < jj; ++j) sum += Bm[c + (size_t)ldb * j] * yv[j];
+      coef[jj + c] = -sum;
+    }
+    rc = upload(ctx, d_coef, coef.data(), jj + kc);
+    if (rc) return rc;
+    KRS_CHECK_HIP(ctx, block_update<T>(s, cols<T>(V, ld, jj, U, ldr, kc), d_coef, 1.0, x, x, n,
+                                       nullptr, 0, part, nblk));
+    ctx->bytes += NW * (jj + kc + 2);
+    ++cycles;
+    // line 14a: recycle-space update
+    if (update && rec) {
+      rc = harmonic_update<T>(ctx, rec, V, ld, jj, Hbar, ldh, Bm, ldb, o->k, part, sc, st);
+      if (rc) return rc;
+    }
+    // line 14: true residual r = b - A~ y (into the first basis column)
+    rc = op.minv(x, z);
+    if (rc) return rc;
+    KRS_CHECK_HIP(ctx, residual_norm<T>(s, op.g, op.bands(), z, b, r0, part));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, d_nrm));
+    ctx->bytes += 10 * NW;
+    ++mv;
+    kc = rec ? rec->dim : 0;
+    if (kc > 0) {
+      // re-project against the (new) C: xi = C^T r, r -= C xi, y += U xi
+      KRS_CHECK_HIP(ctx, block_dot<T>(s, cols<T>(C, ldr, kc), r0, n, 0, part, nblk));
+      KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, kc, d_xi));
+      KRS_CHECK_HIP(ctx, block_update<T>(s, cols<T>(C, ldr, kc), d_xi, -1.0, r0, r0, n, nullptr, 1,
+                                         part, nblk));
+      KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, d_nrm));
+      KRS_CHECK_HIP(ctx, block_update<T>(s, cols<T>(U, ldr, kc), d_xi, 1.0, x, x, n, nullptr, 0,
+                                         part, nblk));
+      ctx->bytes += NW * ((kc + 1) + (kc + 2) + (kc + 2));
+    }
+    rc = read_dev(ctx, d_nrm, 1);
+    if (rc) return rc;
+    rho = std::sqrt(ctx->pin[0]);
+    if (!std::isfinite(rho)) {
+      status = KRS_DIVERGED;
+      break;
+    }
+  }
+  if (status != KRS_DIVERGED && rho <= tol * nb) status = KRS_OK;
+  // x = M^-1 y
+  rc = op.minv(x, z);
+  if (rc) return rc;
+  KRS_CHECK_HIP(ctx, copy<T>(s, z, x, n));
+  KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
+  ctx->bytes += 2 * NW;
+  if (st) {
+    st->status = status;
+    st->matvecs = mv;
+    st->iterations = its;
+    st->cycles = cycles;
+    st->history_len = hlen;
+    st->rel_res_true = rho / nb;
+    st->rel_res_est = est / nb;
+    st->time_ms = tm.ms();
+    st->bytes_model = ctx->bytes - bytes0;
+  }
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 3 line 1a: C~ = A~ U, C~ = C R (Cholesky QR, twice), U <- U R^-1
+// ---------------------------------------------------------------------------
+template <class T>
+int recycle_setup_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
+                    void* ws, size_t wsb) {
+  hipStream_t s = ctx->stream;
+  const int64_t n = A->n, ld = vec_ld(n);
+  Carver cv(ws, wsb);
+  T* z = cv.vec<T>(ld);
+  T* tmp = cv.vec<T>(ld);
+  T* part = (T*)cv.take(partials_bytes(sizeof(T)));
+  double* sc = cv.vec<double>(kScalarDoubles);
+  if (!ws || !cv.ok) return set_err(ctx, KRS_ERR_WORKSPACE, "workspace missing or too small");
+  const int kc = rec->dim;
+  if (kc == 0) return 0;
+  T* U = (T*)rec->U;
+  T* C = (T*)rec->C;
+  const int64_t ldr = rec->ld;
+  Op<T> op{ctx, A, M, grid3(A), z, tmp};
+  for (int c = 0; c < kc; ++c) {
+    int rc = op.apply(U + (int64_t)c * ldr, C + (int64_t)c * ldr);
+    if (rc) return rc;
+  }
+  std::vector<double> G((size_t)kc * kc), R((size_t)kc * kc), Ri((size_t)kc * kc);
+  for (int pass = 0; pass < 2; ++pass) {
+    KRS_CHECK_HIP(ctx, gram<T>(s, cols<T>(C, ldr, kc), cols<T>(C, ldr, kc), n, part, kGramBlocks));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, kGramBlocks, kc * kc, sc + Ws<T>::kGram1));
+    int rc = read_dev(ctx, sc + Ws<T>::kGram1, kc * kc);
+    if (rc) return rc;
+    for (int a = 0; a < kc; ++a)
+      for (int b = 0; b < kc; ++b) G[a + (size_t)kc * b] = ctx->pin[a * kc + b];
+    if (!dense::cholesky_upper(kc, G.data(), R.data()) ||
+        !dense::upper_inverse(kc, R.data(), Ri.data()))
+      return set_err(ctx, KRS_ERR_STATE, "recycle setup: A~ U is rank deficient");
+    rc = upload(ctx, sc + Ws<T>::kM, Ri.data(), kc * kc);
+    if (rc) return rc;
+    KRS_CHECK_HIP(ctx, row_transform<T>(s, cols<T>(C, ldr, kc), sc + Ws<T>::kM, kc, C, ldr, n));
+    KRS_CHECK_HIP(ctx, row_transform<T>(s, cols<T>(U, ldr, kc), sc + Ws<T>::kM, kc, U, ldr, n));
+    ctx->bytes += (double)n * sizeof(T) * (kc + 4 * kc);
+  }
+  KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// rBiCGStab with one recycle space (Alg. 4); Alg. 2 when the space is empty
+// ---------------------------------------------------------------------------
+template <class T>
+int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const krs_recycle* rec,
+                const T* b, T* x, const krs_opts* o, void* ws, size_t wsb, krs_stats* st) {
+  Timer tm;
+  const double bytes0 = ctx->bytes;
+  hipStream_t s = ctx->stream;
+  const int64_t n = A->n, ld = vec_ld(n);
+  Carver cv(ws, wsb);
+  T* r = cv.vec<T>(ld);
+  T* rt = cv.vec<T>(ld);
+  T* p = cv.vec<T>(ld);
+  T* v = cv.vec<T>(ld);
+  T* sv = cv.vec<T>(ld);
+  T* t = cv.vec<T>(ld);
+  T* z = cv.vec<T>(ld);
+  T* tmp = cv.vec<T>(ld);
+  T* part = (T*)cv.take(partials_bytes(sizeof(T)));
+  double* sc = cv.vec<double>(kScalarDoubles);
+  if (!ws || !cv.ok) return set_err(ctx, KRS_ERR_WORKSPACE, "workspace missing or too small");
+  const int kSums = 32, kEta1 = 128, kEta2 = 192, kXi = 256, kCtrt = 320, kNrm = 384;
+  const int nblk = red_blocks(n);
+  const double NW = (double)n * sizeof(T);
+  const double tol = o->tol;
+  const int64_t maxmv = o->max_matvecs > 0 ? o->max_matvecs : 2000;
+  Op<T> op{ctx, A, M, grid3(A), z, tmp};
+  init_stats(st);
+  double nb2 = 0;
+  int rc = norm2<T>(ctx, b, n, part, sc + kNrm, nb2);
+  if (rc) return rc;
+  const double nb = std::sqrt(nb2);
+  if (nb == 0 || !std::isfinite(nb)) {
+    KRS_CHECK_HIP(ctx, fill<T>(s, x, n, 0.0));
+    KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
+    if (st) {
+      st->status = std::isfinite(nb) ? KRS_OK : KRS_DIVERGED;
+      st->rel_res_true = 0;
+      st->time_ms = tm.ms();
+    }
+    return std::isfinite(nb) ? KRS_OK : KRS_DIVERGED;
+  }
+  const int kc = rec ? rec->dim : 0;
+  const T* U = rec ? (const T*)rec->U : nullptr;
+  const T* C = rec ? (const T*)rec->C : nullptr;
+  const int64_t ldr = rec ? rec->ld : 0;
+  const Cols<T> Cc = cols<T>(C, ldr, kc);
+  std::vector<double> slots(kSlots, 0.0);
+  double rn2 = nb2;
+  // line 1c: eta1 = C^T b, r0 = b - C eta1, xi = -eta1
+  if (kc > 0) {
+    KRS_CHECK_HIP(ctx, block_dot<T>(s, Cc, b, n, 0, part, nblk));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, kc, sc + kEta1));
+    KRS_CHECK_HIP(ctx, block_update<T>(s, Cc, sc + kEta1, -1.0, b, r, n, nullptr, 1, part, nblk));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, sc + kNrm));
+    ctx->bytes += NW * ((kc + 1) + (kc + 2));
+    rc = read_dev(ctx, sc + kEta1, kc);
+    if (rc) return rc;
+    std::vector<double> xi(kc);
+    for (int c = 0; c < kc; ++c) xi[c] = -ctx->pin[c];
+    rc = upload(ctx, sc + kXi, xi.data(), kc);
+    if (rc) return rc;
+    rc = read_dev(ctx, sc + kNrm, 1);
+    if (rc) return rc;
+    rn2 = ctx->pin[0];
+  } else {
+    KRS_CHECK_HIP(ctx, copy<T>(s, b, r, n));
+    ctx->bytes += 2 * NW;
+  }
+  // line 2: r~ = r_0 ; C^T r~ for the alpha denominator
+  KRS_CHECK_HIP(ctx, copy<T>(s, r, rt, n));
+  if (kc > 0) {
+    KRS_CHECK_HIP(ctx, block_dot<T>(s, Cc, rt, n, 0, part, nblk));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, kc, sc + kCtrt));
+    ctx->bytes += NW * (kc + 1);
+  }
+  KRS_CHECK_HIP(ctx, fill<T>(s, p, n, 0.0));
+  KRS_CHECK_HIP(ctx, fill<T>(s, v, n, 0.0));
+  KRS_CHECK_HIP(ctx, fill<T>(s, x, n, 0.0));
+  ctx->bytes += 5 * NW;
+  slots[kRho] = rn2;  // r~ = r
+  slots[kOmega] = 1.0;
+  slots[kBeta] = 0.0;
+  slots[kRnorm2] = rn2;
+  rc = upload(ctx, sc, slots.data(), kSlots);
+  if (rc) return rc;
+  double rnorm = std::sqrt(rn2);
+  double rho = rn2;
+  int64_t its = 0, mv = 0, hlen = 0;
+  int status = KRS_NOT_CONVERGED;
+  const double div = o->div_factor;
+  auto hist = [&](double val) {
+    if (o->history && hlen < o->history_cap) o->history[hlen] = val;
+    ++hlen;
+  };
+  while (rnorm > tol * nb && mv < maxmv) {
+    if (rho == 0.0) {                                        // line 5
+      status = KRS_BREAKDOWN;
+      break;
+    }
+    KRS_CHECK_HIP(ctx, bicg_p<T>(s, r, p, v, sc, n));       // line 6
+    rc = op.apply(p, v);                                     // line 7
+    if (rc) return rc;
+    ++mv;
+    // line 7a-8: eta1 = C^T v, v -= C eta1, alpha = rho / r~^T v, s = r - alpha v
+    KRS_CHECK_HIP(ctx, block_dot<T>(s, cols<T>(C, ldr, kc, rt, ld, 1), v, n, 0, part, nblk));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, kc + 1, sc + kSums));
+    KRS_CHECK_HIP(ctx, bicg_alpha(s, sc + kSums, kc, sc, kEta1, kCtrt));
+    KRS_CHECK_HIP(ctx, bicg_sv<T>(s, Cc, r, v, sv, sc, kEta1, n, part, nblk));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, sc + kSnorm2));
+    ctx->bytes += NW * (4 + (kc + 2) + (kc + 4));
+    rc = read_dev(ctx, sc, kSlots);
+    if (rc) return rc;
+    std::copy(ctx->pin, ctx->pin + kSlots, slots.begin());
+    ++its;
+    if (slots[kFlag] != 0.0) {
+      status = KRS_BREAKDOWN;
+      break;
+    }
+    const double snorm = std::sqrt(slots[kSnorm2]);
+    hist(snorm / nb);
+    if (!std::isfinite(snorm)) {
+      status = KRS_DIVERGED;
+      break;
+    }
+    if (snorm <= tol * nb) {                                // lines 9-10a
+      KRS_CHECK_HIP(ctx, bicg_exit_s<T>(s, p, x, sv, r, sc, kEta1, kXi, kc, n));
+      ctx->bytes += 5 * NW;
+      rnorm = snorm;
+      break;
+    }
+    rc = op.apply(sv, t);                                    // line 12
+    if (rc) return rc;
+    ++mv;
+    // line 12a-13a: eta2 = C^T t, omega = t^T s / |t - C eta2|^2, xi update
+    KRS_CHECK_HIP(ctx, block_dot<T>(s, cols<T>(C, ldr, kc, sv, ld, 1), t, n, 1, part, nblk));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, kc + 2, sc + kSums));
+    KRS_CHECK_HIP(ctx, bicg_omega(s, sc + kSums, kc, sc, kEta1, kEta2, kXi));
+    // lines 14-16 with the next rho = r~^T r
+    KRS_CHECK_HIP(ctx, bicg_yr<T>(s, Cc, t, sv, p, x, r, rt, sc, kEta2, n, part, nblk));
+    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 2, sc + kSums));
+    KRS_CHECK_HIP(ctx, bicg_rho(s, sc + kSums, sc));
+    ctx->bytes += NW * ((kc + 2) + (kc + 7));
+    rc = read_dev(ctx, sc, kSlots);
+    if (rc) return rc;
+    std::copy(ctx->pin, ctx->pin + kSlots, slots.begin());
+    rnorm = std::sqrt(slots[kRnorm2]);
+    rho = slots[kRho];
+    hist(rnorm / nb);
+    if (slots[kFlag] != 0.0) {
+      status = KRS_BREAKDOWN;
+      break;
+    }
+    if (!std::isfinite(rnorm) || (div > 0 && rnorm > div * nb)) {
+      status = KRS_DIVERGED;
+      break;
+    }
+  }
+  if (status == KRS_NOT_CONVERGED && rnorm <= tol * nb) status = KRS_OK;
+  // line 17a: y -= U xi ; then x = M^-1 y
+  if (kc > 0) {
+    KRS_CHECK_HIP(ctx, block_update<T>(s, cols<T>(U, ldr, kc), sc + kXi, -1.0, x, x, n, nullptr, 0,
+                                       part, nblk));
+    ctx->bytes += NW * (kc + 2);
+  }
+  rc = op.minv(x, z);
+  if (rc) return rc;
+  KRS_CHECK_HIP(ctx, copy<T>(s, z, x, n));
+  // true residual of x
+  KRS_CHECK_HIP(ctx, residual_norm<T>(s, op.g, op.bands(), x, b, t, part));
+  KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, sc + kNrm));
+  ctx->bytes += 12 * NW;
+  rc = read_dev(ctx, sc + kNrm, 1);
+  if (rc) return rc;
+  if (st) {
+    st->status = status;
+    st->matvecs = mv + 1;
+    st->iterations = its;
+    st->history_len = hlen;
+    st->rel_res_true = std::sqrt(ctx->pin[0]) / nb;
+    st->rel_res_est = rnorm / nb;
+    st->time_ms = tm.ms();
+    st->bytes_model = ctx->bytes - bytes0;
+  }
+  return status;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// dtype dispatch
+// ---------------------------------------------------------------------------
+int workspace_bytes(krs_solver solver, int64_t n, int m, int k, krs_dtype dt, size_t* bytes) {
+  (void)k;
+  const bool f64 = dt == KRS_F64;
+  size_t v = 0;
+  switch (solver) {
+    case KRS_SOLVER_GMRES:
+    case KRS_SOLVER_RGCROT:
+      v = f64 ? std::max(ws_gmres<double>(n, m), ws_bicg<double>(n))
+              : std::max(ws_gmres<float>(n, m), ws_bicg<float>(n));
+      break;
+    case KRS_SOLVER_RBICGSTAB:
+      v = f64 ? ws_bicg<double>(n) : ws_bicg<float>(n);
+      break;
+    case KRS_SOLVER_IR:
+      v = ws_ir(n, m);
+      break;
+    default:
+      return KRS_ERR_ARG;
+  }
+  *bytes = v;
+  return KRS_OK;
+}
+
+int precond_apply(krs_ctx* ctx, const krs_precond* M, const void* r, void* z, void* tmp) {
+  const krs_matrix* A = M->A;
+  if (A->dt == KRS_F64) {
+    Op<double> op{ctx, A, M, grid3(A), nullptr, (double*)tmp};
+    return op.minv((const double*)r, (double*)z);
+  }
+  Op<float> op{ctx, A, M, grid3(A), nullptr, (float*)tmp};
+  return op.minv((const float*)r, (float*)z);
+}
+
+int gmres_rgcrot(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
+                 bool update, const void* b, void* x, const krs_opts* o, void* ws, size_t wsb,
+                 krs_stats* st) {
+  ctx->bytes = 0;
+  if (A->dt == KRS_F64)
+    return gmres_rgcrot_t<double>(ctx, A, M, rec, update, (const double*)b, (double*)x, o, ws, wsb,
+                                  st);
+  return gmres_rgcrot_t<float>(ctx, A, M, rec, update, (const float*)b, (float*)x, o, ws, wsb, st);
+}
+
+int rbicgstab(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const krs_recycle* rec,
+              const void* b, void* x, const krs_opts* o, void* ws, size_t wsb, krs_stats* st) {
+  ctx->bytes = 0;
+  if (A->dt == KRS_F64)
+    return rbicgstab_t<double>(ctx, A, M, rec, (const double*)b, (double*)x, o, ws, wsb, st);
+  return rbicgstab_t<float>(ctx, A, M, rec, (const float*)b, (float*)x, o, ws, wsb, st);
+}
+
+int recycle_setup(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
+                  void* ws, size_t wsb) {
+  ctx->bytes = 0;
+  if (A->dt == KRS_F64) return recycle_setup_t<double>(ctx, A, M, rec, ws, wsb);
+  return recycle_setup_t<float>(ctx, A, M, rec, ws, wsb);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 iterative refinement around an FP32 inner solver
+// ---------------------------------------------------------------------------
+int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const krs_precond* M32,
+             krs_recycle* rec32, const void* bv, void* xv, const krs_opts* o, void* ws,
+             size_t wsb, krs_stats* st) {
+  Timer tm;
+  hipStream_t s = ctx->stream;
+  const int64_t n = A64->n, ld = vec_ld(n);
+  const double* b = (const double*)bv;
+  double* x = (double*)xv;
+  const size_t inner_bytes = std::max(ws_gmres<float>(n, o->m), ws_bicg<float>(n));
+  Carver cv(ws, wsb);
+  void* inner = cv.take(inner_bytes);
+  double* r64 = cv.vec<double>(ld);
+  float* b32 = cv.vec<float>(ld);
+  float* d32 = cv.vec<float>(ld);
+  double* part = (double*)cv.take(partials_bytes(sizeof(double)));
+  double* sc = cv.vec<double>(kScalarDoubles);
+  if (!ws || !cv.ok) return set_err(ctx, KRS_ERR_WORKSPACE, "workspace missing or too small");
+  const int nblk = red_blocks(n);
+  const Grid3 g = grid3(A64);
+  init_stats(st);
+  double total_bytes = 0;
+  double nb2 = 0;
+  ctx->bytes = 0;
+  int rc = norm2<double>(ctx, b, n, part, sc, nb2);
+  if (rc) return rc;
+  const double nb = std::sqrt(nb2);
+  KRS_CHECK_HIP(ctx, fill<double>(s, x, n, 0.0));
+  KRS_CHECK_HIP(ctx, copy<double>(s, b, r64, n));
+  total_bytes += ctx->bytes + 3.0 * 8 * n;
+  double rn = nb;
+  int status = KRS_NOT_CONVERGED;
+  int64_t outer = 0, its = 0, mv = 0, cycles = 0;
+  krs_opts io = *o;
+  io.tol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
+  io.history = nullptr;
+  io.history_cap = 0;
+  const int max_outer = o->max_outer > 0 ? o->max_outer : 20;
+  double host_eig = 0;
+  int ties = 0;
+  if (!(nb > 0)) {
+    if (st) {
+      st->status = std::isfinite(nb) ? KRS_OK : KRS_DIVERGED;
+      st->rel_res_true = 0;
+    }
+    return std::isfinite(nb) ? KRS_OK : KRS_DIVERGED;
+  }
+  while (rn > o->tol * nb && outer < max_outer) {
+    // scaled FP32 right-hand side r / ||r||
+    const double sv[2] = {1.0 / rn, rn};
+    rc = upload(ctx, sc + 16, sv, 2);
+    if (rc) return rc;
+    KRS_CHECK_HIP(ctx, cast_scale_f64_f32(s, r64, b32, n, sc + 16));
+    krs_stats ist;
+    int irc;
+    if (o->inner_solver == KRS_SOLVER_RBICGSTAB) {
+      irc = rbicgstab(ctx, A32, M32, rec32, b32, d32, &io, inner, inner_bytes, &ist);
+      if (irc == KRS_BREAKDOWN || irc == KRS_DIVERGED) {
+        // switch back to rGCROT for this correction (Sec. 2.4)
+        its += ist.iterations;
+        mv += ist.matvecs;
+        total_bytes += ist.bytes_model;
+        irc = gmres_rgcrot(ctx, A32, M32, rec32, true, b32, d32, &io, inner, inner_bytes, &ist);
+      }
+    } else {
+      irc = gmres_rgcrot(ctx, A32, M32, rec32, o->update_recycle != 0, b32, d32, &io, inner,
+                         inner_bytes, &ist);
+    }
+    if (irc < 0) return irc;
+    its += ist.iterations;
+    mv += ist.matvecs;
+    cycles += ist.cycles;
+    host_eig += ist.host_eig_ms;
+    ties += ist.eig_ties;
+    total_bytes += ist.bytes_model;
+    // x += ||r|| d ; r = b - A x in FP64
+    KRS_CHECK_HIP(ctx, axpy_f32_into_f64(s, d32, x, n, sc + 17));
+    KRS_CHECK_HIP(ctx, residual_norm<double>(s, g, (const double*)A64->bands, x, b, r64, part));
+    KRS_CHECK_HIP(ctx, finish_sum<double>(s, part, nblk, 1, sc));
+    total_bytes += (double)n * (8 + 4 + 8 + 4 + 8) + 9.0 * 8 * n + 16.0 * n;
+    rc = read_dev(ctx, sc, 1);
+    if (rc) return rc;
+    const double rn_new = std::sqrt(ctx->pin[0]);
+    ++outer;
+    if (o->history && outer - 1 < o->history_cap) o->history[outer - 1] = rn_new / nb;
+    if (!std::isfinite(rn_new)) {
+      status = KRS_DIVERGED;
+      rn = rn_new;
+      break;
+    }
+    const bool stalled = rn_new > 0.9 * rn;
+    rn = rn_new;
+    if (stalled && rn > o->tol * nb) break;
+  }
+  if (status != KRS_DIVERGED && rn <= o->tol * nb) status = KRS_OK;
+  if (st) {
+    st->status = status;
+    st->iterations = its;
+    st->matvecs = mv;
+    st->cycles = cycles;
+    st->outer = outer;
+    st->history_len = outer;
+    st->rel_res_true = rn / nb;
+    st->rel_res_est = rn / nb;
+    st->time_ms = tm.ms();
+    st->host_eig_ms = host_eig;
+    st->eig_ties = ties;
+    st->bytes_model = total_bytes;
+  }
+  return status;
+}
+
+}  // namespace krs

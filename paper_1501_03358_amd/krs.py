@@ -1,0 +1,349 @@
+"""Python binding of the krs C-ABI (include/krs.h).
+
+Argument marshalling only: every operation runs in the HIP library
+``libkrs.so`` built in this directory.  PyTorch supplies device memory
+(``tensor.data_ptr()``) and the HIP stream of the current device.  There is
+no fallback: when the library is not built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkrs.so")
+
+# status codes
+OK, NOT_CONVERGED, BREAKDOWN, DIVERGED = 0, 1, 2, 3
+ERR_ARG, ERR_HIP, ERR_WORKSPACE, ERR_STATE, ERR_EIG = -1, -2, -3, -4, -5
+F64, F32 = 0, 1
+SOLVER_GMRES, SOLVER_RGCROT, SOLVER_RBICGSTAB, SOLVER_IR = 0, 1, 2, 3
+PC_NONE, PC_JACOBI, PC_SCHWARZ_JACOBI = 0, 1, 2
+
+EXPORTS = (
+    "krs_create", "krs_destroy", "krs_last_error", "krs_set_stream", "krs_matrix_create",
+    "krs_matrix_destroy", "krs_precond_create", "krs_precond_workspace_size",
+    "krs_precond_destroy", "krs_recycle_create", "krs_recycle_destroy", "krs_recycle_dim",
+    "krs_recycle_set_dim", "krs_workspace_size", "krs_stencil_apply", "krs_precond_apply",
+    "krs_gmres", "krs_rgcrot_solve", "krs_rbicgstab_solve", "krs_recycle_update",
+    "krs_hybrid_solve", "krs_ir_solve", "krs_version",
+)
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("periodic", ctypes.c_int32 * 3)]
+
+
+class PrecondDesc(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("tile", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("local_sweeps", ctypes.c_int32), ("global_sweeps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("omega_local", ctypes.c_double),
+                ("omega_global", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("k", ctypes.c_int32), ("update_recycle", ctypes.c_int32),
+                ("inner_solver", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_matvecs", ctypes.c_int64), ("div_factor", ctypes.c_double),
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("history", ctypes.POINTER(ctypes.c_double)),
+                ("history_cap", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("eig_ties", ctypes.c_int32),
+                ("matvecs", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("cycles", ctypes.c_int64), ("outer", ctypes.c_int64),
+                ("history_len", ctypes.c_int64), ("rel_res_true", ctypes.c_double),
+                ("rel_res_est", ctypes.c_double), ("time_ms", ctypes.c_double),
+                ("host_eig_ms", ctypes.c_double), ("bytes_model", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_LIB = None
+P = ctypes.c_void_p
+
+
+def _declare(L):
+    i32, i64, dbl, sz = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "krs_create": (i32, [ctypes.POINTER(P), P]),
+        "krs_destroy": (None, [P]),
+        "krs_last_error": (ctypes.c_char_p, [P]),
+        "krs_set_stream": (i32, [P, P]),
+        "krs_matrix_create": (i32, [P, ctypes.POINTER(Grid), i32, P, ctypes.POINTER(P)]),
+        "krs_matrix_destroy": (None, [P]),
+        "krs_precond_create": (i32, [P, P, ctypes.POINTER(PrecondDesc), P, sz, ctypes.POINTER(P)]),
+        "krs_precond_workspace_size": (sz, [P]),
+        "krs_precond_destroy": (None, [P]),
+        "krs_recycle_create": (i32, [P, i64, i32, i32, P, P, i64, ctypes.POINTER(P)]),
+        "krs_recycle_destroy": (None, [P]),
+        "krs_recycle_dim": (i32, [P]),
+        "krs_recycle_set_dim": (i32, [P, i32]),
+        "krs_workspace_size": (i32, [i32, i64, i32, i32, i32, ctypes.POINTER(sz)]),
+        "krs_stencil_apply": (i32, [P, P, P, P, dbl, dbl, P]),
+        "krs_precond_apply": (i32, [P, P, P, P]),
+        "krs_gmres": (i32, [P, P, P, P, P, ctypes.POINTER(Opts), P, sz, ctypes.POINTER(Stats)]),
+        "krs_rgcrot_solve": (i32, [P, P, P, P, P, P, ctypes.POINTER(Opts), P, sz,
+                                   ctypes.POINTER(Stats)]),
+        "krs_rbicgstab_solve": (i32, [P, P, P, P, P, P, ctypes.POINTER(Opts), P, sz,
+                                      ctypes.POINTER(Stats)]),
+        "krs_recycle_update": (i32, [P, P, P, P, P, sz]),
+        "krs_hybrid_solve": (i32, [P, P, P, P, i32, i32, P, P, ctypes.POINTER(Opts), P, sz,
+                                   ctypes.POINTER(Stats)]),
+        "krs_ir_solve": (i32, [P, P, P, P, P, P, P, ctypes.POINTER(Opts), P, sz,
+                               ctypes.POINTER(Stats)]),
+        "krs_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+def lib():
+    """Load libkrs.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libkrs.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _LIB = L
+    return _LIB
+
+
+class KrsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"krs error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dt(t):
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError("tensors must be float64 or float32")
+
+
+def vec_ld(n):
+    return (n + 63) // 64 * 64
+
+
+class Context:
+    def __init__(self, device=None, stream=None):
+        self.device = torch.device(device or "cuda:0")
+        if self.device.type != "cuda":
+            raise RuntimeError("krs needs a GPU device")
+        torch.cuda.set_device(self.device)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = s
+        h = P()
+        rc = lib().krs_create(ctypes.byref(h), ctypes.c_void_p(s.cuda_stream))
+        if rc != OK:
+            raise KrsError(rc, "krs_create failed")
+        self.h = h
+
+    def check(self, rc, allow_outcome=False):
+        if rc < 0 or (rc > 0 and not allow_outcome):
+            raise KrsError(rc, lib().krs_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().krs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Matrix:
+    """7-band operator on an (nx, ny, nz) grid; `bands` is a [7, N] device tensor."""
+
+    def __init__(self, ctx, shape, periodic, bands):
+        if not bands.is_cuda or not bands.is_contiguous() or bands.shape[0] != 7:
+            raise ValueError("bands must be a contiguous [7, N] device tensor")
+        self.ctx, self.bands = ctx, bands
+        self.shape = tuple(int(s) for s in shape)
+        self.n = self.shape[0] * self.shape[1] * self.shape[2]
+        self.dtype = bands.dtype
+        g = Grid(self.shape[0], self.shape[1], self.shape[2],
+                 (ctypes.c_int32 * 3)(*[1 if p else 0 for p in periodic]))
+        h = P()
+        ctx.check(lib().krs_matrix_create(ctx.h, ctypes.byref(g), _dt(bands), _ptr(bands),
+                                          ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        try:
+            lib().krs_matrix_destroy(self.h)
+        except Exception:
+            pass
+
+
+class Precond:
+    def __init__(self, ctx, A, kind="schwarz", tile=8, overlap=1, local_sweeps=5,
+                 omega_local=6.0 / 7.0, global_sweeps=1, omega_global=6.0 / 7.0):
+        t = {"none": PC_NONE, "jacobi": PC_JACOBI, "schwarz": PC_SCHWARZ_JACOBI}[kind]
+        self.ctx, self.A = ctx, A
+        self.desc = PrecondDesc(t, tile, overlap, local_sweeps, global_sweeps, 0, omega_local,
+                                omega_global)
+        nbytes = lib().krs_precond_workspace_size(A.h)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=A.bands.device)
+        h = P()
+        ctx.check(lib().krs_precond_create(ctx.h, A.h, ctypes.byref(self.desc), _ptr(self.ws),
+                                           nbytes, ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        try:
+            lib().krs_precond_destroy(self.h)
+        except Exception:
+            pass
+
+
+class Recycle:
+    """Recycle space (U, C): kmax columns each, leading dimension vec_ld(N)."""
+
+    def __init__(self, ctx, n, kmax, dtype, device=None):
+        self.ctx, self.n, self.kmax = ctx, n, kmax
+        self.ld = vec_ld(n)
+        dev = device or ctx.device
+        self.U = torch.zeros(kmax, self.ld, dtype=dtype, device=dev)
+        self.C = torch.zeros(kmax, self.ld, dtype=dtype, device=dev)
+        h = P()
+        ctx.check(lib().krs_recycle_create(ctx.h, n, kmax, _dt(self.U), _ptr(self.U), _ptr(self.C),
+                                           self.ld, ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def dim(self):
+        return lib().krs_recycle_dim(self.h)
+
+    def set_dim(self, k):
+        rc = lib().krs_recycle_set_dim(self.h, k)
+        if rc != OK:
+            raise KrsError(rc, "bad recycle dimension")
+
+    def views(self):
+        k = self.dim
+        return self.U[:k, :self.n].T, self.C[:k, :self.n].T
+
+    def __del__(self):
+        try:
+            lib().krs_recycle_destroy(self.h)
+        except Exception:
+            pass
+
+
+def workspace_size(solver, n, m, k, dtype):
+    out = ctypes.c_size_t()
+    dt = F64 if dtype == torch.float64 else F32
+    rc = lib().krs_workspace_size(solver, n, m, k, dt, ctypes.byref(out))
+    if rc != OK:
+        raise KrsError(rc, "krs_workspace_size")
+    return out.value
+
+
+class Workspace:
+    """Device scratch buffer, grown on demand."""
+
+    def __init__(self, device):
+        self.device = device
+        self.buf = torch.empty(0, dtype=torch.uint8, device=device)
+
+    def get(self, nbytes):
+        if self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+def make_opts(m=30, k=20, tol=1e-8, max_matvecs=2000, update_recycle=True, inner_solver=None,
+              div_factor=1e2, inner_tol=1e-4, max_outer=20, history=None):
+    o = Opts()
+    o.m, o.k, o.update_recycle = m, k, 1 if update_recycle else 0
+    o.inner_solver = SOLVER_RGCROT if inner_solver is None else inner_solver
+    o.tol, o.max_matvecs, o.div_factor = tol, max_matvecs, div_factor
+    o.inner_tol, o.max_outer = inner_tol, max_outer
+    if history is not None:
+        o.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        o.history_cap = history.size
+    return o
+
+
+# --------------------------------------------------------------------------
+# entry points (same names as the C-ABI)
+# --------------------------------------------------------------------------
+
+def stencil_apply(ctx, A, x, y, alpha=1.0, beta=0.0, b=None):
+    return ctx.check(lib().krs_stencil_apply(ctx.h, A.h, _ptr(x), _ptr(y), alpha, beta, _ptr(b)))
+
+
+def precond_apply(ctx, M, r, z):
+    return ctx.check(lib().krs_precond_apply(ctx.h, M.h, _ptr(r), _ptr(z)))
+
+
+def _h(obj):
+    return None if obj is None else obj.h
+
+
+def gmres(ctx, A, M, b, x, opts, ws, stats=None):
+    st = stats or Stats()
+    rc = lib().krs_gmres(ctx.h, A.h, _h(M), _ptr(b), _ptr(x), ctypes.byref(opts), _ptr(ws),
+                         ws.numel(), ctypes.byref(st))
+    ctx.check(rc, allow_outcome=True)
+    return rc, st
+
+
+def rgcrot_solve(ctx, A, M, rec, b, x, opts, ws, stats=None):
+    st = stats or Stats()
+    rc = lib().krs_rgcrot_solve(ctx.h, A.h, _h(M), _h(rec), _ptr(b), _ptr(x), ctypes.byref(opts),
+                                _ptr(ws), ws.numel(), ctypes.byref(st))
+    ctx.check(rc, allow_outcome=True)
+    return rc, st
+
+
+def rbicgstab_solve(ctx, A, M, rec, b, x, opts, ws, stats=None):
+    st = stats or Stats()
+    rc = lib().krs_rbicgstab_solve(ctx.h, A.h, _h(M), _h(rec), _ptr(b), _ptr(x),
+                                   ctypes.byref(opts), _ptr(ws), ws.numel(), ctypes.byref(st))
+    ctx.check(rc, allow_outcome=True)
+    return rc, st
+
+
+def recycle_update(ctx, A, M, rec, ws):
+    return ctx.check(lib().krs_recycle_update(ctx.h, A.h, _h(M), rec.h, _ptr(ws), ws.numel()))
+
+
+def hybrid_solve(ctx, A, M, rec, step, n_switch, b, x, opts, ws, stats=None):
+    st = stats or Stats()
+    rc = lib().krs_hybrid_solve(ctx.h, A.h, _h(M), rec.h, step, n_switch, _ptr(b), _ptr(x),
+                                ctypes.byref(opts), _ptr(ws), ws.numel(), ctypes.byref(st))
+    ctx.check(rc, allow_outcome=True)
+    return rc, st
+
+
+def ir_solve(ctx, A64, A32, M32, rec32, b, x, opts, ws, stats=None):
+    st = stats or Stats()
+    rc = lib().krs_ir_solve(ctx.h, A64.h, A32.h, _h(M32), _h(rec32), _ptr(b), _ptr(x),
+                            ctypes.byref(opts), _ptr(ws), ws.numel(), ctypes.byref(st))
+    ctx.check(rc, allow_outcome=True)
+    return rc, st
+
+
+def version():
+    return lib().krs_version().decode()

@@ -1,0 +1,251 @@
+"""GPU FP64 solver parity with the oracle: residual history within 1e-10
+(relative) over the first 20 iterations, iteration counts within 2, final x
+within 1e-8 (relative; modulo the constant for singular systems); recycle
+space invariants; FP32 + FP64 iterative refinement to a 1e-8 true residual."""
+import numpy as np
+import pytest
+import scipy.linalg
+import torch
+
+import workloads as W
+from oracle import krylov as K
+from oracle import stencil
+from tests.gpu_util import Dev, SMALL_SCHWARZ, mod_const, oracle_ops, recycle_to_oracle, rel
+
+pytestmark = pytest.mark.gpu
+
+HIST_TOL = 1e-10
+X_TOL = 1e-8
+
+
+def _hist(n=4000):
+    return np.zeros(n)
+
+
+def _check_history(h_gpu, h_ref, nfirst=20, tol=HIST_TOL):
+    n = min(nfirst, len(h_ref), len(h_gpu))
+    assert n > 0
+    a = np.asarray(h_gpu[:n])
+    b = np.asarray(h_ref[:n])
+    assert np.all(np.abs(a - b) <= tol * np.abs(b)), (a, b)
+
+
+def test_gmres_matches_oracle_grf24(gpu_lib):
+    krs = gpu_lib
+    prob = W.grf_problem(24)
+    d = Dev(krs, prob, "jacobi", m=20, k=10)
+    _, Mi, op = oracle_ops(prob, "jacobi")
+    b = W.rhs_perturbed(prob, 1)[0]
+    h = _hist()
+    x = d.empty()
+    rc, st = krs.gmres(d.ctx, d.A, d.M, d.vec(b), x, krs.make_opts(m=20, tol=1e-8, history=h),
+                       d.ws)
+    ref = K.gmres(op, Mi, b, 20, 1e-8)
+    assert rc == krs.OK and ref.status == K.CONVERGED
+    _check_history(h[:st.history_len], ref.history)
+    assert abs(st.iterations - ref.iterations) <= 2
+    assert rel(x.cpu().numpy(), ref.x) <= X_TOL
+    assert st.rel_res_true <= 1e-8
+
+
+def _rgcrot_sequence(krs, prob, pc, params, m, k, steps, bs, tol=1e-8):
+    d = Dev(krs, prob, pc, params, m=m, k=k)
+    _, Mi, op = oracle_ops(prob, pc, params)
+    rec = krs.Recycle(d.ctx, prob.n, k, torch.float64)
+    orec = K.Recycle.empty(prob.n)
+    out = []
+    for t in range(steps):
+        b = bs[t]
+        h = _hist()
+        x = d.empty()
+        rc, st = krs.rgcrot_solve(d.ctx, d.A, d.M, rec, d.vec(b), x,
+                                  krs.make_opts(m=m, k=k, tol=tol, history=h), d.ws)
+        ref = K.rgcrot(op, Mi, b, m, k, tol, orec)
+        out.append((rc, st, h[:st.history_len].copy(), x.cpu().numpy(), ref))
+    return d, rec, orec, op, out
+
+
+def test_rgcrot_sequence_matches_oracle_grf24(gpu_lib):
+    """24^3 GRF workload, point Jacobi, rGCROT(20,10), 5 right-hand sides."""
+    krs = gpu_lib
+    prob = W.grf_problem(24)
+    bs = W.rhs_perturbed(prob, 5)
+    d, rec, orec, op, out = _rgcrot_sequence(krs, prob, "jacobi", None, 20, 10, 5, bs)
+    for t, (rc, st, h, x, ref) in enumerate(out):
+        assert rc == krs.OK and ref.status == K.CONVERGED, t
+        assert st.eig_ties == 0 and ref.eig_ties == 0
+        _check_history(h, ref.history)
+        assert abs(st.iterations - ref.iterations) <= 2, (t, st.iterations, ref.iterations)
+        assert rel(x, ref.x) <= X_TOL, t
+    # recycle spaces: same range, invariants A~ U = C, C^T C = I
+    g = recycle_to_oracle(rec)
+    assert g.dim == orec.dim == 10
+    assert scipy.linalg.subspace_angles(g.C, orec.C).max() < 1e-6
+    AU = np.column_stack([op(g.U[:, i]) for i in range(g.dim)])
+    assert np.linalg.norm(AU - g.C) / np.linalg.norm(g.C) <= 1e-11
+    assert np.linalg.norm(g.C.T @ g.C - np.eye(g.dim)) <= 1e-12
+    # recycling pays: later systems need fewer iterations than the first
+    assert out[-1][1].iterations < out[0][1].iterations
+
+
+@pytest.mark.parametrize("kind", ["channel", "porous"])
+def test_rgcrot_schwarz_matches_oracle(gpu_lib, kind):
+    krs = gpu_lib
+    prob = W.channel_problem(24) if kind == "channel" else W.porous_problem(24, extra=7)
+    bs = list(W.rhs_ar1(prob, 3, extra=7))
+    params = dict(tile=8, overlap=1, local_sweeps=5, omega_local=6 / 7, global_sweeps=1,
+                  omega_global=6 / 7)
+    d, rec, orec, op, out = _rgcrot_sequence(krs, prob, "schwarz", params, 30, 20, 3, bs)
+    for t, (rc, st, h, x, ref) in enumerate(out):
+        assert rc == krs.OK and ref.status == K.CONVERGED
+        _check_history(h, ref.history)
+        assert abs(st.iterations - ref.iterations) <= 2
+        if prob.singular:
+            assert rel(mod_const(x, prob.vol), mod_const(ref.x, prob.vol)) <= X_TOL
+        else:
+            assert rel(x, ref.x) <= X_TOL
+
+
+def test_rbicgstab_plain_and_recycled_match_oracle(gpu_lib):
+    krs = gpu_lib
+    prob = W.grf_problem(24)
+    bs = W.rhs_perturbed(prob, 5)
+    d, rec, orec, op, out = _rgcrot_sequence(krs, prob, "jacobi", None, 20, 10, 3, bs)
+    _, Mi, _ = oracle_ops(prob, "jacobi")
+    g = recycle_to_oracle(rec)             # oracle runs with the GPU's recycle space
+    for use_rec in (False, True):
+        b = bs[4]
+        h = _hist()
+        x = d.empty()
+        rc, st = krs.rbicgstab_solve(d.ctx, d.A, d.M, rec if use_rec else None, d.vec(b), x,
+                                     krs.make_opts(tol=1e-8, history=h), d.ws)
+        ref = K.rbicgstab(op, Mi, b, 1e-8, g if use_rec else None)
+        assert rc == krs.OK and ref.status == K.CONVERGED
+        _check_history(h[:st.history_len], ref.history)
+        assert abs(st.iterations - ref.iterations) <= 2
+        assert rel(x.cpu().numpy(), ref.x) <= X_TOL
+        assert st.rel_res_true <= 2e-8
+        if use_rec:
+            plain_its = st_plain.iterations
+            assert st.iterations < plain_its
+        else:
+            st_plain = st
+
+
+def test_recycle_update_cholqr(gpu_lib):
+    """Line 1a: C = qr(A~ U).Q, U <- U R^-1: invariants and the oracle's range."""
+    krs = gpu_lib
+    prob = W.grf_problem(16, extra=9)
+    d = Dev(krs, prob, "jacobi", m=10, k=6)
+    _, Mi, op = oracle_ops(prob, "jacobi")
+    U0 = np.random.default_rng(4).standard_normal((prob.n, 6))
+    rec = krs.Recycle(d.ctx, prob.n, 8, torch.float64)
+    rec.U[:6, :prob.n] = torch.from_numpy(U0.T.copy()).to(d.dev)
+    rec.set_dim(6)
+    krs.recycle_update(d.ctx, d.A, d.M, rec, d.ws)
+    g = recycle_to_oracle(rec)
+    o = K.Recycle(U0.copy(), np.zeros_like(U0))
+    K.recycle_setup(op, o)
+    AU = np.column_stack([op(g.U[:, i]) for i in range(6)])
+    assert np.linalg.norm(AU - g.C) / np.linalg.norm(g.C) <= 1e-12
+    assert np.linalg.norm(g.C.T @ g.C - np.eye(6)) <= 1e-13
+    assert scipy.linalg.subspace_angles(g.C, o.C).max() < 1e-10
+    assert scipy.linalg.subspace_angles(g.U, o.U).max() < 1e-10
+
+
+def test_hybrid_sequence(gpu_lib):
+    """Hybrid: rGCROT for the first n_switch systems, rBiCGStab with the
+    frozen space afterwards; each solve to the tolerance, and the recycled
+    rBiCGStab systems need fewer matvecs than plain BiCGStab."""
+    krs = gpu_lib
+    prob = W.porous_problem(32, extra=11)
+    params = dict(tile=8, overlap=1, local_sweeps=5, omega_local=6 / 7, global_sweeps=1,
+                  omega_global=6 / 7)
+    d = Dev(krs, prob, "schwarz", params, m=30, k=20)
+    rec = krs.Recycle(d.ctx, prob.n, 20, torch.float64)
+    bs = list(W.rhs_ar1(prob, 5, extra=11))
+    A, Mi, op = oracle_ops(prob, "schwarz", params)
+    orec = K.Recycle.empty(prob.n)
+    for t, b in enumerate(bs):
+        x = d.empty()
+        rc, st = krs.hybrid_solve(d.ctx, d.A, d.M, rec, t, 3, d.vec(b), x,
+                                  krs.make_opts(m=30, k=20, tol=1e-8), d.ws)
+        ref = K.hybrid_step(t, 3, op, Mi, b, 30, 20, 1e-8, orec)
+        assert rc == krs.OK
+        assert (st.cycles > 0) == (t < 3)
+        r = b - A(x.cpu().numpy())
+        assert np.linalg.norm(r) <= 1.5e-8 * np.linalg.norm(b)
+        assert abs(st.iterations - ref.iterations) <= 2
+        assert rel(x.cpu().numpy(), ref.x) <= X_TOL
+        if t == 4:
+            xp = d.empty()
+            rcp, stp = krs.rbicgstab_solve(d.ctx, d.A, d.M, None, d.vec(b), xp,
+                                           krs.make_opts(tol=1e-8), d.ws)
+            assert st.matvecs < stp.matvecs
+
+
+def test_ir_fp32_inner_reaches_fp64_tolerance(gpu_lib):
+    """FP32 stencil/preconditioner/projections inside FP64 refinement reach a
+    1e-8 true residual; error against the FP64 oracle solution reported."""
+    krs = gpu_lib
+    prob = W.porous_problem(32, extra=12)
+    params = dict(tile=8, overlap=1, local_sweeps=5, omega_local=6 / 7, global_sweeps=1,
+                  omega_global=6 / 7)
+    dev = torch.device("cuda:0")
+    ctx = krs.Context(dev)
+    b64 = torch.from_numpy(prob.bands).to(dev)
+    b32 = b64.float()
+    A64 = krs.Matrix(ctx, prob.shape, prob.periodic, b64)
+    A32 = krs.Matrix(ctx, prob.shape, prob.periodic, b32)
+    M32 = krs.Precond(ctx, A32, "schwarz", **params)
+    rec = krs.Recycle(ctx, prob.n, 20, torch.float32)
+    ws = torch.empty(krs.workspace_size(krs.SOLVER_IR, prob.n, 30, 20, torch.float32),
+                     dtype=torch.uint8, device=dev)
+    A, Mi, op = oracle_ops(prob, "schwarz", params)
+    orec = K.Recycle.empty(prob.n)
+    for t, b in enumerate(W.rhs_ar1(prob, 4, extra=12)):
+        x = torch.empty(prob.n, dtype=torch.float64, device=dev)
+        inner = krs.SOLVER_RGCROT if t < 2 else krs.SOLVER_RBICGSTAB
+        rc, st = krs.ir_solve(ctx, A64, A32, M32, rec, torch.from_numpy(b).to(dev), x,
+                              krs.make_opts(m=30, k=20, tol=1e-8, inner_solver=inner,
+                                            inner_tol=1e-4), ws)
+        assert rc == krs.OK, (t, rc, st.as_dict())
+        xc = x.cpu().numpy()
+        assert np.linalg.norm(b - A(xc)) <= 1e-8 * np.linalg.norm(b)
+        ref = K.hybrid_step(t, 2, op, Mi, b, 30, 20, 1e-10, orec)
+        err = rel(xc, ref.x)
+        print(f"IR step {t}: outer {st.outer} inner its {st.iterations} |x-x64|/|x64| {err:.2e}")
+        assert err <= 1e-4
+
+
+def test_edge_cases(gpu_lib):
+    krs = gpu_lib
+    prob = W.grf_problem(8, extra=13)
+    d = Dev(krs, prob, "jacobi", m=10, k=4)
+    x = d.empty()
+    rc, st = krs.gmres(d.ctx, d.A, d.M, d.vec(np.zeros(prob.n)), x, krs.make_opts(m=10), d.ws)
+    assert rc == krs.OK and float(x.abs().max()) == 0.0
+    b = W.random_vector(prob.n, 3)
+    rc, st = krs.gmres(d.ctx, d.A, d.M, d.vec(b), x, krs.make_opts(m=10, tol=1e-14,
+                                                                   max_matvecs=5), d.ws)
+    assert rc == krs.NOT_CONVERGED and st.iterations == 5
+    rc, st = krs.rbicgstab_solve(d.ctx, d.A, d.M, None, d.vec(b), x,
+                                 krs.make_opts(tol=1e-14, max_matvecs=4), d.ws)
+    assert rc == krs.NOT_CONVERGED and st.iterations == 2
+    rc, st = krs.rbicgstab_solve(d.ctx, d.A, d.M, None, d.vec(np.full(prob.n, np.nan)), x,
+                                 krs.make_opts(tol=1e-8), d.ws)
+    assert rc == krs.DIVERGED
+    with pytest.raises(krs.KrsError):
+        krs.gmres(d.ctx, d.A, d.M, d.vec(b), x, krs.make_opts(m=0), d.ws)
+    small = torch.empty(16, dtype=torch.uint8, device=d.dev)
+    with pytest.raises(krs.KrsError):
+        krs.gmres(d.ctx, d.A, d.M, d.vec(b), x, krs.make_opts(m=10), small)
+    # b in range(C): rBiCGStab needs no iteration
+    rec = krs.Recycle(d.ctx, prob.n, 4, torch.float64)
+    rec.U[:4, :prob.n] = torch.from_numpy(np.random.default_rng(1).standard_normal((4, prob.n))).to(d.dev)
+    rec.set_dim(4)
+    krs.recycle_update(d.ctx, d.A, d.M, rec, d.ws)
+    _, C = rec.views()
+    bc = (C @ torch.tensor([1.0, -2.0, 0.5, 3.0], dtype=torch.float64, device=d.dev)).contiguous()
+    rc, st = krs.rbicgstab_solve(d.ctx, d.A, d.M, rec, bc, x, krs.make_opts(tol=1e-10), d.ws)
+    assert rc == krs.OK and st.iterations == 0
