@@ -234,6 +234,33 @@ int krs_ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32,
                  const krs_precond* M32, krs_recycle* rec32, const void* b, void* x,
                  const krs_opts* opts, void* ws, size_t ws_bytes, krs_stats* stats);
 
+/* ---------------- measurement ---------------- */
+
+/* Kernel classes timed by the per-class HIP-event timers. */
+typedef enum krs_kernel_class {
+  KRS_K_STENCIL = 0,        /* y = A x, residual b - A x */
+  KRS_K_SCHWARZ_LOCAL = 1,  /* local sweeps on the extended tiles */
+  KRS_K_JACOBI_SWEEP = 2,   /* global damped Jacobi sweep / point Jacobi */
+  KRS_K_BLOCK_DOT = 3,      /* [C V]^T w and other block dot products */
+  KRS_K_BLOCK_DOT2 = 4,     /* second Gram-Schmidt pass: [C V]^T (w - [C V] h) */
+  KRS_K_BLOCK_UPDATE = 5,   /* w - [C V] h, solution and projection updates */
+  KRS_K_BICG = 6,           /* fused BiCGStab vector updates */
+  KRS_K_GRAM = 7,           /* Gram blocks of the recycle update */
+  KRS_K_ROW_TRANSFORM = 8,  /* in-place (U, C) row-block updates */
+  KRS_K_OTHER = 9,          /* finishing reductions, copies, casts */
+  KRS_K_COUNT = 10
+} krs_kernel_class;
+
+/* While enabled, every kernel launch of the context is bracketed by two HIP
+ * events on the context's stream and its duration and algorithmic bytes
+ * (byte model: every array read once and written once) are accumulated per
+ * class.  Adds two event records per launch. */
+int krs_timing_enable(krs_ctx* ctx, int on);
+int krs_timing_reset(krs_ctx* ctx);
+/* Totals of one class since the last reset: launches, milliseconds, bytes. */
+int krs_timing_read(krs_ctx* ctx, int kernel_class, int64_t* launches, double* ms,
+                    double* bytes);
+
 /* Library version string. */
 const char* krs_version(void);
 

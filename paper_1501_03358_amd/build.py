@@ -15,7 +15,8 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
                 "-munsafe-fp-atomics"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 SOURCES = [("kernels.hip", DEVICE_FLAGS), ("solvers.cpp", HOST_FLAGS),
-           ("dense.cpp", HOST_FLAGS), ("api.cpp", HOST_FLAGS)]
+           ("dense.cpp", HOST_FLAGS), ("api.cpp", HOST_FLAGS),
+           ("timing.cpp", HOST_FLAGS)]
 
 
 def _compile(src, flags):

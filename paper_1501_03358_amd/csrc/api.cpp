@@ -74,6 +74,8 @@ int krs_create(krs_ctx** out, void* hip_stream) {
 
 void krs_destroy(krs_ctx* ctx) {
   if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  krs::timing_release(ctx);
   if (ctx->pin) (void)hipHostFree(ctx->pin);
   delete ctx;
 }

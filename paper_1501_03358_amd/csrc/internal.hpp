@@ -17,6 +17,18 @@ struct krs_ctx {
   std::string err;
   double* pin = nullptr;         // pinned host staging (kPinDoubles)
   double bytes = 0;              // byte-model accumulator of the current call
+  // per-kernel-class timing (krs_timing_*)
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool timing = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  int64_t t_launches[KRS_K_COUNT] = {};
+  double t_ms[KRS_K_COUNT] = {};
+  double t_bytes[KRS_K_COUNT] = {};
 };
 
 struct krs_matrix {
@@ -114,6 +126,25 @@ inline int set_err(krs_ctx* ctx, int code, const std::string& msg) {
     if (_e != hipSuccess)                                                              \
       return krs::set_err((ctx), KRS_ERR_HIP,                                          \
                           std::string(#expr) + ": " + hipGetErrorString(_e));          \
+  } while (0)
+
+namespace krs {
+// kernel-launch bracketing for the timers and the byte model (timing.cpp)
+hipEvent_t launch_begin(krs_ctx* ctx);
+void launch_end(krs_ctx* ctx, int cls, double bytes, hipEvent_t a);
+// after a stream synchronisation: fold completed event pairs into the totals
+void timing_flush(krs_ctx* ctx);
+void timing_release(krs_ctx* ctx);
+}  // namespace krs
+
+// Launch `expr` (returning hipError_t) as kernel class `cls` moving `nbytes`.
+#define KRS_LAUNCH(ctx, cls, nbytes, expr)                                              \
+  do {                                                                                 \
+    hipEvent_t _ev = krs::launch_begin(ctx);                                           \
+    hipError_t _e = (expr);                                                            \
+    krs::launch_end(ctx, (cls), (nbytes), _ev);                                        \
+    if (_e != hipSuccess)                                                              \
+      return krs::set_err((ctx), KRS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
   } while (0)
 
 // solver entry points implemented in solvers.cpp (dtype dispatched)

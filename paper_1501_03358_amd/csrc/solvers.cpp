@@ -41,30 +41,27 @@ struct Op {
     hipStream_t s = ctx->stream;
     const double NW = (double)g.n * sizeof(T);
     if (!M || M->d.type == KRS_PC_NONE) {
-      KRS_CHECK_HIP(ctx, copy<T>(s, r, out, g.n));
-      ctx->bytes += 2 * NW;
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, r, out, g.n));
       return 0;
     }
     if (M->d.type == KRS_PC_JACOBI) {
-      KRS_CHECK_HIP(ctx, point_jacobi<T>(s, g, bands(), r, out));
-      ctx->bytes += 3 * NW;
+      KRS_LAUNCH(ctx, KRS_K_JACOBI_SWEEP, 3 * NW, point_jacobi<T>(s, g, bands(), r, out));
       return 0;
     }
     const int gs = M->d.global_sweeps;
     T* first = (gs % 2 == 0) ? out : tmp;
     if (M->d.local_sweeps > 0) {
-      KRS_CHECK_HIP(ctx, schwarz_local<T>(s, g, M->d.tile, bands(), r, first, M->d.omega_local,
-                                          M->d.local_sweeps));
-      ctx->bytes += 9 * NW;
+      KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, 9 * NW,
+                 schwarz_local<T>(s, g, M->d.tile, bands(), r, first, M->d.omega_local,
+                                  M->d.local_sweeps));
     } else {
-      KRS_CHECK_HIP(ctx, fill<T>(s, first, g.n, 0.0));
-      ctx->bytes += NW;
+      KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, first, g.n, 0.0));
     }
     T* cur = first;
     for (int i = 0; i < gs; ++i) {
       T* nxt = (cur == out) ? tmp : out;
-      KRS_CHECK_HIP(ctx, jacobi_sweep<T>(s, g, bands(), r, cur, nxt, M->d.omega_global));
-      ctx->bytes += 10 * NW;
+      KRS_LAUNCH(ctx, KRS_K_JACOBI_SWEEP, 10 * NW,
+                 jacobi_sweep<T>(s, g, bands(), r, cur, nxt, M->d.omega_global));
       cur = nxt;
     }
     return 0;
@@ -73,8 +70,8 @@ struct Op {
   int apply(const T* v, T* w) {
     int rc = minv(v, z);
     if (rc) return rc;
-    KRS_CHECK_HIP(ctx, stencil<T>(ctx->stream, g, bands(), z, w, 1.0, 0.0, nullptr, 0));
-    ctx->bytes += 9.0 * g.n * sizeof(T);
+    KRS_LAUNCH(ctx, KRS_K_STENCIL, 9.0 * g.n * sizeof(T),
+               stencil<T>(ctx->stream, g, bands(), z, w, 1.0, 0.0, nullptr, 0));
     return 0;
   }
 };
@@ -83,6 +80,7 @@ int read_dev(krs_ctx* ctx, const double* src, int count) {
   KRS_CHECK_HIP(ctx, hipMemcpyAsync(ctx->pin, src, sizeof(double) * count, hipMemcpyDeviceToHost,
                                     ctx->stream));
   KRS_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  timing_flush(ctx);
   return 0;
 }
 
@@ -112,9 +110,9 @@ Cols<T> cols(const T* p1, int64_t ld1, int n1, const T* p2 = nullptr, int64_t ld
 template <class T>
 int norm2(krs_ctx* ctx, const T* w, int64_t n, T* part, double* d_out, double& out) {
   const int nblk = red_blocks(n);
-  KRS_CHECK_HIP(ctx, block_dot<T>(ctx->stream, Cols<T>{}, w, n, 1, part, nblk));
-  KRS_CHECK_HIP(ctx, finish_sum<T>(ctx->stream, part, nblk, 1, d_out));
-  ctx->bytes += (double)n * sizeof(T);
+  KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, (double)n * sizeof(T),
+             block_dot<T>(ctx->stream, Cols<T>{}, w, n, 1, part, nblk));
+  KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(ctx->stream, part, nblk, 1, d_out));
   int rc = read_dev(ctx, d_out, 1);
   if (rc) return rc;
   out = ctx->pin[0];
@@ -180,12 +178,15 @@ int harmonic_update(krs_ctx* ctx, krs_recycle* rec, const T* V, int64_t ld, int 
   std::vector<double> dvec(kc), CtU((size_t)kc * kc), VtU((size_t)(jj + 1) * kc);
   if (kc > 0) {
     const int na = kc + jj + 1;
-    KRS_CHECK_HIP(ctx, gram<T>(s, cols<T>(C, ldr, kc, V, ld, jj + 1), cols<T>(U, ldr, kc), n, part,
-                               kGramBlocks));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, kGramBlocks, na * kc, sc + Ws<T>::kGram1));
-    KRS_CHECK_HIP(ctx, gram<T>(s, cols<T>(U, ldr, kc), cols<T>(U, ldr, kc), n, part, kGramBlocks));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, kGramBlocks, kc * kc, sc + Ws<T>::kGram2));
-    ctx->bytes += (double)n * sizeof(T) * (2 * kc + jj + 1 + kc);
+    const double NW = (double)n * sizeof(T);
+    KRS_LAUNCH(ctx, KRS_K_GRAM, NW * (2 * kc + jj + 1),
+               gram<T>(s, cols<T>(C, ldr, kc, V, ld, jj + 1), cols<T>(U, ldr, kc), n, part,
+                       kGramBlocks));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
+               finish_sum<T>(s, part, kGramBlocks, na * kc, sc + Ws<T>::kGram1));
+    KRS_LAUNCH(ctx, KRS_K_GRAM, NW * kc,
+               gram<T>(s, cols<T>(U, ldr, kc), cols<T>(U, ldr, kc), n, part, kGramBlocks));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, kGramBlocks, kc * kc, sc + Ws<T>::kGram2));
     int rc = read_dev(ctx, sc + Ws<T>::kGram1, na * kc);
     if (rc) return rc;
     for (int a = 0; a < kc; ++a)
@@ -254,11 +255,12 @@ int harmonic_update(krs_ctx* ctx, krs_recycle* rec, const T* V, int64_t ld, int 
   both.insert(both.end(), Q.begin(), Q.end());
   int rc = upload(ctx, sc + Ws<T>::kM, both.data(), (int)both.size());
   if (rc) return rc;
-  KRS_CHECK_HIP(ctx, row_transform<T>(s, cols<T>(U, ldr, kc, V, ld, jj), sc + Ws<T>::kM, kk, U, ldr,
-                                      n));
-  KRS_CHECK_HIP(ctx, row_transform<T>(s, cols<T>(C, ldr, kc, V, ld, jj + 1),
-                                      sc + Ws<T>::kM + (size_t)ng * kk, kk, C, ldr, n));
-  ctx->bytes += (double)n * sizeof(T) * ((kc + jj + kk) + (kc + jj + 1 + kk));
+  const double NWt = (double)n * sizeof(T);
+  KRS_LAUNCH(ctx, KRS_K_ROW_TRANSFORM, NWt * (kc + jj + kk),
+             row_transform<T>(s, cols<T>(U, ldr, kc, V, ld, jj), sc + Ws<T>::kM, kk, U, ldr, n));
+  KRS_LAUNCH(ctx, KRS_K_ROW_TRANSFORM, NWt * (kc + jj + 1 + kk),
+             row_transform<T>(s, cols<T>(C, ldr, kc, V, ld, jj + 1),
+                              sc + Ws<T>::kM + (size_t)ng * kk, kk, C, ldr, n));
   rec->dim = kk;
   return 0;
 }
@@ -303,8 +305,9 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
   if (rc) return rc;
   const double nb = std::sqrt(nb2);
   if (nb == 0 || !std::isfinite(nb)) {
-    KRS_CHECK_HIP(ctx, fill<T>(s, x, n, 0.0));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, x, n, 0.0));
     KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
+    timing_flush(ctx);
     if (st) {
       st->status = std::isfinite(nb) ? KRS_OK : KRS_DIVERGED;
       st->rel_res_true = 0;
@@ -320,21 +323,22 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
   double rho2 = 0;
   // Alg. 3 line 1b: xi = C^T b, r = b - C xi, y = U xi
   if (kc > 0) {
-    KRS_CHECK_HIP(ctx, block_dot<T>(s, cols<T>(C, ldr, kc), b, n, 0, part, nblk));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, kc, d_xi));
-    KRS_CHECK_HIP(ctx, block_update<T>(s, cols<T>(C, ldr, kc), d_xi, -1.0, b, r0, n, nullptr, 1,
-                                       part, nblk));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, d_nrm));
-    KRS_CHECK_HIP(ctx, block_update<T>(s, cols<T>(U, ldr, kc), d_xi, 1.0, nullptr, x, n, nullptr, 0,
-                                       part, nblk));
-    ctx->bytes += NW * ((kc + 1) + (kc + 2) + (kc + 1));
+    KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 1),
+               block_dot<T>(s, cols<T>(C, ldr, kc), b, n, 0, part, nblk));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc, d_xi));
+    KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (kc + 2),
+               block_update<T>(s, cols<T>(C, ldr, kc), d_xi, -1.0, b, r0, n, nullptr, 1, part,
+                               nblk));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, d_nrm));
+    KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (kc + 1),
+               block_update<T>(s, cols<T>(U, ldr, kc), d_xi, 1.0, nullptr, x, n, nullptr, 0, part,
+                               nblk));
     rc = read_dev(ctx, d_nrm, 1);
     if (rc) return rc;
     rho2 = ctx->pin[0];
   } else {
-    KRS_CHECK_HIP(ctx, copy<T>(s, b, r0, n));
-    KRS_CHECK_HIP(ctx, fill<T>(s, x, n, 0.0));
-    ctx->bytes += 3 * NW;
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, b, r0, n));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, x, n, 0.0));
     rho2 = nb2;
   }
   double rho = std::sqrt(rho2);
@@ -352,8 +356,8 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
     const double inv_rho = 1.0 / rho;
     rc = upload(ctx, d_inv, &inv_rho, 1);
     if (rc) return rc;
-    KRS_CHECK_HIP(ctx, block_update<T>(s, Cols<T>{}, nullptr, 0.0, r0, V, n, d_inv, 0, part, nblk));
-    ctx->bytes += 2 * NW;
+    KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, 2 * NW,
+               block_update<T>(s, Cols<T>{}, nullptr, 0.0, r0, V, n, d_inv, 0, part, nblk));
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = rho;
     std::fill(Hbar.begin(), Hbar.end(), 0.0);
@@ -369,25 +373,27 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
       const int ncols = kc + j + 1;
       const Cols<T> Q = cols<T>(C, ldr, kc, V, ld, j + 1);
       // lines 6a-9 as two classical Gram-Schmidt passes against [C, V_j]
-      KRS_CHECK_HIP(ctx, block_dot<T>(s, Q, w, n, 0, part, nblk));
-      KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, ncols, d_h1));
-      KRS_CHECK_HIP(ctx, block_dot_after_update<T>(s, Q, d_h1, w, n, part, nblk));
-      KRS_CHECK_HIP(ctx, finish_cgs2<T>(s, part, nblk, ncols, d_h1, d_h2, d_hcol, d_inv, d_flag));
+      KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (ncols + 1), block_dot<T>(s, Q, w, n, 0, part, nblk));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, ncols, d_h1));
+      KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT2, NW * (ncols + 1),
+                 block_dot_after_update<T>(s, Q, d_h1, w, n, part, nblk));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
+                 finish_cgs2<T>(s, part, nblk, ncols, d_h1, d_h2, d_hcol, d_inv, d_flag));
       // line 10: v_{j+1} = (w - Q h) / h_{j+1,j}
-      KRS_CHECK_HIP(ctx, block_update<T>(s, Q, d_hcol, -1.0, w, vn, n, d_inv, 0, part, nblk));
-      ctx->bytes += NW * ((ncols + 1) + (ncols + 1) + (ncols + 2));
+      KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (ncols + 2),
+                 block_update<T>(s, Q, d_hcol, -1.0, w, vn, n, d_inv, 0, part, nblk));
       rc = read_dev(ctx, sc, Ws<T>::kFlagOff + 1);
       if (rc) return rc;
       std::vector<double> hv(ctx->pin + Ws<T>::kHcol, ctx->pin + Ws<T>::kHcol + ncols + 1);
       int flag = *(int*)(ctx->pin + Ws<T>::kFlagOff);
       if (flag) {
         // norm from the Pythagorean identity unreliable: recompute explicitly
-        KRS_CHECK_HIP(ctx, block_update<T>(s, Q, d_hcol, -1.0, w, vn, n, nullptr, 1, part, nblk));
-        KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, d_nrm));
-        KRS_CHECK_HIP(ctx, set_norm_from_sum(s, d_nrm, d_hcol + ncols, d_inv));
-        KRS_CHECK_HIP(ctx, block_update<T>(s, Cols<T>{}, nullptr, 0.0, vn, vn, n, d_inv, 0, part,
-                                           nblk));
-        ctx->bytes += NW * (ncols + 2 + 2);
+        KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (ncols + 2),
+                   block_update<T>(s, Q, d_hcol, -1.0, w, vn, n, nullptr, 1, part, nblk));
+        KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, d_nrm));
+        KRS_LAUNCH(ctx, KRS_K_OTHER, 0, set_norm_from_sum(s, d_nrm, d_hcol + ncols, d_inv));
+        KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, 2 * NW,
+                   block_update<T>(s, Cols<T>{}, nullptr, 0.0, vn, vn, n, d_inv, 0, part, nblk));
         rc = read_dev(ctx, d_hcol + ncols, 1);
         if (rc) return rc;
         hv[ncols] = ctx->pin[0];
@@ -428,9 +434,9 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
     }
     rc = upload(ctx, d_coef, coef.data(), jj + kc);
     if (rc) return rc;
-    KRS_CHECK_HIP(ctx, block_update<T>(s, cols<T>(V, ld, jj, U, ldr, kc), d_coef, 1.0, x, x, n,
-                                       nullptr, 0, part, nblk));
-    ctx->bytes += NW * (jj + kc + 2);
+    KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (jj + kc + 2),
+               block_update<T>(s, cols<T>(V, ld, jj, U, ldr, kc), d_coef, 1.0, x, x, n, nullptr,
+                               0, part, nblk));
     ++cycles;
     // line 14a: recycle-space update
     if (update && rec) {
@@ -440,21 +446,22 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
     // line 14: true residual r = b - A~ y (into the first basis column)
     rc = op.minv(x, z);
     if (rc) return rc;
-    KRS_CHECK_HIP(ctx, residual_norm<T>(s, op.g, op.bands(), z, b, r0, part));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, d_nrm));
-    ctx->bytes += 10 * NW;
+    KRS_LAUNCH(ctx, KRS_K_STENCIL, 10 * NW, residual_norm<T>(s, op.g, op.bands(), z, b, r0, part));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, d_nrm));
     ++mv;
     kc = rec ? rec->dim : 0;
     if (kc > 0) {
       // re-project against the (new) C: xi = C^T r, r -= C xi, y += U xi
-      KRS_CHECK_HIP(ctx, block_dot<T>(s, cols<T>(C, ldr, kc), r0, n, 0, part, nblk));
-      KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, kc, d_xi));
-      KRS_CHECK_HIP(ctx, block_update<T>(s, cols<T>(C, ldr, kc), d_xi, -1.0, r0, r0, n, nullptr, 1,
-                                         part, nblk));
-      KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, d_nrm));
-      KRS_CHECK_HIP(ctx, block_update<T>(s, cols<T>(U, ldr, kc), d_xi, 1.0, x, x, n, nullptr, 0,
-                                         part, nblk));
-      ctx->bytes += NW * ((kc + 1) + (kc + 2) + (kc + 2));
+      KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 1),
+                 block_dot<T>(s, cols<T>(C, ldr, kc), r0, n, 0, part, nblk));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc, d_xi));
+      KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (kc + 2),
+                 block_update<T>(s, cols<T>(C, ldr, kc), d_xi, -1.0, r0, r0, n, nullptr, 1, part,
+                                 nblk));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, d_nrm));
+      KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (kc + 2),
+                 block_update<T>(s, cols<T>(U, ldr, kc), d_xi, 1.0, x, x, n, nullptr, 0, part,
+                                 nblk));
     }
     rc = read_dev(ctx, d_nrm, 1);
     if (rc) return rc;
@@ -468,9 +475,9 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
   // x = M^-1 y
   rc = op.minv(x, z);
   if (rc) return rc;
-  KRS_CHECK_HIP(ctx, copy<T>(s, z, x, n));
+  KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, z, x, n));
   KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
-  ctx->bytes += 2 * NW;
+  timing_flush(ctx);
   if (st) {
     st->status = status;
     st->matvecs = mv;
@@ -510,9 +517,12 @@ int recycle_setup_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs
     if (rc) return rc;
   }
   std::vector<double> G((size_t)kc * kc), R((size_t)kc * kc), Ri((size_t)kc * kc);
+  const double NW = (double)n * sizeof(T);
   for (int pass = 0; pass < 2; ++pass) {
-    KRS_CHECK_HIP(ctx, gram<T>(s, cols<T>(C, ldr, kc), cols<T>(C, ldr, kc), n, part, kGramBlocks));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, kGramBlocks, kc * kc, sc + Ws<T>::kGram1));
+    KRS_LAUNCH(ctx, KRS_K_GRAM, NW * kc,
+               gram<T>(s, cols<T>(C, ldr, kc), cols<T>(C, ldr, kc), n, part, kGramBlocks));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
+               finish_sum<T>(s, part, kGramBlocks, kc * kc, sc + Ws<T>::kGram1));
     int rc = read_dev(ctx, sc + Ws<T>::kGram1, kc * kc);
     if (rc) return rc;
     for (int a = 0; a < kc; ++a)
@@ -522,11 +532,13 @@ int recycle_setup_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs
       return set_err(ctx, KRS_ERR_STATE, "recycle setup: A~ U is rank deficient");
     rc = upload(ctx, sc + Ws<T>::kM, Ri.data(), kc * kc);
     if (rc) return rc;
-    KRS_CHECK_HIP(ctx, row_transform<T>(s, cols<T>(C, ldr, kc), sc + Ws<T>::kM, kc, C, ldr, n));
-    KRS_CHECK_HIP(ctx, row_transform<T>(s, cols<T>(U, ldr, kc), sc + Ws<T>::kM, kc, U, ldr, n));
-    ctx->bytes += (double)n * sizeof(T) * (kc + 4 * kc);
+    KRS_LAUNCH(ctx, KRS_K_ROW_TRANSFORM, NW * 2 * kc,
+               row_transform<T>(s, cols<T>(C, ldr, kc), sc + Ws<T>::kM, kc, C, ldr, n));
+    KRS_LAUNCH(ctx, KRS_K_ROW_TRANSFORM, NW * 2 * kc,
+               row_transform<T>(s, cols<T>(U, ldr, kc), sc + Ws<T>::kM, kc, U, ldr, n));
   }
   KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
+  timing_flush(ctx);
   return 0;
 }
 
@@ -564,8 +576,9 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   if (rc) return rc;
   const double nb = std::sqrt(nb2);
   if (nb == 0 || !std::isfinite(nb)) {
-    KRS_CHECK_HIP(ctx, fill<T>(s, x, n, 0.0));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, x, n, 0.0));
     KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
+    timing_flush(ctx);
     if (st) {
       st->status = std::isfinite(nb) ? KRS_OK : KRS_DIVERGED;
       st->rel_res_true = 0;
@@ -582,11 +595,11 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   double rn2 = nb2;
   // line 1c: eta1 = C^T b, r0 = b - C eta1, xi = -eta1
   if (kc > 0) {
-    KRS_CHECK_HIP(ctx, block_dot<T>(s, Cc, b, n, 0, part, nblk));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, kc, sc + kEta1));
-    KRS_CHECK_HIP(ctx, block_update<T>(s, Cc, sc + kEta1, -1.0, b, r, n, nullptr, 1, part, nblk));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, sc + kNrm));
-    ctx->bytes += NW * ((kc + 1) + (kc + 2));
+    KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 1), block_dot<T>(s, Cc, b, n, 0, part, nblk));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc, sc + kEta1));
+    KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (kc + 2),
+               block_update<T>(s, Cc, sc + kEta1, -1.0, b, r, n, nullptr, 1, part, nblk));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, sc + kNrm));
     rc = read_dev(ctx, sc + kEta1, kc);
     if (rc) return rc;
     std::vector<double> xi(kc);
@@ -597,20 +610,17 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     if (rc) return rc;
     rn2 = ctx->pin[0];
   } else {
-    KRS_CHECK_HIP(ctx, copy<T>(s, b, r, n));
-    ctx->bytes += 2 * NW;
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, b, r, n));
   }
   // line 2: r~ = r_0 ; C^T r~ for the alpha denominator
-  KRS_CHECK_HIP(ctx, copy<T>(s, r, rt, n));
+  KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, r, rt, n));
   if (kc > 0) {
-    KRS_CHECK_HIP(ctx, block_dot<T>(s, Cc, rt, n, 0, part, nblk));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, kc, sc + kCtrt));
-    ctx->bytes += NW * (kc + 1);
+    KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 1), block_dot<T>(s, Cc, rt, n, 0, part, nblk));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc, sc + kCtrt));
   }
-  KRS_CHECK_HIP(ctx, fill<T>(s, p, n, 0.0));
-  KRS_CHECK_HIP(ctx, fill<T>(s, v, n, 0.0));
-  KRS_CHECK_HIP(ctx, fill<T>(s, x, n, 0.0));
-  ctx->bytes += 5 * NW;
+  KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, p, n, 0.0));
+  KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, v, n, 0.0));
+  KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, x, n, 0.0));
   slots[kRho] = rn2;  // r~ = r
   slots[kOmega] = 1.0;
   slots[kBeta] = 0.0;
@@ -631,17 +641,18 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
       status = KRS_BREAKDOWN;
       break;
     }
-    KRS_CHECK_HIP(ctx, bicg_p<T>(s, r, p, v, sc, n));       // line 6
+    KRS_LAUNCH(ctx, KRS_K_BICG, 4 * NW, bicg_p<T>(s, r, p, v, sc, n));   // line 6
     rc = op.apply(p, v);                                     // line 7
     if (rc) return rc;
     ++mv;
     // line 7a-8: eta1 = C^T v, v -= C eta1, alpha = rho / r~^T v, s = r - alpha v
-    KRS_CHECK_HIP(ctx, block_dot<T>(s, cols<T>(C, ldr, kc, rt, ld, 1), v, n, 0, part, nblk));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, kc + 1, sc + kSums));
-    KRS_CHECK_HIP(ctx, bicg_alpha(s, sc + kSums, kc, sc, kEta1, kCtrt));
-    KRS_CHECK_HIP(ctx, bicg_sv<T>(s, Cc, r, v, sv, sc, kEta1, n, part, nblk));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, sc + kSnorm2));
-    ctx->bytes += NW * (4 + (kc + 2) + (kc + 4));
+    KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 2),
+               block_dot<T>(s, cols<T>(C, ldr, kc, rt, ld, 1), v, n, 0, part, nblk));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc + 1, sc + kSums));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_alpha(s, sc + kSums, kc, sc, kEta1, kCtrt));
+    KRS_LAUNCH(ctx, KRS_K_BICG, NW * (kc + (kc > 0 ? 4 : 3)),
+               bicg_sv<T>(s, Cc, r, v, sv, sc, kEta1, n, part, nblk));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, sc + kSnorm2));
     rc = read_dev(ctx, sc, kSlots);
     if (rc) return rc;
     std::copy(ctx->pin, ctx->pin + kSlots, slots.begin());
@@ -657,8 +668,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
       break;
     }
     if (snorm <= tol * nb) {                                // lines 9-10a
-      KRS_CHECK_HIP(ctx, bicg_exit_s<T>(s, p, x, sv, r, sc, kEta1, kXi, kc, n));
-      ctx->bytes += 5 * NW;
+      KRS_LAUNCH(ctx, KRS_K_BICG, 5 * NW, bicg_exit_s<T>(s, p, x, sv, r, sc, kEta1, kXi, kc, n));
       rnorm = snorm;
       break;
     }
@@ -666,14 +676,15 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     if (rc) return rc;
     ++mv;
     // line 12a-13a: eta2 = C^T t, omega = t^T s / |t - C eta2|^2, xi update
-    KRS_CHECK_HIP(ctx, block_dot<T>(s, cols<T>(C, ldr, kc, sv, ld, 1), t, n, 1, part, nblk));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, kc + 2, sc + kSums));
-    KRS_CHECK_HIP(ctx, bicg_omega(s, sc + kSums, kc, sc, kEta1, kEta2, kXi));
+    KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 2),
+               block_dot<T>(s, cols<T>(C, ldr, kc, sv, ld, 1), t, n, 1, part, nblk));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc + 2, sc + kSums));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_omega(s, sc + kSums, kc, sc, kEta1, kEta2, kXi));
     // lines 14-16 with the next rho = r~^T r
-    KRS_CHECK_HIP(ctx, bicg_yr<T>(s, Cc, t, sv, p, x, r, rt, sc, kEta2, n, part, nblk));
-    KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 2, sc + kSums));
-    KRS_CHECK_HIP(ctx, bicg_rho(s, sc + kSums, sc));
-    ctx->bytes += NW * ((kc + 2) + (kc + 7));
+    KRS_LAUNCH(ctx, KRS_K_BICG, NW * (kc + 7),
+               bicg_yr<T>(s, Cc, t, sv, p, x, r, rt, sc, kEta2, n, part, nblk));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 2, sc + kSums));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_rho(s, sc + kSums, sc));
     rc = read_dev(ctx, sc, kSlots);
     if (rc) return rc;
     std::copy(ctx->pin, ctx->pin + kSlots, slots.begin());
@@ -692,22 +703,21 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   if (status == KRS_NOT_CONVERGED && rnorm <= tol * nb) status = KRS_OK;
   // line 17a: y -= U xi ; then x = M^-1 y
   if (kc > 0) {
-    KRS_CHECK_HIP(ctx, block_update<T>(s, cols<T>(U, ldr, kc), sc + kXi, -1.0, x, x, n, nullptr, 0,
-                                       part, nblk));
-    ctx->bytes += NW * (kc + 2);
+    KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (kc + 2),
+               block_update<T>(s, cols<T>(U, ldr, kc), sc + kXi, -1.0, x, x, n, nullptr, 0, part,
+                               nblk));
   }
   rc = op.minv(x, z);
   if (rc) return rc;
-  KRS_CHECK_HIP(ctx, copy<T>(s, z, x, n));
+  KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, z, x, n));
   // true residual of x
-  KRS_CHECK_HIP(ctx, residual_norm<T>(s, op.g, op.bands(), x, b, t, part));
-  KRS_CHECK_HIP(ctx, finish_sum<T>(s, part, nblk, 1, sc + kNrm));
-  ctx->bytes += 12 * NW;
+  KRS_LAUNCH(ctx, KRS_K_STENCIL, 10 * NW, residual_norm<T>(s, op.g, op.bands(), x, b, t, part));
+  KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, sc + kNrm));
   rc = read_dev(ctx, sc + kNrm, 1);
   if (rc) return rc;
   if (st) {
     st->status = status;
-    st->matvecs = mv + 1;
+    st->matvecs = mv;
     st->iterations = its;
     st->history_len = hlen;
     st->rel_res_true = std::sqrt(ctx->pin[0]) / nb;
@@ -810,9 +820,9 @@ int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const k
   int rc = norm2<double>(ctx, b, n, part, sc, nb2);
   if (rc) return rc;
   const double nb = std::sqrt(nb2);
-  KRS_CHECK_HIP(ctx, fill<double>(s, x, n, 0.0));
-  KRS_CHECK_HIP(ctx, copy<double>(s, b, r64, n));
-  total_bytes += ctx->bytes + 3.0 * 8 * n;
+  KRS_LAUNCH(ctx, KRS_K_OTHER, 8.0 * n, fill<double>(s, x, n, 0.0));
+  KRS_LAUNCH(ctx, KRS_K_OTHER, 16.0 * n, copy<double>(s, b, r64, n));
+  total_bytes += ctx->bytes;
   double rn = nb;
   int status = KRS_NOT_CONVERGED;
   int64_t outer = 0, its = 0, mv = 0, cycles = 0;
@@ -835,7 +845,9 @@ int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const k
     const double sv[2] = {1.0 / rn, rn};
     rc = upload(ctx, sc + 16, sv, 2);
     if (rc) return rc;
-    KRS_CHECK_HIP(ctx, cast_scale_f64_f32(s, r64, b32, n, sc + 16));
+    ctx->bytes = 0;
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 12.0 * n, cast_scale_f64_f32(s, r64, b32, n, sc + 16));
+    total_bytes += ctx->bytes;
     krs_stats ist;
     int irc;
     if (o->inner_solver == KRS_SOLVER_RBICGSTAB) {
@@ -859,10 +871,12 @@ int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const k
     ties += ist.eig_ties;
     total_bytes += ist.bytes_model;
     // x += ||r|| d ; r = b - A x in FP64
-    KRS_CHECK_HIP(ctx, axpy_f32_into_f64(s, d32, x, n, sc + 17));
-    KRS_CHECK_HIP(ctx, residual_norm<double>(s, g, (const double*)A64->bands, x, b, r64, part));
-    KRS_CHECK_HIP(ctx, finish_sum<double>(s, part, nblk, 1, sc));
-    total_bytes += (double)n * (8 + 4 + 8 + 4 + 8) + 9.0 * 8 * n + 16.0 * n;
+    ctx->bytes = 0;
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 20.0 * n, axpy_f32_into_f64(s, d32, x, n, sc + 17));
+    KRS_LAUNCH(ctx, KRS_K_STENCIL, 80.0 * n,
+               residual_norm<double>(s, g, (const double*)A64->bands, x, b, r64, part));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<double>(s, part, nblk, 1, sc));
+    total_bytes += ctx->bytes;
     rc = read_dev(ctx, sc, 1);
     if (rc) return rc;
     const double rn_new = std::sqrt(ctx->pin[0]);

@@ -28,7 +28,8 @@ EXPORTS = (
     "krs_precond_destroy", "krs_recycle_create", "krs_recycle_destroy", "krs_recycle_dim",
     "krs_recycle_set_dim", "krs_workspace_size", "krs_stencil_apply", "krs_precond_apply",
     "krs_gmres", "krs_rgcrot_solve", "krs_rbicgstab_solve", "krs_recycle_update",
-    "krs_hybrid_solve", "krs_ir_solve", "krs_version",
+    "krs_hybrid_solve", "krs_ir_solve", "krs_version", "krs_timing_enable", "krs_timing_reset",
+    "krs_timing_read",
 )
 
 
@@ -99,6 +100,10 @@ def _declare(L):
         "krs_ir_solve": (i32, [P, P, P, P, P, P, P, ctypes.POINTER(Opts), P, sz,
                                ctypes.POINTER(Stats)]),
         "krs_version": (ctypes.c_char_p, []),
+        "krs_timing_enable": (i32, [P, i32]),
+        "krs_timing_reset": (i32, [P]),
+        "krs_timing_read": (i32, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl),
+                                  ctypes.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -343,6 +348,29 @@ def ir_solve(ctx, A64, A32, M32, rec32, b, x, opts, ws, stats=None):
                             ctypes.byref(opts), _ptr(ws), ws.numel(), ctypes.byref(st))
     ctx.check(rc, allow_outcome=True)
     return rc, st
+
+
+KERNEL_CLASSES = ("stencil", "schwarz_local", "jacobi_sweep", "block_dot", "block_dot2",
+                  "block_update", "bicg", "gram", "row_transform", "other")
+
+
+def timing_enable(ctx, on=True):
+    return ctx.check(lib().krs_timing_enable(ctx.h, 1 if on else 0))
+
+
+def timing_reset(ctx):
+    return ctx.check(lib().krs_timing_reset(ctx.h))
+
+
+def timing_read(ctx):
+    """{class: (launches, ms, bytes)} accumulated since the last reset."""
+    out = {}
+    for i, name in enumerate(KERNEL_CLASSES):
+        n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        ctx.check(lib().krs_timing_read(ctx.h, i, ctypes.byref(n), ctypes.byref(ms),
+                                        ctypes.byref(by)))
+        out[name] = (n.value, ms.value, by.value)
+    return out
 
 
 def version():
