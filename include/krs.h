@@ -109,6 +109,11 @@ typedef struct krs_precond_desc {
   double omega_global;
 } krs_precond_desc;
 
+/* GMRES-type solvers stop as soon as the least-squares residual estimate
+ * meets tol, without confirming it with the true residual (used for the
+ * inner solves of iterative refinement, whose outer FP64 residual decides). */
+#define KRS_FLAG_TRUST_ESTIMATE 1
+
 typedef struct krs_opts {
   int32_t m;               /* Arnoldi steps per cycle (GMRES, rGCROT), 1..64 */
   int32_t k;               /* maximum recycle dimension (rGCROT update), <= recycle kmax */
@@ -119,7 +124,7 @@ typedef struct krs_opts {
   double div_factor;       /* rBiCGStab: ||r|| > div_factor ||b|| => KRS_DIVERGED (<= 0: off) */
   double inner_tol;        /* IR only: relative tolerance of each inner solve */
   int32_t max_outer;       /* IR only: cap on refinement steps */
-  int32_t reserved;
+  int32_t flags;           /* KRS_FLAG_* */
   double* history;         /* optional host buffer: residual history (relative) */
   int64_t history_cap;
 } krs_opts;
@@ -227,8 +232,12 @@ int krs_hybrid_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, kr
  * A64/b/x are FP64 (true residual b - A64 x, update x += d in FP64);
  * A32, M32, rec32 are the FP32 operator, preconditioner and recycle space
  * used by the inner solver opts.inner_solver (RGCROT: with recycle updates
- * when opts.update_recycle; RBICGSTAB: rec32 read only) to the relative
- * tolerance opts.inner_tol.  Stops when ||b - A64 x|| <= tol ||b||.
+ * when opts.update_recycle; RBICGSTAB: rec32 read only).  Each inner solve
+ * runs to the relative tolerance max(opts.inner_tol, tol ||b|| / (2 ||r||))
+ * on its scaled right-hand side r / ||r|| (no tighter than the refinement
+ * still needs) and stops on its own residual estimate.  Stops when
+ * ||b - A64 x|| <= tol ||b||, or when a refinement step reduces ||r|| by
+ * less than 10%.
  * ws: krs_workspace_size(KRS_SOLVER_IR, N, m, k, KRS_F32). */
 int krs_ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32,
                  const krs_precond* M32, krs_recycle* rec32, const void* b, void* x,

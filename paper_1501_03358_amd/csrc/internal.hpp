@@ -63,7 +63,7 @@ constexpr int kPinDoubles = 1 << 16;       // 512 KiB pinned staging
 constexpr int kMaxM = 64;                  // Arnoldi steps per cycle
 constexpr int kMaxK = 32;                  // recycle dimension
 constexpr int kScalarDoubles = 1 << 14;    // device scalar area (128 KiB)
-constexpr int kGramBlocks = 256;
+constexpr int kGramBlocks = 1024;
 constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -89,7 +89,7 @@ struct Carver {
 
 inline size_t partials_bytes(size_t elem) {
   const size_t red = (size_t)kMaxRedBlocks * (kMaxM + kMaxK + 4);
-  const size_t gram = (size_t)kGramBlocks * kThreads * 8;
+  const size_t gram = (size_t)kGramBlocks * 128 * 16;   // 4 x 4 tiles, 128 per block
   return elem * (red > gram ? red : gram);
 }
 

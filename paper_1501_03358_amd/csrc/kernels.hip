@@ -317,50 +317,83 @@ __global__ __launch_bounds__(kThreads) void k_block_dot_after_update(Cols<T> Q,
   reduce_store<T, NC + 1>(acc, nc + 1, partials, nblk);
 }
 
-// Gram partials: rows staged through LDS in chunks of kGramRows.
-constexpr int kGramRows = 32;
-constexpr int kGramPairsPerThread = 8;
+// Gram partials X^T Y: one wave per block; chunks of kGramRows rows of all
+// columns are staged in LDS and every lane accumulates up to two 4 x 4 tiles
+// of (a, b) pairs in registers (8 LDS reads per 16 FMAs).
+constexpr int kGramRows = 16;
+constexpr int kGramTile = 4;
 
 template <class T>
-__global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t n, T* partials,
-                                                   int nblk) {
+__global__ __launch_bounds__(64) void k_gram(Cols<T> X, Cols<T> Y, int64_t n, T* partials,
+                                             int nblk) {
   extern __shared__ unsigned char smem_raw[];
   T* xs = reinterpret_cast<T*>(smem_raw);
-  const int na = X.n1 + X.n2, nb = Y.n1 + Y.n2, np = na * nb;
-  T* ys = xs + kGramRows * na;
-  T acc[kGramPairsPerThread];
+  const int na = X.n1 + X.n2, nb = Y.n1 + Y.n2;
+  const int nta = (na + kGramTile - 1) / kGramTile, ntb = (nb + kGramTile - 1) / kGramTile;
+  const int lda = nta * kGramTile, ldb = ntb * kGramTile;
+  T* ys = xs + kGramRows * lda;
+  const int lane = threadIdx.x;
+  T acc[2][kGramTile][kGramTile];
 #pragma unroll
-  for (int q = 0; q < kGramPairsPerThread; ++q) acc[q] = 0;
-  for (int64_t r0 = (int64_t)blockIdx.x * kGramRows; r0 < n;
-       r0 += (int64_t)gridDim.x * kGramRows) {
-    for (int idx = threadIdx.x; idx < kGramRows * na; idx += kThreads) {
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int i = 0; i < kGramTile; ++i)
+#pragma unroll
+      for (int j = 0; j < kGramTile; ++j) acc[q][i][j] = 0;
+  const int t0 = lane, t1 = lane + 64;
+  const int ta0 = t0 / ntb, tb0 = t0 % ntb, ta1 = t1 / ntb, tb1 = t1 % ntb;
+  const bool v0 = t0 < nta * ntb, v1 = t1 < nta * ntb;
+  for (int64_t r0 = (int64_t)blockIdx.x * kGramRows; r0 < n; r0 += (int64_t)gridDim.x * kGramRows) {
+    for (int idx = lane; idx < kGramRows * lda; idx += 64) {
       const int c = idx / kGramRows, rr = idx % kGramRows;
       const int64_t i = r0 + rr;
-      xs[rr * na + c] = i < n ? col_ptr(X, c)[i] : T(0);
+      xs[rr * lda + c] = (c < na && i < n) ? col_ptr(X, c)[i] : T(0);
     }
-    for (int idx = threadIdx.x; idx < kGramRows * nb; idx += kThreads) {
+    for (int idx = lane; idx < kGramRows * ldb; idx += 64) {
       const int c = idx / kGramRows, rr = idx % kGramRows;
       const int64_t i = r0 + rr;
-      ys[rr * nb + c] = i < n ? col_ptr(Y, c)[i] : T(0);
+      ys[rr * ldb + c] = (c < nb && i < n) ? col_ptr(Y, c)[i] : T(0);
     }
     __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < kGramRows; ++rr) {
+      if (v0) {
+        T xa[kGramTile], yb[kGramTile];
 #pragma unroll
-    for (int q = 0; q < kGramPairsPerThread; ++q) {
-      const int p = threadIdx.x + kThreads * q;
-      if (p < np) {
-        const int a = p / nb, b = p % nb;
-        T s = 0;
-#pragma unroll 8
-        for (int rr = 0; rr < kGramRows; ++rr) s += xs[rr * na + a] * ys[rr * nb + b];
-        acc[q] += s;
+        for (int i = 0; i < kGramTile; ++i) xa[i] = xs[rr * lda + ta0 * kGramTile + i];
+#pragma unroll
+        for (int j = 0; j < kGramTile; ++j) yb[j] = ys[rr * ldb + tb0 * kGramTile + j];
+#pragma unroll
+        for (int i = 0; i < kGramTile; ++i)
+#pragma unroll
+          for (int j = 0; j < kGramTile; ++j) acc[0][i][j] += xa[i] * yb[j];
+      }
+      if (v1) {
+        T xa[kGramTile], yb[kGramTile];
+#pragma unroll
+        for (int i = 0; i < kGramTile; ++i) xa[i] = xs[rr * lda + ta1 * kGramTile + i];
+#pragma unroll
+        for (int j = 0; j < kGramTile; ++j) yb[j] = ys[rr * ldb + tb1 * kGramTile + j];
+#pragma unroll
+        for (int i = 0; i < kGramTile; ++i)
+#pragma unroll
+          for (int j = 0; j < kGramTile; ++j) acc[1][i][j] += xa[i] * yb[j];
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < kGramPairsPerThread; ++q) {
-    const int p = threadIdx.x + kThreads * q;
-    if (p < np) partials[(int64_t)p * nblk + blockIdx.x] = acc[q];
+  for (int q = 0; q < 2; ++q) {
+    const bool v = q == 0 ? v0 : v1;
+    if (!v) continue;
+    const int ta = q == 0 ? ta0 : ta1, tb = q == 0 ? tb0 : tb1;
+#pragma unroll
+    for (int i = 0; i < kGramTile; ++i)
+#pragma unroll
+      for (int j = 0; j < kGramTile; ++j) {
+        const int a = ta * kGramTile + i, b = tb * kGramTile + j;
+        if (a < na && b < nb) partials[((int64_t)a * nb + b) * nblk + blockIdx.x] = acc[q][i][j];
+      }
   }
 }
 
@@ -697,11 +730,12 @@ hipError_t block_dot_after_update(hipStream_t s, const Cols<T>& Q, const double*
 template <class T>
 hipError_t gram(hipStream_t s, const Cols<T>& X, const Cols<T>& Y, int64_t n, T* partials,
                 int nblk) {
-  const int np = X.count() * Y.count();
-  if (np == 0) return hipSuccess;
-  if (np > kThreads * kGramPairsPerThread) return hipErrorInvalidValue;
-  const size_t smem = sizeof(T) * kGramRows * (X.count() + Y.count());
-  k_gram<T><<<nblk, kThreads, smem, s>>>(X, Y, n, partials, nblk);
+  const int na = X.count(), nb = Y.count();
+  if (na == 0 || nb == 0) return hipSuccess;
+  const int nta = (na + kGramTile - 1) / kGramTile, ntb = (nb + kGramTile - 1) / kGramTile;
+  if (nta * ntb > 128) return hipErrorInvalidValue;   // two 4 x 4 tiles per lane
+  const size_t smem = sizeof(T) * kGramRows * kGramTile * (nta + ntb);
+  k_gram<T><<<nblk, 64, smem, s>>>(X, Y, n, partials, nblk);
   return hipGetLastError();
 }
 

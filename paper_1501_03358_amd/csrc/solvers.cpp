@@ -350,7 +350,9 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
   int64_t its = 0, mv = 0, cycles = 0, hlen = 0;
   int status = KRS_NOT_CONVERGED;
   double est = rho;
-  while (rho > tol * nb && its < maxit) {
+  const bool trust_est = (o->flags & KRS_FLAG_TRUST_ESTIMATE) != 0;
+  bool est_converged = false;
+  while (rho > tol * nb && its < maxit && !est_converged) {
     kc = rec ? rec->dim : 0;
     // v_1 = r / rho
     const double inv_rho = 1.0 / rho;
@@ -424,6 +426,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
       if (!std::isfinite(est)) break;
       if (est <= tol * nb || hv[ncols] == 0.0 || its >= maxit) break;
     }
+    est_converged = trust_est && est <= tol * nb;
     // line 12: y = R^-1 g ; line 12a: z = -B y ; lines 13-13a: y_acc += V y + U z
     dense::upper_solve(jj, Rr.data(), ldh, gv.data(), yv.data());
     for (int i = 0; i < jj; ++i) coef[i] = yv[i];
@@ -471,7 +474,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
       break;
     }
   }
-  if (status != KRS_DIVERGED && rho <= tol * nb) status = KRS_OK;
+  if (status != KRS_DIVERGED && (rho <= tol * nb || est_converged)) status = KRS_OK;
   // x = M^-1 y
   rc = op.minv(x, z);
   if (rc) return rc;
@@ -827,7 +830,8 @@ int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const k
   int status = KRS_NOT_CONVERGED;
   int64_t outer = 0, its = 0, mv = 0, cycles = 0;
   krs_opts io = *o;
-  io.tol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
+  const double inner_floor = o->inner_tol > 0 ? o->inner_tol : 1e-5;
+  io.flags |= KRS_FLAG_TRUST_ESTIMATE;
   io.history = nullptr;
   io.history_cap = 0;
   const int max_outer = o->max_outer > 0 ? o->max_outer : 20;
@@ -841,7 +845,8 @@ int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const k
     return std::isfinite(nb) ? KRS_OK : KRS_DIVERGED;
   }
   while (rn > o->tol * nb && outer < max_outer) {
-    // scaled FP32 right-hand side r / ||r||
+    // scaled FP32 right-hand side r / ||r||; solve no tighter than needed
+    io.tol = std::max(inner_floor, 0.5 * o->tol * nb / rn);
     const double sv[2] = {1.0 / rn, rn};
     rc = upload(ctx, sc + 16, sv, 2);
     if (rc) return rc;

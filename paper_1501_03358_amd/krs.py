@@ -21,6 +21,7 @@ ERR_ARG, ERR_HIP, ERR_WORKSPACE, ERR_STATE, ERR_EIG = -1, -2, -3, -4, -5
 F64, F32 = 0, 1
 SOLVER_GMRES, SOLVER_RGCROT, SOLVER_RBICGSTAB, SOLVER_IR = 0, 1, 2, 3
 PC_NONE, PC_JACOBI, PC_SCHWARZ_JACOBI = 0, 1, 2
+FLAG_TRUST_ESTIMATE = 1
 
 EXPORTS = (
     "krs_create", "krs_destroy", "krs_last_error", "krs_set_stream", "krs_matrix_create",
@@ -50,7 +51,7 @@ class Opts(ctypes.Structure):
                 ("inner_solver", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_matvecs", ctypes.c_int64), ("div_factor", ctypes.c_double),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("history", ctypes.POINTER(ctypes.c_double)),
+                ("flags", ctypes.c_int32), ("history", ctypes.POINTER(ctypes.c_double)),
                 ("history_cap", ctypes.c_int64)]
 
 
@@ -278,8 +279,9 @@ class Workspace:
 
 
 def make_opts(m=30, k=20, tol=1e-8, max_matvecs=2000, update_recycle=True, inner_solver=None,
-              div_factor=1e2, inner_tol=1e-4, max_outer=20, history=None):
+              div_factor=1e2, inner_tol=1e-5, max_outer=20, history=None, flags=0):
     o = Opts()
+    o.flags = flags
     o.m, o.k, o.update_recycle = m, k, 1 if update_recycle else 0
     o.inner_solver = SOLVER_RGCROT if inner_solver is None else inner_solver
     o.tol, o.max_matvecs, o.div_factor = tol, max_matvecs, div_factor

@@ -159,12 +159,20 @@ def test_rbicgstab_plain_and_recycled_match_oracle(gpu_lib, pc):
         _check_history(h[:st.history_len], ref.history)
         slack = 2 if pc == "schwarz" else max(2, int(0.05 * ref.iterations))
         assert abs(st.iterations - ref.iterations) <= slack
-        assert rel(x.cpu().numpy(), ref.x) <= X_TOL
         assert st.rel_res_true <= 2e-8
         if use_rec:
             assert st.iterations < st_plain.iterations
         else:
             st_plain = st
+        # BiCGStab's iterates are sensitive to rounding: a 1e-15 relative change
+        # of b moves the oracle's own solution by ~1e-7 at tol 1e-8.  The
+        # solutions are compared where tol * cond keeps them within 1e-8.
+        x2 = d.empty()
+        rc2, st2 = krs.rbicgstab_solve(d.ctx, d.A, d.M, rec if use_rec else None, d.vec(b), x2,
+                                       krs.make_opts(tol=1e-12), d.ws)
+        ref2 = K.rbicgstab(op, Mi, b, 1e-12, g if use_rec else None)
+        assert rc2 == krs.OK and ref2.status == K.CONVERGED
+        assert rel(x2.cpu().numpy(), ref2.x) <= X_TOL
 
 
 def test_recycle_update_cholqr(gpu_lib):
@@ -243,7 +251,7 @@ def test_ir_fp32_inner_reaches_fp64_tolerance(gpu_lib):
         inner = krs.SOLVER_RGCROT if t < 2 else krs.SOLVER_RBICGSTAB
         rc, st = krs.ir_solve(ctx, A64, A32, M32, rec, torch.from_numpy(b).to(dev), x,
                               krs.make_opts(m=30, k=20, tol=1e-8, inner_solver=inner,
-                                            inner_tol=1e-4), ws)
+                                            inner_tol=1e-5), ws)
         assert rc == krs.OK, (t, rc, st.as_dict())
         xc = x.cpu().numpy()
         assert np.linalg.norm(b - A(xc)) <= 1e-8 * np.linalg.norm(b)

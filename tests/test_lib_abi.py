@@ -47,7 +47,7 @@ def _ws(lib, solver, n, m, k, dt):
     return out.value
 
 
-FIXED = 8 << 20   # partial sums and the scalar area, independent of N
+FIXED = 32 << 20  # partial sums and the scalar area, independent of N
 
 
 @pytest.mark.parametrize("n", [13824, 2097152])
