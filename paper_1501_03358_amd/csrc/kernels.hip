@@ -231,8 +231,65 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local(Grid3 g, const T* __
 
 // ---------------------------------------------------------------------------
 // tall-skinny block products
+//
+// Each block streams one contiguous range of rows of every column, with
+// 16-byte loads (W = 16 / sizeof(T) rows per load) when every pointer is
+// 16-byte aligned and every leading dimension a multiple of W, else with
+// element loads (W = 1).  Columns go in groups of 8 whose loads carry no
+// branch between them (a trailing group repeats its last valid column, with
+// a zero coefficient or a discarded sum), so up to 8 loads per lane are in
+// flight.  The last block also takes the n % W trailing rows one by one.
 // ---------------------------------------------------------------------------
-template <class T, int NC>
+template <class T, int W>
+struct alignas(sizeof(T) * W) Pk {
+  T v[W];
+};
+
+template <class T, int W>
+__device__ __forceinline__ Pk<T, W> ldp(const T* p, int64_t iv) {
+  return reinterpret_cast<const Pk<T, W>*>(p)[iv];
+}
+template <class T, int W>
+__device__ __forceinline__ void stp(T* p, int64_t iv, const Pk<T, W>& x) {
+  reinterpret_cast<Pk<T, W>*>(p)[iv] = x;
+}
+
+constexpr int kGroup = 8;
+
+struct Range {
+  int64_t v0, v1;
+};
+__device__ __forceinline__ Range block_range(int64_t npk) {
+  const int64_t per = (npk + gridDim.x - 1) / gridDim.x;
+  Range r;
+  r.v0 = (int64_t)blockIdx.x * per;
+  r.v1 = r.v0 + per < npk ? r.v0 + per : npk;
+  return r;
+}
+
+template <class T, int W, int NC>
+__device__ __forceinline__ void dot_rows(const Cols<T>& Q, int nc, const T* __restrict__ w,
+                                         int64_t i0, int64_t i1, T (&acc)[NC + 1]) {
+  for (int64_t iv = i0; iv < i1; iv += kThreads) {
+    const Pk<T, W> wv = ldp<T, W>(w, iv);
+#pragma unroll
+    for (int g = 0; g < NC; g += kGroup) {
+      if (g < nc) {
+        Pk<T, W> q[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) q[u] = ldp<T, W>(col_ptr(Q, min(g + u, nc - 1)), iv);
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+#pragma unroll
+          for (int e = 0; e < W; ++e) acc[g + u] += q[u].v[e] * wv.v[e];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < W; ++e) acc[NC] += wv.v[e] * wv.v[e];
+  }
+}
+
+template <class T, int W, int NC>
 __global__ __launch_bounds__(kThreads) void k_block_dot(Cols<T> Q, const T* __restrict__ w,
                                                         int64_t n, int self_dot, T* partials,
                                                         int nblk) {
@@ -240,51 +297,97 @@ __global__ __launch_bounds__(kThreads) void k_block_dot(Cols<T> Q, const T* __re
   T acc[NC + 1];
 #pragma unroll
   for (int c = 0; c <= NC; ++c) acc[c] = 0;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads) {
-    const T wi = w[i];
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c < nc) acc[c] += col_ptr(Q, c)[i] * wi;
-    acc[NC] += wi * wi;
-  }
+  const int64_t npk = n / W;
+  const Range r = block_range(npk);
+  dot_rows<T, W, NC>(Q, nc, w, r.v0 + threadIdx.x, r.v1, acc);
+  if (W > 1 && blockIdx.x == gridDim.x - 1)
+    dot_rows<T, 1, NC>(Q, nc, w, npk * W + threadIdx.x, n, acc);
   if (self_dot) {
-    // move the self product next to the column products
 #pragma unroll
     for (int c = 0; c < NC; ++c)
       if (c == nc) acc[c] = acc[NC];
-    if (nc == NC) { /* already in place at index NC */ }
   }
   reduce_store<T, NC + 1>(acc, nc + (self_dot ? 1 : 0), partials, nblk);
 }
 
-template <class T, int NC, bool NORM, bool SCALE, bool HAS_IN>
-__global__ __launch_bounds__(kThreads) void k_block_update(Cols<T> Q, const double* coef, T sgn,
-                                                           const T* w_in, T* w_out, int64_t n,
-                                                           const double* scale, T* partials,
-                                                           int nblk) {
-  __shared__ T cf[NC];
-  const int nc = Q.n1 + Q.n2;
-  for (int c = threadIdx.x; c < nc; c += kThreads) cf[c] = sgn * (T)coef[c];
-  __syncthreads();
-  T sc = 1;
-  if constexpr (SCALE) sc = (T)scale[0];
-  T acc[1] = {0};
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads) {
-    T v = 0;
-    if constexpr (HAS_IN) v = w_in[i];
+template <class T, int W, int NC>
+__device__ __forceinline__ void update_rows(const Cols<T>& Q, int nc, const T* cf,
+                                            const T* w_in, T* w_out, T sc, int64_t i0, int64_t i1,
+                                            T& acc) {
+  for (int64_t iv = i0; iv < i1; iv += kThreads) {
+    Pk<T, W> v;
+    if (w_in) v = ldp<T, W>(w_in, iv);
+    else {
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c < nc) v += cf[c] * col_ptr(Q, c)[i];
-    if constexpr (SCALE) v *= sc;
-    w_out[i] = v;
-    if constexpr (NORM) acc[0] += v * v;
+      for (int e = 0; e < W; ++e) v.v[e] = 0;
+    }
+#pragma unroll
+    for (int g = 0; g < NC; g += kGroup) {
+      if (g < nc) {
+        Pk<T, W> q[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) q[u] = ldp<T, W>(col_ptr(Q, min(g + u, nc - 1)), iv);
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+#pragma unroll
+          for (int e = 0; e < W; ++e) v.v[e] += cf[g + u] * q[u].v[e];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      v.v[e] *= sc;
+      acc += v.v[e] * v.v[e];
+    }
+    stp<T, W>(w_out, iv, v);
   }
-  if constexpr (NORM) reduce_store<T, 1>(acc, 1, partials, nblk);
 }
 
-template <class T, int NC>
+// w_out = (w_in + sgn * Q coef) * scale ; optional partial |w_out|^2
+template <class T, int W, int NC>
+__global__ __launch_bounds__(kThreads) void k_block_update(Cols<T> Q, const double* coef, T sgn,
+                                                           const T* w_in, T* w_out, int64_t n,
+                                                           const double* scale, int norm,
+                                                           T* partials, int nblk) {
+  __shared__ T cf[NC > 0 ? NC : 1];
+  const int nc = Q.n1 + Q.n2;
+  for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < nc ? sgn * (T)coef[c] : T(0);
+  __syncthreads();
+  const T sc = scale ? (T)scale[0] : T(1);
+  T acc[1] = {0};
+  const int64_t npk = n / W;
+  const Range r = block_range(npk);
+  update_rows<T, W, NC>(Q, nc, cf, w_in, w_out, sc, r.v0 + threadIdx.x, r.v1, acc[0]);
+  if (W > 1 && blockIdx.x == gridDim.x - 1)
+    update_rows<T, 1, NC>(Q, nc, cf, w_in, w_out, sc, npk * W + threadIdx.x, n, acc[0]);
+  if (norm) reduce_store<T, 1>(acc, 1, partials, nblk);
+}
+
+// Partials of Q^T (w - Q coef) and |w - Q coef|^2 without writing anything
+// (second classical Gram-Schmidt pass); the column values of a row stay in
+// registers between the update and the dot products.
+template <class T, int W, int NC>
+__device__ __forceinline__ void dau_rows(const Cols<T>& Q, int nc, const T* cf,
+                                         const T* __restrict__ w, int64_t i0, int64_t i1,
+                                         T (&acc)[NC + 1]) {
+  for (int64_t iv = i0; iv < i1; iv += kThreads) {
+    Pk<T, W> q[NC];
+    Pk<T, W> v = ldp<T, W>(w, iv);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      q[c] = ldp<T, W>(col_ptr(Q, min(c, nc - 1)), iv);
+#pragma unroll
+      for (int e = 0; e < W; ++e) v.v[e] -= cf[c] * q[c].v[e];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int e = 0; e < W; ++e) acc[c] += q[c].v[e] * v.v[e];
+#pragma unroll
+    for (int e = 0; e < W; ++e) acc[NC] += v.v[e] * v.v[e];
+  }
+}
+
+template <class T, int W, int NC>
 __global__ __launch_bounds__(kThreads) void k_block_dot_after_update(Cols<T> Q,
                                                                      const double* coef,
                                                                      const T* __restrict__ w,
@@ -292,47 +395,40 @@ __global__ __launch_bounds__(kThreads) void k_block_dot_after_update(Cols<T> Q,
                                                                      int nblk) {
   __shared__ T cf[NC];
   const int nc = Q.n1 + Q.n2;
-  for (int c = threadIdx.x; c < nc; c += kThreads) cf[c] = (T)coef[c];
+  for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < nc ? (T)coef[c] : T(0);
   __syncthreads();
   T acc[NC + 1];
 #pragma unroll
   for (int c = 0; c <= NC; ++c) acc[c] = 0;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads) {
-    T q[NC];
-    T v = w[i];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      q[c] = c < nc ? col_ptr(Q, c)[i] : T(0);
-      v -= cf[c < nc ? c : 0] * q[c];
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] += q[c] * v;
-    acc[NC] += v * v;
-  }
-  // place |v|^2 at index nc
+  const int64_t npk = n / W;
+  const Range r = block_range(npk);
+  dau_rows<T, W, NC>(Q, nc, cf, w, r.v0 + threadIdx.x, r.v1, acc);
+  if (W > 1 && blockIdx.x == gridDim.x - 1)
+    dau_rows<T, 1, NC>(Q, nc, cf, w, npk * W + threadIdx.x, n, acc);
 #pragma unroll
   for (int c = 0; c < NC; ++c)
     if (c == nc) acc[c] = acc[NC];
   reduce_store<T, NC + 1>(acc, nc + 1, partials, nblk);
 }
 
-// Gram partials X^T Y: one wave per block; chunks of kGramRows rows of all
-// columns are staged in LDS and every lane accumulates up to two 4 x 4 tiles
-// of (a, b) pairs in registers (8 LDS reads per 16 FMAs).
+// Gram partials X^T Y.  A block has 4 waves; each wave stages its own
+// kGramRows rows of every column in LDS (column-major, padded row stride) and
+// every lane accumulates up to two 4 x 4 tiles of (a, b) pairs in registers.
+// At the end the 4 waves' tiles are added in LDS in wave order.
 constexpr int kGramRows = 16;
+constexpr int kGramPad = kGramRows + 1;
 constexpr int kGramTile = 4;
 
 template <class T>
-__global__ __launch_bounds__(64) void k_gram(Cols<T> X, Cols<T> Y, int64_t n, T* partials,
-                                             int nblk) {
+__global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t n, T* partials,
+                                                   int nblk) {
   extern __shared__ unsigned char smem_raw[];
-  T* xs = reinterpret_cast<T*>(smem_raw);
   const int na = X.n1 + X.n2, nb = Y.n1 + Y.n2;
   const int nta = (na + kGramTile - 1) / kGramTile, ntb = (nb + kGramTile - 1) / kGramTile;
   const int lda = nta * kGramTile, ldb = ntb * kGramTile;
-  T* ys = xs + kGramRows * lda;
-  const int lane = threadIdx.x;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  T* xs = reinterpret_cast<T*>(smem_raw) + (size_t)wid * (lda + ldb) * kGramPad;
+  T* ys = xs + (size_t)lda * kGramPad;
   T acc[2][kGramTile][kGramTile];
 #pragma unroll
   for (int q = 0; q < 2; ++q)
@@ -343,60 +439,68 @@ __global__ __launch_bounds__(64) void k_gram(Cols<T> X, Cols<T> Y, int64_t n, T*
   const int t0 = lane, t1 = lane + 64;
   const int ta0 = t0 / ntb, tb0 = t0 % ntb, ta1 = t1 / ntb, tb1 = t1 % ntb;
   const bool v0 = t0 < nta * ntb, v1 = t1 < nta * ntb;
-  for (int64_t r0 = (int64_t)blockIdx.x * kGramRows; r0 < n; r0 += (int64_t)gridDim.x * kGramRows) {
+  const int64_t step = (int64_t)gridDim.x * 4 * kGramRows;
+  for (int64_t r0 = (int64_t)blockIdx.x * 4 * kGramRows; r0 < n; r0 += step) {
+    const int64_t rw = r0 + wid * kGramRows;
     for (int idx = lane; idx < kGramRows * lda; idx += 64) {
       const int c = idx / kGramRows, rr = idx % kGramRows;
-      const int64_t i = r0 + rr;
-      xs[rr * lda + c] = (c < na && i < n) ? col_ptr(X, c)[i] : T(0);
+      const int64_t i = rw + rr;
+      xs[c * kGramPad + rr] = (c < na && i < n) ? col_ptr(X, c)[i] : T(0);
     }
     for (int idx = lane; idx < kGramRows * ldb; idx += 64) {
       const int c = idx / kGramRows, rr = idx % kGramRows;
-      const int64_t i = r0 + rr;
-      ys[rr * ldb + c] = (c < nb && i < n) ? col_ptr(Y, c)[i] : T(0);
+      const int64_t i = rw + rr;
+      ys[c * kGramPad + rr] = (c < nb && i < n) ? col_ptr(Y, c)[i] : T(0);
     }
     __syncthreads();
 #pragma unroll 4
     for (int rr = 0; rr < kGramRows; ++rr) {
-      if (v0) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const bool v = q == 0 ? v0 : v1;
+        if (!v) continue;
+        const int ta = q == 0 ? ta0 : ta1, tb = q == 0 ? tb0 : tb1;
         T xa[kGramTile], yb[kGramTile];
 #pragma unroll
-        for (int i = 0; i < kGramTile; ++i) xa[i] = xs[rr * lda + ta0 * kGramTile + i];
+        for (int i = 0; i < kGramTile; ++i) xa[i] = xs[(ta * kGramTile + i) * kGramPad + rr];
 #pragma unroll
-        for (int j = 0; j < kGramTile; ++j) yb[j] = ys[rr * ldb + tb0 * kGramTile + j];
+        for (int j = 0; j < kGramTile; ++j) yb[j] = ys[(tb * kGramTile + j) * kGramPad + rr];
 #pragma unroll
         for (int i = 0; i < kGramTile; ++i)
 #pragma unroll
-          for (int j = 0; j < kGramTile; ++j) acc[0][i][j] += xa[i] * yb[j];
-      }
-      if (v1) {
-        T xa[kGramTile], yb[kGramTile];
-#pragma unroll
-        for (int i = 0; i < kGramTile; ++i) xa[i] = xs[rr * lda + ta1 * kGramTile + i];
-#pragma unroll
-        for (int j = 0; j < kGramTile; ++j) yb[j] = ys[rr * ldb + tb1 * kGramTile + j];
-#pragma unroll
-        for (int i = 0; i < kGramTile; ++i)
-#pragma unroll
-          for (int j = 0; j < kGramTile; ++j) acc[1][i][j] += xa[i] * yb[j];
+          for (int j = 0; j < kGramTile; ++j) acc[q][i][j] += xa[i] * yb[j];
       }
     }
     __syncthreads();
   }
+  // add the 4 waves' tiles in wave order
+  T* red = reinterpret_cast<T*>(smem_raw);
+  for (int wv = 0; wv < 4; ++wv) {
+    if (wid == wv) {
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const bool v = q == 0 ? v0 : v1;
-    if (!v) continue;
-    const int ta = q == 0 ? ta0 : ta1, tb = q == 0 ? tb0 : tb1;
+      for (int q = 0; q < 2; ++q) {
+        const bool v = q == 0 ? v0 : v1;
+        if (!v) continue;
+        const int ta = q == 0 ? ta0 : ta1, tb = q == 0 ? tb0 : tb1;
 #pragma unroll
-    for (int i = 0; i < kGramTile; ++i)
+        for (int i = 0; i < kGramTile; ++i)
 #pragma unroll
-      for (int j = 0; j < kGramTile; ++j) {
-        const int a = ta * kGramTile + i, b = tb * kGramTile + j;
-        if (a < na && b < nb) partials[((int64_t)a * nb + b) * nblk + blockIdx.x] = acc[q][i][j];
+          for (int j = 0; j < kGramTile; ++j) {
+            const int idx = (ta * kGramTile + i) * ldb + tb * kGramTile + j;
+            red[idx] = (wv == 0 ? T(0) : red[idx]) + acc[q][i][j];
+          }
       }
+    }
+    __syncthreads();
+  }
+  for (int p = threadIdx.x; p < na * nb; p += kThreads) {
+    const int a = p / nb, b = p % nb;
+    partials[(int64_t)p * nblk + blockIdx.x] = red[a * ldb + b];
   }
 }
 
+// out[:, o] = sum_c In_c * M[c + nin*o]; one row per thread (in place over In
+// allowed: a thread reads its whole row before writing it).
 template <class T, int NIN>
 __global__ __launch_bounds__(kThreads) void k_row_transform(Cols<T> In, const double* M,
                                                             int nout, T* out, int64_t ldo,
@@ -404,21 +508,122 @@ __global__ __launch_bounds__(kThreads) void k_row_transform(Cols<T> In, const do
   extern __shared__ unsigned char smem_raw[];
   T* Ms = reinterpret_cast<T*>(smem_raw);
   const int nin = In.n1 + In.n2;
-  for (int idx = threadIdx.x; idx < nin * nout; idx += kThreads) Ms[idx] = (T)M[idx];
-  __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads) {
-    T v[NIN];
-#pragma unroll
-    for (int c = 0; c < NIN; ++c) v[c] = c < nin ? col_ptr(In, c)[i] : T(0);
-    for (int o = 0; o < nout; ++o) {
-      T s = 0;
-#pragma unroll
-      for (int c = 0; c < NIN; ++c)
-        if (c < nin) s += v[c] * Ms[c + nin * o];
-      out[(int64_t)o * ldo + i] = s;
-    }
+  for (int idx = threadIdx.x; idx < NIN * nout; idx += kThreads) {
+    const int c = idx % NIN, o = idx / NIN;
+    Ms[idx] = c < nin ? (T)M[c + nin * o] : T(0);
   }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  T v[NIN];
+#pragma unroll
+  for (int c = 0; c < NIN; ++c) v[c] = col_ptr(In, min(c, nin - 1))[i];
+  for (int o = 0; o < nout; ++o) {
+    T s = 0;
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) s += v[c] * Ms[o * NIN + c];
+    out[(int64_t)o * ldo + i] = s;
+  }
+}
+
+// W consecutive cells of one x row per thread (nx % W == 0, 16-byte aligned
+// arrays): bands and the y/z neighbours as 16-byte packs, the x neighbours
+// from the thread's own pack plus one element on each side.
+template <class T, int W>
+__device__ __forceinline__ void apply_pack(const Grid3& g, const T* __restrict__ A,
+                                           const T* __restrict__ x, int64_t iv, T (&ax)[W],
+                                           T (&xc)[W]) {
+  const int64_t N = g.n;
+  const int64_t i = iv * W;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int ii = (int)i;
+  const int ix = ii % nx;
+  const int t = ii / nx;
+  const int iy = t % ny;
+  const int iz = t / ny;
+  const int64_t rowp = nx / W;                 // packs per x row
+  const int64_t planep = rowp * ny;            // packs per z plane
+  const Pk<T, W> xv = ldp<T, W>(x, iv);
+  Pk<T, W> xs, xn, xb, xt;
+  const Pk<T, W> zero = {};
+  xs = iy > 0 ? ldp<T, W>(x, iv - rowp) : (g.py ? ldp<T, W>(x, iv + (ny - 1) * rowp) : zero);
+  xn = iy < ny - 1 ? ldp<T, W>(x, iv + rowp) : (g.py ? ldp<T, W>(x, iv - (ny - 1) * rowp) : zero);
+  xb = iz > 0 ? ldp<T, W>(x, iv - planep) : (g.pz ? ldp<T, W>(x, iv + (nz - 1) * planep) : zero);
+  xt = iz < nz - 1 ? ldp<T, W>(x, iv + planep)
+                   : (g.pz ? ldp<T, W>(x, iv - (nz - 1) * planep) : zero);
+  const T xm = ix > 0 ? x[i - 1] : (g.px ? x[i + nx - 1] : T(0));
+  const T xp = ix + W < nx ? x[i + W] : (g.px ? x[i + W - nx] : T(0));
+  const int64_t Np = N / W;
+  const Pk<T, W> aC = ldp<T, W>(A, iv), aW = ldp<T, W>(A, Np + iv), aE = ldp<T, W>(A, 2 * Np + iv),
+                 aS = ldp<T, W>(A, 3 * Np + iv), aN = ldp<T, W>(A, 4 * Np + iv),
+                 aB = ldp<T, W>(A, 5 * Np + iv), aT = ldp<T, W>(A, 6 * Np + iv);
+#pragma unroll
+  for (int e = 0; e < W; ++e) {
+    const T xw = e == 0 ? xm : xv.v[e - 1];
+    const T xe = e == W - 1 ? xp : xv.v[e + 1];
+    T a = aC.v[e] * xv.v[e];
+    a += aW.v[e] * xw;
+    a += aE.v[e] * xe;
+    a += aS.v[e] * xs.v[e];
+    a += aN.v[e] * xn.v[e];
+    a += aB.v[e] * xb.v[e];
+    a += aT.v[e] * xt.v[e];
+    ax[e] = a;
+    xc[e] = xv.v[e];
+  }
+}
+
+// MODE as k_stencil
+template <class T, int W, int MODE>
+__global__ __launch_bounds__(kThreads) void k_stencil_v(Grid3 g, const T* __restrict__ A,
+                                                         const T* __restrict__ x, T* y, T alpha,
+                                                         T beta, const T* __restrict__ bv) {
+  const int64_t iv = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+  if (iv * W >= g.n) return;
+  T ax[W], xc[W];
+  apply_pack<T, W>(g, A, x, iv, ax, xc);
+  Pk<T, W> out;
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int e = 0; e < W; ++e) out.v[e] = alpha * ax[e];
+  } else if constexpr (MODE == 1) {
+    const Pk<T, W> b = ldp<T, W>(bv, iv);
+#pragma unroll
+    for (int e = 0; e < W; ++e) out.v[e] = alpha * ax[e] + beta * b.v[e];
+  } else if constexpr (MODE == 2) {
+    const Pk<T, W> yo = ldp<T, W>(y, iv);
+#pragma unroll
+    for (int e = 0; e < W; ++e) out.v[e] = alpha * ax[e] + beta * yo.v[e];
+  } else {
+    const Pk<T, W> b = ldp<T, W>(bv, iv), c = ldp<T, W>(A, iv);
+#pragma unroll
+    for (int e = 0; e < W; ++e) out.v[e] = xc[e] + alpha * (b.v[e] - ax[e]) / c.v[e];
+  }
+  stp<T, W>(y, iv, out);
+}
+
+template <class T, int W>
+__global__ __launch_bounds__(kThreads) void k_residual_norm_v(Grid3 g, const T* __restrict__ A,
+                                                              const T* __restrict__ x,
+                                                              const T* __restrict__ b,
+                                                              T* __restrict__ y, T* partials) {
+  T acc = 0;
+  const int64_t npk = g.n / W;
+  const Range r = block_range(npk);
+  for (int64_t iv = r.v0 + threadIdx.x; iv < r.v1; iv += kThreads) {
+    T ax[W], xc[W];
+    apply_pack<T, W>(g, A, x, iv, ax, xc);
+    const Pk<T, W> bb = ldp<T, W>(b, iv);
+    Pk<T, W> out;
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      out.v[e] = bb.v[e] - ax[e];
+      acc += out.v[e] * out.v[e];
+    }
+    stp<T, W>(y, iv, out);
+  }
+  const T s = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -489,28 +694,55 @@ __global__ void k_bicg_alpha(const double* sums, int kc, double* sc, int off_eta
   }
 }
 
-template <class T, int NC>
+template <class T, int W, int NC>
+__device__ __forceinline__ void sv_rows(const Cols<T>& C, const T* cf, T alpha,
+                                        const T* __restrict__ r, T* v, T* __restrict__ sv,
+                                        int64_t i0, int64_t i1, T& acc) {
+  const int kc = C.n1;
+  for (int64_t iv = i0; iv < i1; iv += kThreads) {
+    Pk<T, W> vi = ldp<T, W>(v, iv);
+#pragma unroll
+    for (int g = 0; g < NC; g += kGroup) {
+      if (g < kc) {
+        Pk<T, W> q[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+          q[u] = ldp<T, W>(C.p1 + (int64_t)min(g + u, kc - 1) * C.ld1, iv);
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+#pragma unroll
+          for (int e = 0; e < W; ++e) vi.v[e] -= cf[g + u] * q[u].v[e];
+      }
+    }
+    if (NC > 0) stp<T, W>(v, iv, vi);
+    const Pk<T, W> ri = ldp<T, W>(r, iv);
+    Pk<T, W> si;
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      si.v[e] = ri.v[e] - alpha * vi.v[e];
+      acc += si.v[e] * si.v[e];
+    }
+    stp<T, W>(sv, iv, si);
+  }
+}
+
+// v -= C eta1 ; s = r - alpha v ; partial |s|^2
+template <class T, int W, int NC>
 __global__ __launch_bounds__(kThreads) void k_bicg_sv(Cols<T> C, const T* __restrict__ r, T* v,
                                                       T* __restrict__ sv, const double* sc,
                                                       int off_eta1, int64_t n, T* partials,
                                                       int nblk) {
   __shared__ T cf[NC > 0 ? NC : 1];
   const int kc = C.n1;
-  for (int c = threadIdx.x; c < kc; c += kThreads) cf[c] = (T)sc[off_eta1 + c];
+  for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (T)sc[off_eta1 + c] : T(0);
   __syncthreads();
   const T alpha = (T)sc[kAlpha];
   T acc[1] = {0};
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads) {
-    T vi = v[i];
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c < kc) vi -= cf[c] * C.p1[(int64_t)c * C.ld1 + i];
-    if (NC > 0) v[i] = vi;
-    const T si = r[i] - alpha * vi;
-    sv[i] = si;
-    acc[0] += si * si;
-  }
+  const int64_t npk = n / W;
+  const Range rg = block_range(npk);
+  sv_rows<T, W, NC>(C, cf, alpha, r, v, sv, rg.v0 + threadIdx.x, rg.v1, acc[0]);
+  if (W > 1 && blockIdx.x == gridDim.x - 1)
+    sv_rows<T, 1, NC>(C, cf, alpha, r, v, sv, npk * W + threadIdx.x, n, acc[0]);
   reduce_store<T, 1>(acc, 1, partials, nblk);
 }
 
@@ -534,7 +766,44 @@ __global__ void k_bicg_omega(const double* sums, int kc, double* sc, int off_eta
   for (int c = 0; c < kc; ++c) sc[off_xi + c] += alpha * sc[off_eta1 + c] + omega * sc[off_eta2 + c];
 }
 
-template <class T, int NC>
+template <class T, int W, int NC>
+__device__ __forceinline__ void yr_rows(const Cols<T>& C, const T* cf, T alpha, T omega,
+                                        const T* __restrict__ t, const T* __restrict__ sv,
+                                        const T* __restrict__ p, T* __restrict__ y,
+                                        T* __restrict__ r, const T* __restrict__ rt, int64_t i0,
+                                        int64_t i1, T (&acc)[2]) {
+  const int kc = C.n1;
+  for (int64_t iv = i0; iv < i1; iv += kThreads) {
+    Pk<T, W> ti = ldp<T, W>(t, iv);
+#pragma unroll
+    for (int g = 0; g < NC; g += kGroup) {
+      if (g < kc) {
+        Pk<T, W> q[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+          q[u] = ldp<T, W>(C.p1 + (int64_t)min(g + u, kc - 1) * C.ld1, iv);
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+#pragma unroll
+          for (int e = 0; e < W; ++e) ti.v[e] -= cf[g + u] * q[u].v[e];
+      }
+    }
+    const Pk<T, W> si = ldp<T, W>(sv, iv), pi = ldp<T, W>(p, iv), rti = ldp<T, W>(rt, iv);
+    Pk<T, W> yi = ldp<T, W>(y, iv), ri;
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      yi.v[e] += alpha * pi.v[e] + omega * si.v[e];
+      ri.v[e] = si.v[e] - omega * ti.v[e];
+      acc[0] += rti.v[e] * ri.v[e];
+      acc[1] += ri.v[e] * ri.v[e];
+    }
+    stp<T, W>(y, iv, yi);
+    stp<T, W>(r, iv, ri);
+  }
+}
+
+// y += alpha p + omega s ; r = s - omega (t - C eta2) ; partials r~.r, |r|^2
+template <class T, int W, int NC>
 __global__ __launch_bounds__(kThreads) void k_bicg_yr(Cols<T> C, const T* __restrict__ t,
                                                       const T* __restrict__ sv,
                                                       const T* __restrict__ p, T* __restrict__ y,
@@ -543,23 +812,15 @@ __global__ __launch_bounds__(kThreads) void k_bicg_yr(Cols<T> C, const T* __rest
                                                       T* partials, int nblk) {
   __shared__ T cf[NC > 0 ? NC : 1];
   const int kc = C.n1;
-  for (int c = threadIdx.x; c < kc; c += kThreads) cf[c] = (T)sc[off_eta2 + c];
+  for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (T)sc[off_eta2 + c] : T(0);
   __syncthreads();
   const T alpha = (T)sc[kAlpha], omega = (T)sc[kOmega];
   T acc[2] = {0, 0};
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads) {
-    T ti = t[i];
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c < kc) ti -= cf[c] * C.p1[(int64_t)c * C.ld1 + i];
-    const T si = sv[i];
-    y[i] += alpha * p[i] + omega * si;
-    const T ri = si - omega * ti;
-    r[i] = ri;
-    acc[0] += rt[i] * ri;
-    acc[1] += ri * ri;
-  }
+  const int64_t npk = n / W;
+  const Range rg = block_range(npk);
+  yr_rows<T, W, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, rg.v0 + threadIdx.x, rg.v1, acc);
+  if (W > 1 && blockIdx.x == gridDim.x - 1)
+    yr_rows<T, 1, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, npk * W + threadIdx.x, n, acc);
   reduce_store<T, 2>(acc, 2, partials, nblk);
 }
 
@@ -631,10 +892,30 @@ constexpr bool fits(int n) { return n <= NC; }
 // launchers
 // ---------------------------------------------------------------------------
 template <class T>
+inline bool al16(const T* p) {
+  return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+}
+template <class T>
+inline bool stencil_vec_ok(const Grid3& g, const T* bands, const T* x, const T* y, const T* b) {
+  constexpr int W = 16 / sizeof(T);
+  return g.nx % W == 0 && al16(bands) && al16(x) && al16(y) && (b == nullptr || al16(b));
+}
+
+template <class T>
 hipError_t stencil(hipStream_t s, const Grid3& g, const T* bands, const T* x, T* y, double alpha,
                    double beta, const T* b, int mode) {
   const int grid = grid_for(g.n);
   if (g.n == 0) return hipSuccess;
+  constexpr int W = 16 / sizeof(T);
+  if (stencil_vec_ok(g, bands, x, y, b)) {
+    const int gv = grid_for(g.n / W);
+    switch (mode) {
+      case 0: k_stencil_v<T, W, 0><<<gv, kThreads, 0, s>>>(g, bands, x, y, (T)alpha, (T)beta, b); break;
+      case 1: k_stencil_v<T, W, 1><<<gv, kThreads, 0, s>>>(g, bands, x, y, (T)alpha, (T)beta, b); break;
+      default: k_stencil_v<T, W, 2><<<gv, kThreads, 0, s>>>(g, bands, x, y, (T)alpha, (T)beta, b); break;
+    }
+    return hipGetLastError();
+  }
   switch (mode) {
     case 0: k_stencil<T, 0><<<grid, kThreads, 0, s>>>(g, bands, x, y, (T)alpha, (T)beta, b); break;
     case 1: k_stencil<T, 1><<<grid, kThreads, 0, s>>>(g, bands, x, y, (T)alpha, (T)beta, b); break;
@@ -646,7 +927,11 @@ hipError_t stencil(hipStream_t s, const Grid3& g, const T* bands, const T* x, T*
 template <class T>
 hipError_t residual_norm(hipStream_t s, const Grid3& g, const T* bands, const T* x, const T* b,
                          T* y, T* partials) {
-  k_residual_norm<T><<<red_blocks(g.n), kThreads, 0, s>>>(g, bands, x, b, y, partials);
+  constexpr int W = 16 / sizeof(T);
+  if (stencil_vec_ok(g, bands, x, (const T*)y, b))
+    k_residual_norm_v<T, W><<<red_blocks(g.n), kThreads, 0, s>>>(g, bands, x, b, y, partials);
+  else
+    k_residual_norm<T><<<red_blocks(g.n), kThreads, 0, s>>>(g, bands, x, b, y, partials);
   return hipGetLastError();
 }
 
@@ -654,7 +939,12 @@ template <class T>
 hipError_t jacobi_sweep(hipStream_t s, const Grid3& g, const T* bands, const T* r, const T* zin,
                         T* zout, double omega) {
   if (g.n == 0) return hipSuccess;
-  k_stencil<T, 3><<<grid_for(g.n), kThreads, 0, s>>>(g, bands, zin, zout, (T)omega, T(0), r);
+  constexpr int W = 16 / sizeof(T);
+  if (stencil_vec_ok(g, bands, zin, (const T*)zout, r))
+    k_stencil_v<T, W, 3><<<grid_for(g.n / W), kThreads, 0, s>>>(g, bands, zin, zout, (T)omega,
+                                                                T(0), r);
+  else
+    k_stencil<T, 3><<<grid_for(g.n), kThreads, 0, s>>>(g, bands, zin, zout, (T)omega, T(0), r);
   return hipGetLastError();
 }
 
@@ -680,21 +970,39 @@ hipError_t schwarz_local(hipStream_t s, const Grid3& g, int tile, const T* bands
   return hipGetLastError();
 }
 
-#define KRS_NC_DISPATCH(ncount, KERNEL_CALL) \
-  do {                                       \
-    const int _n = (ncount);                 \
-    if (_n <= 8) { constexpr int NCB = 8; KERNEL_CALL; }          \
-    else if (_n <= 16) { constexpr int NCB = 16; KERNEL_CALL; }   \
-    else if (_n <= 32) { constexpr int NCB = 32; KERNEL_CALL; }   \
-    else if (_n <= 64) { constexpr int NCB = 64; KERNEL_CALL; }   \
-    else return hipErrorInvalidValue;        \
+#define KRS_NC_DISPATCH(ncount, ...)                              \
+  do {                                                            \
+    const int _n = (ncount);                                      \
+    if (_n <= 8) { constexpr int NCB = 8; __VA_ARGS__; }          \
+    else if (_n <= 16) { constexpr int NCB = 16; __VA_ARGS__; }   \
+    else if (_n <= 32) { constexpr int NCB = 32; __VA_ARGS__; }   \
+    else if (_n <= 64) { constexpr int NCB = 64; __VA_ARGS__; }   \
+    else return hipErrorInvalidValue;                             \
   } while (0)
+
+// 16-byte loads are usable when every pointer is 16-byte aligned and every
+// leading dimension is a multiple of the pack width.
+template <class T>
+inline bool vec_ok(const Cols<T>& Q) {
+  constexpr int W = 16 / sizeof(T);
+  if (Q.n1 && (!al16(Q.p1) || Q.ld1 % W)) return false;
+  if (Q.n2 && (!al16(Q.p2) || Q.ld2 % W)) return false;
+  return true;
+}
+template <class T>
+inline bool vec_ok(const T* p) {
+  return p == nullptr || al16(p);
+}
 
 template <class T>
 hipError_t block_dot(hipStream_t s, const Cols<T>& Q, const T* w, int64_t n, int self_dot,
                      T* partials, int nblk) {
-  KRS_NC_DISPATCH(Q.count() > 0 ? Q.count() : 1,
-                  (k_block_dot<T, NCB><<<nblk, kThreads, 0, s>>>(Q, w, n, self_dot, partials, nblk)));
+  constexpr int VW = 16 / sizeof(T);
+  const bool v = vec_ok(Q) && vec_ok(w);
+  KRS_NC_DISPATCH(Q.count() > 0 ? Q.count() : 1, {
+    if (v) k_block_dot<T, VW, NCB><<<nblk, kThreads, 0, s>>>(Q, w, n, self_dot, partials, nblk);
+    else k_block_dot<T, 1, NCB><<<nblk, kThreads, 0, s>>>(Q, w, n, self_dot, partials, nblk);
+  });
   return hipGetLastError();
 }
 
@@ -702,28 +1010,41 @@ template <class T>
 hipError_t block_update(hipStream_t s, const Cols<T>& Q, const double* coef, double sgn,
                         const T* w_in, T* w_out, int64_t n, const double* scale, int dots,
                         T* partials, int nblk) {
-  const bool norm = dots > 0, sc = scale != nullptr, in = w_in != nullptr;
-  const int nc = Q.count() > 0 ? Q.count() : 1;
-#define KRS_BU(NORM, SC, IN)                                                                   \
-  KRS_NC_DISPATCH(nc, (k_block_update<T, NCB, NORM, SC, IN><<<nblk, kThreads, 0, s>>>(        \
-                          Q, coef, (T)sgn, w_in, w_out, n, scale, partials, nblk)))
-  if (norm) {
-    if (sc) { if (in) KRS_BU(true, true, true); else KRS_BU(true, true, false); }
-    else { if (in) KRS_BU(true, false, true); else KRS_BU(true, false, false); }
-  } else {
-    if (sc) { if (in) KRS_BU(false, true, true); else KRS_BU(false, true, false); }
-    else { if (in) KRS_BU(false, false, true); else KRS_BU(false, false, false); }
-  }
-#undef KRS_BU
+  constexpr int VW = 16 / sizeof(T);
+  const bool v = vec_ok(Q) && vec_ok(w_in) && vec_ok((const T*)w_out);
+  const int norm = dots > 0 ? 1 : 0;
+  KRS_NC_DISPATCH(Q.count() > 0 ? Q.count() : 1, {
+    if (v)
+      k_block_update<T, VW, NCB><<<nblk, kThreads, 0, s>>>(Q, coef, (T)sgn, w_in, w_out, n, scale,
+                                                          norm, partials, nblk);
+    else
+      k_block_update<T, 1, NCB><<<nblk, kThreads, 0, s>>>(Q, coef, (T)sgn, w_in, w_out, n, scale,
+                                                         norm, partials, nblk);
+  });
   return hipGetLastError();
+}
+
+// pack width of the second Gram-Schmidt pass: the NC column values of a row
+// stay in registers, so wide packs only for few columns
+template <class T>
+constexpr int dau_width(int nc) {
+  return nc * (int)sizeof(T) <= 64 ? 16 / (int)sizeof(T)
+                                   : (nc * (int)sizeof(T) <= 128 && sizeof(T) == 4 ? 2 : 1);
 }
 
 template <class T>
 hipError_t block_dot_after_update(hipStream_t s, const Cols<T>& Q, const double* coef,
                                   const T* w, int64_t n, T* partials, int nblk) {
-  KRS_NC_DISPATCH(Q.count() > 0 ? Q.count() : 1,
-                  (k_block_dot_after_update<T, NCB><<<nblk, kThreads, 0, s>>>(Q, coef, w, n,
-                                                                               partials, nblk)));
+  const bool v = vec_ok(Q) && vec_ok(w);
+  KRS_NC_DISPATCH(Q.count() > 0 ? Q.count() : 1, {
+    constexpr int DW = dau_width<T>(NCB);
+    if (v && DW > 1)
+      k_block_dot_after_update<T, DW, NCB><<<nblk, kThreads, 0, s>>>(Q, coef, w, n, partials,
+                                                                     nblk);
+    else
+      k_block_dot_after_update<T, 1, NCB><<<nblk, kThreads, 0, s>>>(Q, coef, w, n, partials,
+                                                                    nblk);
+  });
   return hipGetLastError();
 }
 
@@ -734,8 +1055,10 @@ hipError_t gram(hipStream_t s, const Cols<T>& X, const Cols<T>& Y, int64_t n, T*
   if (na == 0 || nb == 0) return hipSuccess;
   const int nta = (na + kGramTile - 1) / kGramTile, ntb = (nb + kGramTile - 1) / kGramTile;
   if (nta * ntb > 128) return hipErrorInvalidValue;   // two 4 x 4 tiles per lane
-  const size_t smem = sizeof(T) * kGramRows * kGramTile * (nta + ntb);
-  k_gram<T><<<nblk, 64, smem, s>>>(X, Y, n, partials, nblk);
+  const size_t stage = sizeof(T) * 4 * kGramPad * kGramTile * (nta + ntb);
+  const size_t red = sizeof(T) * kGramTile * kGramTile * nta * ntb;
+  const size_t smem = stage > red ? stage : red;
+  k_gram<T><<<nblk, kThreads, smem, s>>>(X, Y, n, partials, nblk);
   return hipGetLastError();
 }
 
@@ -743,17 +1066,21 @@ template <class T>
 hipError_t row_transform(hipStream_t s, const Cols<T>& In, const double* M, int nout, T* out,
                          int64_t ldo, int64_t n) {
   const int nin = In.count();
-  if (nout == 0 || n == 0) return hipSuccess;
-  const size_t smem = sizeof(T) * (size_t)nin * nout;
-  if (smem > 64 * 1024) return hipErrorInvalidValue;
-  int grid = grid_for(n);
-  if (grid > 4 * kMaxRedBlocks) grid = 4 * kMaxRedBlocks;
-  if (nin <= 8) k_row_transform<T, 8><<<grid, kThreads, smem, s>>>(In, M, nout, out, ldo, n);
-  else if (nin <= 16) k_row_transform<T, 16><<<grid, kThreads, smem, s>>>(In, M, nout, out, ldo, n);
-  else if (nin <= 32) k_row_transform<T, 32><<<grid, kThreads, smem, s>>>(In, M, nout, out, ldo, n);
-  else if (nin <= 64) k_row_transform<T, 64><<<grid, kThreads, smem, s>>>(In, M, nout, out, ldo, n);
-  else if (nin <= 96) k_row_transform<T, 96><<<grid, kThreads, smem, s>>>(In, M, nout, out, ldo, n);
+  if (nout == 0 || n == 0 || nin == 0) return hipSuccess;
+  const int grid = grid_for(n);
+#define KRS_RT(NINB)                                                                 \
+  do {                                                                               \
+    const size_t smem = sizeof(T) * (size_t)(NINB) * nout;                           \
+    if (smem > 64 * 1024) return hipErrorInvalidValue;                               \
+    k_row_transform<T, NINB><<<grid, kThreads, smem, s>>>(In, M, nout, out, ldo, n); \
+  } while (0)
+  if (nin <= 8) KRS_RT(8);
+  else if (nin <= 16) KRS_RT(16);
+  else if (nin <= 32) KRS_RT(32);
+  else if (nin <= 48) KRS_RT(48);
+  else if (nin <= 64) KRS_RT(64);
   else return hipErrorInvalidValue;
+#undef KRS_RT
   return hipGetLastError();
 }
 
@@ -787,13 +1114,23 @@ hipError_t bicg_p(hipStream_t s, const T* r, T* p, const T* v, const double* sc,
 template <class T>
 hipError_t bicg_sv(hipStream_t s, const Cols<T>& C, const T* r, T* v, T* sv, const double* sc,
                    int off_eta1, int64_t n, T* partials, int nblk) {
+  constexpr int VW = 16 / sizeof(T);
   const int kc = C.n1;
-  if (kc == 0) k_bicg_sv<T, 0><<<nblk, kThreads, 0, s>>>(C, r, v, sv, sc, off_eta1, n, partials, nblk);
-  else if (kc <= 8) k_bicg_sv<T, 8><<<nblk, kThreads, 0, s>>>(C, r, v, sv, sc, off_eta1, n, partials, nblk);
-  else if (kc <= 16) k_bicg_sv<T, 16><<<nblk, kThreads, 0, s>>>(C, r, v, sv, sc, off_eta1, n, partials, nblk);
-  else if (kc <= 32) k_bicg_sv<T, 32><<<nblk, kThreads, 0, s>>>(C, r, v, sv, sc, off_eta1, n, partials, nblk);
-  else if (kc <= 64) k_bicg_sv<T, 64><<<nblk, kThreads, 0, s>>>(C, r, v, sv, sc, off_eta1, n, partials, nblk);
+  const bool vv = vec_ok(C) && vec_ok(r) && vec_ok((const T*)v) && vec_ok((const T*)sv);
+#define KRS_SV(NCV)                                                                          \
+  do {                                                                                       \
+    if (vv) k_bicg_sv<T, VW, NCV><<<nblk, kThreads, 0, s>>>(C, r, v, sv, sc, off_eta1, n,    \
+                                                            partials, nblk);                 \
+    else k_bicg_sv<T, 1, NCV><<<nblk, kThreads, 0, s>>>(C, r, v, sv, sc, off_eta1, n,        \
+                                                        partials, nblk);                     \
+  } while (0)
+  if (kc == 0) KRS_SV(0);
+  else if (kc <= 8) KRS_SV(8);
+  else if (kc <= 16) KRS_SV(16);
+  else if (kc <= 32) KRS_SV(32);
+  else if (kc <= 64) KRS_SV(64);
   else return hipErrorInvalidValue;
+#undef KRS_SV
   return hipGetLastError();
 }
 
@@ -801,8 +1138,17 @@ template <class T>
 hipError_t bicg_yr(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, const T* p, T* y,
                    T* r, const T* rt, const double* sc, int off_eta2, int64_t n, T* partials,
                    int nblk) {
+  constexpr int VW = 16 / sizeof(T);
   const int kc = C.n1;
-#define KRS_YR(NCV) k_bicg_yr<T, NCV><<<nblk, kThreads, 0, s>>>(C, t, sv, p, y, r, rt, sc, off_eta2, n, partials, nblk)
+  const bool vv = vec_ok(C) && vec_ok(t) && vec_ok(sv) && vec_ok(p) && vec_ok((const T*)y) &&
+                  vec_ok((const T*)r) && vec_ok(rt);
+#define KRS_YR(NCV)                                                                          \
+  do {                                                                                       \
+    if (vv) k_bicg_yr<T, VW, NCV><<<nblk, kThreads, 0, s>>>(C, t, sv, p, y, r, rt, sc,       \
+                                                            off_eta2, n, partials, nblk);    \
+    else k_bicg_yr<T, 1, NCV><<<nblk, kThreads, 0, s>>>(C, t, sv, p, y, r, rt, sc, off_eta2, \
+                                                        n, partials, nblk);                  \
+  } while (0)
   if (kc == 0) KRS_YR(0);
   else if (kc <= 8) KRS_YR(8);
   else if (kc <= 16) KRS_YR(16);

@@ -157,8 +157,15 @@ def test_rbicgstab_plain_and_recycled_match_oracle(gpu_lib, pc):
         ref = K.rbicgstab(op, Mi, b, 1e-8, g if use_rec else None)
         assert rc == krs.OK and ref.status == K.CONVERGED
         _check_history(h[:st.history_len], ref.history)
-        slack = 2 if pc == "schwarz" else max(2, int(0.05 * ref.iterations))
-        assert abs(st.iterations - ref.iterations) <= slack
+        # within 2 of the oracle, or within the spread of the oracle itself
+        # under a 1e-15 relative perturbation of b (BiCGStab's exit step can
+        # sit on a residual plateau next to tol)
+        spread = 0
+        if abs(st.iterations - ref.iterations) > 2:
+            for eps in (1e-15, -1e-15, 2e-15):
+                alt = K.rbicgstab(op, Mi, b * (1 + eps), 1e-8, g if use_rec else None)
+                spread = max(spread, abs(alt.iterations - ref.iterations))
+        assert abs(st.iterations - ref.iterations) <= max(2, 2 * spread)
         assert st.rel_res_true <= 2e-8
         if use_rec:
             assert st.iterations < st_plain.iterations
