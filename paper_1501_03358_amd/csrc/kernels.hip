@@ -154,78 +154,92 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local(Grid3 g, const T* __
                                                             const T* __restrict__ r,
                                                             T* __restrict__ z, T omega,
                                                             int sweeps, int ntx, int nty) {
+  // Extended tile (TILE+2)^3 stored in LDS inside a box with one more layer of
+  // zeros on every side, so every neighbour read is in bounds and reads 0
+  // outside the extended tile (the zero values of the local problem).
   constexpr int E = TILE + 2;
+  constexpr int P = E + 2;
   constexpr int NE = E * E * E;
+  constexpr int NP = P * P * P;
   constexpr int PER = (NE + kThreads - 1) / kThreads;
-  __shared__ T zs[2][NE];
+  __shared__ T zs[2 * NP];
+  for (int idx = threadIdx.x; idx < 2 * NP; idx += kThreads) zs[idx] = 0;
+  const int tid = threadIdx.x;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = tile % ntx;
   const int ty = (tile / ntx) % nty;
   const int tz = tile / (ntx * nty);
   const int64_t N = g.n;
 
-  T a[PER][7];
-  T rr[PER];
-  T idg[PER];
+  // per cell: d0 = omega r / a_C and c_k = omega a_k / a_C, so that one damped
+  // Jacobi sweep is z <- (1 - omega) z + d0 - sum_k c_k z_k
+  T cf[PER][6];
+  T d0[PER];
+  int li[PER];
   int gi[PER];
-  unsigned nbm[PER];   // bit d: neighbour d (W,E,S,N,B,T) inside the extended tile
-  unsigned ownm = 0;   // bit q: cell q is owned by this tile
+  unsigned ownm = 0;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + kThreads * q;
+    const int e = tid + kThreads * q;
 #pragma unroll
-    for (int d = 0; d < 7; ++d) a[q][d] = 0;
-    rr[q] = 0;
-    idg[q] = 0;
+    for (int d = 0; d < 6; ++d) cf[q][d] = 0;
+    d0[q] = 0;
     gi[q] = -1;
-    nbm[q] = 0;
+    li[q] = 0;
     if (e < NE) {
       const int ex = e % E, ey = (e / E) % E, ez = e / (E * E);
+      li[q] = ((ez + 1) * P + (ey + 1)) * P + ex + 1;
       int gx = tx * TILE + ex - 1, gy = ty * TILE + ey - 1, gz = tz * TILE + ez - 1;
       const bool ok = wrap_coord(gx, g.nx, g.px) && wrap_coord(gy, g.ny, g.py) &&
                       wrap_coord(gz, g.nz, g.pz);
-      nbm[q] = (ex > 0 ? 1u : 0u) | (ex < E - 1 ? 2u : 0u) | (ey > 0 ? 4u : 0u) |
-               (ey < E - 1 ? 8u : 0u) | (ez > 0 ? 16u : 0u) | (ez < E - 1 ? 32u : 0u);
       if (ex >= 1 && ex <= TILE && ey >= 1 && ey <= TILE && ez >= 1 && ez <= TILE)
         ownm |= 1u << q;
       if (ok) {
         const int64_t i = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
         gi[q] = (int)i;
+        const T s = omega / A[i];
 #pragma unroll
-        for (int d = 0; d < 7; ++d) a[q][d] = A[d * N + i];
-        rr[q] = r[i];
-        idg[q] = T(1) / a[q][0];
+        for (int d = 0; d < 6; ++d) cf[q][d] = s * A[(d + 1) * N + i];
+        d0[q] = s * r[i];
       }
-      zs[0][e] = 0;
     }
   }
   __syncthreads();
+  // first sweep from zero: z = d0
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + kThreads * q;
+    if (e < NE) zs[li[q]] = d0[q];
+  }
+  __syncthreads();
+  const T keep = T(1) - omega;
   int cur = 0;
-  for (int s = 0; s < sweeps; ++s) {
+  for (int s = 1; s < sweeps; ++s) {
+    const T* zc = zs + cur * NP;
+    T* zn = zs + (cur ^ 1) * NP;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + kThreads * q;
+      const int e = tid + kThreads * q;
       if (e < NE) {
-        const T* zc = zs[cur];
-        const T zv = zc[e];
-        T az = a[q][0] * zv;
-        const unsigned m = nbm[q];
-        if (m & 1u) az += a[q][1] * zc[e - 1];
-        if (m & 2u) az += a[q][2] * zc[e + 1];
-        if (m & 4u) az += a[q][3] * zc[e - E];
-        if (m & 8u) az += a[q][4] * zc[e + E];
-        if (m & 16u) az += a[q][5] * zc[e - E * E];
-        if (m & 32u) az += a[q][6] * zc[e + E * E];
-        zs[cur ^ 1][e] = zv + omega * (rr[q] - az) * idg[q];
+        const int l = li[q];
+        T v = keep * zc[l] + d0[q];
+        v -= cf[q][0] * zc[l - 1];
+        v -= cf[q][1] * zc[l + 1];
+        v -= cf[q][2] * zc[l - P];
+        v -= cf[q][3] * zc[l + P];
+        v -= cf[q][4] * zc[l - P * P];
+        v -= cf[q][5] * zc[l + P * P];
+        zn[l] = v;
       }
     }
     __syncthreads();
     cur ^= 1;
   }
+  const T* zf = zs + cur * NP;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + kThreads * q;
-    if (e < NE && ((ownm >> q) & 1u)) z[gi[q]] = zs[cur][e];
+    const int e = tid + kThreads * q;
+    if (e < NE && ((ownm >> q) & 1u)) z[gi[q]] = zf[li[q]];
   }
 }
 
@@ -961,6 +975,7 @@ hipError_t schwarz_local(hipStream_t s, const Grid3& g, int tile, const T* bands
   const int ntx = g.nx / tile, nty = g.ny / tile, ntz = g.nz / tile;
   const int nt = ntx * nty * ntz;
   if (nt == 0) return hipSuccess;
+  if (sweeps < 1) return hipErrorInvalidValue;
   if (tile == 8)
     k_schwarz_local<T, 8><<<nt, kThreads, 0, s>>>(g, bands, r, z, (T)omega, sweeps, ntx, nty);
   else if (tile == 4)
