@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-5)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -82,6 +84,16 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        # a plain copy of known size: reads 2^30 bytes, writes 2^30 bytes per launch
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                          "launches": 5}))
+        return
     prob, bs = build_inputs(args.n, args.steps, args.warmup, dev, torch)
     ctx = krs.Context(dev)
     b64 = torch.from_numpy(prob.bands).to(dev)

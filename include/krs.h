@@ -161,11 +161,18 @@ int krs_matrix_create(krs_ctx* ctx, const krs_grid* g, krs_dtype dt, const void*
 void krs_matrix_destroy(krs_matrix* A);
 
 /* Preconditioner for A; `ws` is a device buffer of at least
- * krs_precond_workspace_size() bytes (one temporary vector), owned by the
- * caller; may be NULL when global_sweeps == 0 or type != SCHWARZ_JACOBI. */
+ * krs_precond_workspace_size(A, d) bytes, owned by the caller (NULL allowed
+ * when the size is 0).  For SCHWARZ_JACOBI it holds one temporary vector and a
+ * tile-major copy of the local-solve coefficients (omega_local / a_C and
+ * omega_local * a_k / a_C for every cell of every extended tile, about
+ * 7 (tile+2)^3 / tile^3 values per cell), built here on the context stream
+ * from A's current bands.  If the caller changes A's bands afterwards it must
+ * call krs_precond_refresh. */
 int krs_precond_create(krs_ctx* ctx, const krs_matrix* A, const krs_precond_desc* d,
                        void* ws, size_t ws_bytes, krs_precond** out);
-size_t krs_precond_workspace_size(const krs_matrix* A);
+size_t krs_precond_workspace_size(const krs_matrix* A, const krs_precond_desc* d);
+/* Rebuilds the stored coefficients from A's current bands. Asynchronous. */
+int krs_precond_refresh(krs_ctx* ctx, krs_precond* M);
 void krs_precond_destroy(krs_precond* M);
 
 /* Recycle space: borrows U and C (each kmax columns of ld >= N values of
@@ -247,17 +254,20 @@ int krs_ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32,
 
 /* Kernel classes timed by the per-class HIP-event timers. */
 typedef enum krs_kernel_class {
-  KRS_K_STENCIL = 0,        /* y = A x, residual b - A x */
-  KRS_K_SCHWARZ_LOCAL = 1,  /* local sweeps on the extended tiles */
-  KRS_K_JACOBI_SWEEP = 2,   /* global damped Jacobi sweep / point Jacobi */
-  KRS_K_BLOCK_DOT = 3,      /* [C V]^T w and other block dot products */
-  KRS_K_BLOCK_DOT2 = 4,     /* second Gram-Schmidt pass: [C V]^T (w - [C V] h) */
-  KRS_K_BLOCK_UPDATE = 5,   /* w - [C V] h, solution and projection updates */
-  KRS_K_BICG = 6,           /* fused BiCGStab vector updates */
-  KRS_K_GRAM = 7,           /* Gram blocks of the recycle update */
-  KRS_K_ROW_TRANSFORM = 8,  /* in-place (U, C) row-block updates */
-  KRS_K_OTHER = 9,          /* finishing reductions, copies, casts */
-  KRS_K_COUNT = 10
+  KRS_K_STENCIL = 0,        /* y = alpha A x + beta (b | y) */
+  KRS_K_RESIDUAL = 1,       /* r = b - A x with the partial sums of |r|^2 */
+  KRS_K_SCHWARZ_LOCAL = 2,  /* local sweeps on the extended tiles */
+  KRS_K_JACOBI_SWEEP = 3,   /* global damped Jacobi sweep / point Jacobi */
+  KRS_K_BLOCK_DOT = 4,      /* [C V]^T w and other block dot products */
+  KRS_K_BLOCK_DOT2 = 5,     /* second Gram-Schmidt pass: [C V]^T (w - [C V] h) */
+  KRS_K_BLOCK_UPDATE = 6,   /* w - [C V] h, solution and projection updates */
+  KRS_K_BICG_P = 7,         /* p = r + beta (p - omega v) and the line-10 exit update */
+  KRS_K_BICG_SV = 8,        /* v -= C eta1, s = r - alpha v, |s|^2 */
+  KRS_K_BICG_YR = 9,        /* y += alpha p + omega s, r = s - omega (t - C eta2), dots */
+  KRS_K_GRAM = 10,          /* Gram blocks of the recycle update */
+  KRS_K_ROW_TRANSFORM = 11, /* in-place (U, C) row-block updates */
+  KRS_K_OTHER = 12,         /* finishing reductions, copies, casts, coefficient packing */
+  KRS_K_COUNT = 13
 } krs_kernel_class;
 
 /* While enabled, every kernel launch of the context is bracketed by two HIP

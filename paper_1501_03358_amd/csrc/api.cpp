@@ -115,8 +115,16 @@ int krs_matrix_create(krs_ctx* ctx, const krs_grid* g, krs_dtype dt, const void*
 
 void krs_matrix_destroy(krs_matrix* A) { delete A; }
 
-size_t krs_precond_workspace_size(const krs_matrix* A) {
-  return A ? (size_t)krs::vec_ld(A->n) * dsize(A->dt) : 0;
+size_t krs_precond_workspace_size(const krs_matrix* A, const krs_precond_desc* d) {
+  if (!A || !d) return 0;
+  if (d->type != KRS_PC_SCHWARZ_JACOBI) return 0;
+  size_t v = krs::align_up((size_t)krs::vec_ld(A->n) * dsize(A->dt));
+  return v + krs::align_up(krs::precond_pack_bytes(A, d));
+}
+
+int krs_precond_refresh(krs_ctx* ctx, krs_precond* M) {
+  if (!ctx || !M) return KRS_ERR_ARG;
+  return krs::precond_pack(ctx, M);
 }
 
 int krs_precond_create(krs_ctx* ctx, const krs_matrix* A, const krs_precond_desc* d, void* ws,
@@ -137,7 +145,7 @@ int krs_precond_create(krs_ctx* ctx, const krs_matrix* A, const krs_precond_desc
       if (A->g.periodic[a] && dims[a] <= d->tile + 2 * d->overlap)
         return set_err(ctx, KRS_ERR_ARG, "a periodic axis must be longer than an extended tile");
     }
-    if (d->global_sweeps > 0 && (!ws || ws_bytes < krs_precond_workspace_size(A)))
+    if (!ws || ws_bytes < krs_precond_workspace_size(A, d))
       return set_err(ctx, KRS_ERR_WORKSPACE, "preconditioner workspace too small");
   }
   krs_precond* M = new (std::nothrow) krs_precond();
@@ -145,7 +153,15 @@ int krs_precond_create(krs_ctx* ctx, const krs_matrix* A, const krs_precond_desc
   M->ctx = ctx;
   M->A = A;
   M->d = *d;
-  M->tmp = ws;
+  if (d->type == KRS_PC_SCHWARZ_JACOBI) {
+    M->tmp = ws;
+    M->pack = (char*)ws + krs::align_up((size_t)krs::vec_ld(A->n) * dsize(A->dt));
+    const int rc = krs::precond_pack(ctx, M);
+    if (rc) {
+      delete M;
+      return rc;
+    }
+  }
   *out = M;
   return KRS_OK;
 }

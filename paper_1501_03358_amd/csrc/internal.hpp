@@ -44,6 +44,7 @@ struct krs_precond {
   const krs_matrix* A = nullptr;
   krs_precond_desc d{};
   void* tmp = nullptr;           // one vector, needed when global sweeps > 0
+  void* pack = nullptr;          // tile-major local-solve coefficients (Schwarz-Jacobi)
 };
 
 struct krs_recycle {
@@ -151,6 +152,8 @@ void timing_release(krs_ctx* ctx);
 namespace krs {
 int workspace_bytes(krs_solver solver, int64_t n, int m, int k, krs_dtype dt, size_t* bytes);
 int precond_apply(krs_ctx* ctx, const krs_precond* M, const void* r, void* z, void* tmp);
+int precond_pack(krs_ctx* ctx, const krs_precond* M);
+size_t precond_pack_bytes(const krs_matrix* A, const krs_precond_desc* d);
 int gmres_rgcrot(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
                  bool update, const void* b, void* x, const krs_opts* o, void* ws, size_t wsb,
                  krs_stats* st);

@@ -243,6 +243,127 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local(Grid3 g, const T* __
   }
 }
 
+// Tile-major copy of the local-solve coefficients of every extended tile:
+// pk[tile][k][e], k = 0: s = omega / a_C, k = 1..6: s * a_{W,E,S,N,B,T}; zero for
+// extended-tile cells outside a non-periodic grid.  Built once per operator.
+template <class T, int TILE>
+__global__ __launch_bounds__(kThreads) void k_schwarz_pack(Grid3 g, const T* __restrict__ A,
+                                                           T* __restrict__ pk, T omega, int ntx,
+                                                           int nty) {
+  constexpr int E = TILE + 2;
+  constexpr int NE = E * E * E;
+  const int tile = blockIdx.x;
+  const int tx = tile % ntx;
+  const int ty = (tile / ntx) % nty;
+  const int tz = tile / (ntx * nty);
+  const int64_t N = g.n;
+  T* out = pk + (int64_t)tile * 7 * NE;
+  for (int e = threadIdx.x; e < NE; e += kThreads) {
+    const int ex = e % E, ey = (e / E) % E, ez = e / (E * E);
+    int gx = tx * TILE + ex - 1, gy = ty * TILE + ey - 1, gz = tz * TILE + ez - 1;
+    const bool ok = wrap_coord(gx, g.nx, g.px) && wrap_coord(gy, g.ny, g.py) &&
+                    wrap_coord(gz, g.nz, g.pz);
+    T v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (ok) {
+      const int64_t i = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
+      const T sc = omega / A[i];
+      v[0] = sc;
+#pragma unroll
+      for (int d = 1; d < 7; ++d) v[d] = sc * A[d * N + i];
+    }
+#pragma unroll
+    for (int d = 0; d < 7; ++d) out[d * NE + e] = v[d];
+  }
+}
+
+// Local sweeps reading the packed coefficients (contiguous per tile); only r
+// is gathered from the grid.
+template <class T, int TILE>
+__global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T* __restrict__ pk,
+                                                               const T* __restrict__ r,
+                                                               T* __restrict__ z, T omega,
+                                                               int sweeps, int ntx, int nty) {
+  constexpr int E = TILE + 2;
+  constexpr int P = E + 2;
+  constexpr int NE = E * E * E;
+  constexpr int NP = P * P * P;
+  constexpr int PER = (NE + kThreads - 1) / kThreads;
+  __shared__ T zs[2 * NP];
+  for (int idx = threadIdx.x; idx < 2 * NP; idx += kThreads) zs[idx] = 0;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = tile % ntx;
+  const int ty = (tile / ntx) % nty;
+  const int tz = tile / (ntx * nty);
+  const T* tp = pk + (int64_t)tile * 7 * NE;
+  T cf[PER][6];
+  T d0[PER];
+  int li[PER];
+  int gi[PER];
+  unsigned ownm = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + kThreads * q;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) cf[q][d] = 0;
+    d0[q] = 0;
+    gi[q] = -1;
+    li[q] = 0;
+    if (e < NE) {
+      const int ex = e % E, ey = (e / E) % E, ez = e / (E * E);
+      li[q] = ((ez + 1) * P + (ey + 1)) * P + ex + 1;
+      int gx = tx * TILE + ex - 1, gy = ty * TILE + ey - 1, gz = tz * TILE + ez - 1;
+      const bool ok = wrap_coord(gx, g.nx, g.px) && wrap_coord(gy, g.ny, g.py) &&
+                      wrap_coord(gz, g.nz, g.pz);
+      if (ex >= 1 && ex <= TILE && ey >= 1 && ey <= TILE && ez >= 1 && ez <= TILE)
+        ownm |= 1u << q;
+      const T sc = tp[e];
+#pragma unroll
+      for (int d = 0; d < 6; ++d) cf[q][d] = tp[(d + 1) * NE + e];
+      if (ok) {
+        const int64_t i = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
+        gi[q] = (int)i;
+        d0[q] = sc * r[i];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + kThreads * q;
+    if (e < NE) zs[li[q]] = d0[q];
+  }
+  __syncthreads();
+  const T keep = T(1) - omega;
+  int cur = 0;
+  for (int s = 1; s < sweeps; ++s) {
+    const T* zc = zs + cur * NP;
+    T* zn = zs + (cur ^ 1) * NP;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + kThreads * q;
+      if (e < NE) {
+        const int l = li[q];
+        T v = keep * zc[l] + d0[q];
+        v -= cf[q][0] * zc[l - 1];
+        v -= cf[q][1] * zc[l + 1];
+        v -= cf[q][2] * zc[l - P];
+        v -= cf[q][3] * zc[l + P];
+        v -= cf[q][4] * zc[l - P * P];
+        v -= cf[q][5] * zc[l + P * P];
+        zn[l] = v;
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  const T* zf = zs + cur * NP;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + kThreads * q;
+    if (e < NE && ((ownm >> q) & 1u)) z[gi[q]] = zf[li[q]];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // tall-skinny block products
 //
@@ -970,6 +1091,34 @@ hipError_t point_jacobi(hipStream_t s, const Grid3& g, const T* bands, const T* 
 }
 
 template <class T>
+hipError_t schwarz_pack(hipStream_t s, const Grid3& g, int tile, const T* bands, T* pk,
+                        double omega) {
+  const int ntx = g.nx / tile, nty = g.ny / tile, ntz = g.nz / tile;
+  const int nt = ntx * nty * ntz;
+  if (nt == 0) return hipSuccess;
+  if (tile == 8) k_schwarz_pack<T, 8><<<nt, kThreads, 0, s>>>(g, bands, pk, (T)omega, ntx, nty);
+  else if (tile == 4) k_schwarz_pack<T, 4><<<nt, kThreads, 0, s>>>(g, bands, pk, (T)omega, ntx, nty);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t schwarz_local_packed(hipStream_t s, const Grid3& g, int tile, const T* pk, const T* r,
+                                T* z, double omega, int sweeps) {
+  const int ntx = g.nx / tile, nty = g.ny / tile, ntz = g.nz / tile;
+  const int nt = ntx * nty * ntz;
+  if (nt == 0) return hipSuccess;
+  if (sweeps < 1) return hipErrorInvalidValue;
+  if (tile == 8)
+    k_schwarz_local_pk<T, 8><<<nt, kThreads, 0, s>>>(g, pk, r, z, (T)omega, sweeps, ntx, nty);
+  else if (tile == 4)
+    k_schwarz_local_pk<T, 4><<<nt, kThreads, 0, s>>>(g, pk, r, z, (T)omega, sweeps, ntx, nty);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t schwarz_local(hipStream_t s, const Grid3& g, int tile, const T* bands, const T* r, T* z,
                          double omega, int sweeps) {
   const int ntx = g.nx / tile, nty = g.ny / tile, ntz = g.nz / tile;
@@ -1235,6 +1384,9 @@ hipError_t axpy_f32_into_f64(hipStream_t s, const float* d, double* x, int64_t n
   template hipError_t point_jacobi<T>(hipStream_t, const Grid3&, const T*, const T*, T*);         \
   template hipError_t schwarz_local<T>(hipStream_t, const Grid3&, int, const T*, const T*, T*,    \
                                        double, int);                                              \
+  template hipError_t schwarz_pack<T>(hipStream_t, const Grid3&, int, const T*, T*, double);      \
+  template hipError_t schwarz_local_packed<T>(hipStream_t, const Grid3&, int, const T*, const T*, \
+                                              T*, double, int);                                   \
   template hipError_t block_dot<T>(hipStream_t, const Cols<T>&, const T*, int64_t, int, T*, int); \
   template hipError_t block_update<T>(hipStream_t, const Cols<T>&, const double*, double,         \
                                       const T*, T*, int64_t, const double*, int, T*, int);        \

@@ -59,6 +59,16 @@ template <class T>
 hipError_t schwarz_local(hipStream_t s, const Grid3& g, int tile, const T* bands, const T* r, T* z,
                          double omega, int sweeps);
 
+// Tile-major coefficients of the local solves (7 * (tile+2)^3 values per tile):
+// s = omega / a_C and s * a_k; rebuilt whenever A changes.
+template <class T>
+hipError_t schwarz_pack(hipStream_t s, const Grid3& g, int tile, const T* bands, T* pk,
+                        double omega);
+// Local Schwarz-Jacobi from the packed coefficients (omega must match the pack).
+template <class T>
+hipError_t schwarz_local_packed(hipStream_t s, const Grid3& g, int tile, const T* pk, const T* r,
+                                T* z, double omega, int sweeps);
+
 // partials[c*nblk + blk] = sum_rows Q_c * w  (c < ncols), then w.w if self_dot
 template <class T>
 hipError_t block_dot(hipStream_t s, const Cols<T>& Q, const T* w, int64_t n, int self_dot,

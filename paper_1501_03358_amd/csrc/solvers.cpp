@@ -50,7 +50,11 @@ struct Op {
     }
     const int gs = M->d.global_sweeps;
     T* first = (gs % 2 == 0) ? out : tmp;
-    if (M->d.local_sweeps > 0) {
+    if (M->d.local_sweeps > 0 && M->pack) {
+      KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, 9 * NW,
+                 schwarz_local_packed<T>(s, g, M->d.tile, (const T*)M->pack, r, first,
+                                         M->d.omega_local, M->d.local_sweeps));
+    } else if (M->d.local_sweeps > 0) {
       KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, 9 * NW,
                  schwarz_local<T>(s, g, M->d.tile, bands(), r, first, M->d.omega_local,
                                   M->d.local_sweeps));
@@ -449,7 +453,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
     // line 14: true residual r = b - A~ y (into the first basis column)
     rc = op.minv(x, z);
     if (rc) return rc;
-    KRS_LAUNCH(ctx, KRS_K_STENCIL, 10 * NW, residual_norm<T>(s, op.g, op.bands(), z, b, r0, part));
+    KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 10 * NW, residual_norm<T>(s, op.g, op.bands(), z, b, r0, part));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, d_nrm));
     ++mv;
     kc = rec ? rec->dim : 0;
@@ -644,7 +648,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
       status = KRS_BREAKDOWN;
       break;
     }
-    KRS_LAUNCH(ctx, KRS_K_BICG, 4 * NW, bicg_p<T>(s, r, p, v, sc, n));   // line 6
+    KRS_LAUNCH(ctx, KRS_K_BICG_P, 4 * NW, bicg_p<T>(s, r, p, v, sc, n));   // line 6
     rc = op.apply(p, v);                                     // line 7
     if (rc) return rc;
     ++mv;
@@ -653,7 +657,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
                block_dot<T>(s, cols<T>(C, ldr, kc, rt, ld, 1), v, n, 0, part, nblk));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc + 1, sc + kSums));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_alpha(s, sc + kSums, kc, sc, kEta1, kCtrt));
-    KRS_LAUNCH(ctx, KRS_K_BICG, NW * (kc + (kc > 0 ? 4 : 3)),
+    KRS_LAUNCH(ctx, KRS_K_BICG_SV, NW * (kc + (kc > 0 ? 4 : 3)),
                bicg_sv<T>(s, Cc, r, v, sv, sc, kEta1, n, part, nblk));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, sc + kSnorm2));
     rc = read_dev(ctx, sc, kSlots);
@@ -671,7 +675,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
       break;
     }
     if (snorm <= tol * nb) {                                // lines 9-10a
-      KRS_LAUNCH(ctx, KRS_K_BICG, 5 * NW, bicg_exit_s<T>(s, p, x, sv, r, sc, kEta1, kXi, kc, n));
+      KRS_LAUNCH(ctx, KRS_K_BICG_P, 5 * NW, bicg_exit_s<T>(s, p, x, sv, r, sc, kEta1, kXi, kc, n));
       rnorm = snorm;
       break;
     }
@@ -684,7 +688,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc + 2, sc + kSums));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_omega(s, sc + kSums, kc, sc, kEta1, kEta2, kXi));
     // lines 14-16 with the next rho = r~^T r
-    KRS_LAUNCH(ctx, KRS_K_BICG, NW * (kc + 7),
+    KRS_LAUNCH(ctx, KRS_K_BICG_YR, NW * (kc + 7),
                bicg_yr<T>(s, Cc, t, sv, p, x, r, rt, sc, kEta2, n, part, nblk));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 2, sc + kSums));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_rho(s, sc + kSums, sc));
@@ -714,7 +718,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   if (rc) return rc;
   KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, z, x, n));
   // true residual of x
-  KRS_LAUNCH(ctx, KRS_K_STENCIL, 10 * NW, residual_norm<T>(s, op.g, op.bands(), x, b, t, part));
+  KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 10 * NW, residual_norm<T>(s, op.g, op.bands(), x, b, t, part));
   KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, sc + kNrm));
   rc = read_dev(ctx, sc + kNrm, 1);
   if (rc) return rc;
@@ -757,6 +761,30 @@ int workspace_bytes(krs_solver solver, int64_t n, int m, int k, krs_dtype dt, si
   }
   *bytes = v;
   return KRS_OK;
+}
+
+size_t precond_pack_bytes(const krs_matrix* A, const krs_precond_desc* d) {
+  if (!d || d->type != KRS_PC_SCHWARZ_JACOBI || d->tile <= 0) return 0;
+  const int64_t t = d->tile, e = t + 2;
+  const int64_t nt = (A->g.nx / t) * (A->g.ny / t) * (A->g.nz / t);
+  return (size_t)nt * 7 * e * e * e * (A->dt == KRS_F64 ? sizeof(double) : sizeof(float));
+}
+
+int precond_pack(krs_ctx* ctx, const krs_precond* M) {
+  if (!M->pack) return 0;
+  const krs_matrix* A = M->A;
+  const Grid3 g = grid3(A);
+  const double bytes = (double)precond_pack_bytes(A, &M->d) + 7.0 * A->n *
+                       (A->dt == KRS_F64 ? 8 : 4);
+  if (A->dt == KRS_F64)
+    KRS_LAUNCH(ctx, KRS_K_OTHER, bytes,
+               schwarz_pack<double>(ctx->stream, g, M->d.tile, (const double*)A->bands,
+                                    (double*)M->pack, M->d.omega_local));
+  else
+    KRS_LAUNCH(ctx, KRS_K_OTHER, bytes,
+               schwarz_pack<float>(ctx->stream, g, M->d.tile, (const float*)A->bands,
+                                   (float*)M->pack, M->d.omega_local));
+  return 0;
 }
 
 int precond_apply(krs_ctx* ctx, const krs_precond* M, const void* r, void* z, void* tmp) {
@@ -878,7 +906,7 @@ int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const k
     // x += ||r|| d ; r = b - A x in FP64
     ctx->bytes = 0;
     KRS_LAUNCH(ctx, KRS_K_OTHER, 20.0 * n, axpy_f32_into_f64(s, d32, x, n, sc + 17));
-    KRS_LAUNCH(ctx, KRS_K_STENCIL, 80.0 * n,
+    KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 80.0 * n,
                residual_norm<double>(s, g, (const double*)A64->bands, x, b, r64, part));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<double>(s, part, nblk, 1, sc));
     total_bytes += ctx->bytes;

@@ -26,7 +26,7 @@ FLAG_TRUST_ESTIMATE = 1
 EXPORTS = (
     "krs_create", "krs_destroy", "krs_last_error", "krs_set_stream", "krs_matrix_create",
     "krs_matrix_destroy", "krs_precond_create", "krs_precond_workspace_size",
-    "krs_precond_destroy", "krs_recycle_create", "krs_recycle_destroy", "krs_recycle_dim",
+    "krs_precond_refresh", "krs_precond_destroy", "krs_recycle_create", "krs_recycle_destroy", "krs_recycle_dim",
     "krs_recycle_set_dim", "krs_workspace_size", "krs_stencil_apply", "krs_precond_apply",
     "krs_gmres", "krs_rgcrot_solve", "krs_rbicgstab_solve", "krs_recycle_update",
     "krs_hybrid_solve", "krs_ir_solve", "krs_version", "krs_timing_enable", "krs_timing_reset",
@@ -81,7 +81,8 @@ def _declare(L):
         "krs_matrix_create": (i32, [P, ctypes.POINTER(Grid), i32, P, ctypes.POINTER(P)]),
         "krs_matrix_destroy": (None, [P]),
         "krs_precond_create": (i32, [P, P, ctypes.POINTER(PrecondDesc), P, sz, ctypes.POINTER(P)]),
-        "krs_precond_workspace_size": (sz, [P]),
+        "krs_precond_workspace_size": (sz, [P, ctypes.POINTER(PrecondDesc)]),
+        "krs_precond_refresh": (i32, [P, P]),
         "krs_precond_destroy": (None, [P]),
         "krs_recycle_create": (i32, [P, i64, i32, i32, P, P, i64, ctypes.POINTER(P)]),
         "krs_recycle_destroy": (None, [P]),
@@ -208,12 +209,16 @@ class Precond:
         self.ctx, self.A = ctx, A
         self.desc = PrecondDesc(t, tile, overlap, local_sweeps, global_sweeps, 0, omega_local,
                                 omega_global)
-        nbytes = lib().krs_precond_workspace_size(A.h)
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=A.bands.device)
+        nbytes = lib().krs_precond_workspace_size(A.h, ctypes.byref(self.desc))
+        self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=A.bands.device)
         h = P()
         ctx.check(lib().krs_precond_create(ctx.h, A.h, ctypes.byref(self.desc), _ptr(self.ws),
                                            nbytes, ctypes.byref(h)))
         self.h = h
+
+    def refresh(self):
+        """Rebuild the stored coefficients after the matrix bands changed."""
+        return self.ctx.check(lib().krs_precond_refresh(self.ctx.h, self.h))
 
     def __del__(self):
         try:
@@ -352,8 +357,9 @@ def ir_solve(ctx, A64, A32, M32, rec32, b, x, opts, ws, stats=None):
     return rc, st
 
 
-KERNEL_CLASSES = ("stencil", "schwarz_local", "jacobi_sweep", "block_dot", "block_dot2",
-                  "block_update", "bicg", "gram", "row_transform", "other")
+KERNEL_CLASSES = ("stencil", "residual", "schwarz_local", "jacobi_sweep", "block_dot",
+                  "block_dot2", "block_update", "bicg_p", "bicg_sv", "bicg_yr", "gram",
+                  "row_transform", "other")
 
 
 def timing_enable(ctx, on=True):

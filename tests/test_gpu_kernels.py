@@ -131,3 +131,20 @@ def test_stencil_rejects_aliasing(gpu_lib):
     x = d.vec(np.ones(d.prob.n))
     with pytest.raises(krs.KrsError):
         krs.stencil_apply(d.ctx, d.A, x, x)
+
+
+def test_schwarz_refresh_after_band_change(gpu_lib):
+    """The preconditioner stores its local-solve coefficients; after the
+    bands change, refresh() makes it follow the new operator."""
+    krs = gpu_lib
+    prob = W.grf_problem(16, extra=21)
+    p = dict(tile=8, overlap=1, local_sweeps=5, omega_local=6 / 7, global_sweeps=1,
+             omega_global=6 / 7)
+    d = Dev(krs, prob, "schwarz", p)
+    r = np.random.default_rng(5).standard_normal(prob.n)
+    d.bands.mul_(2.0)
+    d.M.refresh()
+    z = d.empty()
+    krs.precond_apply(d.ctx, d.M, d.vec(r), z)
+    ref = precond.schwarz_jacobi(2.0 * prob.bands, prob.shape, prob.periodic, r, **p)
+    assert rel(z.cpu().numpy(), ref) <= 1e-12
