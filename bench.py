@@ -84,7 +84,9 @@ def serve_main(args):
     for i in range(args.matrices):
         n = int(rng.choice(grids))
         if i % 2 == 0:
-            p = W.channel_problem(n, ratio=float(rng.uniform(1.05, 1.2)))
+            # the wall clustering of the 128^3 channel grid at every
+            # resolution, varied slightly between matrices
+            p = W.channel_problem(n, g=W.CHANNEL_G128 * float(rng.uniform(0.9, 1.0)))
         else:
             p = W.porous_problem(n, seed_cfg=5, extra=i)
         probs.append(p)
@@ -127,7 +129,21 @@ def serve_main(args):
             r.done.wait()
         dt = time.perf_counter() - t
         log(f"[serve] {label}: {len(reqs)} solves in {dt:.2f}s -> {len(reqs) / dt:.1f} solves/s")
+        report(reqs)
         return reqs, dt
+
+    def report(reqs):
+        for r in reqs:
+            if r.status != 0:
+                p = probs[r.mid]
+                log(f"[serve]   not converged: matrix {r.mid} {p.name} step {r.step} status "
+                    f"{r.status} rel_res {r.stats['rel_res_true']:.2e} outer {r.stats['outer']} "
+                    f"its {r.stats['iterations']} {1e3 * (r.t_done - r.t_start):.0f} ms")
+        by = {}
+        for r in reqs:
+            by.setdefault(probs[r.mid].name, []).append(1e3 * (r.t_done - r.t_start))
+        log("[serve]   service ms by matrix kind: " + ", ".join(
+            f"{k} {np.mean(v):.1f} (x{len(v)})" for k, v in sorted(by.items())))
 
     warm, t_warm = run_closed(N_SWITCH, "warm-up (rGCROT steps building U, C)")
     cap_reqs, t_cap = run_closed(args.capacity_steps, "capacity (closed loop)")
@@ -154,6 +170,7 @@ def serve_main(args):
     for r in load:
         r.done.wait()
     t_open = time.perf_counter() - t_open
+    report(load)
     srv.close()
     if srv.errors:
         raise RuntimeError(f"serving errors: {srv.errors[:3]}")

@@ -103,13 +103,18 @@ def sphere_pack(shape_zyx, rmin, rmax, solid_fraction, rng):
     return solid
 
 
+def tanh_faces_widths(n, length, g):
+    """Cell widths for faces y_j = (L/2) tanh(g (2j/n - 1)) / tanh(g)."""
+    s = np.tanh(g * (2.0 * np.arange(n + 1) / n - 1.0)) / np.tanh(g)
+    return np.diff(s) * (length / 2.0)
+
+
 def tanh_widths(n, length, ratio):
     """Cell widths of a wall-clustered grid with faces
     y_j = (L/2) tanh(g (2j/n - 1)) / tanh(g), g chosen by bisection so that the
     largest ratio of adjacent widths equals `ratio`."""
     def widths(g):
-        s = np.tanh(g * (2.0 * np.arange(n + 1) / n - 1.0)) / np.tanh(g)
-        return np.diff(s) * (length / 2.0)
+        return tanh_faces_widths(n, length, g)
 
     def max_ratio(g):
         w = widths(g)
@@ -213,14 +218,21 @@ def grf_problem(n=24, seed_cfg=1, extra=0, ell=4.0):
                    vol.reshape(-1), False)
 
 
-def channel_problem(n=128, ratio=1.1):
+# tanh clustering strength of the 128^3 channel grid with adjacent width
+# ratio 1.1; the same wall clustering at other resolutions (largest/smallest
+# width ~ 94..112 for 32^3..192^3)
+CHANNEL_G128 = 3.0646
+
+
+def channel_problem(n=128, ratio=1.1, g=None):
     """Channel-like grid: Lx = 2 pi, Ly = 2, Lz = pi, periodic in x and z,
-    Neumann walls in y with tanh clustering; k = 1; volumes are the cell
-    volumes, so the row scaling makes A nonsymmetric.  Singular (constant
-    null vector)."""
+    Neumann walls in y with tanh clustering (largest adjacent width ratio
+    `ratio`, or the clustering strength `g` when given); k = 1; volumes are
+    the cell volumes, so the row scaling makes A nonsymmetric.  Singular
+    (constant null vector)."""
     dx = np.full(n, 2.0 * np.pi / n)
     dz = np.full(n, np.pi / n)
-    dy = tanh_widths(n, 2.0, ratio)
+    dy = tanh_widths(n, 2.0, ratio) if g is None else tanh_faces_widths(n, 2.0, g)
     vol = dz[:, None, None] * dy[None, :, None] * dx[None, None, :]
     kcell = np.ones((n, n, n))
     bc = {'x': 'periodic', 'y': ('neumann', 'neumann'), 'z': 'periodic'}
