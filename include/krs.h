@@ -113,6 +113,21 @@ typedef struct krs_precond_desc {
  * meets tol, without confirming it with the true residual (used for the
  * inner solves of iterative refinement, whose outer FP64 residual decides). */
 #define KRS_FLAG_TRUST_ESTIMATE 1
+/* rBiCGStab: test convergence on the host after every half step (two host
+ * round trips per iteration).  By default the stopping tests of Alg. 4 run on
+ * the device and the host enqueues several iterations between reads; passes
+ * enqueued after the stop leave the iterate untouched, so both modes give
+ * bitwise the same result, history and counts. */
+#define KRS_FLAG_HOST_LOOP 2
+/* rBiCGStab, device-driven loop: replay a captured HIP graph of one
+ * iteration instead of enqueuing its kernels one by one (grids of at most
+ * 2^20 cells, kernel timing off).  The context keeps up to 8 graphs, keyed by
+ * every pointer and size they contain (matrix, preconditioner, recycle space,
+ * workspace), and releases them in krs_destroy.  Results are bitwise the same
+ * either way.  Off by default: on gfx950 the replay saves no time per
+ * iteration (the kernels' own dispatch latency dominates, not host launch
+ * cost) and the first replay of a key pays for capture and instantiation. */
+#define KRS_FLAG_GRAPH 4
 
 typedef struct krs_opts {
   int32_t m;               /* Arnoldi steps per cycle (GMRES, rGCROT), 1..64 */

@@ -76,6 +76,8 @@ void krs_destroy(krs_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
   krs::timing_release(ctx);
+  for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   if (ctx->pin) (void)hipHostFree(ctx->pin);
   delete ctx;
 }

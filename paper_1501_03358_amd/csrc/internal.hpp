@@ -29,6 +29,17 @@ struct krs_ctx {
   int64_t t_launches[KRS_K_COUNT] = {};
   double t_ms[KRS_K_COUNT] = {};
   double t_bytes[KRS_K_COUNT] = {};
+  // captured rBiCGStab iterations (one pass of the loop per graph), keyed by
+  // every pointer and size baked into the launches; least recently used out
+  struct Graph {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec = nullptr;
+    double bytes = 0;              // byte model of one replay
+    uint64_t used = 0;
+  };
+  std::vector<Graph> graphs;
+  hipStream_t capture = nullptr;   // private stream, used only to record graphs
+  uint64_t clock = 0;
 };
 
 struct krs_matrix {
@@ -65,6 +76,8 @@ constexpr int kMaxM = 64;                  // Arnoldi steps per cycle
 constexpr int kMaxK = 32;                  // recycle dimension
 constexpr int kScalarDoubles = 1 << 14;    // device scalar area (128 KiB)
 constexpr int kGramBlocks = 1024;
+constexpr int kMaxGraphs = 8;                // cached captured iterations per context
+constexpr int64_t kGraphMaxN = int64_t(1) << 20;   // larger grids keep the GPU ahead of the host
 constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }

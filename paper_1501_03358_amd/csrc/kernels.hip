@@ -807,13 +807,14 @@ template <class T>
 __global__ __launch_bounds__(kThreads) void k_bicg_p(const T* __restrict__ r, T* __restrict__ p,
                                                      const T* __restrict__ v, const double* sc,
                                                      int64_t n) {
+  if (sc[kDone] != 0.0) return;
   const T beta = (T)sc[kBeta], omega = (T)sc[kOmega];
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i < n) p[i] = r[i] + beta * (p[i] - omega * v[i]);
 }
 
 __global__ void k_bicg_alpha(const double* sums, int kc, double* sc, int off_eta1, int off_ctrt) {
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || sc[kDone] != 0.0) return;
   double corr = 0;
   for (int c = 0; c < kc; ++c) {
     sc[off_eta1 + c] = sums[c];
@@ -867,6 +868,7 @@ __global__ __launch_bounds__(kThreads) void k_bicg_sv(Cols<T> C, const T* __rest
                                                       T* __restrict__ sv, const double* sc,
                                                       int off_eta1, int64_t n, T* partials,
                                                       int nblk) {
+  if (sc[kDone] != 0.0) return;
   __shared__ T cf[NC > 0 ? NC : 1];
   const int kc = C.n1;
   for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (T)sc[off_eta1 + c] : T(0);
@@ -883,7 +885,7 @@ __global__ __launch_bounds__(kThreads) void k_bicg_sv(Cols<T> C, const T* __rest
 
 __global__ void k_bicg_omega(const double* sums, int kc, double* sc, int off_eta1, int off_eta2,
                              int off_xi) {
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || sc[kDone] != 0.0) return;
   double q = 0;
   for (int c = 0; c < kc; ++c) {
     sc[off_eta2 + c] = sums[c];
@@ -945,6 +947,7 @@ __global__ __launch_bounds__(kThreads) void k_bicg_yr(Cols<T> C, const T* __rest
                                                       T* __restrict__ r, const T* __restrict__ rt,
                                                       const double* sc, int off_eta2, int64_t n,
                                                       T* partials, int nblk) {
+  if (sc[kDone] != 0.0) return;
   __shared__ T cf[NC > 0 ? NC : 1];
   const int kc = C.n1;
   for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (T)sc[off_eta2 + c] : T(0);
@@ -960,7 +963,7 @@ __global__ __launch_bounds__(kThreads) void k_bicg_yr(Cols<T> C, const T* __rest
 }
 
 __global__ void k_bicg_rho(const double* sums, double* sc) {
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || sc[kDone] != 0.0) return;
   const double rho = sums[0];
   sc[kRnorm2] = sums[1];
   sc[kRhoOld] = sc[kRho];
@@ -971,7 +974,8 @@ __global__ void k_bicg_rho(const double* sums, double* sc) {
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_bicg_exit_s(const T* __restrict__ p, T* y,
                                                           const T* __restrict__ sv, T* r,
-                                                          const double* sc, int64_t n) {
+                                                          const double* sc, int64_t n, int cond) {
+  if (cond && sc[kDone] != (double)kConvHalf) return;
   const T alpha = (T)sc[kAlpha];
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i < n) {
@@ -980,11 +984,50 @@ __global__ __launch_bounds__(kThreads) void k_bicg_exit_s(const T* __restrict__ 
   }
 }
 
-__global__ void k_bicg_exit_xi(double* sc, int off_eta1, int off_xi, int kc) {
+__global__ void k_bicg_exit_xi(double* sc, int off_eta1, int off_xi, int kc, int cond) {
   if (threadIdx.x != 0) return;
+  if (cond && sc[kDone] != (double)kConvHalf) return;
   const double alpha = sc[kAlpha];
   for (int c = 0; c < kc; ++c) sc[off_xi + c] += alpha * sc[off_eta1 + c];
   sc[kRnorm2] = sc[kSnorm2];
+  if (cond) sc[kDone] = kExited;
+}
+
+__device__ inline void hist_push(double* sc, double v) {
+  const int h = (int)sc[kHlen];
+  sc[kHistOff + h % kHistRing] = v;
+  sc[kHlen] = h + 1;
+}
+
+// after |s|^2 is finished: the tests of the half step (lines 9-10)
+__global__ void k_bicg_check_half(double* sc) {
+  if (threadIdx.x != 0 || sc[kDone] != 0.0) return;
+  sc[kIts] += 1.0;
+  if (sc[kFlag] != 0.0) {
+    sc[kDone] = kBreak;
+    sc[kEndHalf] = 1.0;
+    return;
+  }
+  const double sn = sqrt(sc[kSnorm2]);
+  hist_push(sc, sn);
+  if (!isfinite(sn)) {
+    sc[kDone] = kDiverge;
+    sc[kEndHalf] = 1.0;
+  } else if (sn <= sc[kTolAbs]) {
+    sc[kDone] = kConvHalf;
+    sc[kEndHalf] = 1.0;
+  }
+}
+
+// after the full step: |r|, breakdown flags, divergence guard, rho = 0 (line 5)
+__global__ void k_bicg_check_full(double* sc) {
+  if (threadIdx.x != 0 || sc[kDone] != 0.0) return;
+  const double rn = sqrt(sc[kRnorm2]);
+  hist_push(sc, rn);
+  if (sc[kFlag] != 0.0) sc[kDone] = kBreak;
+  else if (!isfinite(rn) || rn > sc[kDivAbs]) sc[kDone] = kDiverge;
+  else if (rn <= sc[kTolAbs]) sc[kDone] = kConvFull;
+  else if (sc[kRho] == 0.0) sc[kDone] = kBreak;
 }
 
 template <class T>
@@ -1340,9 +1383,19 @@ hipError_t bicg_rho(hipStream_t s, const double* sums, double* sc) {
 
 template <class T>
 hipError_t bicg_exit_s(hipStream_t s, const T* p, T* y, const T* sv, T* r, double* sc,
-                       int off_eta1, int off_xi, int kc, int64_t n) {
-  if (n > 0) k_bicg_exit_s<T><<<grid_for(n), kThreads, 0, s>>>(p, y, sv, r, sc, n);
-  k_bicg_exit_xi<<<1, 64, 0, s>>>(sc, off_eta1, off_xi, kc);
+                       int off_eta1, int off_xi, int kc, int64_t n, bool cond) {
+  if (n > 0) k_bicg_exit_s<T><<<grid_for(n), kThreads, 0, s>>>(p, y, sv, r, sc, n, cond ? 1 : 0);
+  k_bicg_exit_xi<<<1, 64, 0, s>>>(sc, off_eta1, off_xi, kc, cond ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t bicg_check_half(hipStream_t s, double* sc) {
+  k_bicg_check_half<<<1, 64, 0, s>>>(sc);
+  return hipGetLastError();
+}
+
+hipError_t bicg_check_full(hipStream_t s, double* sc) {
+  k_bicg_check_full<<<1, 64, 0, s>>>(sc);
   return hipGetLastError();
 }
 
@@ -1404,7 +1457,7 @@ hipError_t axpy_f32_into_f64(hipStream_t s, const float* d, double* x, int64_t n
   template hipError_t bicg_yr<T>(hipStream_t, const Cols<T>&, const T*, const T*, const T*, T*,   \
                                  T*, const T*, const double*, int, int64_t, T*, int);             \
   template hipError_t bicg_exit_s<T>(hipStream_t, const T*, T*, const T*, T*, double*, int, int,  \
-                                     int, int64_t);                                               \
+                                     int, int64_t, bool);                                               \
   template hipError_t fill<T>(hipStream_t, T*, int64_t, double);                                  \
   template hipError_t copy<T>(hipStream_t, const T*, T*, int64_t);
 

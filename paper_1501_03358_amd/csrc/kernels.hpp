@@ -106,8 +106,19 @@ hipError_t finish_cgs2(hipStream_t s, const T* partials, int nblk, int ncols, co
 // scalar slots
 enum BicgSlot {
   kRho = 0, kRhoOld, kAlpha, kOmega, kBeta, kRtv, kSnorm2, kRnorm2, kTs, kTt, kFlag,
+  // device-driven iteration: state (kDone), iterations started, history
+  // entries written, absolute stopping and divergence thresholds, and whether
+  // the stop came at the half step
+  kDone, kIts, kHlen, kTolAbs, kDivAbs, kEndHalf,
   kSlots
 };
+// kDone values: 0 running, 1 converged at the half step (early exit still to
+// apply), 2 converged at the full step, 3 breakdown, 4 diverged or non-finite,
+// 5 early exit applied.  Every BiCGStab pass returns at once when kDone != 0,
+// so iterations enqueued after the stop change nothing that the result reads.
+enum BicgDone { kRunning = 0, kConvHalf = 1, kConvFull = 2, kBreak = 3, kDiverge = 4, kExited = 5 };
+// history ring of the device-driven loop (absolute norms, 2 per iteration)
+constexpr int kHistOff = 512, kHistRing = 128;
 // BiCGStab pieces; `sums` are finished FP64 dot products.
 template <class T>
 hipError_t bicg_p(hipStream_t s, const T* r, T* p, const T* v, const double* sc, int64_t n);
@@ -128,10 +139,14 @@ hipError_t bicg_yr(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, con
                    int nblk);
 // rho_old = rho, rho = sums[0], rnorm2 = sums[1], beta = (rho/rho_old)(alpha/omega)
 hipError_t bicg_rho(hipStream_t s, const double* sums, double* sc);
-// line 10/10a early exit: y += alpha p ; r = s ; xi += alpha eta1
+// line 10/10a early exit: y += alpha p ; r = s ; xi += alpha eta1.  With
+// `cond` the pass runs only when kDone == kConvHalf and then sets kExited.
 template <class T>
 hipError_t bicg_exit_s(hipStream_t s, const T* p, T* y, const T* sv, T* r, double* sc,
-                       int off_eta1, int off_xi, int kc, int64_t n);
+                       int off_eta1, int off_xi, int kc, int64_t n, bool cond = false);
+// device-side stopping tests after the half step (|s|) and the full step (|r|)
+hipError_t bicg_check_half(hipStream_t s, double* sc);
+hipError_t bicg_check_full(hipStream_t s, double* sc);
 // hcol_last = sqrt(*nrm2), inv = 1/hcol_last
 hipError_t set_norm_from_sum(hipStream_t s, const double* nrm2, double* hcol_last, double* inv);
 

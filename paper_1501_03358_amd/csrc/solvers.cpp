@@ -37,8 +37,11 @@ struct Op {
   T* tmp;   // preconditioner temporary
   const T* bands() const { return (const T*)A->bands; }
 
-  int minv(const T* r, T* out) {
+  int minv(const T* r, T* out) { return minv_s(r, out, tmp); }
+  // z = M^-1 r using `scratch` (distinct from r and out) as the temporary
+  int minv_s(const T* r, T* out, T* scratch) {
     hipStream_t s = ctx->stream;
+    T* tmp = scratch;
     const double NW = (double)g.n * sizeof(T);
     if (!M || M->d.type == KRS_PC_NONE) {
       KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, r, out, g.n));
@@ -71,8 +74,9 @@ struct Op {
     return 0;
   }
   // w = A M^-1 v
+  // (w, not yet written, is the preconditioner's temporary)
   int apply(const T* v, T* w) {
-    int rc = minv(v, z);
+    int rc = minv_s(v, z, w);
     if (rc) return rc;
     KRS_LAUNCH(ctx, KRS_K_STENCIL, 9.0 * g.n * sizeof(T),
                stencil<T>(ctx->stream, g, bands(), z, w, 1.0, 0.0, nullptr, 0));
@@ -567,7 +571,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   T* sv = cv.vec<T>(ld);
   T* t = cv.vec<T>(ld);
   T* z = cv.vec<T>(ld);
-  T* tmp = cv.vec<T>(ld);
+  T* y = cv.vec<T>(ld);   // iterate of A~ y = b (x = M^-1 y at the end)
   T* part = (T*)cv.take(partials_bytes(sizeof(T)));
   double* sc = cv.vec<double>(kScalarDoubles);
   if (!ws || !cv.ok) return set_err(ctx, KRS_ERR_WORKSPACE, "workspace missing or too small");
@@ -576,7 +580,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   const double NW = (double)n * sizeof(T);
   const double tol = o->tol;
   const int64_t maxmv = o->max_matvecs > 0 ? o->max_matvecs : 2000;
-  Op<T> op{ctx, A, M, grid3(A), z, tmp};
+  Op<T> op{ctx, A, M, grid3(A), z, nullptr};
   init_stats(st);
   double nb2 = 0;
   int rc = norm2<T>(ctx, b, n, part, sc + kNrm, nb2);
@@ -627,11 +631,13 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   }
   KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, p, n, 0.0));
   KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, v, n, 0.0));
-  KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, x, n, 0.0));
+  KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, y, n, 0.0));
   slots[kRho] = rn2;  // r~ = r
   slots[kOmega] = 1.0;
   slots[kBeta] = 0.0;
   slots[kRnorm2] = rn2;
+  slots[kTolAbs] = tol * nb;
+  slots[kDivAbs] = o->div_factor > 0 ? o->div_factor * nb : INFINITY;
   rc = upload(ctx, sc, slots.data(), kSlots);
   if (rc) return rc;
   double rnorm = std::sqrt(rn2);
@@ -643,80 +649,224 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     if (o->history && hlen < o->history_cap) o->history[hlen] = val;
     ++hlen;
   };
-  while (rnorm > tol * nb && mv < maxmv) {
-    if (rho == 0.0) {                                        // line 5
-      status = KRS_BREAKDOWN;
-      break;
-    }
-    KRS_LAUNCH(ctx, KRS_K_BICG_P, 4 * NW, bicg_p<T>(s, r, p, v, sc, n));   // line 6
-    rc = op.apply(p, v);                                     // line 7
-    if (rc) return rc;
-    ++mv;
+  // one pass of the while loop of Alg. 4 up to the half-step test / after it
+  // In the device-driven mode the passes that may be skipped after the stop
+  // are charged to the byte model from the counts read back (dev = true).
+  const double bytes_p = 4 * NW, bytes_sv = NW * (kc + (kc > 0 ? 4 : 3)), bytes_yr = NW * (kc + 7);
+  auto first_half = [&](bool dev) -> int {
+    KRS_LAUNCH(ctx, KRS_K_BICG_P, dev ? 0 : bytes_p, bicg_p<T>(s, r, p, v, sc, n));   // line 6
+    int e = op.apply(p, v);                                  // line 7
+    if (e) return e;
     // line 7a-8: eta1 = C^T v, v -= C eta1, alpha = rho / r~^T v, s = r - alpha v
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 2),
                block_dot<T>(s, cols<T>(C, ldr, kc, rt, ld, 1), v, n, 0, part, nblk));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc + 1, sc + kSums));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_alpha(s, sc + kSums, kc, sc, kEta1, kCtrt));
-    KRS_LAUNCH(ctx, KRS_K_BICG_SV, NW * (kc + (kc > 0 ? 4 : 3)),
+    KRS_LAUNCH(ctx, KRS_K_BICG_SV, dev ? 0 : bytes_sv,
                bicg_sv<T>(s, Cc, r, v, sv, sc, kEta1, n, part, nblk));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, sc + kSnorm2));
-    rc = read_dev(ctx, sc, kSlots);
-    if (rc) return rc;
-    std::copy(ctx->pin, ctx->pin + kSlots, slots.begin());
-    ++its;
-    if (slots[kFlag] != 0.0) {
-      status = KRS_BREAKDOWN;
-      break;
-    }
-    const double snorm = std::sqrt(slots[kSnorm2]);
-    hist(snorm / nb);
-    if (!std::isfinite(snorm)) {
-      status = KRS_DIVERGED;
-      break;
-    }
-    if (snorm <= tol * nb) {                                // lines 9-10a
-      KRS_LAUNCH(ctx, KRS_K_BICG_P, 5 * NW, bicg_exit_s<T>(s, p, x, sv, r, sc, kEta1, kXi, kc, n));
-      rnorm = snorm;
-      break;
-    }
-    rc = op.apply(sv, t);                                    // line 12
-    if (rc) return rc;
-    ++mv;
+    return 0;
+  };
+  auto second_half = [&](bool dev) -> int {
+    int e = op.apply(sv, t);                                 // line 12
+    if (e) return e;
     // line 12a-13a: eta2 = C^T t, omega = t^T s / |t - C eta2|^2, xi update
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 2),
                block_dot<T>(s, cols<T>(C, ldr, kc, sv, ld, 1), t, n, 1, part, nblk));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc + 2, sc + kSums));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_omega(s, sc + kSums, kc, sc, kEta1, kEta2, kXi));
     // lines 14-16 with the next rho = r~^T r
-    KRS_LAUNCH(ctx, KRS_K_BICG_YR, NW * (kc + 7),
-               bicg_yr<T>(s, Cc, t, sv, p, x, r, rt, sc, kEta2, n, part, nblk));
+    KRS_LAUNCH(ctx, KRS_K_BICG_YR, dev ? 0 : bytes_yr,
+               bicg_yr<T>(s, Cc, t, sv, p, y, r, rt, sc, kEta2, n, part, nblk));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 2, sc + kSums));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_rho(s, sc + kSums, sc));
-    rc = read_dev(ctx, sc, kSlots);
-    if (rc) return rc;
-    std::copy(ctx->pin, ctx->pin + kSlots, slots.begin());
-    rnorm = std::sqrt(slots[kRnorm2]);
-    rho = slots[kRho];
-    hist(rnorm / nb);
-    if (slots[kFlag] != 0.0) {
-      status = KRS_BREAKDOWN;
-      break;
+    return 0;
+  };
+  if (o->flags & KRS_FLAG_HOST_LOOP) {
+    while (rnorm > tol * nb && mv < maxmv) {
+      if (rho == 0.0) {                                      // line 5
+        status = KRS_BREAKDOWN;
+        break;
+      }
+      rc = first_half(false);
+      if (rc) return rc;
+      ++mv;
+      rc = read_dev(ctx, sc, kSlots);
+      if (rc) return rc;
+      std::copy(ctx->pin, ctx->pin + kSlots, slots.begin());
+      ++its;
+      if (slots[kFlag] != 0.0) {
+        status = KRS_BREAKDOWN;
+        break;
+      }
+      const double snorm = std::sqrt(slots[kSnorm2]);
+      hist(snorm / nb);
+      if (!std::isfinite(snorm)) {
+        status = KRS_DIVERGED;
+        break;
+      }
+      if (snorm <= tol * nb) {                              // lines 9-10a
+        KRS_LAUNCH(ctx, KRS_K_BICG_P, 5 * NW,
+                   bicg_exit_s<T>(s, p, y, sv, r, sc, kEta1, kXi, kc, n));
+        rnorm = snorm;
+        break;
+      }
+      rc = second_half(false);
+      if (rc) return rc;
+      ++mv;
+      rc = read_dev(ctx, sc, kSlots);
+      if (rc) return rc;
+      std::copy(ctx->pin, ctx->pin + kSlots, slots.begin());
+      rnorm = std::sqrt(slots[kRnorm2]);
+      rho = slots[kRho];
+      hist(rnorm / nb);
+      if (slots[kFlag] != 0.0) {
+        status = KRS_BREAKDOWN;
+        break;
+      }
+      if (!std::isfinite(rnorm) || (div > 0 && rnorm > div * nb)) {
+        status = KRS_DIVERGED;
+        break;
+      }
     }
-    if (!std::isfinite(rnorm) || (div > 0 && rnorm > div * nb)) {
-      status = KRS_DIVERGED;
-      break;
+  } else if (rnorm > tol * nb) {
+    auto one_pass = [&]() -> int {
+      int e = first_half(true);
+      if (e) return e;
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_check_half(s, sc));
+      KRS_LAUNCH(ctx, KRS_K_BICG_P, 0,
+                 bicg_exit_s<T>(s, p, y, sv, r, sc, kEta1, kXi, kc, n, true));
+      e = second_half(true);
+      if (e) return e;
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_check_full(s, sc));
+      return 0;
+    };
+    // optionally replay one captured pass per iteration
+    krs_ctx::Graph* graph = nullptr;
+    if ((o->flags & KRS_FLAG_GRAPH) && !ctx->timing && n <= kGraphMaxN) {
+      const krs_precond* Mp = M;
+      std::vector<uint64_t> key = {
+          sizeof(T), (uint64_t)n, (uint64_t)kc, (uint64_t)(uintptr_t)A->bands,
+          (uint64_t)A->g.nx, (uint64_t)A->g.ny, (uint64_t)A->g.nz,
+          (uint64_t)(A->g.periodic[0] | (A->g.periodic[1] << 1) | (A->g.periodic[2] << 2)),
+          (uint64_t)(uintptr_t)Mp, (uint64_t)(uintptr_t)(Mp ? Mp->pack : nullptr),
+          (uint64_t)(Mp ? Mp->d.type : -1), (uint64_t)(Mp ? Mp->d.tile : 0),
+          (uint64_t)(Mp ? Mp->d.overlap : 0), (uint64_t)(Mp ? Mp->d.local_sweeps : 0),
+          (uint64_t)(Mp ? Mp->d.global_sweeps : 0), 0, 0, (uint64_t)(uintptr_t)C,
+          (uint64_t)ldr, (uint64_t)(uintptr_t)ws};
+      if (Mp) {
+        std::memcpy(&key[15], &Mp->d.omega_local, 8);
+        std::memcpy(&key[16], &Mp->d.omega_global, 8);
+      }
+      for (auto& g : ctx->graphs)
+        if (g.key == key) graph = &g;
+      if (!graph) {
+        if (!ctx->capture)
+          KRS_CHECK_HIP(ctx, hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+        const hipStream_t saved = ctx->stream;
+        const double b0 = ctx->bytes;
+        ctx->stream = ctx->capture;
+        s = ctx->capture;
+        hipGraph_t gr = nullptr;
+        hipError_t eb = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal);
+        int e = eb == hipSuccess ? one_pass() : 0;
+        hipError_t ee = eb == hipSuccess ? hipStreamEndCapture(ctx->capture, &gr) : eb;
+        ctx->stream = saved;
+        s = saved;
+        const double gbytes = ctx->bytes - b0;
+        ctx->bytes = b0;
+        if (e || ee != hipSuccess) {
+          if (gr) (void)hipGraphDestroy(gr);
+          if (e) return e;
+          return set_err(ctx, KRS_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ee));
+        }
+        hipGraphExec_t ex = nullptr;
+        hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (ei != hipSuccess)
+          return set_err(ctx, KRS_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        if ((int)ctx->graphs.size() >= kMaxGraphs) {
+          auto lru = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                      [](const krs_ctx::Graph& a, const krs_ctx::Graph& b) {
+                                        return a.used < b.used;
+                                      });
+          (void)hipGraphExecDestroy(lru->exec);
+          ctx->graphs.erase(lru);
+        }
+        krs_ctx::Graph g;
+        g.key = key;
+        g.exec = ex;
+        g.bytes = gbytes;
+        ctx->graphs.push_back(g);
+        graph = &ctx->graphs.back();
+      }
+      graph->used = ++ctx->clock;
+    }
+    // Device-driven: the stopping tests run in single-thread kernels and the
+    // host reads the state once per batch of iterations.  The batch length
+    // follows the observed convergence rate so that few iterations run past
+    // the stop (they are no-ops: every pass returns once kDone != 0).
+    const int64_t allowed = (maxmv + 1) / 2;                // passes with mv < maxmv at entry
+    const int kcap = n <= (int64_t(1) << 18) ? 32 : (n <= (int64_t(1) << 21) ? 8 : 4);
+    int batch = std::min(2, kcap);
+    int64_t hseen = 0;
+    double last = rnorm;
+    int64_t its_prev = 0;
+    while (its < allowed) {
+      const int kb = (int)std::min<int64_t>(batch, allowed - its);
+      for (int q = 0; q < kb; ++q) {
+        if (graph) {
+          KRS_CHECK_HIP(ctx, hipGraphLaunch(graph->exec, s));
+          ctx->bytes += graph->bytes;
+        } else {
+          rc = one_pass();
+          if (rc) return rc;
+        }
+      }
+      rc = read_dev(ctx, sc, kHistOff + kHistRing);
+      if (rc) return rc;
+      const double* d = ctx->pin;
+      const int64_t started = (int64_t)d[kIts] - its;
+      const int done_now = (int)d[kDone];
+      const bool half = done_now != kRunning && d[kEndHalf] != 0.0;
+      ctx->bytes += started * (bytes_p + bytes_sv) + (started - (half ? 1 : 0)) * bytes_yr +
+                    (done_now == kExited ? 5 * NW : 0.0);
+      its = (int64_t)d[kIts];
+      const int64_t hl = (int64_t)d[kHlen];
+      for (int64_t h = hseen; h < hl; ++h) hist(d[kHistOff + h % kHistRing] / nb);
+      hseen = hl;
+      const int done = (int)d[kDone];
+      if (done != kRunning) {
+        mv = 2 * its - (d[kEndHalf] != 0.0 ? 1 : 0);
+        rnorm = std::sqrt(d[kRnorm2]);
+        if (done == kBreak) status = KRS_BREAKDOWN;
+        else if (done == kDiverge) status = KRS_DIVERGED;
+        break;
+      }
+      mv = 2 * its;
+      rnorm = std::sqrt(d[kRnorm2]);
+      // next batch: about half the iterations the recent rate still needs
+      const int64_t dits = its - its_prev;
+      its_prev = its;
+      if (dits > 0 && rnorm > 0 && rnorm < last) {
+        const double rate = std::pow(rnorm / last, 1.0 / (double)dits);
+        const double need = std::log(tol * nb / rnorm) / std::log(rate);
+        batch = (int)std::max(1.0, std::min((double)kcap, 0.5 * need));
+      } else {
+        batch = std::min(kcap, std::max(1, batch));
+      }
+      last = rnorm;
     }
   }
   if (status == KRS_NOT_CONVERGED && rnorm <= tol * nb) status = KRS_OK;
   // line 17a: y -= U xi ; then x = M^-1 y
   if (kc > 0) {
     KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (kc + 2),
-               block_update<T>(s, cols<T>(U, ldr, kc), sc + kXi, -1.0, x, x, n, nullptr, 0, part,
+               block_update<T>(s, cols<T>(U, ldr, kc), sc + kXi, -1.0, y, y, n, nullptr, 0, part,
                                nblk));
   }
-  rc = op.minv(x, z);
+  rc = op.minv_s(y, x, z);
   if (rc) return rc;
-  KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, z, x, n));
   // true residual of x
   KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 10 * NW, residual_norm<T>(s, op.g, op.bands(), x, b, t, part));
   KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, sc + kNrm));

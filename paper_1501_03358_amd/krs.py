@@ -22,6 +22,8 @@ F64, F32 = 0, 1
 SOLVER_GMRES, SOLVER_RGCROT, SOLVER_RBICGSTAB, SOLVER_IR = 0, 1, 2, 3
 PC_NONE, PC_JACOBI, PC_SCHWARZ_JACOBI = 0, 1, 2
 FLAG_TRUST_ESTIMATE = 1
+FLAG_HOST_LOOP = 2
+FLAG_GRAPH = 4
 
 EXPORTS = (
     "krs_create", "krs_destroy", "krs_last_error", "krs_set_stream", "krs_matrix_create",
