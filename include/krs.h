@@ -213,6 +213,17 @@ int krs_stencil_apply(krs_ctx* ctx, const krs_matrix* A, const void* x, void* y,
 /* z = M^-1 r (Sec. 2.1, "Preconditioners"); z may not alias r. Asynchronous. */
 int krs_precond_apply(krs_ctx* ctx, const krs_precond* M, const void* r, void* z);
 
+/* w = A M^-1 v, the right-preconditioned operator every solver iterates on
+ * (Sec. 2.2: A and b stand for the preconditioned matrix and right-hand
+ * side).  `tmp` is a caller device buffer of N values of A's dtype that
+ * receives intermediate values; v, w and tmp must not alias one another.
+ * With Schwarz-Jacobi and one global sweep on grids of at least 2^22 cells,
+ * the sweep and the matvec run as one fused pass and tmp holds the
+ * local-solve result, not M^-1 v (elsewhere tmp holds M^-1 v); both forms
+ * give bitwise the same w.  M may be NULL (w = A v).  Asynchronous. */
+int krs_operator_apply(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const void* v,
+                       void* w, void* tmp);
+
 /* GMRES(m), Alg. 1, right-preconditioned (M may be NULL: no preconditioner).
  * b, x: N values of A's dtype. Uses opts.m, tol, max_matvecs. */
 int krs_gmres(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const void* b, void* x,
@@ -282,7 +293,8 @@ typedef enum krs_kernel_class {
   KRS_K_GRAM = 10,          /* Gram blocks of the recycle update */
   KRS_K_ROW_TRANSFORM = 11, /* in-place (U, C) row-block updates */
   KRS_K_OTHER = 12,         /* finishing reductions, copies, casts, coefficient packing */
-  KRS_K_COUNT = 13
+  KRS_K_SWEEP_STENCIL = 13, /* global Jacobi sweep fused with the matvec of A M^-1 */
+  KRS_K_COUNT = 14
 } krs_kernel_class;
 
 /* While enabled, every kernel launch of the context is bracketed by two HIP

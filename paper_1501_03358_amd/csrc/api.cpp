@@ -230,6 +230,16 @@ int krs_precond_apply(krs_ctx* ctx, const krs_precond* M, const void* r, void* z
   return krs::precond_apply(ctx, M, r, z, M->tmp);
 }
 
+int krs_operator_apply(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const void* v,
+                       void* w, void* tmp) {
+  if (!ctx || !A || !v || !w || !tmp) return KRS_ERR_ARG;
+  if (v == w || v == tmp || w == tmp)
+    return set_err(ctx, KRS_ERR_ARG, "v, w and tmp must be distinct buffers");
+  int rc = check_precond(ctx, A, M);
+  if (rc) return rc;
+  return krs::operator_apply(ctx, A, M, v, w, tmp);
+}
+
 int krs_gmres(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const void* b, void* x,
               const krs_opts* opts, void* ws, size_t ws_bytes, krs_stats* stats) {
   if (!ctx || !A || !b || !x) return KRS_ERR_ARG;

@@ -76,6 +76,7 @@ constexpr int kMaxM = 64;                  // Arnoldi steps per cycle
 constexpr int kMaxK = 32;                  // recycle dimension
 constexpr int kScalarDoubles = 1 << 14;    // device scalar area (128 KiB)
 constexpr int kGramBlocks = 1024;
+constexpr int64_t kFuseMinN = int64_t(1) << 22;  // fused sweep + matvec from this size
 constexpr int kMaxGraphs = 8;                // cached captured iterations per context
 constexpr int64_t kGraphMaxN = int64_t(1) << 20;   // larger grids keep the GPU ahead of the host
 constexpr size_t kAlign = 256;
@@ -149,6 +150,8 @@ void launch_end(krs_ctx* ctx, int cls, double bytes, hipEvent_t a);
 // after a stream synchronisation: fold completed event pairs into the totals
 void timing_flush(krs_ctx* ctx);
 void timing_release(krs_ctx* ctx);
+// byte-model bytes of launches whose count is known only after they ran
+void timing_add_bytes(krs_ctx* ctx, int cls, double bytes);
 }  // namespace krs
 
 // Launch `expr` (returning hipError_t) as kernel class `cls` moving `nbytes`.
@@ -165,6 +168,8 @@ void timing_release(krs_ctx* ctx);
 namespace krs {
 int workspace_bytes(krs_solver solver, int64_t n, int m, int k, krs_dtype dt, size_t* bytes);
 int precond_apply(krs_ctx* ctx, const krs_precond* M, const void* r, void* z, void* tmp);
+int operator_apply(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const void* v, void* w,
+                   void* tmp);
 int precond_pack(krs_ctx* ctx, const krs_precond* M);
 size_t precond_pack_bytes(const krs_matrix* A, const krs_precond_desc* d);
 int gmres_rgcrot(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,

@@ -9,6 +9,7 @@
 // in the same L2.
 #include "kernels.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace krs {
@@ -109,6 +110,214 @@ __global__ __launch_bounds__(kThreads) void k_stencil(Grid3 g, const T* __restri
   else if constexpr (MODE == 2) out = alpha * ax + beta * y[i];
   else out = x[i] + alpha * (bv[i] - ax) / A[i];
   y[i] = out;
+}
+
+// ---------------------------------------------------------------------------
+// fused global Jacobi sweep + matvec: w = A zg, zg = zl + omega (r - A zl) / a_C
+//
+// zg (the preconditioned vector) is never written: a block owns a TX x TY
+// column of cells and marches through planes z0..z1-1 of it, keeping three
+// planes of zl (two-cell halo) and three planes of zg (one-cell halo) in LDS.
+// The bands of a cell are read once for both products (held in registers
+// from the sweep of plane z+1 until the matvec of that plane); halo cells
+// re-read theirs (from L2: the neighbouring columns read the same rows).
+// Same operation order as the separate sweep and matvec kernels.
+// ---------------------------------------------------------------------------
+template <class T, int TX, int TY>
+__global__ __launch_bounds__(kThreads) void k_sweep_stencil(Grid3 g, const T* __restrict__ A,
+                                                            const T* __restrict__ r,
+                                                            const T* __restrict__ zl,
+                                                            T* __restrict__ w, T omega, int ntx,
+                                                            int nty, int zc) {
+  constexpr int LX = TX + 4, LY = TY + 4;   // zl plane with a two-cell halo
+  constexpr int GX = TX + 2, GY = TY + 2;   // zg plane with a one-cell halo
+  constexpr int PER = TX * TY / kThreads;   // interior cells per thread
+  constexpr int NR = GX * GY - TX * TY;     // halo ring of a zg plane
+  static_assert((TX * TY) % kThreads == 0 && NR <= kThreads, "tile shape");
+  __shared__ T sl[3][LX * LY];
+  __shared__ T sg[3][GX * GY];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int bx = b % ntx, rest = b / ntx;
+  const int by = rest % nty, bz = rest / nty;
+  const int x0 = bx * TX, y0 = by * TY, z0 = bz * zc;
+  const int z1 = min(z0 + zc, g.nz);
+  const int64_t N = g.n;
+  const int t = threadIdx.x;
+
+  // grid index of local cell (lx, ly) of plane z; -1 beyond a non-periodic face
+  auto gidx = [&](int lx, int ly, int z) -> int64_t {
+    int gx = x0 + lx, gy = y0 + ly, gz = z;
+    if (gx < 0 || gx >= g.nx) {
+      if (!g.px) return -1;
+      gx = ((gx % g.nx) + g.nx) % g.nx;
+    }
+    if (gy < 0 || gy >= g.ny) {
+      if (!g.py) return -1;
+      gy = ((gy % g.ny) + g.ny) % g.ny;
+    }
+    if (gz < 0 || gz >= g.nz) {
+      if (!g.pz) return -1;
+      gz = ((gz % g.nz) + g.nz) % g.nz;
+    }
+    return gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
+  };
+  auto slot = [](int z) { return (z + 3) % 3; };
+  constexpr int NL = (LX * LY + kThreads - 1) / kThreads;   // zl loads per thread and plane
+  // halo-ring cell q of a zg plane: rows -1 and TY, then columns -1 and TX
+  auto ring = [](int q, int& lx, int& ly) {
+    if (q < 2 * GX) {
+      lx = q % GX - 1;
+      ly = q < GX ? -1 : TY;
+    } else {
+      q -= 2 * GX;
+      lx = q < TY ? -1 : TX;
+      ly = q % TY;
+    }
+  };
+  int rlx = 0, rly = 0;
+  if (t < NR) ring(t, rlx, rly);
+  // Loads are issued into registers ahead of the barriers that precede their
+  // use, so that a plane costs one exposed memory latency, not two.
+  T lz[NL];
+  auto fetch_l = [&](int z) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = t + kThreads * q;
+      lz[q] = T(0);
+      if (e < LX * LY) {
+        const int64_t i = gidx(e % LX - 2, e / LX - 2, z);
+        if (i >= 0) lz[q] = zl[i];
+      }
+    }
+  };
+  auto store_l = [&](int z) {
+    T* d = sl[slot(z)];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = t + kThreads * q;
+      if (e < LX * LY) d[e] = lz[q];
+    }
+  };
+  // bands and r of one cell; false beyond a non-periodic face (zeros)
+  auto fetch_cell = [&](int lx, int ly, int z, T (&bd)[7], T& rv) -> bool {
+    const int64_t i = gidx(lx, ly, z);
+    if (i < 0) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) bd[k] = T(0);
+      rv = T(0);
+      return false;
+    }
+#pragma unroll
+    for (int k = 0; k < 7; ++k) bd[k] = A[k * N + i];
+    rv = r[i];
+    return true;
+  };
+  // register sets: bc = bands of the plane whose matvec is next, bn = the
+  // plane swept next, bf = the plane being fetched (two planes ahead)
+  T bc[PER][7], bn[PER][7], bf[PER][7], rn[PER], rf[PER], rbn[7], rbf[7], rrn = T(0), rrf = T(0);
+  bool vn[PER], vf[PER], vrn = false, vrf = false;
+  auto fetch_plane = [&](int z) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int q = t + kThreads * j;
+      vf[j] = fetch_cell(q % TX, q / TX, z, bf[j], rf[j]);
+    }
+    if (t < NR) vrf = fetch_cell(rlx, rly, z, rbf, rrf);
+  };
+  auto advance = [&]() {   // bn <- bf
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) bn[j][k] = bf[j][k];
+      rn[j] = rf[j];
+      vn[j] = vf[j];
+    }
+#pragma unroll
+    for (int k = 0; k < 7; ++k) rbn[k] = rbf[k];
+    rrn = rrf;
+    vrn = vrf;
+  };
+  // zg of one cell from its bands, r and the zl planes in LDS
+  auto sweep = [&](int lx, int ly, int z, bool valid, const T (&bd)[7], T rv) -> T {
+    if (!valid) return T(0);   // beyond a non-periodic face
+    const T* P = sl[slot(z)];
+    const int e = (ly + 2) * LX + (lx + 2);
+    T a = bd[0] * P[e];
+    a += bd[1] * P[e - 1];
+    a += bd[2] * P[e + 1];
+    a += bd[3] * P[e - LX];
+    a += bd[4] * P[e + LX];
+    a += bd[5] * sl[slot(z - 1)][e];
+    a += bd[6] * sl[slot(z + 1)][e];
+    return P[e] + omega * (rv - a) / bd[0];
+  };
+  auto sweep_plane = [&](int z) {
+    T* G = sg[slot(z)];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int q = t + kThreads * j, lx = q % TX, ly = q / TX;
+      G[(ly + 1) * GX + lx + 1] = sweep(lx, ly, z, vn[j], bn[j], rn[j]);
+    }
+    if (t < NR) G[(rly + 1) * GX + rlx + 1] = sweep(rlx, rly, z, vrn, rbn, rrn);
+  };
+
+  // prologue: zl planes z0-2 .. z0+1 and zg planes z0-1, z0 in LDS; bands of
+  // z0 in bc, of z0+1 in bn; zl of z0+2 in lz
+  fetch_l(z0 - 2);
+  store_l(z0 - 2);
+  fetch_l(z0 - 1);
+  store_l(z0 - 1);
+  fetch_l(z0);
+  store_l(z0);
+  fetch_plane(z0 - 1);
+  advance();
+  __syncthreads();
+  sweep_plane(z0 - 1);
+  fetch_l(z0 + 1);
+  fetch_plane(z0);
+  __syncthreads();
+  store_l(z0 + 1);
+  advance();
+  __syncthreads();
+  sweep_plane(z0);
+#pragma unroll
+  for (int j = 0; j < PER; ++j)
+#pragma unroll
+    for (int k = 0; k < 7; ++k) bc[j][k] = bn[j][k];
+  fetch_l(z0 + 2);
+  fetch_plane(z0 + 1);
+  advance();
+  for (int z = z0; z < z1; ++z) {
+    __syncthreads();
+    store_l(z + 2);
+    // loads of the planes two ahead stay in flight during this plane's work
+    if (z + 3 <= z1 + 1) fetch_l(z + 3);
+    if (z + 2 <= z1) fetch_plane(z + 2);
+    __syncthreads();
+    sweep_plane(z + 1);
+    __syncthreads();
+    const T* G = sg[slot(z)];
+    const T* Gb = sg[slot(z - 1)];
+    const T* Gt = sg[slot(z + 1)];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int q = t + kThreads * j, lx = q % TX, ly = q / TX;
+      if (x0 + lx < g.nx && y0 + ly < g.ny) {
+        const int e = (ly + 1) * GX + lx + 1;
+        T a = bc[j][0] * G[e];
+        a += bc[j][1] * G[e - 1];
+        a += bc[j][2] * G[e + 1];
+        a += bc[j][3] * G[e - GX];
+        a += bc[j][4] * G[e + GX];
+        a += bc[j][5] * Gb[e];
+        a += bc[j][6] * Gt[e];
+        w[x0 + lx + (int64_t)g.nx * (y0 + ly + (int64_t)g.ny * z)] = a;
+      }
+#pragma unroll
+      for (int k = 0; k < 7; ++k) bc[j][k] = bn[j][k];
+    }
+    advance();
+  }
 }
 
 template <class T>
@@ -1127,6 +1336,30 @@ hipError_t jacobi_sweep(hipStream_t s, const Grid3& g, const T* bands, const T* 
 }
 
 template <class T>
+hipError_t sweep_stencil(hipStream_t s, const Grid3& g, const T* bands, const T* r, const T* zl,
+                         T* w, double omega) {
+  if (g.n == 0) return hipSuccess;
+  const bool wide = g.nx > 32;
+  const int TX = wide ? 64 : 32, TY = wide ? 8 : 16;
+  const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY;
+  // planes per block: about 1024 blocks (four per CU), 4..32 planes (each
+  // block recomputes two halo planes of the sweep)
+  const int64_t cols = (int64_t)ntx * nty;
+  int zc = (int)std::min<int64_t>(32, std::max<int64_t>(8, cols * g.nz / 1024));
+  zc = std::min(zc, g.nz);
+  const int ntz = (g.nz + zc - 1) / zc;
+  const int64_t nb = cols * ntz;
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  if (wide)
+    k_sweep_stencil<T, 64, 8><<<(int)nb, kThreads, 0, s>>>(g, bands, r, zl, w, (T)omega, ntx, nty,
+                                                          zc);
+  else
+    k_sweep_stencil<T, 32, 16><<<(int)nb, kThreads, 0, s>>>(g, bands, r, zl, w, (T)omega, ntx,
+                                                           nty, zc);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t point_jacobi(hipStream_t s, const Grid3& g, const T* bands, const T* r, T* z) {
   if (g.n == 0) return hipSuccess;
   k_point_jacobi<T><<<grid_for(g.n), kThreads, 0, s>>>(g.n, bands, r, z);
@@ -1432,6 +1665,8 @@ hipError_t axpy_f32_into_f64(hipStream_t s, const float* d, double* x, int64_t n
                                  double, const T*, int);                                          \
   template hipError_t residual_norm<T>(hipStream_t, const Grid3&, const T*, const T*, const T*,   \
                                        T*, T*);                                                   \
+  template hipError_t sweep_stencil<T>(hipStream_t, const Grid3&, const T*, const T*, const T*,   \
+                                       T*, double);                                              \
   template hipError_t jacobi_sweep<T>(hipStream_t, const Grid3&, const T*, const T*, const T*,    \
                                       T*, double);                                                \
   template hipError_t point_jacobi<T>(hipStream_t, const Grid3&, const T*, const T*, T*);         \

@@ -51,6 +51,11 @@ hipError_t residual_norm(hipStream_t s, const Grid3& g, const T* bands, const T*
 template <class T>
 hipError_t jacobi_sweep(hipStream_t s, const Grid3& g, const T* bands, const T* r, const T* zin,
                         T* zout, double omega);
+// w = A (zl + omega (r - A zl) / diag(A)): one global damped Jacobi sweep
+// fused with the following matvec (the swept vector is not stored)
+template <class T>
+hipError_t sweep_stencil(hipStream_t s, const Grid3& g, const T* bands, const T* r, const T* zl,
+                         T* w, double omega);
 // z = r / diag(A)
 template <class T>
 hipError_t point_jacobi(hipStream_t s, const Grid3& g, const T* bands, const T* r, T* z);

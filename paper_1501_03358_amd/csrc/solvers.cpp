@@ -76,6 +76,28 @@ struct Op {
   // w = A M^-1 v
   // (w, not yet written, is the preconditioner's temporary)
   int apply(const T* v, T* w) {
+    if (M && M->d.type == KRS_PC_SCHWARZ_JACOBI && M->d.global_sweeps == 1 &&
+        g.n >= kFuseMinN) {
+      // local solves into z, then the global sweep and the matvec in one pass
+      // (on smaller grids the two streaming kernels are as fast: the fused
+      // pass recomputes two halo planes per column chunk)
+      hipStream_t s = ctx->stream;
+      const double NW = (double)g.n * sizeof(T);
+      if (M->d.local_sweeps > 0 && M->pack) {
+        KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, 9 * NW,
+                   schwarz_local_packed<T>(s, g, M->d.tile, (const T*)M->pack, v, z,
+                                           M->d.omega_local, M->d.local_sweeps));
+      } else if (M->d.local_sweeps > 0) {
+        KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, 9 * NW,
+                   schwarz_local<T>(s, g, M->d.tile, bands(), v, z, M->d.omega_local,
+                                    M->d.local_sweeps));
+      } else {
+        KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, z, g.n, 0.0));
+      }
+      KRS_LAUNCH(ctx, KRS_K_SWEEP_STENCIL, 10 * NW,
+                 sweep_stencil<T>(s, g, bands(), v, z, w, M->d.omega_global));
+      return 0;
+    }
     int rc = minv_s(v, z, w);
     if (rc) return rc;
     KRS_LAUNCH(ctx, KRS_K_STENCIL, 9.0 * g.n * sizeof(T),
@@ -829,8 +851,9 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
       const int64_t started = (int64_t)d[kIts] - its;
       const int done_now = (int)d[kDone];
       const bool half = done_now != kRunning && d[kEndHalf] != 0.0;
-      ctx->bytes += started * (bytes_p + bytes_sv) + (started - (half ? 1 : 0)) * bytes_yr +
-                    (done_now == kExited ? 5 * NW : 0.0);
+      timing_add_bytes(ctx, KRS_K_BICG_P, started * bytes_p + (done_now == kExited ? 5 * NW : 0.0));
+      timing_add_bytes(ctx, KRS_K_BICG_SV, started * bytes_sv);
+      timing_add_bytes(ctx, KRS_K_BICG_YR, (started - (half ? 1 : 0)) * bytes_yr);
       its = (int64_t)d[kIts];
       const int64_t hl = (int64_t)d[kHlen];
       for (int64_t h = hseen; h < hl; ++h) hist(d[kHistOff + h % kHistRing] / nb);
@@ -945,6 +968,16 @@ int precond_apply(krs_ctx* ctx, const krs_precond* M, const void* r, void* z, vo
   }
   Op<float> op{ctx, A, M, grid3(A), nullptr, (float*)tmp};
   return op.minv((const float*)r, (float*)z);
+}
+
+int operator_apply(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const void* v, void* w,
+                   void* tmp) {
+  if (A->dt == KRS_F64) {
+    Op<double> op{ctx, A, M, grid3(A), (double*)tmp, nullptr};
+    return op.apply((const double*)v, (double*)w);
+  }
+  Op<float> op{ctx, A, M, grid3(A), (float*)tmp, nullptr};
+  return op.apply((const float*)v, (float*)w);
 }
 
 int gmres_rgcrot(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,

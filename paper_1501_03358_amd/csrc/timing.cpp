@@ -52,6 +52,11 @@ void timing_flush(krs_ctx* ctx) {
   ctx->pending.clear();
 }
 
+void timing_add_bytes(krs_ctx* ctx, int cls, double bytes) {
+  ctx->bytes += bytes;
+  if (ctx->timing) ctx->t_bytes[cls] += bytes;
+}
+
 void timing_release(krs_ctx* ctx) {
   timing_flush(ctx);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);

@@ -30,7 +30,7 @@ EXPORTS = (
     "krs_matrix_destroy", "krs_precond_create", "krs_precond_workspace_size",
     "krs_precond_refresh", "krs_precond_destroy", "krs_recycle_create", "krs_recycle_destroy", "krs_recycle_dim",
     "krs_recycle_set_dim", "krs_workspace_size", "krs_stencil_apply", "krs_precond_apply",
-    "krs_gmres", "krs_rgcrot_solve", "krs_rbicgstab_solve", "krs_recycle_update",
+    "krs_operator_apply", "krs_gmres", "krs_rgcrot_solve", "krs_rbicgstab_solve", "krs_recycle_update",
     "krs_hybrid_solve", "krs_ir_solve", "krs_version", "krs_timing_enable", "krs_timing_reset",
     "krs_timing_read",
 )
@@ -93,6 +93,7 @@ def _declare(L):
         "krs_workspace_size": (i32, [i32, i64, i32, i32, i32, ctypes.POINTER(sz)]),
         "krs_stencil_apply": (i32, [P, P, P, P, dbl, dbl, P]),
         "krs_precond_apply": (i32, [P, P, P, P]),
+        "krs_operator_apply": (i32, [P, P, P, P, P, P]),
         "krs_gmres": (i32, [P, P, P, P, P, ctypes.POINTER(Opts), P, sz, ctypes.POINTER(Stats)]),
         "krs_rgcrot_solve": (i32, [P, P, P, P, P, P, ctypes.POINTER(Opts), P, sz,
                                    ctypes.POINTER(Stats)]),
@@ -311,6 +312,10 @@ def precond_apply(ctx, M, r, z):
     return ctx.check(lib().krs_precond_apply(ctx.h, M.h, _ptr(r), _ptr(z)))
 
 
+def operator_apply(ctx, A, M, v, w, tmp):
+    return ctx.check(lib().krs_operator_apply(ctx.h, A.h, _h(M), _ptr(v), _ptr(w), _ptr(tmp)))
+
+
 def _h(obj):
     return None if obj is None else obj.h
 
@@ -361,7 +366,7 @@ def ir_solve(ctx, A64, A32, M32, rec32, b, x, opts, ws, stats=None):
 
 KERNEL_CLASSES = ("stencil", "residual", "schwarz_local", "jacobi_sweep", "block_dot",
                   "block_dot2", "block_update", "bicg_p", "bicg_sv", "bicg_yr", "gram",
-                  "row_transform", "other")
+                  "row_transform", "other", "sweep_stencil")
 
 
 def timing_enable(ctx, on=True):
