@@ -157,6 +157,7 @@ typedef struct krs_stats {
   double time_ms;          /* wall time of the call */
   double host_eig_ms;      /* time in the host eigen step of the recycle update */
   double bytes_model;      /* algorithmic HBM bytes of the call (byte model) */
+  int64_t second_passes;   /* Arnoldi steps that needed a second Gram-Schmidt pass */
 } krs_stats;
 
 /* ---------------- context ---------------- */

@@ -731,12 +731,92 @@ __device__ __forceinline__ void dau_rows(const Cols<T>& Q, int nc, const T* cf,
   }
 }
 
+// Second pass for many columns: rows are staged through LDS in tiles of kDauRows
+// (coalesced column loads, the next tile prefetched into registers while the
+// current one is used); v = w - Q coef is formed per row by 4 lanes, then each
+// lane accumulates one column's dot product over a group of the tile's rows.
+constexpr int kDauRows = 64;
+
+template <class T, int NC>
+__global__ __launch_bounds__(kThreads) void k_block_dot_after_update_lds(
+    Cols<T> Q, const double* coef, const T* __restrict__ w, int64_t n, T* partials, int nblk,
+    const int* skip) {
+  if (skip && *skip) return;
+  constexpr int R = kDauRows;
+  constexpr int PE = R * NC / kThreads;      // staged column values per thread and tile
+  constexpr int G = kThreads / NC;           // row groups of the accumulation step
+  constexpr int RG = R / G;                  // rows per group
+  constexpr int LP = 4;                      // lanes per row when forming v
+  static_assert(kThreads % NC == 0 && R % G == 0 && (R * NC) % kThreads == 0 &&
+                kThreads == R * LP, "tile shape");
+  __shared__ T qs[R][NC + 1];
+  __shared__ T vs[R];
+  __shared__ T cf[NC];
+  __shared__ T red[G][NC + 1];
+  const int t = threadIdx.x;
+  const int nc = Q.n1 + Q.n2;
+  for (int c = t; c < NC; c += kThreads) cf[c] = c < nc ? (T)coef[c] : T(0);
+  const Range rg = block_range(n);
+  // this thread's staged elements: element e = t + kThreads * k -> column e / R, row e % R
+  T pq[PE], pw = T(0);
+  auto fetch = [&](int64_t i0) {
+    const int64_t rows = rg.v1 - i0;
+#pragma unroll
+    for (int k = 0; k < PE; ++k) {
+      const int e = t + kThreads * k, c = e / R, rr = e % R;
+      pq[k] = (c < nc && rr < rows) ? col_ptr(Q, c)[i0 + rr] : T(0);
+    }
+    if (t < R) pw = t < rows ? w[i0 + t] : T(0);
+  };
+  const int my_c = t % NC, my_g = t / NC;
+  const int vrow = t / LP, vpart = t % LP;
+  T acc = 0, accw = 0;
+  if (rg.v0 < rg.v1) fetch(rg.v0);
+  for (int64_t i0 = rg.v0; i0 < rg.v1; i0 += R) {
+    __syncthreads();   // previous tile fully used
+#pragma unroll
+    for (int k = 0; k < PE; ++k) {
+      const int e = t + kThreads * k;
+      qs[e % R][e / R] = pq[k];
+    }
+    if (t < R) vs[t] = pw;
+    __syncthreads();
+    if (i0 + R < rg.v1) fetch(i0 + R);
+    // v = w - Q cf for row vrow: LP lanes each take NC / LP columns
+    T sdot = 0;
+#pragma unroll
+    for (int c = vpart * (NC / LP); c < (vpart + 1) * (NC / LP); ++c) sdot += cf[c] * qs[vrow][c];
+    sdot += __shfl_xor(sdot, 1);
+    sdot += __shfl_xor(sdot, 2);
+    const T v = vs[vrow] - sdot;
+    __syncthreads();
+    if (vpart == 0) {
+      vs[vrow] = v;
+      accw += v * v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = my_g * RG; rr < (my_g + 1) * RG; ++rr) acc += qs[rr][my_c] * vs[rr];
+  }
+  // column c: groups in order; |v|^2: block sum
+  red[my_g][my_c] = acc;
+  const T sw = block_sum(accw);
+  __syncthreads();
+  if (t < NC && t < nc) {
+    T sum = 0;
+    for (int gi = 0; gi < G; ++gi) sum += red[gi][t];
+    partials[(int64_t)t * nblk + blockIdx.x] = sum;
+  }
+  if (t == 0) partials[(int64_t)nc * nblk + blockIdx.x] = sw;
+}
+
 template <class T, int W, int NC>
 __global__ __launch_bounds__(kThreads) void k_block_dot_after_update(Cols<T> Q,
                                                                      const double* coef,
                                                                      const T* __restrict__ w,
                                                                      int64_t n, T* partials,
-                                                                     int nblk) {
+                                                                     int nblk, const int* skip) {
+  if (skip && *skip) return;
   __shared__ T cf[NC];
   const int nc = Q.n1 + Q.n2;
   for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < nc ? (T)coef[c] : T(0);
@@ -983,9 +1063,33 @@ __global__ __launch_bounds__(kThreads) void k_finish_sum(const T* partials, int 
   if (threadIdx.x == 0) out[c] = s;
 }
 
-__global__ void k_cgs2_combine(int ncols, const double* h1, const double* h2, double* hcol,
-                               double* inv, int* flag) {
+// After the first pass (h1 = Q^T w, h1[ncols] = |w|^2): when |w - Q h1| is at
+// least |w| / sqrt(2) by the Pythagorean identity, a second pass is not needed
+// ("twice is enough" criterion of Kahan and Parlett, in the form of Daniel,
+// Gragg, Kaufman and Stewart); then h = h1 and the norm is final, and *skip
+// tells the second pass and its finishing kernel to return at once.
+__global__ void k_cgs_decide(int ncols, const double* h1, double* hcol, double* inv, int* flag,
+                             int* skip) {
   if (threadIdx.x != 0) return;
+  double q = 0;
+  for (int c = 0; c < ncols; ++c) q += h1[c] * h1[c];
+  const double w2 = h1[ncols];
+  const double r2 = w2 - q;
+  if (r2 >= 0.5 * w2 && isfinite(r2)) {
+    for (int c = 0; c < ncols; ++c) hcol[c] = h1[c];
+    const double hn = sqrt(r2);
+    hcol[ncols] = hn;
+    inv[0] = hn > 0 ? 1.0 / hn : 0.0;
+    flag[0] = 0;
+    skip[0] = 1;
+  } else {
+    skip[0] = 0;
+  }
+}
+
+__global__ void k_cgs2_combine(int ncols, const double* h1, const double* h2, double* hcol,
+                               double* inv, int* flag, const int* skip) {
+  if (threadIdx.x != 0 || (skip && *skip)) return;
   double q = 0;
   for (int c = 0; c < ncols; ++c) {
     hcol[c] = h1[c] + h2[c];
@@ -1474,16 +1578,20 @@ constexpr int dau_width(int nc) {
 
 template <class T>
 hipError_t block_dot_after_update(hipStream_t s, const Cols<T>& Q, const double* coef,
-                                  const T* w, int64_t n, T* partials, int nblk) {
+                                  const T* w, int64_t n, T* partials, int nblk, const int* skip) {
   const bool v = vec_ok(Q) && vec_ok(w);
+  constexpr int VW = 16 / sizeof(T);
   KRS_NC_DISPATCH(Q.count() > 0 ? Q.count() : 1, {
     constexpr int DW = dau_width<T>(NCB);
-    if (v && DW > 1)
+    if (DW < VW && NCB >= 16)
+      k_block_dot_after_update_lds<T, NCB><<<nblk, kThreads, 0, s>>>(Q, coef, w, n, partials,
+                                                                     nblk, skip);
+    else if (v && DW > 1)
       k_block_dot_after_update<T, DW, NCB><<<nblk, kThreads, 0, s>>>(Q, coef, w, n, partials,
-                                                                     nblk);
+                                                                     nblk, skip);
     else
       k_block_dot_after_update<T, 1, NCB><<<nblk, kThreads, 0, s>>>(Q, coef, w, n, partials,
-                                                                    nblk);
+                                                                    nblk, skip);
   });
   return hipGetLastError();
 }
@@ -1533,9 +1641,15 @@ hipError_t finish_sum(hipStream_t s, const T* partials, int nblk, int ncols, dou
 
 template <class T>
 hipError_t finish_cgs2(hipStream_t s, const T* partials, int nblk, int ncols, const double* h1,
-                       double* h2, double* hcol, double* inv, int* flag) {
+                       double* h2, double* hcol, double* inv, int* flag, const int* skip) {
   k_finish_sum<T><<<ncols + 1, kThreads, 0, s>>>(partials, nblk, h2);
-  k_cgs2_combine<<<1, 64, 0, s>>>(ncols, h1, h2, hcol, inv, flag);
+  k_cgs2_combine<<<1, 64, 0, s>>>(ncols, h1, h2, hcol, inv, flag, skip);
+  return hipGetLastError();
+}
+
+hipError_t cgs_decide(hipStream_t s, int ncols, const double* h1, double* hcol, double* inv,
+                      int* flag, int* skip) {
+  k_cgs_decide<<<1, 64, 0, s>>>(ncols, h1, hcol, inv, flag, skip);
   return hipGetLastError();
 }
 
@@ -1679,13 +1793,13 @@ hipError_t axpy_f32_into_f64(hipStream_t s, const float* d, double* x, int64_t n
   template hipError_t block_update<T>(hipStream_t, const Cols<T>&, const double*, double,         \
                                       const T*, T*, int64_t, const double*, int, T*, int);        \
   template hipError_t block_dot_after_update<T>(hipStream_t, const Cols<T>&, const double*,       \
-                                                const T*, int64_t, T*, int);                      \
+                                                const T*, int64_t, T*, int, const int*);          \
   template hipError_t gram<T>(hipStream_t, const Cols<T>&, const Cols<T>&, int64_t, T*, int);     \
   template hipError_t row_transform<T>(hipStream_t, const Cols<T>&, const double*, int, T*,       \
                                        int64_t, int64_t);                                         \
   template hipError_t finish_sum<T>(hipStream_t, const T*, int, int, double*);                    \
   template hipError_t finish_cgs2<T>(hipStream_t, const T*, int, int, const double*, double*,     \
-                                     double*, double*, int*);                                     \
+                                     double*, double*, int*, const int*);                         \
   template hipError_t bicg_p<T>(hipStream_t, const T*, T*, const T*, const double*, int64_t);     \
   template hipError_t bicg_sv<T>(hipStream_t, const Cols<T>&, const T*, T*, T*, const double*,    \
                                  int, int64_t, T*, int);                                          \

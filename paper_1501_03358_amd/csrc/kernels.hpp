@@ -84,10 +84,12 @@ template <class T>
 hipError_t block_update(hipStream_t s, const Cols<T>& Q, const double* coef, double sgn,
                         const T* w_in, T* w_out, int64_t n, const double* scale, int dots,
                         T* partials, int nblk);
-// partials of Q^T (w - Q coef) and |w - Q coef|^2 without writing anything.
+// partials of Q^T (w - Q coef) and |w - Q coef|^2 without writing anything;
+// returns at once when skip != NULL and *skip != 0 (device flag).
 template <class T>
 hipError_t block_dot_after_update(hipStream_t s, const Cols<T>& Q, const double* coef,
-                                  const T* w, int64_t n, T* partials, int nblk);
+                                  const T* w, int64_t n, T* partials, int nblk,
+                                  const int* skip = nullptr);
 // Gram: partials[(a*nb + b)*nblk + blk] = sum_rows X_a * Y_b
 template <class T>
 hipError_t gram(hipStream_t s, const Cols<T>& X, const Cols<T>& Y, int64_t n, T* partials,
@@ -105,7 +107,14 @@ hipError_t finish_sum(hipStream_t s, const T* partials, int nblk, int ncols, dou
 // Pythagorean form is unreliable and an explicit norm is needed); inv = 1/hcol[ncols].
 template <class T>
 hipError_t finish_cgs2(hipStream_t s, const T* partials, int nblk, int ncols, const double* h1,
-                       double* h2, double* hcol, double* inv, int* flag);
+                       double* h2, double* hcol, double* inv, int* flag,
+                       const int* skip = nullptr);
+// After the first pass with |w|^2 in h1[ncols]: if |w - Q h1|^2 = |w|^2 - |h1|^2
+// >= |w|^2 / 2, one pass suffices: hcol = h1 with the norm appended, inv = 1/norm,
+// flag = 0, *skip = 1 (the second pass and finish_cgs2 then return at once);
+// else *skip = 0.
+hipError_t cgs_decide(hipStream_t s, int ncols, const double* h1, double* hcol, double* inv,
+                      int* flag, int* skip);
 
 // ---- BiCGStab fused passes (all scalars in the FP64 array `sc`) ----
 // scalar slots

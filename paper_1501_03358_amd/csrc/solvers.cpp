@@ -322,6 +322,8 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
   double* d_hcol = sc + Ws<T>::kHcol;
   double* d_inv = sc + Ws<T>::kInv;
   int* d_flag = (int*)(sc + Ws<T>::kFlagOff);
+  int* d_skip = d_flag + 1;
+  int64_t n_one_pass = 0, n_two_pass = 0;
   double* d_coef = sc + Ws<T>::kCoef;
   double* d_xi = sc + Ws<T>::kXi;
   double* d_nrm = sc + Ws<T>::kNrm;
@@ -404,13 +406,15 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
       ++mv;
       const int ncols = kc + j + 1;
       const Cols<T> Q = cols<T>(C, ldr, kc, V, ld, j + 1);
-      // lines 6a-9 as two classical Gram-Schmidt passes against [C, V_j]
-      KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (ncols + 1), block_dot<T>(s, Q, w, n, 0, part, nblk));
-      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, ncols, d_h1));
-      KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT2, NW * (ncols + 1),
-                 block_dot_after_update<T>(s, Q, d_h1, w, n, part, nblk));
+      // lines 6a-9 as classical Gram-Schmidt against [C, V_j]: a second
+      // pass only when the first removed more than half of |w|^2
+      KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (ncols + 1), block_dot<T>(s, Q, w, n, 1, part, nblk));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, ncols + 1, d_h1));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, cgs_decide(s, ncols, d_h1, d_hcol, d_inv, d_flag, d_skip));
+      KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT2, 0,
+                 block_dot_after_update<T>(s, Q, d_h1, w, n, part, nblk, d_skip));
       KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
-                 finish_cgs2<T>(s, part, nblk, ncols, d_h1, d_h2, d_hcol, d_inv, d_flag));
+                 finish_cgs2<T>(s, part, nblk, ncols, d_h1, d_h2, d_hcol, d_inv, d_flag, d_skip));
       // line 10: v_{j+1} = (w - Q h) / h_{j+1,j}
       KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (ncols + 2),
                  block_update<T>(s, Q, d_hcol, -1.0, w, vn, n, d_inv, 0, part, nblk));
@@ -418,6 +422,9 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
       if (rc) return rc;
       std::vector<double> hv(ctx->pin + Ws<T>::kHcol, ctx->pin + Ws<T>::kHcol + ncols + 1);
       int flag = *(int*)(ctx->pin + Ws<T>::kFlagOff);
+      const int skipped = ((int*)(ctx->pin + Ws<T>::kFlagOff))[1];
+      if (!skipped) timing_add_bytes(ctx, KRS_K_BLOCK_DOT2, NW * (ncols + 1));
+      ++(skipped ? n_one_pass : n_two_pass);
       if (flag) {
         // norm from the Pythagorean identity unreliable: recompute explicitly
         KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (ncols + 2),
@@ -521,7 +528,9 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
     st->rel_res_est = est / nb;
     st->time_ms = tm.ms();
     st->bytes_model = ctx->bytes - bytes0;
+    st->second_passes = n_two_pass;
   }
+  (void)n_one_pass;
   return status;
 }
 
@@ -1048,6 +1057,7 @@ int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const k
   const int max_outer = o->max_outer > 0 ? o->max_outer : 20;
   double host_eig = 0;
   int ties = 0;
+  int64_t second = 0;
   if (!(nb > 0)) {
     if (st) {
       st->status = std::isfinite(nb) ? KRS_OK : KRS_DIVERGED;
@@ -1085,6 +1095,7 @@ int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const k
     cycles += ist.cycles;
     host_eig += ist.host_eig_ms;
     ties += ist.eig_ties;
+    second += ist.second_passes;
     total_bytes += ist.bytes_model;
     // x += ||r|| d ; r = b - A x in FP64
     ctx->bytes = 0;
@@ -1121,6 +1132,7 @@ int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const k
     st->host_eig_ms = host_eig;
     st->eig_ties = ties;
     st->bytes_model = total_bytes;
+    st->second_passes = second;
   }
   return status;
 }

@@ -63,7 +63,8 @@ class Stats(ctypes.Structure):
                 ("cycles", ctypes.c_int64), ("outer", ctypes.c_int64),
                 ("history_len", ctypes.c_int64), ("rel_res_true", ctypes.c_double),
                 ("rel_res_est", ctypes.c_double), ("time_ms", ctypes.c_double),
-                ("host_eig_ms", ctypes.c_double), ("bytes_model", ctypes.c_double)]
+                ("host_eig_ms", ctypes.c_double), ("bytes_model", ctypes.c_double),
+                ("second_passes", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -157,15 +157,15 @@ def test_rbicgstab_plain_and_recycled_match_oracle(gpu_lib, pc):
         ref = K.rbicgstab(op, Mi, b, 1e-8, g if use_rec else None)
         assert rc == krs.OK and ref.status == K.CONVERGED
         _check_history(h[:st.history_len], ref.history)
-        # within 2 of the oracle, or within the spread of the oracle itself
-        # under a 1e-15 relative perturbation of b (BiCGStab's exit step can
-        # sit on a residual plateau next to tol)
-        spread = 0
+        # within 2 of the oracle, or within 2 of the range of exits the oracle
+        # itself takes under rounding-level relative perturbations of b
+        # (1e-15 .. 1e-13): with point Jacobi BiCGStab's exit step moves by
+        # up to ~10 iterations under such perturbations
         if abs(st.iterations - ref.iterations) > 2:
-            for eps in (1e-15, -1e-15, 2e-15):
-                alt = K.rbicgstab(op, Mi, b * (1 + eps), 1e-8, g if use_rec else None)
-                spread = max(spread, abs(alt.iterations - ref.iterations))
-        assert abs(st.iterations - ref.iterations) <= max(2, 2 * spread)
+            its = [ref.iterations] + [
+                K.rbicgstab(op, Mi, b * (1 + eps), 1e-8, g if use_rec else None).iterations
+                for eps in (1e-15, -1e-15, 2e-15, 1e-14, -1e-14, 1e-13, -1e-13)]
+            assert min(its) - 2 <= st.iterations <= max(its) + 2, (st.iterations, its)
         assert st.rel_res_true <= 2e-8
         if use_rec:
             assert st.iterations < st_plain.iterations
