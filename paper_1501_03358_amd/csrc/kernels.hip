@@ -731,6 +731,64 @@ __device__ __forceinline__ void dau_rows(const Cols<T>& Q, int nc, const T* cf,
   }
 }
 
+// First pass (Q^T w, optionally |w|^2) for many columns in FP64: the same LDS
+// row tiles as the second pass below, so that no thread holds a register per
+// column pack (the register-tiled kernel drops to a few waves per SIMD there).
+template <class T, int NC>
+__global__ __launch_bounds__(kThreads) void k_block_dot_lds(Cols<T> Q, const T* __restrict__ w,
+                                                            int64_t n, int self_dot, T* partials,
+                                                            int nblk) {
+  constexpr int R = 64;
+  constexpr int PE = R * NC / kThreads;
+  constexpr int G = kThreads / NC;
+  constexpr int RG = R / G;
+  static_assert(kThreads % NC == 0 && R % G == 0 && (R * NC) % kThreads == 0, "tile shape");
+  __shared__ T qs[R][NC + 1];
+  __shared__ T ws_[R];
+  __shared__ T red[G][NC + 1];
+  const int t = threadIdx.x;
+  const int nc = Q.n1 + Q.n2;
+  const Range rg = block_range(n);
+  T pq[PE], pw = T(0);
+  auto fetch = [&](int64_t i0) {
+    const int64_t rows = rg.v1 - i0;
+#pragma unroll
+    for (int k = 0; k < PE; ++k) {
+      const int e = t + kThreads * k, c = e / R, rr = e % R;
+      pq[k] = (c < nc && rr < rows) ? col_ptr(Q, c)[i0 + rr] : T(0);
+    }
+    if (t < R) pw = t < rows ? w[i0 + t] : T(0);
+  };
+  const int my_c = t % NC, my_g = t / NC;
+  T acc = 0, accw = 0;
+  if (rg.v0 < rg.v1) fetch(rg.v0);
+  for (int64_t i0 = rg.v0; i0 < rg.v1; i0 += R) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PE; ++k) {
+      const int e = t + kThreads * k;
+      qs[e % R][e / R] = pq[k];
+    }
+    if (t < R) {
+      ws_[t] = pw;
+      accw += pw * pw;
+    }
+    __syncthreads();
+    if (i0 + R < rg.v1) fetch(i0 + R);
+#pragma unroll 4
+    for (int rr = my_g * RG; rr < (my_g + 1) * RG; ++rr) acc += qs[rr][my_c] * ws_[rr];
+  }
+  red[my_g][my_c] = acc;
+  const T sw = block_sum(accw);
+  __syncthreads();
+  if (t < NC && t < nc) {
+    T sum = 0;
+    for (int gi = 0; gi < G; ++gi) sum += red[gi][t];
+    partials[(int64_t)t * nblk + blockIdx.x] = sum;
+  }
+  if (self_dot && t == 0) partials[(int64_t)nc * nblk + blockIdx.x] = sw;
+}
+
 // Second pass for many columns: rows are staged through LDS in tiles of kDauRows
 // (coalesced column loads, the next tile prefetched into registers while the
 // current one is used); v = w - Q coef is formed per row by 4 lanes, then each
@@ -1544,8 +1602,12 @@ hipError_t block_dot(hipStream_t s, const Cols<T>& Q, const T* w, int64_t n, int
   constexpr int VW = 16 / sizeof(T);
   const bool v = vec_ok(Q) && vec_ok(w);
   KRS_NC_DISPATCH(Q.count() > 0 ? Q.count() : 1, {
-    if (v) k_block_dot<T, VW, NCB><<<nblk, kThreads, 0, s>>>(Q, w, n, self_dot, partials, nblk);
-    else k_block_dot<T, 1, NCB><<<nblk, kThreads, 0, s>>>(Q, w, n, self_dot, partials, nblk);
+    if (sizeof(T) == 8 && NCB >= 64 && Q.count() > 0)
+      k_block_dot_lds<T, NCB><<<nblk, kThreads, 0, s>>>(Q, w, n, self_dot, partials, nblk);
+    else if (v)
+      k_block_dot<T, VW, NCB><<<nblk, kThreads, 0, s>>>(Q, w, n, self_dot, partials, nblk);
+    else
+      k_block_dot<T, 1, NCB><<<nblk, kThreads, 0, s>>>(Q, w, n, self_dot, partials, nblk);
   });
   return hipGetLastError();
 }
