@@ -34,6 +34,30 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# per-launch HBM bytes of each kernel class from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE counters (scaled by a plain copy of known size), valid for the
+# kernel source whose SHA-256 it records
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_porous256_ir.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1501_03358_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of kernel class `cls` from the committed counter
+    summary, or None when absent or taken on other kernel code."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None, "no counter summary"
+    if tr.get("kernels_sha256") != sha:
+        return None, "kernels changed since the counters were taken"
+    c = tr.get("classes", {}).get(cls)
+    if not c:
+        return None, "class not in the counter summary"
+    return c["fetch_bytes"] + c["write_bytes"], None
 N_SWITCH = 3
 M, K = 30, 20
 
@@ -442,6 +466,7 @@ def main():
                    "GB_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
                for c, v in kt.items() if v[0] > 0}
 
+    traffic, traffic_note = measured_traffic(dom)
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle sample ...")
@@ -467,7 +492,10 @@ def main():
         "fp64": fp64,
         "speedup_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 counters)",
+                     "traffic_note": traffic_note,
+                     "algorithmic_bytes_per_launch": by_l / max(n_l, 1),
                      "launches": n_l, "avg_launch_us": 1e3 * ms_l / max(n_l, 1)},
         "kernels": kernels,
         "cpu_baseline": cpu,
