@@ -179,11 +179,13 @@ void krs_matrix_destroy(krs_matrix* A);
 /* Preconditioner for A; `ws` is a device buffer of at least
  * krs_precond_workspace_size(A, d) bytes, owned by the caller (NULL allowed
  * when the size is 0).  For SCHWARZ_JACOBI it holds one temporary vector and a
- * tile-major copy of the local-solve coefficients (omega_local / a_C and
- * omega_local * a_k / a_C for every cell of every extended tile, about
- * 7 (tile+2)^3 / tile^3 values per cell), built here on the context stream
- * from A's current bands.  If the caller changes A's bands afterwards it must
- * call krs_precond_refresh. */
+ * copy of the local-solve coefficients (omega_local / a_C and
+ * omega_local * a_k / a_C) for every cell of the extended tiles, grouped in
+ * bricks of 2x2x2 tiles when every tile count is even (each cell stored once
+ * per brick: 7 (2 tile+2)^3 / (2 tile)^3 values per cell, 9.97 for tile 8),
+ * else per tile (7 (tile+2)^3 / tile^3, 13.7 for tile 8); built here on the
+ * context stream from A's current bands.  If the caller changes A's bands
+ * afterwards it must call krs_precond_refresh. */
 int krs_precond_create(krs_ctx* ctx, const krs_matrix* A, const krs_precond_desc* d,
                        void* ws, size_t ws_bytes, krs_precond** out);
 size_t krs_precond_workspace_size(const krs_matrix* A, const krs_precond_desc* d);

@@ -64,8 +64,22 @@ template <class T>
 hipError_t schwarz_local(hipStream_t s, const Grid3& g, int tile, const T* bands, const T* r, T* z,
                          double omega, int sweeps);
 
-// Tile-major coefficients of the local solves (7 * (tile+2)^3 values per tile):
-// s = omega / a_C and s * a_k; rebuilt whenever A changes.
+// Tiles per brick edge of the coefficient pack: 2 when every tile count is
+// even (a brick of 2^3 tiles stores each cell of its extended tiles once),
+// else 1 (one extended tile per brick).
+inline int schwarz_brick(const Grid3& g, int tile) {
+  const int ntx = g.nx / tile, nty = g.ny / tile, ntz = g.nz / tile;
+  return (ntx % 2 == 0 && nty % 2 == 0 && ntz % 2 == 0) ? 2 : 1;
+}
+// Values in the pack: 7 * (brick*tile + 2)^3 per brick.
+inline int64_t schwarz_pack_values(const Grid3& g, int tile) {
+  const int br = schwarz_brick(g, tile);
+  const int64_t nb = (int64_t)(g.nx / tile / br) * (g.ny / tile / br) * (g.nz / tile / br);
+  const int64_t eb = (int64_t)br * tile + 2;
+  return nb * 7 * eb * eb * eb;
+}
+// Brick-major coefficients of the local solves: s = omega / a_C and s * a_k
+// for every cell of a brick's extended tiles; rebuilt whenever A changes.
 template <class T>
 hipError_t schwarz_pack(hipStream_t s, const Grid3& g, int tile, const T* bands, T* pk,
                         double omega);

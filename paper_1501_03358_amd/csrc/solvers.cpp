@@ -947,9 +947,8 @@ int workspace_bytes(krs_solver solver, int64_t n, int m, int k, krs_dtype dt, si
 
 size_t precond_pack_bytes(const krs_matrix* A, const krs_precond_desc* d) {
   if (!d || d->type != KRS_PC_SCHWARZ_JACOBI || d->tile <= 0) return 0;
-  const int64_t t = d->tile, e = t + 2;
-  const int64_t nt = (A->g.nx / t) * (A->g.ny / t) * (A->g.nz / t);
-  return (size_t)nt * 7 * e * e * e * (A->dt == KRS_F64 ? sizeof(double) : sizeof(float));
+  return (size_t)schwarz_pack_values(grid3(A), d->tile) *
+         (A->dt == KRS_F64 ? sizeof(double) : sizeof(float));
 }
 
 int precond_pack(krs_ctx* ctx, const krs_precond* M) {
