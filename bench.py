@@ -295,12 +295,15 @@ def seq_main(args):
         main_name, other = "rgcrot", "gmres"
     else:
         res["hybrid"], kt = run("hybrid", lambda rec, i, b: krs.hybrid_solve(
-            ctx, A, Mp, rec, i, N_SWITCH, b, x, opts(), ws))
-        res["bicgstab"], _ = run("bicgstab", lambda rec, i, b: krs.rbicgstab_solve(
-            ctx, A, Mp, None, b, x, opts(), ws))
-        res["rgcrot"], _ = run("rgcrot", lambda rec, i, b: krs.rgcrot_solve(
-            ctx, A, Mp, rec, b, x, opts(), ws))
+            ctx, A, Mp, rec, i, args.n_switch, b, x, opts(), ws))
         main_name, other = "hybrid", "bicgstab"
+        if args.hybrid_only:
+            other = "hybrid"
+        else:
+            res["bicgstab"], _ = run("bicgstab", lambda rec, i, b: krs.rbicgstab_solve(
+                ctx, A, Mp, None, b, x, opts(), ws))
+            res["rgcrot"], _ = run("rgcrot", lambda rec, i, b: krs.rgcrot_solve(
+                ctx, A, Mp, rec, b, x, opts(), ws))
     dom = max(kt, key=lambda c: kt[c][1])
     n_l, ms_l, by_l = kt[dom]
     achieved = by_l / (ms_l * 1e-3) / 1e9 if ms_l > 0 else 0.0
@@ -315,6 +318,7 @@ def seq_main(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{prob.name}_fp64", "grid": f"{n}^3", "unknowns": prob.n,
                    "time_steps": steps, "m": M, "k": K, "tol": 1e-8,
+                   "n_switch": None if channel else args.n_switch,
                    "precond": "Schwarz-Jacobi 8^3 tiles overlap 1, 5 local + 1 global sweeps"},
         "methods": res,
         f"speedup_vs_{other}": r0["solves_per_s"] / res[other]["solves_per_s"],
@@ -346,6 +350,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="grid size per axis")
     ap.add_argument("--inner-tol", type=float, default=1e-5)
+    ap.add_argument("--n-switch", type=int, default=N_SWITCH,
+                    help="porous128: systems solved by rGCROT before rBiCGStab")
+    ap.add_argument("--hybrid-only", action="store_true",
+                    help="porous128: time only the hybrid (switch-point sweeps)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",

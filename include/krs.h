@@ -142,6 +142,10 @@ typedef struct krs_opts {
   int32_t flags;           /* KRS_FLAG_* */
   double* history;         /* optional host buffer: residual history (relative) */
   int64_t history_cap;
+  double switch_back;      /* hybrid only: > 0 => after an rBiCGStab system needing more than
+                              switch_back times the matvecs of the first rBiCGStab system
+                              since the last rGCROT one, the next system runs rGCROT
+                              (recycle space refreshed); 0 = off */
 } krs_opts;
 
 typedef struct krs_stats {
@@ -158,6 +162,8 @@ typedef struct krs_stats {
   double host_eig_ms;      /* time in the host eigen step of the recycle update */
   double bytes_model;      /* algorithmic HBM bytes of the call (byte model) */
   int64_t second_passes;   /* Arnoldi steps that needed a second Gram-Schmidt pass */
+  int64_t solver;          /* krs_hybrid_solve: solver that produced x (KRS_SOLVER_*) */
+  int64_t refreshed;       /* krs_hybrid_solve: 1 if line 1a ran first (space marked stale) */
 } krs_stats;
 
 /* ---------------- context ---------------- */
@@ -202,6 +208,11 @@ int krs_recycle_dim(const krs_recycle* rec);
 /* Sets the dimension (0..kmax), e.g. after U was filled by the caller; call
  * krs_recycle_update before solving if C does not hold A~ U. */
 int krs_recycle_set_dim(krs_recycle* rec, int k);
+/* Marks (U, C) stale: A or M changed since C = A~ U was formed.  The next
+ * krs_hybrid_solve first re-forms C from U (Alg. 3 line 1a: "if the matrix
+ * has changed"), keeping range(U).  Sec. 2.4 leaves the policy for changing
+ * matrices open (intermittent rGCROT); this is the cheapest consistent one. */
+int krs_recycle_mark_stale(krs_recycle* rec);
 
 /* Workspace (bytes) for `solver` on N unknowns with parameters m, k. */
 int krs_workspace_size(krs_solver solver, int64_t N, int m, int k, krs_dtype dt, size_t* bytes);
@@ -258,8 +269,13 @@ int krs_recycle_update(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, 
 /* Hybrid solver step (Sec. 2.4): systems with step < n_switch are solved by
  * rGCROT(m,k) with recycle updates, later ones by rBiCGStab with (U, C)
  * fixed; when rBiCGStab diverges, breaks down or does not converge, the
- * system is solved again by rGCROT (switch back).  stats->cycles > 0 tells
- * which solver produced x.  ws: krs_workspace_size(KRS_SOLVER_RGCROT). */
+ * system is solved again by rGCROT (switch back).  With opts.switch_back > 0
+ * a system whose rBiCGStab solve needed more than switch_back times the
+ * matvecs of the first rBiCGStab system since the last rGCROT one makes the
+ * next system run rGCROT (Sec. 2.4: switch back when convergence becomes
+ * poor).  A space marked stale is re-formed first (line 1a).  stats->solver
+ * and stats->refreshed tell what ran.  The policy state lives in rec.
+ * ws: krs_workspace_size(KRS_SOLVER_RGCROT). */
 int krs_hybrid_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
                      int step, int n_switch, const void* b, void* x, const krs_opts* opts,
                      void* ws, size_t ws_bytes, krs_stats* stats);

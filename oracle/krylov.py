@@ -51,6 +51,21 @@ class Result:
     eig_ties: int = 0
     fallback: bool = False
     events: list = dataclasses.field(default_factory=list)
+    solver: str = ""         # hybrid: "rgcrot" or "rbicgstab" (the one that produced x)
+    refreshed: bool = False  # hybrid: line 1a re-formed C first
+
+
+@dataclasses.dataclass
+class HybridState:
+    """State of the hybrid policy across a sequence of systems.
+
+    stale: A or M changed since C = A~ U was formed (Alg. 3 line 1a: form C
+    again when the matrix has changed); force_rgcrot: the next system runs
+    rGCROT; ref_mv: matvecs of the first rBiCGStab system since the last
+    rGCROT one (the reference for switching back, Sec. 2.4)."""
+    stale: bool = False
+    force_rgcrot: bool = False
+    ref_mv: int = 0
 
 
 def _norm(v):
@@ -410,17 +425,45 @@ def rbicgstab(op, minv, b, tol, rec: Recycle | None = None, max_matvecs=2000,
 # ---------------------------------------------------------------------------
 
 def hybrid_step(step, n_switch, op, minv, b, m, k, tol, rec: Recycle,
-                max_its=2000, orth="cgs2", div_factor=1e2):
-    """One system of the hybrid sequence: the first n_switch systems are solved
-    by rGCROT(m,k), which builds (U, C); later systems by rBiCGStab with that
-    space held fixed.  If rBiCGStab diverges, breaks down or fails to
-    converge, the system is solved again by rGCROT (switch back, Sec. 2.4)."""
-    if step < n_switch:
-        return rgcrot(op, minv, b, m, k, tol, rec, True, max_its, orth)
+                max_its=2000, orth="cgs2", div_factor=1e2, switch_back=0.0,
+                state: HybridState = None):
+    """One system of the hybrid sequence (Sec. 2.4): the first n_switch systems
+    are solved by rGCROT(m,k), which builds (U, C); later systems by
+    rBiCGStab with that space held fixed.  If rBiCGStab diverges, breaks down
+    or fails to converge, the system is solved again by rGCROT.
+
+    Readings for the two options Sec. 2.4 names without fixing them:
+    * a changing matrix (state.stale): C is formed again from U (line 1a)
+      before the system is solved;
+    * switching back when convergence becomes poor (switch_back > 0): if a
+      converged rBiCGStab system needed more than switch_back times the
+      matvecs of the first rBiCGStab system since the last rGCROT one, the
+      next system runs rGCROT (which also refreshes the space)."""
+    state = state if state is not None else HybridState()
+    refreshed = False
+    if state.stale:
+        if rec.dim > 0:
+            recycle_setup(op, rec)
+            refreshed = True
+        state.stale = False
+    if step < n_switch or state.force_rgcrot:
+        state.force_rgcrot = False
+        state.ref_mv = 0
+        res = rgcrot(op, minv, b, m, k, tol, rec, True, max_its, orth)
+        res.solver, res.refreshed = "rgcrot", refreshed
+        return res
     res = rbicgstab(op, minv, b, tol, rec, max_its, div_factor)
     if res.status == CONVERGED:
+        if switch_back > 0:
+            if state.ref_mv == 0:
+                state.ref_mv = res.matvecs
+            elif res.matvecs > switch_back * state.ref_mv:
+                state.force_rgcrot = True
+        res.solver, res.refreshed = "rbicgstab", refreshed
         return res
+    state.ref_mv = 0
     again = rgcrot(op, minv, b, m, k, tol, rec, True, max_its, orth)
     again.fallback = True
     again.events = [("rbicgstab_status", res.status)]
+    again.solver, again.refreshed = "rgcrot", refreshed
     return again

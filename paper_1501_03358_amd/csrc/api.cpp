@@ -1,5 +1,6 @@
 // C-ABI of the krs library: argument checking and dispatch to the drivers.
 #include <climits>
+#include <cmath>
 #include <new>
 
 #include "internal.hpp"
@@ -202,6 +203,12 @@ int krs_recycle_set_dim(krs_recycle* rec, int k) {
   return KRS_OK;
 }
 
+int krs_recycle_mark_stale(krs_recycle* rec) {
+  if (!rec) return KRS_ERR_ARG;
+  rec->stale = true;
+  return KRS_OK;
+}
+
 int krs_workspace_size(krs_solver solver, int64_t N, int m, int k, krs_dtype dt, size_t* bytes) {
   if (!bytes || N < 1 || m < 0 || m > krs::kMaxM || !valid_dtype(dt)) return KRS_ERR_ARG;
   return krs::workspace_bytes(solver, N, m, k, dt, bytes);
@@ -292,22 +299,51 @@ int krs_hybrid_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, kr
   if (rc) return rc;
   if ((rc = check_precond(ctx, A, M))) return rc;
   if ((rc = check_rec(ctx, A, rec, opts, true))) return rc;
-  if (step < n_switch)
-    return krs::gmres_rgcrot(ctx, A, M, rec, true, b, x, opts, ws, ws_bytes, stats);
+  if (opts->switch_back < 0 || !std::isfinite(opts->switch_back))
+    return set_err(ctx, KRS_ERR_ARG, "switch_back must be >= 0");
+  bool refreshed = false;
+  if (rec->stale) {
+    // line 1a: the operator changed, so C = qr(A~ U).Q and U <- U R^-1
+    if (rec->dim > 0) {
+      rc = krs::recycle_setup(ctx, A, M, rec, ws, ws_bytes);
+      if (rc) return rc;
+      refreshed = true;
+    }
+    rec->stale = false;
+  }
+  auto finish = [&](int code, int64_t solver) {
+    if (stats) {
+      stats->solver = solver;
+      stats->refreshed = refreshed ? 1 : 0;
+    }
+    return code;
+  };
+  if (step < n_switch || rec->force_rgcrot) {
+    rec->force_rgcrot = false;
+    rec->ref_mv = 0;
+    rc = krs::gmres_rgcrot(ctx, A, M, rec, true, b, x, opts, ws, ws_bytes, stats);
+    return finish(rc, KRS_SOLVER_RGCROT);
+  }
   krs_stats first;
   rc = krs::rbicgstab(ctx, A, M, rec, b, x, opts, ws, ws_bytes, &first);
   if (rc <= 0) {
     if (stats) *stats = first;
-    return rc;
+    if (rc == KRS_OK && opts->switch_back > 0) {
+      if (rec->ref_mv == 0) rec->ref_mv = first.matvecs;
+      else if ((double)first.matvecs > opts->switch_back * (double)rec->ref_mv)
+        rec->force_rgcrot = true;
+    }
+    return finish(rc, KRS_SOLVER_RBICGSTAB);
   }
   // rBiCGStab failed: solve this system again with rGCROT (switch back)
+  rec->ref_mv = 0;
   rc = krs::gmres_rgcrot(ctx, A, M, rec, true, b, x, opts, ws, ws_bytes, stats);
   if (stats) {
     stats->matvecs += first.matvecs;
     stats->time_ms += first.time_ms;
     stats->bytes_model += first.bytes_model;
   }
-  return rc;
+  return finish(rc, KRS_SOLVER_RGCROT);
 }
 
 int krs_ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32,

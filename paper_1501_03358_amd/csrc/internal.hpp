@@ -67,6 +67,10 @@ struct krs_recycle {
   void* C = nullptr;
   int64_t ld = 0;
   int dim = 0;
+  // hybrid policy state (krs_hybrid_solve)
+  bool stale = false;            // A or M changed since C = A~ U
+  bool force_rgcrot = false;     // next hybrid system runs rGCROT
+  int64_t ref_mv = 0;            // matvecs of the first rBiCGStab system since rGCROT
 };
 
 namespace krs {

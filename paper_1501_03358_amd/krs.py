@@ -29,7 +29,7 @@ EXPORTS = (
     "krs_create", "krs_destroy", "krs_last_error", "krs_set_stream", "krs_matrix_create",
     "krs_matrix_destroy", "krs_precond_create", "krs_precond_workspace_size",
     "krs_precond_refresh", "krs_precond_destroy", "krs_recycle_create", "krs_recycle_destroy", "krs_recycle_dim",
-    "krs_recycle_set_dim", "krs_workspace_size", "krs_stencil_apply", "krs_precond_apply",
+    "krs_recycle_set_dim", "krs_recycle_mark_stale", "krs_workspace_size", "krs_stencil_apply", "krs_precond_apply",
     "krs_operator_apply", "krs_gmres", "krs_rgcrot_solve", "krs_rbicgstab_solve", "krs_recycle_update",
     "krs_hybrid_solve", "krs_ir_solve", "krs_version", "krs_timing_enable", "krs_timing_reset",
     "krs_timing_read",
@@ -54,7 +54,7 @@ class Opts(ctypes.Structure):
                 ("max_matvecs", ctypes.c_int64), ("div_factor", ctypes.c_double),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("history", ctypes.POINTER(ctypes.c_double)),
-                ("history_cap", ctypes.c_int64)]
+                ("history_cap", ctypes.c_int64), ("switch_back", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -64,7 +64,8 @@ class Stats(ctypes.Structure):
                 ("history_len", ctypes.c_int64), ("rel_res_true", ctypes.c_double),
                 ("rel_res_est", ctypes.c_double), ("time_ms", ctypes.c_double),
                 ("host_eig_ms", ctypes.c_double), ("bytes_model", ctypes.c_double),
-                ("second_passes", ctypes.c_int64)]
+                ("second_passes", ctypes.c_int64), ("solver", ctypes.c_int64),
+                ("refreshed", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -91,6 +92,7 @@ def _declare(L):
         "krs_recycle_destroy": (None, [P]),
         "krs_recycle_dim": (i32, [P]),
         "krs_recycle_set_dim": (i32, [P, i32]),
+        "krs_recycle_mark_stale": (i32, [P]),
         "krs_workspace_size": (i32, [i32, i64, i32, i32, i32, ctypes.POINTER(sz)]),
         "krs_stencil_apply": (i32, [P, P, P, P, dbl, dbl, P]),
         "krs_precond_apply": (i32, [P, P, P, P]),
@@ -254,6 +256,12 @@ class Recycle:
         if rc != OK:
             raise KrsError(rc, "bad recycle dimension")
 
+    def mark_stale(self):
+        """A or M changed: the next hybrid solve re-forms C = qr(A~ U).Q first."""
+        rc = lib().krs_recycle_mark_stale(self.h)
+        if rc != OK:
+            raise KrsError(rc, "krs_recycle_mark_stale")
+
     def views(self):
         k = self.dim
         return self.U[:k, :self.n].T, self.C[:k, :self.n].T
@@ -288,8 +296,10 @@ class Workspace:
 
 
 def make_opts(m=30, k=20, tol=1e-8, max_matvecs=2000, update_recycle=True, inner_solver=None,
-              div_factor=1e2, inner_tol=1e-5, max_outer=20, history=None, flags=0):
+              div_factor=1e2, inner_tol=1e-5, max_outer=20, history=None, flags=0,
+              switch_back=0.0):
     o = Opts()
+    o.switch_back = switch_back
     o.flags = flags
     o.m, o.k, o.update_recycle = m, k, 1 if update_recycle else 0
     o.inner_solver = SOLVER_RGCROT if inner_solver is None else inner_solver

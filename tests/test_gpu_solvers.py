@@ -299,3 +299,57 @@ def test_edge_cases(gpu_lib):
     bc = (C @ torch.tensor([1.0, -2.0, 0.5, 3.0], dtype=torch.float64, device=d.dev)).contiguous()
     rc, st = krs.rbicgstab_solve(d.ctx, d.A, d.M, rec, bc, x, krs.make_opts(tol=1e-10), d.ws)
     assert rc == krs.OK and st.iterations == 0
+
+
+def test_hybrid_changing_matrix_and_switch_back(gpu_lib):
+    """Sequence on two different 32^3 porous media (the matrix changes at
+    system 5): the space is marked stale and re-formed (line 1a) before the
+    next solve, the poor convergence that follows makes the next system run
+    rGCROT (switch back, Sec. 2.4).  The solver chosen at every step, the
+    re-forming, the iteration counts and x match the oracle."""
+    krs = gpu_lib
+    params = dict(tile=8, overlap=1, local_sweeps=5, omega_local=6 / 7, global_sweeps=1,
+                  omega_global=6 / 7)
+    p1 = W.porous_problem(32, extra=11)
+    p2 = W.porous_problem(32, extra=12)
+    d = Dev(krs, p1, "schwarz", params, m=30, k=20)
+    rec = krs.Recycle(d.ctx, p1.n, 20, torch.float64)
+    bs = list(W.rhs_ar1(p1, 9, extra=11))
+    o1, o2 = oracle_ops(p1, "schwarz", params), oracle_ops(p2, "schwarz", params)
+    orec, ost = K.Recycle.empty(p1.n), K.HybridState()
+    names = {krs.SOLVER_RGCROT: "rgcrot", krs.SOLVER_RBICGSTAB: "rbicgstab"}
+    seq = []
+    for t, b in enumerate(bs):
+        A, Mi, op = o1 if t < 5 else o2
+        if t == 5:
+            d.bands.copy_(torch.from_numpy(p2.bands).to(d.dev))
+            d.M.refresh()
+            rec.mark_stale()
+            ost.stale = True
+        x = d.empty()
+        rc, st = krs.hybrid_solve(d.ctx, d.A, d.M, rec, t, 2, d.vec(b), x,
+                                  krs.make_opts(m=30, k=20, tol=1e-8, switch_back=1.3), d.ws)
+        ref = K.hybrid_step(t, 2, op, Mi, b, 30, 20, 1e-8, orec, switch_back=1.3, state=ost)
+        assert rc == krs.OK and ref.status == K.CONVERGED
+        assert names[st.solver] == ref.solver, (t, names[st.solver], ref.solver)
+        assert bool(st.refreshed) == ref.refreshed
+        r = b - A(x.cpu().numpy())
+        assert np.linalg.norm(r) <= 1.5e-8 * np.linalg.norm(b)
+        if ref.solver == "rgcrot":
+            assert abs(st.iterations - ref.iterations) <= 2, (t, st.iterations, ref.iterations)
+            assert rel(x.cpu().numpy(), ref.x) <= X_TOL
+        else:
+            # with the poorly matched space after the change BiCGStab converges
+            # irregularly: the count must lie within 2 of the range of exits
+            # the oracle takes under rounding-level perturbations of b, and x
+            # within the oracle's own spread (1e-7 .. 1e-6 at tol 1e-8)
+            its = [ref.iterations]
+            if abs(st.iterations - ref.iterations) > 2:
+                its += [K.rbicgstab(op, Mi, b * (1 + eps), 1e-8, orec).iterations
+                        for eps in (1e-15, -1e-15, 2e-15, 1e-14, -1e-14, 1e-13, -1e-13)]
+            assert min(its) - 2 <= st.iterations <= max(its) + 2, (t, st.iterations, its)
+            assert rel(x.cpu().numpy(), ref.x) <= 1e-6
+        seq.append(ref.solver)
+        # the oracle continues from the GPU's recycle space (step-wise parity)
+        orec = recycle_to_oracle(rec)
+    assert seq[:2] == ["rgcrot"] * 2 and seq[5] == "rbicgstab" and seq[6] == "rgcrot", seq

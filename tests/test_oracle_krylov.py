@@ -341,3 +341,64 @@ def test_hybrid_switches_and_falls_back():
     # forced failure of rBiCGStab (tiny matvec budget) -> rGCROT re-solve
     r3 = K.hybrid_step(3, 2, op, Mi, bs[3], 12, 6, 1e-10, rec, max_its=3)
     assert r3.fallback
+
+
+def _two_porous(n=16):
+    params = dict(tile=8, overlap=1, local_sweeps=5, omega_local=6 / 7, global_sweeps=1,
+                  omega_global=6 / 7)
+    p1 = W.porous_problem(n, extra=61)
+    p2 = W.porous_problem(n, extra=62)
+    ops = []
+    for p in (p1, p2):
+        Mi = lambda v, p=p: precond.schwarz_jacobi(p.bands, p.shape, p.periodic, v, **params)
+        op = lambda v, p=p, Mi=Mi: stencil.apply(p.bands, p.shape, p.periodic, Mi(v))
+        ops.append((p, Mi, op))
+    return ops
+
+
+def test_hybrid_stale_space_is_reformed_for_the_new_matrix():
+    """Alg. 3 line 1a when the matrix changed: after the hybrid step on the
+    new operator, A~_new U = C and C^T C = I hold, and the system converges."""
+    (p1, Mi1, op1), (p2, Mi2, op2) = _two_porous()
+    bs = list(W.rhs_ar1(p1, 4, extra=61))
+    rec, st = K.Recycle.empty(p1.n), K.HybridState()
+    for t in range(3):
+        K.hybrid_step(t, 2, op1, Mi1, bs[t], 20, 8, 1e-10, rec, state=st)
+    st.stale = True
+    res = K.hybrid_step(3, 2, op2, Mi2, bs[3], 20, 8, 1e-10, rec, state=st)
+    assert res.refreshed and res.solver == "rbicgstab" and res.status == K.CONVERGED
+    AU = np.column_stack([op2(rec.U[:, i]) for i in range(rec.dim)])
+    assert np.linalg.norm(AU - rec.C) <= 1e-10 * np.linalg.norm(rec.C)
+    assert np.linalg.norm(rec.C.T @ rec.C - np.eye(rec.dim)) <= 1e-12
+    A2 = lambda v: stencil.apply(p2.bands, p2.shape, p2.periodic, v)
+    assert np.linalg.norm(bs[3] - A2(res.x)) <= 2e-10 * np.linalg.norm(bs[3])
+
+
+def test_hybrid_switches_back_after_poor_convergence():
+    """Sec. 2.4 switch back: a converged rBiCGStab system needing more than
+    switch_back times the matvecs of the first one since rGCROT makes the next
+    system run rGCROT; the reference restarts after it."""
+    (p1, Mi1, op1), (p2, Mi2, op2) = _two_porous()
+    bs = list(W.rhs_ar1(p1, 8, extra=63))
+    rec, st = K.Recycle.empty(p1.n), K.HybridState()
+    seq, mvs, ref = [], [], 0
+    expect_rg = False
+    for t, b in enumerate(bs):
+        op, Mi = (op1, Mi1) if t < 4 else (op2, Mi2)
+        if t == 4:
+            st.stale = True
+        res = K.hybrid_step(t, 2, op, Mi, b, 20, 8, 1e-10, rec, switch_back=1.3, state=st)
+        seq.append(res.solver)
+        assert res.status == K.CONVERGED
+        want = "rgcrot" if (t < 2 or expect_rg) else "rbicgstab"
+        assert res.solver == want, (t, seq)
+        if want == "rgcrot":
+            ref, expect_rg = 0, False
+        elif ref == 0:
+            ref = res.matvecs
+        else:
+            expect_rg = res.matvecs > 1.3 * ref
+        mvs.append(res.matvecs)
+    # the new matrix with the old (re-formed) space converged poorly, and the
+    # policy reacted within the sequence
+    assert "rgcrot" in seq[5:], (seq, mvs)
