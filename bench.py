@@ -236,10 +236,17 @@ def seq_main(args):
 
     dev = torch.device("cuda:0")
     channel = args.workload == "channel128"
+    changing = args.workload == "porous128_changing"
     n = args.n if args.n != 256 else 128
     steps = args.steps if args.steps is not None else (50 if channel else 100)
     t0 = time.time()
     prob = W.channel_problem(n) if channel else W.porous_problem(n, seed_cfg=3)
+    # changing matrix: the solid conductivity drifts by 10% every
+    # `change_every` systems (same pore geometry)
+    probs_t = None
+    if changing:
+        probs_t = {c: W.porous_problem(n, seed_cfg=3, k_solid=1e-3 * (1.1 ** c))
+                   for c in range((steps + args.change_every - 1) // args.change_every)}
     gen = W.rhs_ar1(prob, steps, seed_cfg=2 if channel else 3)
     bs = [torch.from_numpy(next(gen)).to(dev) for _ in range(steps)]
     log(f"[bench] inputs: {prob.name} N={prob.n}, {steps} systems ({time.time() - t0:.1f}s)")
@@ -252,6 +259,16 @@ def seq_main(args):
                      dtype=torch.uint8, device=dev)
     x = torch.zeros(prob.n, dtype=torch.float64, device=dev)
 
+    def set_matrix(i, rec):
+        """changing workload: load the bands of system i's matrix if new."""
+        if not changing or i % args.change_every != 0:
+            return False
+        bands.copy_(torch.from_numpy(probs_t[i // args.change_every].bands))
+        Mp.refresh()
+        if rec is not None:
+            rec.mark_stale()
+        return True
+
     def run(name, solve):
         rec = krs.Recycle(ctx, prob.n, K, torch.float64)
         krs.timing_reset(ctx)
@@ -261,6 +278,9 @@ def seq_main(args):
         t = time.perf_counter()
         for i in range(steps):
             s0 = time.perf_counter()
+            changed = set_matrix(i, rec if name.startswith("hybrid") else None)
+            if changed and name == "rgcrot" and rec.dim > 0:
+                krs.recycle_update(ctx, A, Mp, rec, ws)   # line 1a for the new matrix
             rc, st = solve(rec, i, bs[i])
             lat.append((time.perf_counter() - s0) * 1e3)
             mvs.append(st.matvecs)
@@ -268,9 +288,10 @@ def seq_main(args):
             byt += st.bytes_model
             sp += st.second_passes
             bad += rc != 0
-            if i < 3 or i == steps - 1 or rc != 0:
+            if i < 3 or i == steps - 1 or rc != 0 or changed:
                 log(f"[bench] {name} step {i}: status {rc} matvecs {st.matvecs} "
-                    f"rel_res {st.rel_res_true:.2e} {lat[-1]:.0f} ms")
+                    f"rel_res {st.rel_res_true:.2e} {lat[-1]:.0f} ms"
+                    + (" (new matrix)" if changed else ""))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         krs.timing_enable(ctx, False)
@@ -296,6 +317,11 @@ def seq_main(args):
     else:
         res["hybrid"], kt = run("hybrid", lambda rec, i, b: krs.hybrid_solve(
             ctx, A, Mp, rec, i, args.n_switch, b, x, opts(), ws))
+        if changing:
+            res["hybrid_switch_back"], _ = run("hybrid_switch_back", lambda rec, i, b: (
+                krs.hybrid_solve(ctx, A, Mp, rec, i, args.n_switch, b, x,
+                                 krs.make_opts(m=M, k=K, tol=1e-8, max_matvecs=6000,
+                                               switch_back=1.3), ws)))
         main_name, other = "hybrid", "bicgstab"
         if args.hybrid_only:
             other = "hybrid"
@@ -333,8 +359,11 @@ def seq_main(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["porous_ir", "serve", "channel128", "porous128"],
+    ap.add_argument("--workload", choices=["porous_ir", "serve", "channel128", "porous128",
+                                           "porous128_changing"],
                     default="porous_ir")
+    ap.add_argument("--change-every", type=int, default=10,
+                    help="porous128_changing: systems per matrix")
     ap.add_argument("--matrices", type=int, default=64, help="serve: number of matrices")
     ap.add_argument("--grids", default="32,64,96,128,192", help="serve: grid sizes per axis")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent solves")
@@ -373,7 +402,7 @@ def main():
     if args.workload == "serve":
         serve_main(args)
         return
-    if args.workload in ("channel128", "porous128"):
+    if args.workload in ("channel128", "porous128", "porous128_changing"):
         seq_main(args)
         return
     if args.calibrate_copy:
