@@ -13,6 +13,13 @@ problem is A restricted to the extended tile with zero values outside it; the
 local sweeps start from zero; each cell takes the value computed by the tile
 that owns it (restricted additive Schwarz); the global sweep is damped Jacobi
 on the full operator started from that value.
+
+The paper's alternative local smoother is SSOR (Sec. 2.1, and the porous
+medium tables of Sec. 3 comparing the two).  Reading: one SSOR iteration is a
+forward SOR sweep followed by a backward one over the extended tile, with
+the cells ordered by colour (x + y + z of the extended-tile position even,
+then odd; backward: odd, then even) so that each colour is updated at once;
+relaxation omega_local (1 = symmetric Gauss-Seidel).
 """
 import numpy as np
 
@@ -42,8 +49,13 @@ def _axis_windows(n, tile, overlap, periodic):
 
 
 def schwarz_jacobi(bands, shape, periodic, r, tile=8, overlap=1, local_sweeps=5,
-                   omega_local=6.0 / 7.0, global_sweeps=1, omega_global=6.0 / 7.0):
-    """Two-level Schwarz-Jacobi preconditioner applied to r."""
+                   omega_local=6.0 / 7.0, global_sweeps=1, omega_global=6.0 / 7.0,
+                   local_solver="jacobi"):
+    """Two-level Schwarz preconditioner applied to r: `local_sweeps` damped
+    Jacobi sweeps (local_solver="jacobi") or SSOR iterations ("ssor") on every
+    extended tile, restricted write-back, then global damped Jacobi sweeps."""
+    if local_solver not in ("jacobi", "ssor"):
+        raise ValueError(local_solver)
     nx, ny, nz = shape
     ix, vx = _axis_windows(nx, tile, overlap, periodic[0])
     iy, vy = _axis_windows(ny, tile, overlap, periodic[1])
@@ -62,11 +74,12 @@ def schwarz_jacobi(bands, shape, periodic, r, tile=8, overlap=1, local_sweeps=5,
     bs = np.where(valid[None], bands[:, g], 0.0)
     diag = np.where(valid, bs[0], 1.0)
 
-    # local damped Jacobi sweeps on every extended tile, starting from zero;
-    # neighbours outside the extended tile count as zero
+    # local sweeps on every extended tile, starting from zero; neighbours
+    # outside the extended tile count as zero
     z = np.zeros_like(rs)
     nbrs = ((1, 5, -1), (2, 5, +1), (3, 4, -1), (4, 4, +1), (5, 3, -1), (6, 3, +1))
-    for _ in range(local_sweeps):
+
+    def a_times(z):
         az = bs[0] * z
         for band, ax, off in nbrs:
             nb = np.zeros_like(z)
@@ -80,7 +93,18 @@ def schwarz_jacobi(bands, shape, periodic, r, tile=8, overlap=1, local_sweeps=5,
                 src[ax] = slice(0, E - 1)
             nb[tuple(dst)] = z[tuple(src)]
             az = az + bs[band] * nb
-        z = z + omega_local * (rs - az) / diag
+        return az
+
+    if local_solver == "jacobi":
+        for _ in range(local_sweeps):
+            z = z + omega_local * (rs - a_times(z)) / diag
+    else:
+        e = np.arange(E)
+        colour = (e[:, None, None] + e[None, :, None] + e[None, None, :]) % 2   # [ez, ey, ex]
+        for _ in range(local_sweeps):
+            for c in (0, 1, 1, 0):            # forward sweep, then backward sweep
+                upd = z + omega_local * (rs - a_times(z)) / diag
+                z = np.where(colour == c, upd, z)
     # restricted write-back: each tile provides its owned cells
     own = slice(overlap, overlap + tile)
     zo = z[:, :, :, own, own, own]                    # [tz, ty, tx, T, T, T]

@@ -121,3 +121,79 @@ def test_periodic_axis_must_exceed_extended_tile():
     bands, _, periodic = _random_problem(shape, bc, 6)
     with pytest.raises(ValueError):
         precond.schwarz_jacobi(bands, shape, periodic, np.ones(512), tile=4, overlap=2)
+
+
+def _dense_schwarz_ssor(A, shape, periodic, r, tile, overlap, sweeps, w, gsweeps, wg):
+    """Restricted additive Schwarz with SSOR local solves written out cell by
+    cell: Gauss-Seidel with relaxation w over the cells of each extended tile
+    in the order even colour then odd colour (forward), odd then even
+    (backward), colour = parity of the extended-tile position."""
+    nx, ny, nz = shape
+    dims = (nx, ny, nz)
+    z = np.zeros(A.shape[0])
+    tiles = [range(d // tile) for d in dims]
+    for t in itertools.product(*tiles):
+        ext = []
+        for e in itertools.product(*[range(-overlap, tile + overlap)] * 3):
+            c = [t[a] * tile + e[a] for a in range(3)]
+            ok = True
+            for a in range(3):
+                if periodic[a]:
+                    c[a] %= dims[a]
+                elif not 0 <= c[a] < dims[a]:
+                    ok = False
+            if ok:
+                owned = all(0 <= e[a] < tile for a in range(3))
+                colour = (e[0] + e[1] + e[2] + 3 * overlap) % 2
+                ext.append((c[0] + nx * (c[1] + ny * c[2]), owned, colour))
+        idx = [g for g, _, _ in ext]
+        R = np.zeros((len(idx), A.shape[0]))
+        R[np.arange(len(idx)), idx] = 1.0
+        As = R @ A @ R.T
+        rs = R @ r
+        zs = np.zeros(len(idx))
+        even = [i for i, (_, _, c) in enumerate(ext) if c == 0]
+        odd = [i for i, (_, _, c) in enumerate(ext) if c == 1]
+        for _ in range(sweeps):
+            for i in even + odd + odd[::-1] + even[::-1]:
+                zs[i] += w * (rs[i] - As[i] @ zs) / As[i, i]
+        for (g, owned, _), val in zip(ext, zs):
+            if owned:
+                z[g] = val
+    D = np.diag(A)
+    for _ in range(gsweeps):
+        z = z + wg * (r - A @ z) / D
+    return z
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("w", [1.0, 1.3])
+def test_ssor_local_solver_matches_cellwise_gauss_seidel(case, w):
+    shape, bc, tile, overlap = CASES[case]
+    bands, A, periodic = _random_problem(shape, bc, 200 + case)
+    r = np.random.default_rng(17).standard_normal(A.shape[0])
+    z = precond.schwarz_jacobi(bands, shape, periodic, r, tile=tile, overlap=overlap,
+                               local_sweeps=3, omega_local=w, global_sweeps=1,
+                               omega_global=6 / 7, local_solver="ssor")
+    ref = _dense_schwarz_ssor(A, shape, periodic, r, tile, overlap, 3, w, 1, 6 / 7)
+    assert np.linalg.norm(z - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_ssor_single_tile_converges_to_inverse():
+    """Symmetric Gauss-Seidel on one tile covering the grid converges to A^-1 r
+    (and faster than damped Jacobi)."""
+    shape = (8, 8, 8)
+    bc = {'x': ('dirichlet', 'dirichlet'), 'y': ('dirichlet', 'dirichlet'),
+          'z': ('dirichlet', 'dirichlet')}
+    bands, A, periodic = _random_problem(shape, bc, 24)
+    r = np.random.default_rng(25).standard_normal(A.shape[0])
+    ref = np.linalg.solve(A, r)
+    z = precond.schwarz_jacobi(bands, shape, periodic, r, tile=8, overlap=0,
+                               local_sweeps=400, omega_local=1.0, global_sweeps=0,
+                               local_solver="ssor")
+    assert np.linalg.norm(z - ref) <= 1e-10 * np.linalg.norm(ref)
+    zs = precond.schwarz_jacobi(bands, shape, periodic, r, tile=8, overlap=0, local_sweeps=5,
+                                omega_local=1.0, global_sweeps=0, local_solver="ssor")
+    zj = precond.schwarz_jacobi(bands, shape, periodic, r, tile=8, overlap=0, local_sweeps=10,
+                                omega_local=1.0, global_sweeps=0)
+    assert np.linalg.norm(zs - ref) < np.linalg.norm(zj - ref)
