@@ -91,20 +91,28 @@ typedef struct krs_grid {
   int32_t periodic[3];   /* nonzero: axis x / y / z wraps */
 } krs_grid;
 
+/* Local smoother of the Schwarz preconditioner (Sec. 2.1: Jacobi or SSOR). */
+typedef enum krs_local_solver {
+  KRS_LOCAL_JACOBI = 0,  /* damped Jacobi sweeps (factor omega_local) */
+  KRS_LOCAL_SSOR = 1     /* SSOR iterations (relaxation omega_local): a forward SOR sweep
+                            over the even-parity cells of the extended tile, then the odd
+                            ones, and a backward sweep odd then even */
+} krs_local_solver;
+
 /* Preconditioner (Sec. 2.1, "Preconditioners in GenIDLEST"): cubic tiles of
  * `tile` owned cells per axis (4 or 8; grid sizes must be multiples; a
  * periodic axis must be longer than tile + 2*overlap), extended by `overlap`
- * (= 1) cells; `local_sweeps` damped Jacobi sweeps (factor omega_local) from
- * zero on each extended tile with zero values outside it; every cell keeps
- * the value of the tile owning it; then `global_sweeps` damped point-Jacobi
- * sweeps (factor omega_global) on the whole grid. */
+ * (= 1) cells; `local_sweeps` iterations of the local smoother from zero on
+ * each extended tile with zero values outside it; every cell keeps the value
+ * of the tile owning it; then `global_sweeps` damped point-Jacobi sweeps
+ * (factor omega_global) on the whole grid. */
 typedef struct krs_precond_desc {
   int32_t type;            /* krs_pc_type */
   int32_t tile;
   int32_t overlap;
   int32_t local_sweeps;
   int32_t global_sweeps;
-  int32_t reserved;
+  int32_t local_solver;    /* krs_local_solver */
   double omega_local;
   double omega_global;
 } krs_precond_desc;

@@ -141,6 +141,8 @@ int krs_precond_create(krs_ctx* ctx, const krs_matrix* A, const krs_precond_desc
     if (d->overlap != 1) return set_err(ctx, KRS_ERR_ARG, "overlap must be 1");
     if (d->local_sweeps < 0 || d->global_sweeps < 0)
       return set_err(ctx, KRS_ERR_ARG, "sweep counts must be >= 0");
+    if (d->local_solver != KRS_LOCAL_JACOBI && d->local_solver != KRS_LOCAL_SSOR)
+      return set_err(ctx, KRS_ERR_ARG, "unknown local solver");
     const int64_t dims[3] = {A->g.nx, A->g.ny, A->g.nz};
     for (int a = 0; a < 3; ++a) {
       if (dims[a] % d->tile)

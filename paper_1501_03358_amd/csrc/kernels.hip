@@ -494,7 +494,7 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_pack(Grid3 g, const T* __r
 // grid.  One block per tile; the BR^3 tiles of a brick are consecutive blocks
 // (after the XCD remap, on one XCD), so the cells they share come from L2.
 // The extended tile lives in LDS with a zero border, double-buffered.
-template <class T, int TILE, int BR>
+template <class T, int TILE, int BR, bool SSOR>
 __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T* __restrict__ pk,
                                                                const T* __restrict__ r,
                                                                T* __restrict__ z, T omega,
@@ -548,13 +548,52 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T*
     }
   }
   __syncthreads();
+  const T keep = T(1) - omega;
+  if constexpr (SSOR) {
+    // in place, one colour at a time (cells of one colour are not coupled):
+    // forward even, odd; backward odd, even; the first update of each even
+    // cell sees zeros, as from the zero start
+    unsigned odd = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + kThreads * q;
+      if (e < NE && ((e % E + (e / E) % E + e / (E * E)) & 1)) odd |= 1u << q;
+    }
+    for (int s = 0; s < sweeps; ++s) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const unsigned want = (h == 1 || h == 2) ? 1u : 0u;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int e = threadIdx.x + kThreads * q;
+          if (e < NE && ((odd >> q) & 1u) == want) {
+            const int l = li[q];
+            T v = keep * zs[l] + d0[q];
+            v -= cf[q][0] * zs[l - 1];
+            v -= cf[q][1] * zs[l + 1];
+            v -= cf[q][2] * zs[l - P];
+            v -= cf[q][3] * zs[l + P];
+            v -= cf[q][4] * zs[l - P * P];
+            v -= cf[q][5] * zs[l + P * P];
+            zs[l] = v;
+          }
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + kThreads * q;
+      if (e < NE && ((ownm >> q) & 1u)) z[gi[q]] = zs[li[q]];
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + kThreads * q;
     if (e < NE) zs[li[q]] = d0[q];
   }
   __syncthreads();
-  const T keep = T(1) - omega;
   int cur = 0;
   for (int s = 1; s < sweeps; ++s) {
     const T* zc = zs + cur * NP;
@@ -1560,15 +1599,22 @@ hipError_t schwarz_pack(hipStream_t s, const Grid3& g, int tile, const T* bands,
 
 template <class T>
 hipError_t schwarz_local_packed(hipStream_t s, const Grid3& g, int tile, const T* pk, const T* r,
-                                T* z, double omega, int sweeps) {
+                                T* z, double omega, int sweeps, bool ssor) {
   const int ntx = g.nx / tile, nty = g.ny / tile, ntz = g.nz / tile;
   const int nt = ntx * nty * ntz;
   if (nt == 0) return hipSuccess;
   if (sweeps < 1) return hipErrorInvalidValue;
   const int br = schwarz_brick(g, tile);
   const int nbx = ntx / br, nby = nty / br;
-#define KRS_LOCAL(TL, B)                                                                       \
-  k_schwarz_local_pk<T, TL, B><<<nt, kThreads, 0, s>>>(g, pk, r, z, (T)omega, sweeps, nbx, nby)
+#define KRS_LOCAL(TL, B)                                                                        \
+  do {                                                                                          \
+    if (ssor)                                                                                   \
+      k_schwarz_local_pk<T, TL, B, true><<<nt, kThreads, 0, s>>>(g, pk, r, z, (T)omega, sweeps, \
+                                                                 nbx, nby);                     \
+    else                                                                                        \
+      k_schwarz_local_pk<T, TL, B, false><<<nt, kThreads, 0, s>>>(g, pk, r, z, (T)omega,        \
+                                                                  sweeps, nbx, nby);            \
+  } while (0)
   if (tile == 8 && br == 2) KRS_LOCAL(8, 2);
   else if (tile == 8) KRS_LOCAL(8, 1);
   else if (tile == 4 && br == 2) KRS_LOCAL(4, 2);
@@ -1872,7 +1918,7 @@ hipError_t axpy_f32_into_f64(hipStream_t s, const float* d, double* x, int64_t n
                                        double, int);                                              \
   template hipError_t schwarz_pack<T>(hipStream_t, const Grid3&, int, const T*, T*, double);      \
   template hipError_t schwarz_local_packed<T>(hipStream_t, const Grid3&, int, const T*, const T*, \
-                                              T*, double, int);                                   \
+                                              T*, double, int, bool);                             \
   template hipError_t block_dot<T>(hipStream_t, const Cols<T>&, const T*, int64_t, int, T*, int); \
   template hipError_t block_update<T>(hipStream_t, const Cols<T>&, const double*, double,         \
                                       const T*, T*, int64_t, const double*, int, T*, int);        \

@@ -86,7 +86,7 @@ hipError_t schwarz_pack(hipStream_t s, const Grid3& g, int tile, const T* bands,
 // Local Schwarz-Jacobi from the packed coefficients (omega must match the pack).
 template <class T>
 hipError_t schwarz_local_packed(hipStream_t s, const Grid3& g, int tile, const T* pk, const T* r,
-                                T* z, double omega, int sweeps);
+                                T* z, double omega, int sweeps, bool ssor = false);
 
 // partials[c*nblk + blk] = sum_rows Q_c * w  (c < ncols), then w.w if self_dot
 template <class T>

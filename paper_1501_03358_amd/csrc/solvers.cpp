@@ -56,7 +56,8 @@ struct Op {
     if (M->d.local_sweeps > 0 && M->pack) {
       KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, 9 * NW,
                  schwarz_local_packed<T>(s, g, M->d.tile, (const T*)M->pack, r, first,
-                                         M->d.omega_local, M->d.local_sweeps));
+                                         M->d.omega_local, M->d.local_sweeps,
+                                         M->d.local_solver == KRS_LOCAL_SSOR));
     } else if (M->d.local_sweeps > 0) {
       KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, 9 * NW,
                  schwarz_local<T>(s, g, M->d.tile, bands(), r, first, M->d.omega_local,
@@ -86,7 +87,8 @@ struct Op {
       if (M->d.local_sweeps > 0 && M->pack) {
         KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, 9 * NW,
                    schwarz_local_packed<T>(s, g, M->d.tile, (const T*)M->pack, v, z,
-                                           M->d.omega_local, M->d.local_sweeps));
+                                           M->d.omega_local, M->d.local_sweeps,
+                                           M->d.local_solver == KRS_LOCAL_SSOR));
       } else if (M->d.local_sweeps > 0) {
         KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, 9 * NW,
                    schwarz_local<T>(s, g, M->d.tile, bands(), v, z, M->d.omega_local,

@@ -21,6 +21,7 @@ ERR_ARG, ERR_HIP, ERR_WORKSPACE, ERR_STATE, ERR_EIG = -1, -2, -3, -4, -5
 F64, F32 = 0, 1
 SOLVER_GMRES, SOLVER_RGCROT, SOLVER_RBICGSTAB, SOLVER_IR = 0, 1, 2, 3
 PC_NONE, PC_JACOBI, PC_SCHWARZ_JACOBI = 0, 1, 2
+LOCAL_JACOBI, LOCAL_SSOR = 0, 1
 FLAG_TRUST_ESTIMATE = 1
 FLAG_HOST_LOOP = 2
 FLAG_GRAPH = 4
@@ -44,7 +45,7 @@ class Grid(ctypes.Structure):
 class PrecondDesc(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("tile", ctypes.c_int32), ("overlap", ctypes.c_int32),
                 ("local_sweeps", ctypes.c_int32), ("global_sweeps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("omega_local", ctypes.c_double),
+                ("local_solver", ctypes.c_int32), ("omega_local", ctypes.c_double),
                 ("omega_global", ctypes.c_double)]
 
 
@@ -210,10 +211,12 @@ class Matrix:
 
 class Precond:
     def __init__(self, ctx, A, kind="schwarz", tile=8, overlap=1, local_sweeps=5,
-                 omega_local=6.0 / 7.0, global_sweeps=1, omega_global=6.0 / 7.0):
+                 omega_local=6.0 / 7.0, global_sweeps=1, omega_global=6.0 / 7.0,
+                 local_solver="jacobi"):
         t = {"none": PC_NONE, "jacobi": PC_JACOBI, "schwarz": PC_SCHWARZ_JACOBI}[kind]
+        ls = {"jacobi": LOCAL_JACOBI, "ssor": LOCAL_SSOR}[local_solver]
         self.ctx, self.A = ctx, A
-        self.desc = PrecondDesc(t, tile, overlap, local_sweeps, global_sweeps, 0, omega_local,
+        self.desc = PrecondDesc(t, tile, overlap, local_sweeps, global_sweeps, ls, omega_local,
                                 omega_global)
         nbytes = lib().krs_precond_workspace_size(A.h, ctypes.byref(self.desc))
         self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=A.bands.device)

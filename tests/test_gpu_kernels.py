@@ -72,6 +72,13 @@ PC_CASES = [
     ("porous32_t8", lambda: W.porous_problem(32, extra=5), dict(tile=8)),
     ("grf8_t4_nosweep", lambda: W.grf_problem(8, extra=4), dict(tile=4, global_sweeps=0)),
     ("grf8_t4_2global", lambda: W.grf_problem(8, extra=4), dict(tile=4, global_sweeps=2)),
+    # SSOR local smoother (colour-ordered forward and backward sweeps)
+    ("grf16_t8_ssor", lambda: W.grf_problem(16, extra=3),
+     dict(tile=8, local_solver="ssor", omega_local=1.0)),
+    ("channel24_t8_ssor13", lambda: W.channel_problem(24),
+     dict(tile=8, local_solver="ssor", omega_local=1.3)),
+    ("porous32_t4_ssor", lambda: W.porous_problem(32, extra=5),
+     dict(tile=4, local_solver="ssor", omega_local=1.0, local_sweeps=3)),
 ]
 
 

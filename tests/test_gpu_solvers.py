@@ -353,3 +353,36 @@ def test_hybrid_changing_matrix_and_switch_back(gpu_lib):
         # the oracle continues from the GPU's recycle space (step-wise parity)
         orec = recycle_to_oracle(rec)
     assert seq[:2] == ["rgcrot"] * 2 and seq[5] == "rbicgstab" and seq[6] == "rgcrot", seq
+
+
+def test_hybrid_with_ssor_local_smoother(gpu_lib):
+    """Hybrid sequence with the SSOR local smoother (Sec. 2.1 alternative):
+    parity with the oracle using the same smoother, and fewer matvecs per
+    recycled system than with damped Jacobi on the same sequence."""
+    krs = gpu_lib
+    prob = W.porous_problem(32, extra=11)
+    bs = list(W.rhs_ar1(prob, 5, extra=11))
+    counts = {}
+    for smoother, w in (("jacobi", 6 / 7), ("ssor", 1.0)):
+        params = dict(tile=8, overlap=1, local_sweeps=5, omega_local=w, global_sweeps=1,
+                      omega_global=6 / 7, local_solver=smoother)
+        d = Dev(krs, prob, "schwarz", params, m=30, k=20)
+        rec = krs.Recycle(d.ctx, prob.n, 20, torch.float64)
+        A, Mi, op = oracle_ops(prob, "schwarz", params)
+        orec = K.Recycle.empty(prob.n)
+        mv = 0
+        for t, b in enumerate(bs):
+            x = d.empty()
+            rc, st = krs.hybrid_solve(d.ctx, d.A, d.M, rec, t, 2, d.vec(b), x,
+                                      krs.make_opts(m=30, k=20, tol=1e-8), d.ws)
+            ref = K.hybrid_step(t, 2, op, Mi, b, 30, 20, 1e-8, orec)
+            assert rc == krs.OK and ref.status == K.CONVERGED
+            r = b - A(x.cpu().numpy())
+            assert np.linalg.norm(r) <= 1.5e-8 * np.linalg.norm(b)
+            assert abs(st.iterations - ref.iterations) <= 2, (smoother, t)
+            assert rel(x.cpu().numpy(), ref.x) <= X_TOL
+            orec = recycle_to_oracle(rec)
+            if t >= 2:
+                mv += st.matvecs
+        counts[smoother] = mv
+    assert counts["ssor"] < counts["jacobi"], counts
