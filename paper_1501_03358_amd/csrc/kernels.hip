@@ -944,11 +944,12 @@ __global__ __launch_bounds__(kThreads) void k_block_dot_after_update(Cols<T> Q,
   reduce_store<T, NC + 1>(acc, nc + 1, partials, nblk);
 }
 
-// Gram partials X^T Y.  A block has 4 waves; each wave stages its own
-// kGramRows rows of every column in LDS (column-major, padded row stride) and
-// every lane accumulates up to two 4 x 4 tiles of (a, b) pairs in registers.
-// At the end the 4 waves' tiles are added in LDS in wave order.
-constexpr int kGramRows = 16;
+// Gram partials X^T Y.  A block streams its contiguous row range in tiles of
+// kGramRows rows: every column's rows are loaded coalesced (64 consecutive
+// rows per wave load) into LDS (column-major, padded row stride); each of the
+// up to 128 4 x 4 output tiles is accumulated by two threads, each over half
+// of the tile's rows, and the halves are added in LDS at the end.
+constexpr int kGramRows = 64;
 constexpr int kGramPad = kGramRows + 1;
 constexpr int kGramTile = 4;
 
@@ -959,40 +960,33 @@ __global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t
   const int na = X.n1 + X.n2, nb = Y.n1 + Y.n2;
   const int nta = (na + kGramTile - 1) / kGramTile, ntb = (nb + kGramTile - 1) / kGramTile;
   const int lda = nta * kGramTile, ldb = ntb * kGramTile;
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  T* xs = reinterpret_cast<T*>(smem_raw) + (size_t)wid * (lda + ldb) * kGramPad;
+  T* xs = reinterpret_cast<T*>(smem_raw);
   T* ys = xs + (size_t)lda * kGramPad;
-  T acc[2][kGramTile][kGramTile];
+  const int t = threadIdx.x;
+  const int tile = t % 128, half = t / 128;
+  const bool active = tile < nta * ntb;
+  const int ta = active ? tile / ntb : 0, tb = active ? tile % ntb : 0;
+  T acc[kGramTile][kGramTile];
 #pragma unroll
-  for (int q = 0; q < 2; ++q)
+  for (int i = 0; i < kGramTile; ++i)
 #pragma unroll
-    for (int i = 0; i < kGramTile; ++i)
-#pragma unroll
-      for (int j = 0; j < kGramTile; ++j) acc[q][i][j] = 0;
-  const int t0 = lane, t1 = lane + 64;
-  const int ta0 = t0 / ntb, tb0 = t0 % ntb, ta1 = t1 / ntb, tb1 = t1 % ntb;
-  const bool v0 = t0 < nta * ntb, v1 = t1 < nta * ntb;
-  const int64_t step = (int64_t)gridDim.x * 4 * kGramRows;
-  for (int64_t r0 = (int64_t)blockIdx.x * 4 * kGramRows; r0 < n; r0 += step) {
-    const int64_t rw = r0 + wid * kGramRows;
-    for (int idx = lane; idx < kGramRows * lda; idx += 64) {
+    for (int j = 0; j < kGramTile; ++j) acc[i][j] = 0;
+  const Range rg = block_range(n);
+  for (int64_t r0 = rg.v0; r0 < rg.v1; r0 += kGramRows) {
+    const int64_t rows = rg.v1 - r0;
+    for (int idx = t; idx < kGramRows * lda; idx += kThreads) {
       const int c = idx / kGramRows, rr = idx % kGramRows;
-      const int64_t i = rw + rr;
-      xs[c * kGramPad + rr] = (c < na && i < n) ? col_ptr(X, c)[i] : T(0);
+      xs[c * kGramPad + rr] = (c < na && rr < rows) ? col_ptr(X, c)[r0 + rr] : T(0);
     }
-    for (int idx = lane; idx < kGramRows * ldb; idx += 64) {
+    for (int idx = t; idx < kGramRows * ldb; idx += kThreads) {
       const int c = idx / kGramRows, rr = idx % kGramRows;
-      const int64_t i = rw + rr;
-      ys[c * kGramPad + rr] = (c < nb && i < n) ? col_ptr(Y, c)[i] : T(0);
+      ys[c * kGramPad + rr] = (c < nb && rr < rows) ? col_ptr(Y, c)[r0 + rr] : T(0);
     }
     __syncthreads();
+    if (active) {
+      const int rb = half * (kGramRows / 2);
 #pragma unroll 4
-    for (int rr = 0; rr < kGramRows; ++rr) {
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const bool v = q == 0 ? v0 : v1;
-        if (!v) continue;
-        const int ta = q == 0 ? ta0 : ta1, tb = q == 0 ? tb0 : tb1;
+      for (int rr = rb; rr < rb + kGramRows / 2; ++rr) {
         T xa[kGramTile], yb[kGramTile];
 #pragma unroll
         for (int i = 0; i < kGramTile; ++i) xa[i] = xs[(ta * kGramTile + i) * kGramPad + rr];
@@ -1001,34 +995,30 @@ __global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t
 #pragma unroll
         for (int i = 0; i < kGramTile; ++i)
 #pragma unroll
-          for (int j = 0; j < kGramTile; ++j) acc[q][i][j] += xa[i] * yb[j];
+          for (int j = 0; j < kGramTile; ++j) acc[i][j] += xa[i] * yb[j];
       }
     }
     __syncthreads();
   }
-  // add the 4 waves' tiles in wave order
+  // second half's tiles into LDS, added to the first half's in a fixed order
   T* red = reinterpret_cast<T*>(smem_raw);
-  for (int wv = 0; wv < 4; ++wv) {
-    if (wid == wv) {
+  if (active && half == 1) {
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const bool v = q == 0 ? v0 : v1;
-        if (!v) continue;
-        const int ta = q == 0 ? ta0 : ta1, tb = q == 0 ? tb0 : tb1;
+    for (int i = 0; i < kGramTile; ++i)
 #pragma unroll
-        for (int i = 0; i < kGramTile; ++i)
-#pragma unroll
-          for (int j = 0; j < kGramTile; ++j) {
-            const int idx = (ta * kGramTile + i) * ldb + tb * kGramTile + j;
-            red[idx] = (wv == 0 ? T(0) : red[idx]) + acc[q][i][j];
-          }
-      }
-    }
-    __syncthreads();
+      for (int j = 0; j < kGramTile; ++j)
+        red[(ta * kGramTile + i) * ldb + tb * kGramTile + j] = acc[i][j];
   }
-  for (int p = threadIdx.x; p < na * nb; p += kThreads) {
-    const int a = p / nb, b = p % nb;
-    partials[(int64_t)p * nblk + blockIdx.x] = red[a * ldb + b];
+  __syncthreads();
+  if (active && half == 0) {
+#pragma unroll
+    for (int i = 0; i < kGramTile; ++i)
+#pragma unroll
+      for (int j = 0; j < kGramTile; ++j) {
+        const int a = ta * kGramTile + i, b = tb * kGramTile + j;
+        const T v = acc[i][j] + red[a * ldb + b];
+        if (a < na && b < nb) partials[(int64_t)(a * nb + b) * nblk + blockIdx.x] = v;
+      }
   }
 }
 
@@ -1733,7 +1723,7 @@ hipError_t gram(hipStream_t s, const Cols<T>& X, const Cols<T>& Y, int64_t n, T*
   if (na == 0 || nb == 0) return hipSuccess;
   const int nta = (na + kGramTile - 1) / kGramTile, ntb = (nb + kGramTile - 1) / kGramTile;
   if (nta * ntb > 128) return hipErrorInvalidValue;   // two 4 x 4 tiles per lane
-  const size_t stage = sizeof(T) * 4 * kGramPad * kGramTile * (nta + ntb);
+  const size_t stage = sizeof(T) * kGramPad * kGramTile * (nta + ntb);
   const size_t red = sizeof(T) * kGramTile * kGramTile * nta * ntb;
   const size_t smem = stage > red ? stage : red;
   k_gram<T><<<nblk, kThreads, smem, s>>>(X, Y, n, partials, nblk);
