@@ -505,7 +505,24 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T*
   constexpr int NP = P * P * P;
   constexpr int EB = BR * TILE + 2;
   constexpr int NB = EB * EB * EB;
-  constexpr int PER = (NE + kThreads - 1) / kThreads;
+  // SSOR: a thread's cells are split by colour (slots 0 .. PC-1 even,
+  // PC .. 2 PC-1 odd), so that every lane works in every colour phase
+  constexpr int HALF = NE / 2, PC = (HALF + kThreads - 1) / kThreads;
+  constexpr int PER = SSOR ? 2 * PC : (NE + kThreads - 1) / kThreads;
+  static_assert(!SSOR || E % 2 == 0, "colours");
+  auto cell = [](int q) -> int {   // extended-tile index of this thread's slot q (or NE)
+    if constexpr (SSOR) {
+      const int c = q < PC ? 0 : 1;
+      const int k = threadIdx.x + kThreads * (q < PC ? q : q - PC);
+      if (k >= HALF) return NE;
+      const int row = k / (E / 2), j = k % (E / 2);
+      const int ey = row % E, ez = row / E;
+      const int ex = 2 * j + ((ey + ez + c) & 1);
+      return (ez * E + ey) * E + ex;
+    } else {
+      return threadIdx.x + kThreads * q;
+    }
+  };
   __shared__ T zs[2 * NP];
   for (int idx = threadIdx.x; idx < 2 * NP; idx += kThreads) zs[idx] = 0;
   const int lt = xcd_remap(blockIdx.x, gridDim.x);
@@ -522,7 +539,7 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T*
   unsigned ownm = 0;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + kThreads * q;
+    const int e = cell(q);
 #pragma unroll
     for (int d = 0; d < 6; ++d) cf[q][d] = 0;
     d0[q] = 0;
@@ -552,21 +569,22 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T*
   if constexpr (SSOR) {
     // in place, one colour at a time (cells of one colour are not coupled):
     // forward even, odd; backward odd, even; the first update of each even
-    // cell sees zeros, as from the zero start
-    unsigned odd = 0;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + kThreads * q;
-      if (e < NE && ((e % E + (e / E) % E + e / (E * E)) & 1)) odd |= 1u << q;
-    }
+    // cell sees zeros, as from the zero start.  With omega = 1 an update
+    // repeated right after one of the same colour reproduces it exactly (its
+    // inputs, the other colour, did not change), so it is skipped.
+    const bool gs = omega == T(1);
+    int last = -1;
     for (int s = 0; s < sweeps; ++s) {
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        const unsigned want = (h == 1 || h == 2) ? 1u : 0u;
+        const int colour = (h == 1 || h == 2) ? 1 : 0;
+        if (gs && colour == last) continue;
+        last = colour;
+        const int q0 = colour ? PC : 0;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int e = threadIdx.x + kThreads * q;
-          if (e < NE && ((odd >> q) & 1u) == want) {
+        for (int qq = 0; qq < PC; ++qq) {
+          const int q = q0 + qq;
+          if (cell(q) < NE) {
             const int l = li[q];
             T v = keep * zs[l] + d0[q];
             v -= cf[q][0] * zs[l - 1];
@@ -582,10 +600,8 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T*
       }
     }
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + kThreads * q;
-      if (e < NE && ((ownm >> q) & 1u)) z[gi[q]] = zs[li[q]];
-    }
+    for (int q = 0; q < PER; ++q)
+      if (cell(q) < NE && ((ownm >> q) & 1u)) z[gi[q]] = zs[li[q]];
     return;
   }
 #pragma unroll
