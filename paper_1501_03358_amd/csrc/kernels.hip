@@ -1241,23 +1241,6 @@ __global__ __launch_bounds__(kThreads) void k_bicg_p(const T* __restrict__ r, T*
   if (i < n) p[i] = r[i] + beta * (p[i] - omega * v[i]);
 }
 
-__global__ void k_bicg_alpha(const double* sums, int kc, double* sc, int off_eta1, int off_ctrt) {
-  if (threadIdx.x != 0 || sc[kDone] != 0.0) return;
-  double corr = 0;
-  for (int c = 0; c < kc; ++c) {
-    sc[off_eta1 + c] = sums[c];
-    corr += sc[off_ctrt + c] * sums[c];
-  }
-  const double rtv = sums[kc] - corr;
-  sc[kRtv] = rtv;
-  if (rtv == 0.0 || !isfinite(rtv)) {
-    sc[kAlpha] = 0.0;   // breakdown: leave s = r, the host stops
-    sc[kFlag] = 1.0;
-  } else {
-    sc[kAlpha] = sc[kRho] / rtv;
-  }
-}
-
 template <class T, int W, int NC>
 __device__ __forceinline__ void sv_rows(const Cols<T>& C, const T* cf, T alpha,
                                         const T* __restrict__ r, T* v, T* __restrict__ sv,
@@ -1309,26 +1292,6 @@ __global__ __launch_bounds__(kThreads) void k_bicg_sv(Cols<T> C, const T* __rest
   if (W > 1 && blockIdx.x == gridDim.x - 1)
     sv_rows<T, 1, NC>(C, cf, alpha, r, v, sv, npk * W + threadIdx.x, n, acc[0]);
   reduce_store<T, 1>(acc, 1, partials, nblk);
-}
-
-__global__ void k_bicg_omega(const double* sums, int kc, double* sc, int off_eta1, int off_eta2,
-                             int off_xi) {
-  if (threadIdx.x != 0 || sc[kDone] != 0.0) return;
-  double q = 0;
-  for (int c = 0; c < kc; ++c) {
-    sc[off_eta2 + c] = sums[c];
-    q += sums[c] * sums[c];
-  }
-  const double ts = sums[kc];
-  const double tt = sums[kc + 1] - q;  // |t - C eta2|^2 with C^T C = I
-  sc[kTs] = ts;
-  sc[kTt] = tt;
-  double omega = 0.0;  // t = 0 (breakdown): y += alpha p, r = s, the host stops
-  if (tt > 0.0 && isfinite(tt)) omega = ts / tt;
-  else sc[kFlag] = 2.0;
-  sc[kOmega] = omega;
-  const double alpha = sc[kAlpha];
-  for (int c = 0; c < kc; ++c) sc[off_xi + c] += alpha * sc[off_eta1 + c] + omega * sc[off_eta2 + c];
 }
 
 template <class T, int W, int NC>
@@ -1390,20 +1353,117 @@ __global__ __launch_bounds__(kThreads) void k_bicg_yr(Cols<T> C, const T* __rest
   reduce_store<T, 2>(acc, 2, partials, nblk);
 }
 
-__global__ void k_bicg_rho(const double* sums, double* sc) {
-  if (threadIdx.x != 0 || sc[kDone] != 0.0) return;
-  const double rho = sums[0];
-  sc[kRnorm2] = sums[1];
-  sc[kRhoOld] = sc[kRho];
-  sc[kBeta] = sc[kOmega] != 0.0 ? (rho / sc[kRho]) * (sc[kAlpha] / sc[kOmega]) : 0.0;
-  sc[kRho] = rho;
+__device__ inline void hist_push(double* sc, double v) {
+  const int h = (int)sc[kHlen];
+  sc[kHistOff + h % kHistRing] = v;
+  sc[kHlen] = h + 1;
 }
 
+// ---------------------------------------------------------------------------
+// BiCGStab finishing reductions fused with the scalar step that consumes them
+// (one launch instead of two).  One block: wave w sums columns w, w+4, ...
+// of the per-block partials (lane-strided, fixed order, FP64) into out[];
+// then thread 0 runs the scalar step.  Every kernel returns at once when the
+// device-side stop state is set.
+// ---------------------------------------------------------------------------
+// Column sums go to `out` (device memory, for the host) and to `sh` (LDS):
+// the scalar step reads them from LDS, never back from memory it wrote in
+// this kernel.
+constexpr int kFinishCols = 72;
+
 template <class T>
-__global__ __launch_bounds__(kThreads) void k_bicg_exit_s(const T* __restrict__ p, T* y,
-                                                          const T* __restrict__ sv, T* r,
-                                                          const double* sc, int64_t n, int cond) {
-  if (cond && sc[kDone] != (double)kConvHalf) return;
+__device__ __forceinline__ void finish_cols(const T* partials, int nblk, int ncols,
+                                            double* out, double* sh) {
+  constexpr int NW = kThreads / 64, NJ = kFinishCols / NW;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // wave w takes columns w, w + NW, ...; each lane's loads for all of them
+  // are issued together
+  double acc[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) acc[j] = 0;
+  for (int b = lane; b < nblk; b += 64) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int c = wid + NW * j;
+      if (c < ncols) acc[j] += (double)partials[(int64_t)c * nblk + b];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int c = wid + NW * j;
+    if (c < ncols) {
+      const double v = wave_sum(acc[j]);
+      if (lane == 0) {
+        out[c] = v;
+        sh[c] = v;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// eta1 = C^T v, r~^T v; alpha = rho / (r~^T v - (C^T r~) . eta1)
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_bicg_finish_alpha(const T* partials, int nblk,
+                                                                int kc, double* sums, double* sc,
+                                                                int off_eta1, int off_ctrt) {
+  __shared__ double sh[kFinishCols];
+  if (sc[kDone] != 0.0) return;
+  finish_cols<T>(partials, nblk, kc + 1, sums, sh);
+  if (threadIdx.x != 0) return;
+  double corr = 0;
+  for (int c = 0; c < kc; ++c) {
+    sc[off_eta1 + c] = sh[c];
+    corr += sc[off_ctrt + c] * sh[c];
+  }
+  const double rtv = sh[kc] - corr;
+  sc[kRtv] = rtv;
+  if (rtv == 0.0 || !isfinite(rtv)) {
+    sc[kAlpha] = 0.0;   // breakdown: leave s = r; the stop state is set next
+    sc[kFlag] = 1.0;
+  } else {
+    sc[kAlpha] = sc[kRho] / rtv;
+  }
+}
+
+// |s|^2, then the half-step tests; on convergence at the half step the
+// scalar part of the early exit (xi += alpha eta1) is applied here and the
+// vector part by the conditional exit kernel that follows.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_bicg_finish_half(const T* partials, int nblk,
+                                                               double* sc, int off_eta1,
+                                                               int off_xi, int kc) {
+  __shared__ double sh[kFinishCols];
+  if (sc[kDone] != 0.0) return;
+  finish_cols<T>(partials, nblk, 1, sc + kSnorm2, sh);
+  if (threadIdx.x != 0) return;
+  sc[kIts] += 1.0;
+  if (sc[kFlag] != 0.0) {
+    sc[kDone] = kBreak;
+    sc[kEndHalf] = 1.0;
+    return;
+  }
+  const double sn2 = sh[0];
+  const double sn = sqrt(sn2);
+  hist_push(sc, sn);
+  if (!isfinite(sn)) {
+    sc[kDone] = kDiverge;
+    sc[kEndHalf] = 1.0;
+  } else if (sn <= sc[kTolAbs]) {
+    const double alpha = sc[kAlpha];
+    for (int c = 0; c < kc; ++c) sc[off_xi + c] += alpha * sc[off_eta1 + c];
+    sc[kRnorm2] = sn2;
+    sc[kDone] = kConvHalf;
+    sc[kEndHalf] = 1.0;
+  }
+}
+
+// y += alpha p ; r = s when the half-step test converged (kDone == kConvHalf)
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_bicg_exit_vec(const T* __restrict__ p, T* y,
+                                                            const T* __restrict__ sv, T* r,
+                                                            const double* sc, int64_t n) {
+  if (sc[kDone] != (double)kConvHalf) return;
   const T alpha = (T)sc[kAlpha];
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i < n) {
@@ -1412,50 +1472,61 @@ __global__ __launch_bounds__(kThreads) void k_bicg_exit_s(const T* __restrict__ 
   }
 }
 
-__global__ void k_bicg_exit_xi(double* sc, int off_eta1, int off_xi, int kc, int cond) {
-  if (threadIdx.x != 0) return;
-  if (cond && sc[kDone] != (double)kConvHalf) return;
-  const double alpha = sc[kAlpha];
-  for (int c = 0; c < kc; ++c) sc[off_xi + c] += alpha * sc[off_eta1 + c];
-  sc[kRnorm2] = sc[kSnorm2];
-  if (cond) sc[kDone] = kExited;
-}
-
-__device__ inline void hist_push(double* sc, double v) {
-  const int h = (int)sc[kHlen];
-  sc[kHistOff + h % kHistRing] = v;
-  sc[kHlen] = h + 1;
-}
-
-// after |s|^2 is finished: the tests of the half step (lines 9-10)
-__global__ void k_bicg_check_half(double* sc) {
-  if (threadIdx.x != 0 || sc[kDone] != 0.0) return;
-  sc[kIts] += 1.0;
-  if (sc[kFlag] != 0.0) {
-    sc[kDone] = kBreak;
-    sc[kEndHalf] = 1.0;
+// eta2 = C^T t; omega = t^T s / (|t|^2 - |eta2|^2); xi += alpha eta1 + omega eta2
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_bicg_finish_omega(const T* partials, int nblk,
+                                                                int kc, double* sums, double* sc,
+                                                                int off_eta1, int off_eta2,
+                                                                int off_xi) {
+  __shared__ double sh[kFinishCols];
+  // the pass after a half-step exit: mark the exit applied (so the vector
+  // part runs once) and do nothing else
+  if (sc[kDone] == (double)kConvHalf) {
+    __syncthreads();
+    if (threadIdx.x == 0) sc[kDone] = kExited;
     return;
   }
-  const double sn = sqrt(sc[kSnorm2]);
-  hist_push(sc, sn);
-  if (!isfinite(sn)) {
-    sc[kDone] = kDiverge;
-    sc[kEndHalf] = 1.0;
-  } else if (sn <= sc[kTolAbs]) {
-    sc[kDone] = kConvHalf;
-    sc[kEndHalf] = 1.0;
+  if (sc[kDone] != 0.0) return;
+  finish_cols<T>(partials, nblk, kc + 2, sums, sh);
+  if (threadIdx.x != 0) return;
+  double q = 0;
+  for (int c = 0; c < kc; ++c) {
+    sc[off_eta2 + c] = sh[c];
+    q += sh[c] * sh[c];
   }
+  const double ts = sh[kc];
+  const double tt = sh[kc + 1] - q;  // |t - C eta2|^2 with C^T C = I
+  sc[kTs] = ts;
+  sc[kTt] = tt;
+  double omega = 0.0;  // t = 0 (breakdown): y += alpha p, r = s; the stop state is set next
+  if (tt > 0.0 && isfinite(tt)) omega = ts / tt;
+  else sc[kFlag] = 2.0;
+  sc[kOmega] = omega;
+  const double alpha = sc[kAlpha];
+  for (int c = 0; c < kc; ++c) sc[off_xi + c] += alpha * sc[off_eta1 + c] + omega * sc[off_eta2 + c];
 }
 
-// after the full step: |r|, breakdown flags, divergence guard, rho = 0 (line 5)
-__global__ void k_bicg_check_full(double* sc) {
-  if (threadIdx.x != 0 || sc[kDone] != 0.0) return;
-  const double rn = sqrt(sc[kRnorm2]);
+// rho = r~^T r, |r|^2, beta; then the full-step tests (line 3, breakdowns,
+// divergence guard, rho = 0 of line 5)
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_bicg_finish_full(const T* partials, int nblk,
+                                                               double* sums, double* sc) {
+  __shared__ double sh[kFinishCols];
+  if (sc[kDone] != 0.0) return;
+  finish_cols<T>(partials, nblk, 2, sums, sh);
+  if (threadIdx.x != 0) return;
+  const double rho = sh[0], rn2 = sh[1];
+  const double rho_old = sc[kRho];
+  sc[kRnorm2] = rn2;
+  sc[kRhoOld] = rho_old;
+  sc[kBeta] = sc[kOmega] != 0.0 ? (rho / rho_old) * (sc[kAlpha] / sc[kOmega]) : 0.0;
+  sc[kRho] = rho;
+  const double rn = sqrt(rn2);
   hist_push(sc, rn);
   if (sc[kFlag] != 0.0) sc[kDone] = kBreak;
   else if (!isfinite(rn) || rn > sc[kDivAbs]) sc[kDone] = kDiverge;
   else if (rn <= sc[kTolAbs]) sc[kDone] = kConvFull;
-  else if (sc[kRho] == 0.0) sc[kDone] = kBreak;
+  else if (rho == 0.0) sc[kDone] = kBreak;
 }
 
 template <class T>
@@ -1849,36 +1920,34 @@ hipError_t bicg_yr(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, con
   return hipGetLastError();
 }
 
-hipError_t bicg_alpha(hipStream_t s, const double* sums, int kc, double* sc, int off_eta1,
-                      int off_ctrt) {
-  k_bicg_alpha<<<1, 64, 0, s>>>(sums, kc, sc, off_eta1, off_ctrt);
-  return hipGetLastError();
-}
-hipError_t bicg_omega(hipStream_t s, const double* sums, int kc, double* sc, int off_eta1,
-                      int off_eta2, int off_xi) {
-  k_bicg_omega<<<1, 64, 0, s>>>(sums, kc, sc, off_eta1, off_eta2, off_xi);
-  return hipGetLastError();
-}
-hipError_t bicg_rho(hipStream_t s, const double* sums, double* sc) {
-  k_bicg_rho<<<1, 64, 0, s>>>(sums, sc);
-  return hipGetLastError();
-}
-
 template <class T>
-hipError_t bicg_exit_s(hipStream_t s, const T* p, T* y, const T* sv, T* r, double* sc,
-                       int off_eta1, int off_xi, int kc, int64_t n, bool cond) {
-  if (n > 0) k_bicg_exit_s<T><<<grid_for(n), kThreads, 0, s>>>(p, y, sv, r, sc, n, cond ? 1 : 0);
-  k_bicg_exit_xi<<<1, 64, 0, s>>>(sc, off_eta1, off_xi, kc, cond ? 1 : 0);
+hipError_t bicg_finish_alpha(hipStream_t s, const T* partials, int nblk, int kc, double* sums,
+                             double* sc, int off_eta1, int off_ctrt) {
+  k_bicg_finish_alpha<T><<<1, kThreads, 0, s>>>(partials, nblk, kc, sums, sc, off_eta1, off_ctrt);
   return hipGetLastError();
 }
-
-hipError_t bicg_check_half(hipStream_t s, double* sc) {
-  k_bicg_check_half<<<1, 64, 0, s>>>(sc);
+template <class T>
+hipError_t bicg_finish_half(hipStream_t s, const T* partials, int nblk, double* sc, int off_eta1,
+                            int off_xi, int kc) {
+  k_bicg_finish_half<T><<<1, kThreads, 0, s>>>(partials, nblk, sc, off_eta1, off_xi, kc);
   return hipGetLastError();
 }
-
-hipError_t bicg_check_full(hipStream_t s, double* sc) {
-  k_bicg_check_full<<<1, 64, 0, s>>>(sc);
+template <class T>
+hipError_t bicg_exit_vec(hipStream_t s, const T* p, T* y, const T* sv, T* r, const double* sc,
+                         int64_t n) {
+  if (n > 0) k_bicg_exit_vec<T><<<grid_for(n), kThreads, 0, s>>>(p, y, sv, r, sc, n);
+  return hipGetLastError();
+}
+template <class T>
+hipError_t bicg_finish_omega(hipStream_t s, const T* partials, int nblk, int kc, double* sums,
+                             double* sc, int off_eta1, int off_eta2, int off_xi) {
+  k_bicg_finish_omega<T><<<1, kThreads, 0, s>>>(partials, nblk, kc, sums, sc, off_eta1, off_eta2,
+                                                off_xi);
+  return hipGetLastError();
+}
+template <class T>
+hipError_t bicg_finish_full(hipStream_t s, const T* partials, int nblk, double* sums, double* sc) {
+  k_bicg_finish_full<T><<<1, kThreads, 0, s>>>(partials, nblk, sums, sc);
   return hipGetLastError();
 }
 
@@ -1941,8 +2010,14 @@ hipError_t axpy_f32_into_f64(hipStream_t s, const float* d, double* x, int64_t n
                                  int, int64_t, T*, int);                                          \
   template hipError_t bicg_yr<T>(hipStream_t, const Cols<T>&, const T*, const T*, const T*, T*,   \
                                  T*, const T*, const double*, int, int64_t, T*, int);             \
-  template hipError_t bicg_exit_s<T>(hipStream_t, const T*, T*, const T*, T*, double*, int, int,  \
-                                     int, int64_t, bool);                                               \
+  template hipError_t bicg_finish_alpha<T>(hipStream_t, const T*, int, int, double*, double*, int, \
+                                           int);                                                 \
+  template hipError_t bicg_finish_half<T>(hipStream_t, const T*, int, double*, int, int, int);     \
+  template hipError_t bicg_exit_vec<T>(hipStream_t, const T*, T*, const T*, T*, const double*,     \
+                                       int64_t);                                                 \
+  template hipError_t bicg_finish_omega<T>(hipStream_t, const T*, int, int, double*, double*, int, \
+                                           int, int);                                            \
+  template hipError_t bicg_finish_full<T>(hipStream_t, const T*, int, double*, double*);           \
   template hipError_t fill<T>(hipStream_t, T*, int64_t, double);                                  \
   template hipError_t copy<T>(hipStream_t, const T*, T*, int64_t);
 

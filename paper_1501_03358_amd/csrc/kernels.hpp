@@ -150,31 +150,33 @@ constexpr int kHistOff = 512, kHistRing = 128;
 // BiCGStab pieces; `sums` are finished FP64 dot products.
 template <class T>
 hipError_t bicg_p(hipStream_t s, const T* r, T* p, const T* v, const double* sc, int64_t n);
-// eta1 = sums[0..kc), alpha = rho / (sums[kc] - ctrt . eta1)
-hipError_t bicg_alpha(hipStream_t s, const double* sums, int kc, double* sc, int off_eta1,
-                      int off_ctrt);
 // v -= C eta1 ; s = r - alpha v ; partial |s|^2
 template <class T>
 hipError_t bicg_sv(hipStream_t s, const Cols<T>& C, const T* r, T* v, T* sv, const double* sc,
                    int off_eta1, int64_t n, T* partials, int nblk);
-// eta2 = sums[0..kc), omega = sums[kc] / (sums[kc+1] - |eta2|^2), xi += alpha eta1 + omega eta2
-hipError_t bicg_omega(hipStream_t s, const double* sums, int kc, double* sc, int off_eta1,
-                      int off_eta2, int off_xi);
 // y += alpha p + omega s ; r = s - omega (t - C eta2) ; partials r~.r, |r|^2
 template <class T>
 hipError_t bicg_yr(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, const T* p, T* y,
                    T* r, const T* rt, const double* sc, int off_eta2, int64_t n, T* partials,
                    int nblk);
-// rho_old = rho, rho = sums[0], rnorm2 = sums[1], beta = (rho/rho_old)(alpha/omega)
-hipError_t bicg_rho(hipStream_t s, const double* sums, double* sc);
-// line 10/10a early exit: y += alpha p ; r = s ; xi += alpha eta1.  With
-// `cond` the pass runs only when kDone == kConvHalf and then sets kExited.
+// Finishing reductions fused with the scalar step that uses them (one block):
+// finish + alpha; finish |s|^2 + half-step tests (with the scalar part of the
+// line-10 exit); the vector part of that exit (runs only when it fired);
+// finish + omega/xi; finish rho, |r|^2 + beta + full-step tests.
 template <class T>
-hipError_t bicg_exit_s(hipStream_t s, const T* p, T* y, const T* sv, T* r, double* sc,
-                       int off_eta1, int off_xi, int kc, int64_t n, bool cond = false);
-// device-side stopping tests after the half step (|s|) and the full step (|r|)
-hipError_t bicg_check_half(hipStream_t s, double* sc);
-hipError_t bicg_check_full(hipStream_t s, double* sc);
+hipError_t bicg_finish_alpha(hipStream_t s, const T* partials, int nblk, int kc, double* sums,
+                             double* sc, int off_eta1, int off_ctrt);
+template <class T>
+hipError_t bicg_finish_half(hipStream_t s, const T* partials, int nblk, double* sc, int off_eta1,
+                            int off_xi, int kc);
+template <class T>
+hipError_t bicg_exit_vec(hipStream_t s, const T* p, T* y, const T* sv, T* r, const double* sc,
+                         int64_t n);
+template <class T>
+hipError_t bicg_finish_omega(hipStream_t s, const T* partials, int nblk, int kc, double* sums,
+                             double* sc, int off_eta1, int off_eta2, int off_xi);
+template <class T>
+hipError_t bicg_finish_full(hipStream_t s, const T* partials, int nblk, double* sums, double* sc);
 // hcol_last = sqrt(*nrm2), inv = 1/hcol_last
 hipError_t set_norm_from_sum(hipStream_t s, const double* nrm2, double* hcol_last, double* inv);
 

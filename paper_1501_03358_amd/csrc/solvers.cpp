@@ -693,11 +693,14 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     // line 7a-8: eta1 = C^T v, v -= C eta1, alpha = rho / r~^T v, s = r - alpha v
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 2),
                block_dot<T>(s, cols<T>(C, ldr, kc, rt, ld, 1), v, n, 0, part, nblk));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc + 1, sc + kSums));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_alpha(s, sc + kSums, kc, sc, kEta1, kCtrt));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
+               bicg_finish_alpha<T>(s, part, nblk, kc, sc + kSums, sc, kEta1, kCtrt));
     KRS_LAUNCH(ctx, KRS_K_BICG_SV, dev ? 0 : bytes_sv,
                bicg_sv<T>(s, Cc, r, v, sv, sc, kEta1, n, part, nblk));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, sc + kSnorm2));
+    // lines 9-10a: |s| tests; on convergence xi += alpha eta1 here and
+    // y += alpha p, r = s in the conditional pass that follows
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_finish_half<T>(s, part, nblk, sc, kEta1, kXi, kc));
+    KRS_LAUNCH(ctx, KRS_K_BICG_P, 0, bicg_exit_vec<T>(s, p, y, sv, r, sc, n));
     return 0;
   };
   auto second_half = [&](bool dev) -> int {
@@ -706,13 +709,12 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     // line 12a-13a: eta2 = C^T t, omega = t^T s / |t - C eta2|^2, xi update
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 2),
                block_dot<T>(s, cols<T>(C, ldr, kc, sv, ld, 1), t, n, 1, part, nblk));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc + 2, sc + kSums));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_omega(s, sc + kSums, kc, sc, kEta1, kEta2, kXi));
-    // lines 14-16 with the next rho = r~^T r
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
+               bicg_finish_omega<T>(s, part, nblk, kc, sc + kSums, sc, kEta1, kEta2, kXi));
+    // lines 14-16 with the next rho = r~^T r, then the tests of line 3
     KRS_LAUNCH(ctx, KRS_K_BICG_YR, dev ? 0 : bytes_yr,
                bicg_yr<T>(s, Cc, t, sv, p, y, r, rt, sc, kEta2, n, part, nblk));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 2, sc + kSums));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_rho(s, sc + kSums, sc));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_finish_full<T>(s, part, nblk, sc + kSums, sc));
     return 0;
   };
   if (o->flags & KRS_FLAG_HOST_LOOP) {
@@ -738,9 +740,8 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
         status = KRS_DIVERGED;
         break;
       }
-      if (snorm <= tol * nb) {                              // lines 9-10a
-        KRS_LAUNCH(ctx, KRS_K_BICG_P, 5 * NW,
-                   bicg_exit_s<T>(s, p, y, sv, r, sc, kEta1, kXi, kc, n));
+      if (snorm <= tol * nb) {                              // lines 9-10a (applied)
+        timing_add_bytes(ctx, KRS_K_BICG_P, 5 * NW);
         rnorm = snorm;
         break;
       }
@@ -766,13 +767,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     auto one_pass = [&]() -> int {
       int e = first_half(true);
       if (e) return e;
-      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_check_half(s, sc));
-      KRS_LAUNCH(ctx, KRS_K_BICG_P, 0,
-                 bicg_exit_s<T>(s, p, y, sv, r, sc, kEta1, kXi, kc, n, true));
-      e = second_half(true);
-      if (e) return e;
-      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_check_full(s, sc));
-      return 0;
+      return second_half(true);
     };
     // optionally replay one captured pass per iteration
     krs_ctx::Graph* graph = nullptr;
@@ -862,7 +857,8 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
       const int64_t started = (int64_t)d[kIts] - its;
       const int done_now = (int)d[kDone];
       const bool half = done_now != kRunning && d[kEndHalf] != 0.0;
-      timing_add_bytes(ctx, KRS_K_BICG_P, started * bytes_p + (done_now == kExited ? 5 * NW : 0.0));
+      const bool exited = done_now == kExited || done_now == kConvHalf;
+      timing_add_bytes(ctx, KRS_K_BICG_P, started * bytes_p + (exited ? 5 * NW : 0.0));
       timing_add_bytes(ctx, KRS_K_BICG_SV, started * bytes_sv);
       timing_add_bytes(ctx, KRS_K_BICG_YR, (started - (half ? 1 : 0)) * bytes_yr);
       its = (int64_t)d[kIts];
