@@ -136,6 +136,14 @@ typedef struct krs_precond_desc {
  * iteration (the kernels' own dispatch latency dominates, not host launch
  * cost) and the first replay of a key pays for capture and instantiation. */
 #define KRS_FLAG_GRAPH 4
+/* GMRES / rGCROT only: precondition from the left, as the paper does for
+ * these solvers (Sec. 2.1): iterate on M^-1 A x = M^-1 b and stop when
+ * ||M^-1 (b - A x)|| <= tol ||M^-1 b||; stats->rel_res_est reports that ratio
+ * and stats->rel_res_true the unpreconditioned ||b - A x|| / ||b||.  A
+ * recycle space built this way belongs to M^-1 A and serves only
+ * left-preconditioned solves.  The hybrid and refinement drivers reject it
+ * (rBiCGStab is right-preconditioned, Sec. 2.1). */
+#define KRS_FLAG_LEFT_PRECOND 8
 
 typedef struct krs_opts {
   int32_t m;               /* Arnoldi steps per cycle (GMRES, rGCROT), 1..64 */

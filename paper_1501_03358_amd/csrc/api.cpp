@@ -276,6 +276,8 @@ int krs_rbicgstab_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M,
   if (!ctx || !A || !b || !x) return KRS_ERR_ARG;
   int rc = check_opts(ctx, opts, false);
   if (rc) return rc;
+  if (opts->flags & KRS_FLAG_LEFT_PRECOND)
+    return set_err(ctx, KRS_ERR_ARG, "rBiCGStab is right-preconditioned");
   if ((rc = check_precond(ctx, A, M))) return rc;
   if (rec) {
     if (rec->n != A->n || rec->dt != A->dt)
@@ -299,6 +301,8 @@ int krs_hybrid_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, kr
   if (!ctx || !A || !b || !x || !rec) return KRS_ERR_ARG;
   int rc = check_opts(ctx, opts, true);
   if (rc) return rc;
+  if (opts->flags & KRS_FLAG_LEFT_PRECOND)
+    return set_err(ctx, KRS_ERR_ARG, "the hybrid is right-preconditioned");
   if ((rc = check_precond(ctx, A, M))) return rc;
   if ((rc = check_rec(ctx, A, rec, opts, true))) return rc;
   if (opts->switch_back < 0 || !std::isfinite(opts->switch_back))
@@ -354,6 +358,8 @@ int krs_ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32,
   if (!ctx || !A64 || !A32 || !b || !x) return KRS_ERR_ARG;
   int rc = check_opts(ctx, opts, true);
   if (rc) return rc;
+  if (opts->flags & KRS_FLAG_LEFT_PRECOND)
+    return set_err(ctx, KRS_ERR_ARG, "refinement runs right-preconditioned inner solves");
   if (A64->dt != KRS_F64 || A32->dt != KRS_F32)
     return set_err(ctx, KRS_ERR_STATE, "IR needs an FP64 and an FP32 matrix");
   if (A64->n != A32->n) return set_err(ctx, KRS_ERR_STATE, "IR matrices differ in size");

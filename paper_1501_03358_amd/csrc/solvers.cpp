@@ -167,6 +167,8 @@ size_t ws_gmres(int64_t n, int m) {
   c.vec<T>(ld);
   c.take(partials_bytes(sizeof(T)));
   c.vec<double>(kScalarDoubles);
+  c.vec<T>(ld);   // left preconditioning: M^-1 b
+  c.vec<T>(ld);   // left preconditioning: preconditioner temporary
   return c.off;
 }
 
@@ -318,6 +320,9 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
   T* w = cv.vec<T>(ld);  // A~ v_j; doubles as the preconditioner temporary
   T* part = (T*)cv.take(partials_bytes(sizeof(T)));
   double* sc = cv.vec<double>(kScalarDoubles);
+  const bool left = (o->flags & KRS_FLAG_LEFT_PRECOND) != 0 && M && M->d.type != KRS_PC_NONE;
+  T* bl = left ? cv.vec<T>(ld) : nullptr;     // M^-1 b
+  T* ptmp = left ? cv.vec<T>(ld) : nullptr;   // preconditioner temporary
   if (!ws || !cv.ok) return set_err(ctx, KRS_ERR_WORKSPACE, "workspace missing or too small");
   double* d_h1 = sc + Ws<T>::kH1;
   double* d_h2 = sc + Ws<T>::kH2;
@@ -332,8 +337,27 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
   const int nblk = red_blocks(n);
   Op<T> op{ctx, A, M, grid3(A), z, w};
   const double NW = (double)n * sizeof(T);
+  // the operator of the iteration: A M^-1 (right) or M^-1 A (left, into w
+  // through z, with ptmp as the preconditioner's temporary)
+  auto apply = [&](const T* v, T* out) -> int {
+    if (!left) return op.apply(v, out);
+    KRS_LAUNCH(ctx, KRS_K_STENCIL, 9 * NW,
+               stencil<T>(s, op.g, op.bands(), v, z, 1.0, 0.0, nullptr, 0));
+    return op.minv_s(z, out, ptmp);
+  };
 
   init_stats(st);
+  const T* b_orig = b;
+  double nb_orig = 0;
+  if (left) {
+    double nbo2 = 0;
+    int e = norm2<T>(ctx, b, n, part, d_nrm, nbo2);
+    if (e) return e;
+    nb_orig = std::sqrt(nbo2);
+    e = op.minv_s(b, bl, ptmp);   // the system M^-1 A x = M^-1 b
+    if (e) return e;
+    b = bl;
+  }
   double nb2 = 0;
   int rc = norm2<T>(ctx, b, n, part, d_nrm, nb2);
   if (rc) return rc;
@@ -402,7 +426,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
     for (int j = 0; j < m; ++j) {
       T* vj = V + (int64_t)j * ld;
       T* vn = V + (int64_t)(j + 1) * ld;
-      rc = op.apply(vj, w);                              // line 6
+      rc = apply(vj, w);                                 // line 6
       if (rc) return rc;
       ++its;
       ++mv;
@@ -486,9 +510,19 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
       if (rc) return rc;
     }
     // line 14: true residual r = b - A~ y (into the first basis column)
-    rc = op.minv(x, z);
-    if (rc) return rc;
-    KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 10 * NW, residual_norm<T>(s, op.g, op.bands(), z, b, r0, part));
+    if (left) {
+      // r = M^-1 (b - A x) = M^-1 b - M^-1 A x
+      KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 10 * NW,
+                 residual_norm<T>(s, op.g, op.bands(), x, b_orig, z, part));
+      rc = op.minv_s(z, r0, ptmp);
+      if (rc) return rc;
+      KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW, block_dot<T>(s, Cols<T>{}, r0, n, 1, part, nblk));
+    } else {
+      rc = op.minv(x, z);
+      if (rc) return rc;
+      KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 10 * NW,
+                 residual_norm<T>(s, op.g, op.bands(), z, b, r0, part));
+    }
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, d_nrm));
     ++mv;
     kc = rec ? rec->dim : 0;
@@ -514,10 +548,21 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
     }
   }
   if (status != KRS_DIVERGED && (rho <= tol * nb || est_converged)) status = KRS_OK;
-  // x = M^-1 y
-  rc = op.minv(x, z);
-  if (rc) return rc;
-  KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, z, x, n));
+  double rel_true = rho / nb;
+  if (left) {
+    // x is the iterate itself; report the unpreconditioned residual
+    KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 10 * NW,
+               residual_norm<T>(s, op.g, op.bands(), x, b_orig, z, part));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, d_nrm));
+    rc = read_dev(ctx, d_nrm, 1);
+    if (rc) return rc;
+    rel_true = nb_orig > 0 ? std::sqrt(ctx->pin[0]) / nb_orig : 0.0;
+  } else {
+    // x = M^-1 y
+    rc = op.minv(x, z);
+    if (rc) return rc;
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, z, x, n));
+  }
   KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
   timing_flush(ctx);
   if (st) {
@@ -526,8 +571,8 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
     st->iterations = its;
     st->cycles = cycles;
     st->history_len = hlen;
-    st->rel_res_true = rho / nb;
-    st->rel_res_est = est / nb;
+    st->rel_res_true = rel_true;
+    st->rel_res_est = left ? rho / nb : est / nb;
     st->time_ms = tm.ms();
     st->bytes_model = ctx->bytes - bytes0;
     st->second_passes = n_two_pass;

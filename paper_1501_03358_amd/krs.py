@@ -25,6 +25,7 @@ LOCAL_JACOBI, LOCAL_SSOR = 0, 1
 FLAG_TRUST_ESTIMATE = 1
 FLAG_HOST_LOOP = 2
 FLAG_GRAPH = 4
+FLAG_LEFT_PRECOND = 8
 
 EXPORTS = (
     "krs_create", "krs_destroy", "krs_last_error", "krs_set_stream", "krs_matrix_create",

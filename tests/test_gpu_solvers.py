@@ -431,3 +431,58 @@ def test_full_size_porous256_fp32_ir_properties(gpu_lib):
     z = precond.schwarz_jacobi(b32h, prob.shape, prob.periodic, u, **params)
     au = stencil.apply(b32h, prob.shape, prob.periodic, z)
     assert rel(au, C[:, c].double().cpu().numpy()) <= 2e-2
+
+
+@pytest.mark.parametrize("pc", ["jacobi", "schwarz"])
+def test_left_preconditioned_gmres_and_rgcrot(gpu_lib, pc):
+    """Paper-literal left preconditioning (Sec. 2.1) for GMRES(m) and
+    rGCROT(m,k): the oracle's solvers on M^-1 A x = M^-1 b (no final M^-1);
+    history, counts and x match, the stop is on the preconditioned residual,
+    and the reported true residual is the unpreconditioned one."""
+    krs = gpu_lib
+    prob = W.grf_problem(24, extra=71)
+    params = dict(tile=8) if pc == "schwarz" else None
+    d = Dev(krs, prob, pc, params, m=20, k=10)
+    A, Mi, _ = oracle_ops(prob, pc, params)
+    opL = lambda v: Mi(A(v))
+    ident = lambda v: np.array(v, copy=True)
+    bs = W.rhs_perturbed(prob, 3, extra=71)
+    left = krs.FLAG_LEFT_PRECOND
+    # GMRES(20)
+    b = bs[0]
+    h = _hist()
+    x = d.empty()
+    rc, st = krs.gmres(d.ctx, d.A, d.M, d.vec(b), x,
+                       krs.make_opts(m=20, tol=1e-8, history=h, flags=left), d.ws)
+    ref = K.gmres(opL, ident, Mi(b), 20, 1e-8)
+    assert rc == krs.OK and ref.status == K.CONVERGED
+    _check_history(h[:st.history_len], ref.history)
+    assert abs(st.iterations - ref.iterations) <= 2
+    xg = x.cpu().numpy()
+    assert rel(xg, ref.x) <= X_TOL
+    assert st.rel_res_true == pytest.approx(np.linalg.norm(b - A(xg)) / np.linalg.norm(b),
+                                            rel=1e-6)
+    assert np.linalg.norm(Mi(b - A(xg))) <= 1.5e-8 * np.linalg.norm(Mi(b))
+    # rGCROT(20,10) over three systems, the oracle stepping from the GPU's space
+    rec = krs.Recycle(d.ctx, prob.n, 10, torch.float64)
+    for t in range(3):
+        b = bs[t]
+        orec = recycle_to_oracle(rec)
+        h = _hist()
+        x = d.empty()
+        rc, st = krs.rgcrot_solve(d.ctx, d.A, d.M, rec, d.vec(b), x,
+                                  krs.make_opts(m=20, k=10, tol=1e-8, history=h, flags=left),
+                                  d.ws)
+        ref = K.rgcrot(opL, ident, Mi(b), 20, 10, 1e-8, orec)
+        assert rc == krs.OK and ref.status == K.CONVERGED, t
+        _check_history(h[:st.history_len], ref.history)
+        assert abs(st.iterations - ref.iterations) <= 2, (t, st.iterations, ref.iterations)
+        assert rel(x.cpu().numpy(), ref.x) <= X_TOL
+    # the space belongs to M^-1 A
+    g = recycle_to_oracle(rec)
+    AU = np.column_stack([opL(g.U[:, i]) for i in range(g.dim)])
+    assert np.linalg.norm(AU - g.C) <= 1e-10 * np.linalg.norm(g.C)
+    # drivers that are right-preconditioned refuse the flag
+    with pytest.raises(krs.KrsError):
+        krs.rbicgstab_solve(d.ctx, d.A, d.M, None, d.vec(b), x,
+                            krs.make_opts(tol=1e-8, flags=left), d.ws)
