@@ -313,7 +313,8 @@ def seq_main(args):
                                "p99": float(np.percentile(lat, 99))}}, kt
 
     def opts():
-        return krs.make_opts(m=M, k=K, tol=1e-8, max_matvecs=6000)
+        return krs.make_opts(m=M, k=K, tol=1e-8, max_matvecs=6000,
+                             flags=krs.FLAG_LEFT_PRECOND if args.left else 0)
 
     res = {}
     if channel:
@@ -349,7 +350,9 @@ def seq_main(args):
         "value": r0["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": steps,
         "warmup": 0, "ms_per_step": r0["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{prob.name}_fp64", "grid": f"{n}^3", "unknowns": prob.n,
+        "config": {"workload": f"{prob.name}_fp64" + ("_left" if args.left else ""),
+                   "grid": f"{n}^3", "unknowns": prob.n,
+                   "preconditioning": "left" if args.left else "right",
                    "time_steps": steps, "m": M, "k": K, "tol": 1e-8,
                    "n_switch": None if channel else args.n_switch,
                    "precond": f"Schwarz 8^3 tiles overlap 1, 5 local {args.local_solver} "
@@ -372,6 +375,8 @@ def main():
                     default="porous_ir")
     ap.add_argument("--local-solver", choices=["jacobi", "ssor"], default="jacobi",
                     help="local smoother of the Schwarz preconditioner")
+    ap.add_argument("--left", action="store_true",
+                    help="channel128: GMRES and rGCROT preconditioned from the left")
     ap.add_argument("--change-every", type=int, default=10,
                     help="porous128_changing: systems per matrix")
     ap.add_argument("--matrices", type=int, default=64, help="serve: number of matrices")
@@ -413,6 +418,10 @@ def main():
         serve_main(args)
         return
     if args.workload in ("channel128", "porous128", "porous128_changing"):
+        if args.left and args.workload != "channel128":
+            print("--left applies to channel128 (GMRES and rGCROT); the hybrid and BiCGStab "
+                  "are right-preconditioned", file=sys.stderr)
+            sys.exit(2)
         seq_main(args)
         return
     if args.calibrate_copy:
