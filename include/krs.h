@@ -180,6 +180,8 @@ typedef struct krs_stats {
   int64_t second_passes;   /* Arnoldi steps that needed a second Gram-Schmidt pass */
   int64_t solver;          /* krs_hybrid_solve: solver that produced x (KRS_SOLVER_*) */
   int64_t refreshed;       /* krs_hybrid_solve: 1 if line 1a ran first (space marked stale) */
+  int64_t breakdown_site;  /* (r)BiCGStab: 0 none, 1 r~^T v = 0 (alpha, line 8), 2 t^T t = 0
+                              (omega, line 13), 3 rho = 0 (line 5) */
 } krs_stats;
 
 /* ---------------- context ---------------- */
@@ -225,8 +227,8 @@ int krs_recycle_dim(const krs_recycle* rec);
  * krs_recycle_update before solving if C does not hold A~ U. */
 int krs_recycle_set_dim(krs_recycle* rec, int k);
 /* Marks (U, C) stale: A or M changed since C = A~ U was formed.  The next
- * krs_hybrid_solve first re-forms C from U (Alg. 3 line 1a: "if the matrix
- * has changed"), keeping range(U).  Sec. 2.4 leaves the policy for changing
+ * krs_hybrid_solve first re-forms C from U (Alg. 3 line 1a, which applies
+ * whenever the matrix changes), keeping range(U).  Sec. 2.4 leaves the policy for changing
  * matrices open (intermittent rGCROT); this is the cheapest consistent one. */
 int krs_recycle_mark_stale(krs_recycle* rec);
 

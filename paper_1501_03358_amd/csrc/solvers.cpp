@@ -934,6 +934,13 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     }
   }
   if (status == KRS_NOT_CONVERGED && rnorm <= tol * nb) status = KRS_OK;
+  int64_t site = 0;
+  if (status == KRS_BREAKDOWN) {
+    // the flag the scalar steps left (1: alpha, 2: omega), else rho = 0
+    int e = read_dev(ctx, sc, kSlots);
+    if (e) return e;
+    site = ctx->pin[kFlag] != 0.0 ? (int64_t)ctx->pin[kFlag] : 3;
+  }
   // line 17a: y -= U xi ; then x = M^-1 y
   if (kc > 0) {
     KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (kc + 2),
@@ -956,6 +963,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     st->rel_res_est = rnorm / nb;
     st->time_ms = tm.ms();
     st->bytes_model = ctx->bytes - bytes0;
+    st->breakdown_site = site;
   }
   return status;
 }

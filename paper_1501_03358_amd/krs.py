@@ -67,7 +67,7 @@ class Stats(ctypes.Structure):
                 ("rel_res_est", ctypes.c_double), ("time_ms", ctypes.c_double),
                 ("host_eig_ms", ctypes.c_double), ("bytes_model", ctypes.c_double),
                 ("second_passes", ctypes.c_int64), ("solver", ctypes.c_int64),
-                ("refreshed", ctypes.c_int64)]
+                ("refreshed", ctypes.c_int64), ("breakdown_site", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -94,3 +94,32 @@ def test_graph_cache_eviction_and_reuse(gpu_lib):
         for d, b, r in zip(devs, bs, ref):
             _same(r, _solve(krs, d, None, b, 1e-8, 2000, krs.FLAG_GRAPH))
             torch.cuda.synchronize()
+
+
+def test_breakdown_site_reported_alike(gpu_lib):
+    """A skew-symmetric operator (periodic central difference in x, zero
+    diagonal) gives r~^T A r~ = 0, so BiCGStab breaks down at alpha (line 8)
+    in the first pass: both loops report the breakdown and its site, like the
+    oracle."""
+    from oracle import krylov as K
+    from oracle import stencil as S
+    krs = gpu_lib
+    nx, ny, nz = 16, 4, 4
+    n = nx * ny * nz
+    bands = np.zeros((7, n))
+    bands[1] = -1.0     # west
+    bands[2] = 1.0      # east
+    prob = W.Problem("skew", (nx, ny, nz), (True, False, False), bands, np.ones(n), False)
+    d = Dev(krs, prob, "none", m=4, k=2)
+    # b lives on even x positions and A b on odd ones: r~^T v = b^T A b = 0 exactly
+    b = np.random.default_rng(3).standard_normal(n)
+    b[np.arange(n) % 2 == 1] = 0.0
+    op = lambda v: S.apply(bands, prob.shape, prob.periodic, v)
+    ref = K.rbicgstab(op, lambda v: v.copy(), b, 1e-8, None)
+    assert ref.status == K.BREAKDOWN
+    for flags in (krs.FLAG_HOST_LOOP, 0):
+        x = d.empty()
+        rc, st = krs.rbicgstab_solve(d.ctx, d.A, None, None, d.vec(b), x,
+                                     krs.make_opts(tol=1e-8, flags=flags), d.ws)
+        assert rc == krs.BREAKDOWN and st.breakdown_site == 1, (flags, rc, st.breakdown_site)
+        assert st.matvecs == ref.matvecs == 1
