@@ -262,7 +262,7 @@ def seq_main(args):
     bands = torch.from_numpy(prob.bands).to(dev)
     A = krs.Matrix(ctx, prob.shape, prob.periodic, bands)
     Mp = krs.Precond(ctx, A, "schwarz", **local_params(args))
-    ws = torch.empty(krs.workspace_size(krs.SOLVER_RGCROT, prob.n, M, K, torch.float64),
+    ws = torch.empty(krs.workspace_size(krs.SOLVER_RGCROT, prob.n, args.m, args.k, torch.float64),
                      dtype=torch.uint8, device=dev)
     x = torch.zeros(prob.n, dtype=torch.float64, device=dev)
 
@@ -277,7 +277,7 @@ def seq_main(args):
         return True
 
     def run(name, solve):
-        rec = krs.Recycle(ctx, prob.n, K, torch.float64)
+        rec = krs.Recycle(ctx, prob.n, args.k, torch.float64)
         krs.timing_reset(ctx)
         krs.timing_enable(ctx, True)
         mvs, its, byt, lat, bad, sp = [], 0, 0.0, [], 0, 0
@@ -313,7 +313,7 @@ def seq_main(args):
                                "p99": float(np.percentile(lat, 99))}}, kt
 
     def opts():
-        return krs.make_opts(m=M, k=K, tol=1e-8, max_matvecs=6000,
+        return krs.make_opts(m=args.m, k=args.k, tol=1e-8, max_matvecs=6000,
                              flags=krs.FLAG_LEFT_PRECOND if args.left else 0)
 
     res = {}
@@ -328,7 +328,7 @@ def seq_main(args):
         if changing:
             res["hybrid_switch_back"], _ = run("hybrid_switch_back", lambda rec, i, b: (
                 krs.hybrid_solve(ctx, A, Mp, rec, i, args.n_switch, b, x,
-                                 krs.make_opts(m=M, k=K, tol=1e-8, max_matvecs=6000,
+                                 krs.make_opts(m=args.m, k=args.k, tol=1e-8, max_matvecs=6000,
                                                switch_back=1.3), ws)))
         main_name, other = "hybrid", "bicgstab"
         if args.hybrid_only:
@@ -353,7 +353,7 @@ def seq_main(args):
         "config": {"workload": f"{prob.name}_fp64" + ("_left" if args.left else ""),
                    "grid": f"{n}^3", "unknowns": prob.n,
                    "preconditioning": "left" if args.left else "right",
-                   "time_steps": steps, "m": M, "k": K, "tol": 1e-8,
+                   "time_steps": steps, "m": args.m, "k": args.k, "tol": 1e-8,
                    "n_switch": None if channel else args.n_switch,
                    "precond": f"Schwarz 8^3 tiles overlap 1, 5 local {args.local_solver} "
                               f"iterations + 1 global Jacobi sweep"},
@@ -393,6 +393,8 @@ def main():
                     help="systems timed (default 20; 50 channel128, 100 porous128)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="grid size per axis")
+    ap.add_argument("--m", type=int, default=M, help="rGCROT cycle length")
+    ap.add_argument("--k", type=int, default=K, help="recycle dimension")
     ap.add_argument("--inner-tol", type=float, default=1e-5)
     ap.add_argument("--n-switch", type=int, default=N_SWITCH,
                     help="porous128: systems solved by rGCROT before rBiCGStab")
@@ -445,21 +447,21 @@ def main():
     pc = local_params(args)
     M32 = krs.Precond(ctx, A32, "schwarz", **pc)
     M64 = krs.Precond(ctx, A64, "schwarz", **pc)
-    ws_ir = torch.empty(krs.workspace_size(krs.SOLVER_IR, prob.n, M, K, torch.float32),
+    ws_ir = torch.empty(krs.workspace_size(krs.SOLVER_IR, prob.n, args.m, args.k, torch.float32),
                         dtype=torch.uint8, device=dev)
-    ws64 = torch.empty(krs.workspace_size(krs.SOLVER_RGCROT, prob.n, M, K, torch.float64),
-                       dtype=torch.uint8, device=dev)
+    ws64 = torch.empty(krs.workspace_size(krs.SOLVER_RGCROT, prob.n, args.m, args.k,
+                                          torch.float64), dtype=torch.uint8, device=dev)
     xs = [torch.zeros(prob.n, dtype=torch.float64, device=dev) for _ in range(args.steps)]
     x64s = [torch.zeros(prob.n, dtype=torch.float64, device=dev) for _ in range(args.steps)]
 
     def ir_step(rec, t, b, x):
-        inner = krs.SOLVER_RGCROT if t < N_SWITCH else krs.SOLVER_RBICGSTAB
-        o = krs.make_opts(m=M, k=K, tol=1e-8, inner_solver=inner, inner_tol=args.inner_tol,
-                          max_matvecs=4000)
+        inner = krs.SOLVER_RGCROT if t < args.n_switch else krs.SOLVER_RBICGSTAB
+        o = krs.make_opts(m=args.m, k=args.k, tol=1e-8, inner_solver=inner,
+                          inner_tol=args.inner_tol, max_matvecs=4000)
         return krs.ir_solve(ctx, A64, A32, M32, rec, b, x, o, ws_ir)
 
     # warmup: throwaway recycle space, warmup right-hand sides
-    wrec = krs.Recycle(ctx, prob.n, K, torch.float32)
+    wrec = krs.Recycle(ctx, prob.n, args.k, torch.float32)
     for w in range(args.warmup):
         xw = torch.zeros(prob.n, dtype=torch.float64, device=dev)
         rc, st = ir_step(wrec, w, bs[w], xw)
@@ -468,7 +470,7 @@ def main():
     del wrec
 
     # ---- timed: FP32 inner solves inside FP64 refinement -------------------
-    rec32 = krs.Recycle(ctx, prob.n, K, torch.float32)
+    rec32 = krs.Recycle(ctx, prob.n, args.k, torch.float32)
     krs.timing_reset(ctx)
     krs.timing_enable(ctx, True)
     lat, its, mvs, byt, outer, statuses, second = [], 0, 0, 0.0, [], [], 0
@@ -494,13 +496,13 @@ def main():
     # ---- comparison: the same sequence all in FP64 -------------------------
     fp64 = None
     if not args.no_fp64:
-        rec64 = krs.Recycle(ctx, prob.n, K, torch.float64)
+        rec64 = krs.Recycle(ctx, prob.n, args.k, torch.float64)
         its64 = 0
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for t in range(args.steps):
-            o = krs.make_opts(m=M, k=K, tol=1e-8, max_matvecs=4000)
-            rc, st = krs.hybrid_solve(ctx, A64, M64, rec64, t, N_SWITCH, bs[args.warmup + t],
+            o = krs.make_opts(m=args.m, k=args.k, tol=1e-8, max_matvecs=4000)
+            rc, st = krs.hybrid_solve(ctx, A64, M64, rec64, t, args.n_switch, bs[args.warmup + t],
                                       x64s[t], o, ws64)
             its64 += st.iterations
             log(f"[bench] fp64 step {t}: status {rc} its {st.iterations} "
@@ -535,7 +537,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"porous{args.n}_ir", "grid": f"{args.n}^3",
                    "unknowns": prob.n, "time_steps": args.steps,
-                   "solver": f"hybrid rGCROT({M},{K}) x{N_SWITCH} -> rBiCGStab(k={K})",
+                   "solver": (f"hybrid rGCROT({args.m},{args.k}) x{args.n_switch} -> "
+                              f"rBiCGStab(k={args.k})"),
                    "precond": f"Schwarz 8^3 tiles overlap 1, 5 local {args.local_solver} "
                               f"iterations + 1 global Jacobi sweep",
                    "tol": 1e-8, "inner_tol": args.inner_tol},

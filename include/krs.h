@@ -147,7 +147,8 @@ typedef struct krs_precond_desc {
 
 typedef struct krs_opts {
   int32_t m;               /* Arnoldi steps per cycle (GMRES, rGCROT), 1..64 */
-  int32_t k;               /* maximum recycle dimension (rGCROT update), <= recycle kmax */
+  int32_t k;               /* maximum recycle dimension (rGCROT update), <= recycle kmax;
+                              rGCROT needs k + m + 1 <= 64 (one block pass over [C, V]) */
   int32_t update_recycle;  /* rGCROT: update (U, C) at every cycle end (Alg. 3 line 14a) */
   int32_t inner_solver;    /* IR only: KRS_SOLVER_RGCROT or KRS_SOLVER_RBICGSTAB */
   double tol;              /* relative tolerance on ||b - A x|| / ||b|| */
@@ -218,7 +219,7 @@ int krs_precond_refresh(krs_ctx* ctx, krs_precond* M);
 void krs_precond_destroy(krs_precond* M);
 
 /* Recycle space: borrows U and C (each kmax columns of ld >= N values of
- * `dt`); starts with dimension 0 (no recycling). */
+ * `dt`, 1 <= kmax <= 62); starts with dimension 0 (no recycling). */
 int krs_recycle_create(krs_ctx* ctx, int64_t N, int kmax, krs_dtype dt, void* U, void* C,
                        int64_t ld, krs_recycle** out);
 void krs_recycle_destroy(krs_recycle* rec);

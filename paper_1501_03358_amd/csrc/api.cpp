@@ -179,7 +179,7 @@ int krs_recycle_create(krs_ctx* ctx, int64_t N, int kmax, krs_dtype dt, void* U,
   *out = nullptr;
   if (!valid_dtype(dt)) return set_err(ctx, KRS_ERR_ARG, "unknown dtype");
   if (N < 1 || kmax < 1 || kmax > krs::kMaxK)
-    return set_err(ctx, KRS_ERR_ARG, "recycle space: need N >= 1 and 1 <= kmax <= 32");
+    return set_err(ctx, KRS_ERR_ARG, "recycle space: need N >= 1 and 1 <= kmax <= 62");
   if (ld < N || !U || !C) return set_err(ctx, KRS_ERR_ARG, "recycle space: bad U, C or ld");
   krs_recycle* r = new (std::nothrow) krs_recycle();
   if (!r) return KRS_ERR_ARG;

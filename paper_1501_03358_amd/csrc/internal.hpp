@@ -77,9 +77,9 @@ namespace krs {
 
 constexpr int kPinDoubles = 1 << 16;       // 512 KiB pinned staging
 constexpr int kMaxM = 64;                  // Arnoldi steps per cycle
-constexpr int kMaxK = 32;                  // recycle dimension
-constexpr int kScalarDoubles = 1 << 14;    // device scalar area (128 KiB)
-constexpr int kGramBlocks = 1024;
+constexpr int kMaxK = 62;                  // recycle dimension (block passes take <= 64 columns)
+constexpr int kScalarDoubles = 1 << 15;    // device scalar area (256 KiB)
+constexpr int kGramBlocks = 512;
 constexpr int64_t kFuseMinN = int64_t(1) << 22;  // fused sweep + matvec from this size
 constexpr int kMaxGraphs = 8;                // cached captured iterations per context
 constexpr int64_t kGraphMaxN = int64_t(1) << 20;   // larger grids keep the GPU ahead of the host
@@ -108,7 +108,7 @@ struct Carver {
 
 inline size_t partials_bytes(size_t elem) {
   const size_t red = (size_t)kMaxRedBlocks * (kMaxM + kMaxK + 4);
-  const size_t gram = (size_t)kGramBlocks * 128 * 16;   // 4 x 4 tiles, 128 per block
+  const size_t gram = (size_t)kGramBlocks * 64 * 64;    // Gram blocks up to 64 x 64
   return elem * (red > gram ? red : gram);
 }
 

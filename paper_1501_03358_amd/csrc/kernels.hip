@@ -961,25 +961,27 @@ __global__ __launch_bounds__(kThreads) void k_block_dot_after_update(Cols<T> Q,
 }
 
 // Gram partials X^T Y.  A block streams its contiguous row range in tiles of
-// kGramRows rows: every column's rows are loaded coalesced (64 consecutive
-// rows per wave load) into LDS (column-major, padded row stride); each of the
-// up to 128 4 x 4 output tiles is accumulated by two threads, each over half
-// of the tile's rows, and the halves are added in LDS at the end.
-constexpr int kGramRows = 64;
-constexpr int kGramPad = kGramRows + 1;
+// ROWS rows: every column's rows are loaded coalesced into LDS (column-major,
+// padded row stride ROWS + 1); up to 128 4 x 4 output tiles are accumulated by
+// two threads each, each over half of the tile's rows, the halves added in LDS
+// at the end; up to 256 tiles take one thread each.  ROWS = 64 unless the
+// staged tile would exceed 64 KiB of LDS (FP64 with more than 120 columns).
 constexpr int kGramTile = 4;
 
-template <class T>
+template <class T, int ROWS>
 __global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t n, T* partials,
                                                    int nblk) {
+  constexpr int PAD = ROWS + 1;
   extern __shared__ unsigned char smem_raw[];
   const int na = X.n1 + X.n2, nb = Y.n1 + Y.n2;
   const int nta = (na + kGramTile - 1) / kGramTile, ntb = (nb + kGramTile - 1) / kGramTile;
   const int lda = nta * kGramTile, ldb = ntb * kGramTile;
   T* xs = reinterpret_cast<T*>(smem_raw);
-  T* ys = xs + (size_t)lda * kGramPad;
+  T* ys = xs + (size_t)lda * PAD;
   const int t = threadIdx.x;
-  const int tile = t % 128, half = t / 128;
+  // up to 128 tiles: two threads per tile (halves of the rows); more: one
+  const bool split = nta * ntb <= 128;
+  const int tile = split ? t % 128 : t, half = split ? t / 128 : 0;
   const bool active = tile < nta * ntb;
   const int ta = active ? tile / ntb : 0, tb = active ? tile % ntb : 0;
   T acc[kGramTile][kGramTile];
@@ -988,26 +990,27 @@ __global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t
 #pragma unroll
     for (int j = 0; j < kGramTile; ++j) acc[i][j] = 0;
   const Range rg = block_range(n);
-  for (int64_t r0 = rg.v0; r0 < rg.v1; r0 += kGramRows) {
+  for (int64_t r0 = rg.v0; r0 < rg.v1; r0 += ROWS) {
     const int64_t rows = rg.v1 - r0;
-    for (int idx = t; idx < kGramRows * lda; idx += kThreads) {
-      const int c = idx / kGramRows, rr = idx % kGramRows;
-      xs[c * kGramPad + rr] = (c < na && rr < rows) ? col_ptr(X, c)[r0 + rr] : T(0);
+    for (int idx = t; idx < ROWS * lda; idx += kThreads) {
+      const int c = idx / ROWS, rr = idx % ROWS;
+      xs[c * PAD + rr] = (c < na && rr < rows) ? col_ptr(X, c)[r0 + rr] : T(0);
     }
-    for (int idx = t; idx < kGramRows * ldb; idx += kThreads) {
-      const int c = idx / kGramRows, rr = idx % kGramRows;
-      ys[c * kGramPad + rr] = (c < nb && rr < rows) ? col_ptr(Y, c)[r0 + rr] : T(0);
+    for (int idx = t; idx < ROWS * ldb; idx += kThreads) {
+      const int c = idx / ROWS, rr = idx % ROWS;
+      ys[c * PAD + rr] = (c < nb && rr < rows) ? col_ptr(Y, c)[r0 + rr] : T(0);
     }
     __syncthreads();
     if (active) {
-      const int rb = half * (kGramRows / 2);
+      const int rb = split ? half * (ROWS / 2) : 0;
+      const int re = split ? rb + ROWS / 2 : ROWS;
 #pragma unroll 4
-      for (int rr = rb; rr < rb + kGramRows / 2; ++rr) {
+      for (int rr = rb; rr < re; ++rr) {
         T xa[kGramTile], yb[kGramTile];
 #pragma unroll
-        for (int i = 0; i < kGramTile; ++i) xa[i] = xs[(ta * kGramTile + i) * kGramPad + rr];
+        for (int i = 0; i < kGramTile; ++i) xa[i] = xs[(ta * kGramTile + i) * PAD + rr];
 #pragma unroll
-        for (int j = 0; j < kGramTile; ++j) yb[j] = ys[(tb * kGramTile + j) * kGramPad + rr];
+        for (int j = 0; j < kGramTile; ++j) yb[j] = ys[(tb * kGramTile + j) * PAD + rr];
 #pragma unroll
         for (int i = 0; i < kGramTile; ++i)
 #pragma unroll
@@ -1018,7 +1021,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t
   }
   // second half's tiles into LDS, added to the first half's in a fixed order
   T* red = reinterpret_cast<T*>(smem_raw);
-  if (active && half == 1) {
+  if (active && split && half == 1) {
 #pragma unroll
     for (int i = 0; i < kGramTile; ++i)
 #pragma unroll
@@ -1032,7 +1035,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t
 #pragma unroll
       for (int j = 0; j < kGramTile; ++j) {
         const int a = ta * kGramTile + i, b = tb * kGramTile + j;
-        const T v = acc[i][j] + red[a * ldb + b];
+        const T v = split ? acc[i][j] + red[a * ldb + b] : acc[i][j];
         if (a < na && b < nb) partials[(int64_t)(a * nb + b) * nblk + blockIdx.x] = v;
       }
   }
@@ -1809,11 +1812,18 @@ hipError_t gram(hipStream_t s, const Cols<T>& X, const Cols<T>& Y, int64_t n, T*
   const int na = X.count(), nb = Y.count();
   if (na == 0 || nb == 0) return hipSuccess;
   const int nta = (na + kGramTile - 1) / kGramTile, ntb = (nb + kGramTile - 1) / kGramTile;
-  if (nta * ntb > 128) return hipErrorInvalidValue;   // two 4 x 4 tiles per lane
-  const size_t stage = sizeof(T) * kGramPad * kGramTile * (nta + ntb);
+  if (nta * ntb > kThreads) return hipErrorInvalidValue;   // one 4 x 4 tile per thread
   const size_t red = sizeof(T) * kGramTile * kGramTile * nta * ntb;
-  const size_t smem = stage > red ? stage : red;
-  k_gram<T><<<nblk, kThreads, smem, s>>>(X, Y, n, partials, nblk);
+  auto smem_for = [&](int rows) {
+    const size_t stage = sizeof(T) * (rows + 1) * kGramTile * (nta + ntb);
+    return stage > red ? stage : red;
+  };
+  if (smem_for(64) <= 64 * 1024)
+    k_gram<T, 64><<<nblk, kThreads, smem_for(64), s>>>(X, Y, n, partials, nblk);
+  else if (smem_for(32) <= 64 * 1024)
+    k_gram<T, 32><<<nblk, kThreads, smem_for(32), s>>>(X, Y, n, partials, nblk);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

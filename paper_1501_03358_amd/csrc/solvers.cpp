@@ -22,8 +22,10 @@ template <class T>
 struct Ws {
   // scalar area layout (doubles)
   static constexpr int kH1 = 0, kH2 = 128, kHcol = 256, kInv = 384, kFlagOff = 392;
-  static constexpr int kCoef = 512, kXi = 768, kNrm = 832, kAux = 840, kM = 1024;
-  static constexpr int kGram1 = 4096, kGram2 = 8192;
+  // Gram results: up to 64 x 62 and 62 x 62; kM: the recycle update's two
+  // coefficient blocks, up to (63 + 64) x 62
+  static constexpr int kCoef = 512, kXi = 768, kNrm = 832, kAux = 840;
+  static constexpr int kGram1 = 4096, kGram2 = 8192, kM = 12288;
 };
 
 // y-space operator A~ = A M^-1 and its pieces
