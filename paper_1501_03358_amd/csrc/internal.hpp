@@ -79,7 +79,17 @@ constexpr int kPinDoubles = 1 << 16;       // 512 KiB pinned staging
 constexpr int kMaxM = 64;                  // Arnoldi steps per cycle
 constexpr int kMaxK = 62;                  // recycle dimension (block passes take <= 64 columns)
 constexpr int kScalarDoubles = 1 << 15;    // device scalar area (256 KiB)
-constexpr int kGramBlocks = 512;
+constexpr int64_t kGramPartials = int64_t(1) << 21;   // Gram partial sums (entries)
+constexpr int kGramMaxBlocks = 2048;
+// Blocks of a Gram product of na x nb entries over n rows: as many as the
+// partials hold (one partial per entry and block), at most one per 256 rows.
+inline int gram_blocks(int na, int nb, int64_t n) {
+  int64_t b = kGramPartials / ((int64_t)(na > 0 ? na : 1) * (nb > 0 ? nb : 1));
+  if (b > kGramMaxBlocks) b = kGramMaxBlocks;
+  const int64_t by_rows = (n + 255) / 256;
+  if (b > by_rows) b = by_rows;
+  return b < 1 ? 1 : (int)b;
+}
 constexpr int64_t kFuseMinN = int64_t(1) << 22;  // fused sweep + matvec from this size
 constexpr int kMaxGraphs = 8;                // cached captured iterations per context
 constexpr int64_t kGraphMaxN = int64_t(1) << 20;   // larger grids keep the GPU ahead of the host
@@ -108,7 +118,7 @@ struct Carver {
 
 inline size_t partials_bytes(size_t elem) {
   const size_t red = (size_t)kMaxRedBlocks * (kMaxM + kMaxK + 4);
-  const size_t gram = (size_t)kGramBlocks * 64 * 64;    // Gram blocks up to 64 x 64
+  const size_t gram = (size_t)kGramPartials;
   return elem * (red > gram ? red : gram);
 }
 

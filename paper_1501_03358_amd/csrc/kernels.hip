@@ -643,7 +643,7 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T*
 // ---------------------------------------------------------------------------
 // tall-skinny block products
 //
-// Each block streams one contiguous range of rows of every column, with
+// The grid streams every column in turn-dealt packs (first_row, grid_step), with
 // 16-byte loads (W = 16 / sizeof(T) rows per load) when every pointer is
 // 16-byte aligned and every leading dimension a multiple of W, else with
 // element loads (W = 1).  Columns go in groups of 8 whose loads carry no
@@ -660,6 +660,22 @@ template <class T, int W>
 __device__ __forceinline__ Pk<T, W> ldp(const T* p, int64_t iv) {
   return reinterpret_cast<const Pk<T, W>*>(p)[iv];
 }
+// Nontemporal load of a pack: for data streamed once per kernel (the column
+// sets and vectors of the block products), so that it does not displace
+// cache lines that are reused.
+template <class T, int W>
+__device__ __forceinline__ Pk<T, W> ldn(const T* p, int64_t iv) {
+  Pk<T, W> x;
+  if constexpr (W == 1) {
+    x.v[0] = __builtin_nontemporal_load(p + iv);
+  } else {
+    typedef T V __attribute__((ext_vector_type(W)));
+    const V a = __builtin_nontemporal_load(reinterpret_cast<const V*>(p) + iv);
+#pragma unroll
+    for (int e = 0; e < W; ++e) x.v[e] = a[e];
+  }
+  return x;
+}
 template <class T, int W>
 __device__ __forceinline__ void stp(T* p, int64_t iv, const Pk<T, W>& x) {
   reinterpret_cast<Pk<T, W>*>(p)[iv] = x;
@@ -667,34 +683,54 @@ __device__ __forceinline__ void stp(T* p, int64_t iv, const Pk<T, W>& x) {
 
 constexpr int kGroup = 8;
 
-struct Range {
-  int64_t v0, v1;
-};
-__device__ __forceinline__ Range block_range(int64_t npk) {
-  const int64_t per = (npk + gridDim.x - 1) / gridDim.x;
-  Range r;
-  r.v0 = (int64_t)blockIdx.x * per;
-  r.v1 = r.v0 + per < npk ? r.v0 + per : npk;
-  return r;
+// Rows (or packs of W rows) are dealt to the grid's threads in turn: at any
+// moment the whole grid reads one contiguous stretch of every column, which
+// streams from HBM faster than one far-apart range per block.
+__device__ __forceinline__ int64_t first_row() {
+  return (int64_t)blockIdx.x * kThreads + threadIdx.x;
+}
+__device__ __forceinline__ int64_t grid_step() { return (int64_t)gridDim.x * kThreads; }
+
+// Calls f(c, pack) for the columns c = 0, 1, ... of row pack iv, in order.
+// The loads of up to kBatch columns are all issued before the first is used
+// (one branch per group of kGroup), so that many loads per lane are in flight;
+// a trailing group repeats column nc - 1, and f sees those repeats with c >= nc.
+constexpr int kBatch = 32;
+
+template <class T, int W, int NC, class ColPtr, class F>
+__device__ __forceinline__ void for_cols(const ColPtr& colp, int nc, int64_t iv, const F& f) {
+  constexpr int NB = NC == 0 ? kGroup : (NC < kBatch ? NC : kBatch);
+#pragma unroll
+  for (int b = 0; b < NC; b += NB) {
+    if (b < nc) {
+      Pk<T, W> q[NB];
+#pragma unroll
+      for (int g = 0; g < NB; g += kGroup)
+        if (b + g < nc) {
+#pragma unroll
+          for (int u = 0; u < kGroup; ++u) q[g + u] = ldn<T, W>(colp(min(b + g + u, nc - 1)), iv);
+        }
+#pragma unroll
+      for (int g = 0; g < NB; g += kGroup)
+        if (b + g < nc) {
+#pragma unroll
+          for (int u = 0; u < kGroup; ++u) f(b + g + u, q[g + u]);
+        }
+    }
+  }
 }
 
 template <class T, int W, int NC>
 __device__ __forceinline__ void dot_rows(const Cols<T>& Q, int nc, const T* __restrict__ w,
-                                         int64_t i0, int64_t i1, T (&acc)[NC + 1]) {
-  for (int64_t iv = i0; iv < i1; iv += kThreads) {
-    const Pk<T, W> wv = ldp<T, W>(w, iv);
+                                         int64_t i0, int64_t i1, int64_t step,
+                                         T (&acc)[NC + 1]) {
+  for (int64_t iv = i0; iv < i1; iv += step) {
+    const Pk<T, W> wv = ldn<T, W>(w, iv);
+    for_cols<T, W, NC>([&](int c) { return col_ptr(Q, c); }, nc, iv,
+                       [&](int c, const Pk<T, W>& q) {
 #pragma unroll
-    for (int g = 0; g < NC; g += kGroup) {
-      if (g < nc) {
-        Pk<T, W> q[kGroup];
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) q[u] = ldp<T, W>(col_ptr(Q, min(g + u, nc - 1)), iv);
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u)
-#pragma unroll
-          for (int e = 0; e < W; ++e) acc[g + u] += q[u].v[e] * wv.v[e];
-      }
-    }
+                         for (int e = 0; e < W; ++e) acc[c] += q.v[e] * wv.v[e];
+                       });
 #pragma unroll
     for (int e = 0; e < W; ++e) acc[NC] += wv.v[e] * wv.v[e];
   }
@@ -709,10 +745,9 @@ __global__ __launch_bounds__(kThreads) void k_block_dot(Cols<T> Q, const T* __re
 #pragma unroll
   for (int c = 0; c <= NC; ++c) acc[c] = 0;
   const int64_t npk = n / W;
-  const Range r = block_range(npk);
-  dot_rows<T, W, NC>(Q, nc, w, r.v0 + threadIdx.x, r.v1, acc);
+  dot_rows<T, W, NC>(Q, nc, w, first_row(), npk, grid_step(), acc);
   if (W > 1 && blockIdx.x == gridDim.x - 1)
-    dot_rows<T, 1, NC>(Q, nc, w, npk * W + threadIdx.x, n, acc);
+    dot_rows<T, 1, NC>(Q, nc, w, npk * W + threadIdx.x, n, kThreads, acc);
   if (self_dot) {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -724,26 +759,19 @@ __global__ __launch_bounds__(kThreads) void k_block_dot(Cols<T> Q, const T* __re
 template <class T, int W, int NC>
 __device__ __forceinline__ void update_rows(const Cols<T>& Q, int nc, const T* cf,
                                             const T* w_in, T* w_out, T sc, int64_t i0, int64_t i1,
-                                            T& acc) {
-  for (int64_t iv = i0; iv < i1; iv += kThreads) {
+                                            int64_t step, T& acc) {
+  for (int64_t iv = i0; iv < i1; iv += step) {
     Pk<T, W> v;
-    if (w_in) v = ldp<T, W>(w_in, iv);
+    if (w_in) v = ldn<T, W>(w_in, iv);
     else {
 #pragma unroll
       for (int e = 0; e < W; ++e) v.v[e] = 0;
     }
+    for_cols<T, W, NC>([&](int c) { return col_ptr(Q, c); }, nc, iv,
+                       [&](int c, const Pk<T, W>& q) {
 #pragma unroll
-    for (int g = 0; g < NC; g += kGroup) {
-      if (g < nc) {
-        Pk<T, W> q[kGroup];
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) q[u] = ldp<T, W>(col_ptr(Q, min(g + u, nc - 1)), iv);
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u)
-#pragma unroll
-          for (int e = 0; e < W; ++e) v.v[e] += cf[g + u] * q[u].v[e];
-      }
-    }
+                         for (int e = 0; e < W; ++e) v.v[e] += cf[c] * q.v[e];
+                       });
 #pragma unroll
     for (int e = 0; e < W; ++e) {
       v.v[e] *= sc;
@@ -766,10 +794,10 @@ __global__ __launch_bounds__(kThreads) void k_block_update(Cols<T> Q, const doub
   const T sc = scale ? (T)scale[0] : T(1);
   T acc[1] = {0};
   const int64_t npk = n / W;
-  const Range r = block_range(npk);
-  update_rows<T, W, NC>(Q, nc, cf, w_in, w_out, sc, r.v0 + threadIdx.x, r.v1, acc[0]);
+  update_rows<T, W, NC>(Q, nc, cf, w_in, w_out, sc, first_row(), npk, grid_step(), acc[0]);
   if (W > 1 && blockIdx.x == gridDim.x - 1)
-    update_rows<T, 1, NC>(Q, nc, cf, w_in, w_out, sc, npk * W + threadIdx.x, n, acc[0]);
+    update_rows<T, 1, NC>(Q, nc, cf, w_in, w_out, sc, npk * W + threadIdx.x, n, kThreads,
+                          acc[0]);
   if (norm) reduce_store<T, 1>(acc, 1, partials, nblk);
 }
 
@@ -779,13 +807,13 @@ __global__ __launch_bounds__(kThreads) void k_block_update(Cols<T> Q, const doub
 template <class T, int W, int NC>
 __device__ __forceinline__ void dau_rows(const Cols<T>& Q, int nc, const T* cf,
                                          const T* __restrict__ w, int64_t i0, int64_t i1,
-                                         T (&acc)[NC + 1]) {
-  for (int64_t iv = i0; iv < i1; iv += kThreads) {
+                                         int64_t step, T (&acc)[NC + 1]) {
+  for (int64_t iv = i0; iv < i1; iv += step) {
     Pk<T, W> q[NC];
-    Pk<T, W> v = ldp<T, W>(w, iv);
+    Pk<T, W> v = ldn<T, W>(w, iv);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      q[c] = ldp<T, W>(col_ptr(Q, min(c, nc - 1)), iv);
+      q[c] = ldn<T, W>(col_ptr(Q, min(c, nc - 1)), iv);
 #pragma unroll
       for (int e = 0; e < W; ++e) v.v[e] -= cf[c] * q[c].v[e];
     }
@@ -815,10 +843,10 @@ __global__ __launch_bounds__(kThreads) void k_block_dot_lds(Cols<T> Q, const T* 
   __shared__ T red[G][NC + 1];
   const int t = threadIdx.x;
   const int nc = Q.n1 + Q.n2;
-  const Range rg = block_range(n);
+  const int64_t i_first = (int64_t)blockIdx.x * R, i_step = (int64_t)gridDim.x * R;
   T pq[PE], pw = T(0);
   auto fetch = [&](int64_t i0) {
-    const int64_t rows = rg.v1 - i0;
+    const int64_t rows = n - i0;
 #pragma unroll
     for (int k = 0; k < PE; ++k) {
       const int e = t + kThreads * k, c = e / R, rr = e % R;
@@ -828,8 +856,8 @@ __global__ __launch_bounds__(kThreads) void k_block_dot_lds(Cols<T> Q, const T* 
   };
   const int my_c = t % NC, my_g = t / NC;
   T acc = 0, accw = 0;
-  if (rg.v0 < rg.v1) fetch(rg.v0);
-  for (int64_t i0 = rg.v0; i0 < rg.v1; i0 += R) {
+  if (i_first < n) fetch(i_first);
+  for (int64_t i0 = i_first; i0 < n; i0 += i_step) {
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < PE; ++k) {
@@ -841,7 +869,7 @@ __global__ __launch_bounds__(kThreads) void k_block_dot_lds(Cols<T> Q, const T* 
       accw += pw * pw;
     }
     __syncthreads();
-    if (i0 + R < rg.v1) fetch(i0 + R);
+    if (i0 + i_step < n) fetch(i0 + i_step);
 #pragma unroll 4
     for (int rr = my_g * RG; rr < (my_g + 1) * RG; ++rr) acc += qs[rr][my_c] * ws_[rr];
   }
@@ -881,11 +909,11 @@ __global__ __launch_bounds__(kThreads) void k_block_dot_after_update_lds(
   const int t = threadIdx.x;
   const int nc = Q.n1 + Q.n2;
   for (int c = t; c < NC; c += kThreads) cf[c] = c < nc ? (T)coef[c] : T(0);
-  const Range rg = block_range(n);
+  const int64_t i_first = (int64_t)blockIdx.x * R, i_step = (int64_t)gridDim.x * R;
   // this thread's staged elements: element e = t + kThreads * k -> column e / R, row e % R
   T pq[PE], pw = T(0);
   auto fetch = [&](int64_t i0) {
-    const int64_t rows = rg.v1 - i0;
+    const int64_t rows = n - i0;
 #pragma unroll
     for (int k = 0; k < PE; ++k) {
       const int e = t + kThreads * k, c = e / R, rr = e % R;
@@ -896,8 +924,8 @@ __global__ __launch_bounds__(kThreads) void k_block_dot_after_update_lds(
   const int my_c = t % NC, my_g = t / NC;
   const int vrow = t / LP, vpart = t % LP;
   T acc = 0, accw = 0;
-  if (rg.v0 < rg.v1) fetch(rg.v0);
-  for (int64_t i0 = rg.v0; i0 < rg.v1; i0 += R) {
+  if (i_first < n) fetch(i_first);
+  for (int64_t i0 = i_first; i0 < n; i0 += i_step) {
     __syncthreads();   // previous tile fully used
 #pragma unroll
     for (int k = 0; k < PE; ++k) {
@@ -906,7 +934,7 @@ __global__ __launch_bounds__(kThreads) void k_block_dot_after_update_lds(
     }
     if (t < R) vs[t] = pw;
     __syncthreads();
-    if (i0 + R < rg.v1) fetch(i0 + R);
+    if (i0 + i_step < n) fetch(i0 + i_step);
     // v = w - Q cf for row vrow: LP lanes each take NC / LP columns
     T sdot = 0;
 #pragma unroll
@@ -950,19 +978,18 @@ __global__ __launch_bounds__(kThreads) void k_block_dot_after_update(Cols<T> Q,
 #pragma unroll
   for (int c = 0; c <= NC; ++c) acc[c] = 0;
   const int64_t npk = n / W;
-  const Range r = block_range(npk);
-  dau_rows<T, W, NC>(Q, nc, cf, w, r.v0 + threadIdx.x, r.v1, acc);
+  dau_rows<T, W, NC>(Q, nc, cf, w, first_row(), npk, grid_step(), acc);
   if (W > 1 && blockIdx.x == gridDim.x - 1)
-    dau_rows<T, 1, NC>(Q, nc, cf, w, npk * W + threadIdx.x, n, acc);
+    dau_rows<T, 1, NC>(Q, nc, cf, w, npk * W + threadIdx.x, n, kThreads, acc);
 #pragma unroll
   for (int c = 0; c < NC; ++c)
     if (c == nc) acc[c] = acc[NC];
   reduce_store<T, NC + 1>(acc, nc + 1, partials, nblk);
 }
 
-// Gram partials X^T Y.  A block streams its contiguous row range in tiles of
-// ROWS rows: every column's rows are loaded coalesced into LDS (column-major,
-// padded row stride ROWS + 1); up to 128 4 x 4 output tiles are accumulated by
+// Gram partials X^T Y.  The grid streams the rows in turn-dealt tiles of
+// ROWS rows: every column's rows are loaded coalesced, one tile ahead, into
+// registers and then into LDS (column-major, padded row stride ROWS + 1); up to 128 4 x 4 output tiles are accumulated by
 // two threads each, each over half of the tile's rows, the halves added in LDS
 // at the end; up to 256 tiles take one thread each.  ROWS = 64 unless the
 // staged tile would exceed 64 KiB of LDS (FP64 with more than 120 columns).
@@ -989,18 +1016,32 @@ __global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t
   for (int i = 0; i < kGramTile; ++i)
 #pragma unroll
     for (int j = 0; j < kGramTile; ++j) acc[i][j] = 0;
-  const Range rg = block_range(n);
-  for (int64_t r0 = rg.v0; r0 < rg.v1; r0 += ROWS) {
-    const int64_t rows = rg.v1 - r0;
-    for (int idx = t; idx < ROWS * lda; idx += kThreads) {
-      const int c = idx / ROWS, rr = idx % ROWS;
-      xs[c * PAD + rr] = (c < na && rr < rows) ? col_ptr(X, c)[r0 + rr] : T(0);
+  // staged element idx = t + kThreads * k: column idx / ROWS, row idx % ROWS;
+  // the next tile is loaded into registers while the current one is used
+  constexpr int MAXP = ROWS * 64 / kThreads;     // lda, ldb <= 64
+  const int nx = ROWS * lda, ny = ROWS * ldb;
+  T rx[MAXP], ry[MAXP];
+  auto fetch = [&](int64_t r0) {
+    const int64_t rows = n - r0;
+#pragma unroll
+    for (int k = 0; k < MAXP; ++k) {
+      const int idx = t + kThreads * k, c = idx / ROWS, rr = idx % ROWS;
+      rx[k] = (c < na && rr < rows) ? col_ptr(X, c)[r0 + rr] : T(0);
+      ry[k] = (c < nb && rr < rows) ? col_ptr(Y, c)[r0 + rr] : T(0);
     }
-    for (int idx = t; idx < ROWS * ldb; idx += kThreads) {
-      const int c = idx / ROWS, rr = idx % ROWS;
-      ys[c * PAD + rr] = (c < nb && rr < rows) ? col_ptr(Y, c)[r0 + rr] : T(0);
+  };
+  const int64_t step = (int64_t)gridDim.x * ROWS;
+  if ((int64_t)blockIdx.x * ROWS < n) fetch((int64_t)blockIdx.x * ROWS);
+  for (int64_t r0 = (int64_t)blockIdx.x * ROWS; r0 < n; r0 += step) {
+    __syncthreads();   // the previous tile is no longer read
+#pragma unroll
+    for (int k = 0; k < MAXP; ++k) {
+      const int idx = t + kThreads * k, c = idx / ROWS, rr = idx % ROWS;
+      if (idx < nx) xs[c * PAD + rr] = rx[k];
+      if (idx < ny) ys[c * PAD + rr] = ry[k];
     }
     __syncthreads();
+    if (r0 + step < n) fetch(r0 + step);
     if (active) {
       const int rb = split ? half * (ROWS / 2) : 0;
       const int re = split ? rb + ROWS / 2 : ROWS;
@@ -1017,8 +1058,8 @@ __global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t
           for (int j = 0; j < kGramTile; ++j) acc[i][j] += xa[i] * yb[j];
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   // second half's tiles into LDS, added to the first half's in a fixed order
   T* red = reinterpret_cast<T*>(smem_raw);
   if (active && split && half == 1) {
@@ -1151,8 +1192,7 @@ __global__ __launch_bounds__(kThreads) void k_residual_norm_v(Grid3 g, const T* 
                                                               T* __restrict__ y, T* partials) {
   T acc = 0;
   const int64_t npk = g.n / W;
-  const Range r = block_range(npk);
-  for (int64_t iv = r.v0 + threadIdx.x; iv < r.v1; iv += kThreads) {
+  for (int64_t iv = first_row(); iv < npk; iv += grid_step()) {
     T ax[W], xc[W];
     apply_pack<T, W>(g, A, x, iv, ax, xc);
     const Pk<T, W> bb = ldp<T, W>(b, iv);
@@ -1247,25 +1287,17 @@ __global__ __launch_bounds__(kThreads) void k_bicg_p(const T* __restrict__ r, T*
 template <class T, int W, int NC>
 __device__ __forceinline__ void sv_rows(const Cols<T>& C, const T* cf, T alpha,
                                         const T* __restrict__ r, T* v, T* __restrict__ sv,
-                                        int64_t i0, int64_t i1, T& acc) {
+                                        int64_t i0, int64_t i1, int64_t step, T& acc) {
   const int kc = C.n1;
-  for (int64_t iv = i0; iv < i1; iv += kThreads) {
-    Pk<T, W> vi = ldp<T, W>(v, iv);
+  for (int64_t iv = i0; iv < i1; iv += step) {
+    Pk<T, W> vi = ldn<T, W>(v, iv);
+    const Pk<T, W> ri = ldn<T, W>(r, iv);
+    for_cols<T, W, NC>([&](int c) { return C.p1 + (int64_t)c * C.ld1; }, kc, iv,
+                       [&](int c, const Pk<T, W>& q) {
 #pragma unroll
-    for (int g = 0; g < NC; g += kGroup) {
-      if (g < kc) {
-        Pk<T, W> q[kGroup];
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u)
-          q[u] = ldp<T, W>(C.p1 + (int64_t)min(g + u, kc - 1) * C.ld1, iv);
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u)
-#pragma unroll
-          for (int e = 0; e < W; ++e) vi.v[e] -= cf[g + u] * q[u].v[e];
-      }
-    }
+                         for (int e = 0; e < W; ++e) vi.v[e] -= cf[c] * q.v[e];
+                       });
     if (NC > 0) stp<T, W>(v, iv, vi);
-    const Pk<T, W> ri = ldp<T, W>(r, iv);
     Pk<T, W> si;
 #pragma unroll
     for (int e = 0; e < W; ++e) {
@@ -1290,10 +1322,9 @@ __global__ __launch_bounds__(kThreads) void k_bicg_sv(Cols<T> C, const T* __rest
   const T alpha = (T)sc[kAlpha];
   T acc[1] = {0};
   const int64_t npk = n / W;
-  const Range rg = block_range(npk);
-  sv_rows<T, W, NC>(C, cf, alpha, r, v, sv, rg.v0 + threadIdx.x, rg.v1, acc[0]);
+  sv_rows<T, W, NC>(C, cf, alpha, r, v, sv, first_row(), npk, grid_step(), acc[0]);
   if (W > 1 && blockIdx.x == gridDim.x - 1)
-    sv_rows<T, 1, NC>(C, cf, alpha, r, v, sv, npk * W + threadIdx.x, n, acc[0]);
+    sv_rows<T, 1, NC>(C, cf, alpha, r, v, sv, npk * W + threadIdx.x, n, kThreads, acc[0]);
   reduce_store<T, 1>(acc, 1, partials, nblk);
 }
 
@@ -1302,25 +1333,17 @@ __device__ __forceinline__ void yr_rows(const Cols<T>& C, const T* cf, T alpha, 
                                         const T* __restrict__ t, const T* __restrict__ sv,
                                         const T* __restrict__ p, T* __restrict__ y,
                                         T* __restrict__ r, const T* __restrict__ rt, int64_t i0,
-                                        int64_t i1, T (&acc)[2]) {
+                                        int64_t i1, int64_t step, T (&acc)[2]) {
   const int kc = C.n1;
-  for (int64_t iv = i0; iv < i1; iv += kThreads) {
-    Pk<T, W> ti = ldp<T, W>(t, iv);
+  for (int64_t iv = i0; iv < i1; iv += step) {
+    Pk<T, W> ti = ldn<T, W>(t, iv);
+    const Pk<T, W> si = ldn<T, W>(sv, iv), pi = ldn<T, W>(p, iv), rti = ldn<T, W>(rt, iv);
+    Pk<T, W> yi = ldn<T, W>(y, iv), ri;
+    for_cols<T, W, NC>([&](int c) { return C.p1 + (int64_t)c * C.ld1; }, kc, iv,
+                       [&](int c, const Pk<T, W>& q) {
 #pragma unroll
-    for (int g = 0; g < NC; g += kGroup) {
-      if (g < kc) {
-        Pk<T, W> q[kGroup];
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u)
-          q[u] = ldp<T, W>(C.p1 + (int64_t)min(g + u, kc - 1) * C.ld1, iv);
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u)
-#pragma unroll
-          for (int e = 0; e < W; ++e) ti.v[e] -= cf[g + u] * q[u].v[e];
-      }
-    }
-    const Pk<T, W> si = ldp<T, W>(sv, iv), pi = ldp<T, W>(p, iv), rti = ldp<T, W>(rt, iv);
-    Pk<T, W> yi = ldp<T, W>(y, iv), ri;
+                         for (int e = 0; e < W; ++e) ti.v[e] -= cf[c] * q.v[e];
+                       });
 #pragma unroll
     for (int e = 0; e < W; ++e) {
       yi.v[e] += alpha * pi.v[e] + omega * si.v[e];
@@ -1349,10 +1372,11 @@ __global__ __launch_bounds__(kThreads) void k_bicg_yr(Cols<T> C, const T* __rest
   const T alpha = (T)sc[kAlpha], omega = (T)sc[kOmega];
   T acc[2] = {0, 0};
   const int64_t npk = n / W;
-  const Range rg = block_range(npk);
-  yr_rows<T, W, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, rg.v0 + threadIdx.x, rg.v1, acc);
+  yr_rows<T, W, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, first_row(), npk, grid_step(),
+                    acc);
   if (W > 1 && blockIdx.x == gridDim.x - 1)
-    yr_rows<T, 1, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, npk * W + threadIdx.x, n, acc);
+    yr_rows<T, 1, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, npk * W + threadIdx.x, n,
+                      kThreads, acc);
   reduce_store<T, 2>(acc, 2, partials, nblk);
 }
 

@@ -215,14 +215,13 @@ int harmonic_update(krs_ctx* ctx, krs_recycle* rec, const T* V, int64_t ld, int 
   if (kc > 0) {
     const int na = kc + jj + 1;
     const double NW = (double)n * sizeof(T);
+    const int gb1 = gram_blocks(na, kc, n), gb2 = gram_blocks(kc, kc, n);
     KRS_LAUNCH(ctx, KRS_K_GRAM, NW * (2 * kc + jj + 1),
-               gram<T>(s, cols<T>(C, ldr, kc, V, ld, jj + 1), cols<T>(U, ldr, kc), n, part,
-                       kGramBlocks));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
-               finish_sum<T>(s, part, kGramBlocks, na * kc, sc + Ws<T>::kGram1));
+               gram<T>(s, cols<T>(C, ldr, kc, V, ld, jj + 1), cols<T>(U, ldr, kc), n, part, gb1));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, gb1, na * kc, sc + Ws<T>::kGram1));
     KRS_LAUNCH(ctx, KRS_K_GRAM, NW * kc,
-               gram<T>(s, cols<T>(U, ldr, kc), cols<T>(U, ldr, kc), n, part, kGramBlocks));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, kGramBlocks, kc * kc, sc + Ws<T>::kGram2));
+               gram<T>(s, cols<T>(U, ldr, kc), cols<T>(U, ldr, kc), n, part, gb2));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, gb2, kc * kc, sc + Ws<T>::kGram2));
     int rc = read_dev(ctx, sc + Ws<T>::kGram1, na * kc);
     if (rc) return rc;
     for (int a = 0; a < kc; ++a)
@@ -610,10 +609,10 @@ int recycle_setup_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs
   std::vector<double> G((size_t)kc * kc), R((size_t)kc * kc), Ri((size_t)kc * kc);
   const double NW = (double)n * sizeof(T);
   for (int pass = 0; pass < 2; ++pass) {
+    const int gb = gram_blocks(kc, kc, n);
     KRS_LAUNCH(ctx, KRS_K_GRAM, NW * kc,
-               gram<T>(s, cols<T>(C, ldr, kc), cols<T>(C, ldr, kc), n, part, kGramBlocks));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
-               finish_sum<T>(s, part, kGramBlocks, kc * kc, sc + Ws<T>::kGram1));
+               gram<T>(s, cols<T>(C, ldr, kc), cols<T>(C, ldr, kc), n, part, gb));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, gb, kc * kc, sc + Ws<T>::kGram1));
     int rc = read_dev(ctx, sc + Ws<T>::kGram1, kc * kc);
     if (rc) return rc;
     for (int a = 0; a < kc; ++a)
