@@ -1226,15 +1226,20 @@ __global__ __launch_bounds__(kThreads) void k_finish_sum(const T* partials, int 
 // ("twice is enough" criterion of Kahan and Parlett, in the form of Daniel,
 // Gragg, Kaufman and Stewart); then h = h1 and the norm is final, and *skip
 // tells the second pass and its finishing kernel to return at once.
+// One wave: lane l takes columns l, l + 64, ...
 __global__ void k_cgs_decide(int ncols, const double* h1, double* hcol, double* inv, int* flag,
                              int* skip) {
-  if (threadIdx.x != 0) return;
-  double q = 0;
-  for (int c = 0; c < ncols; ++c) q += h1[c] * h1[c];
+  const int lane = threadIdx.x;
+  double ql = 0;
+  for (int c = lane; c < ncols; c += 64) ql += h1[c] * h1[c];
+  const double q = wave_sum(ql);
   const double w2 = h1[ncols];
   const double r2 = w2 - q;
-  if (r2 >= 0.5 * w2 && isfinite(r2)) {
-    for (int c = 0; c < ncols; ++c) hcol[c] = h1[c];
+  const bool one_pass = r2 >= 0.5 * w2 && isfinite(r2);
+  if (one_pass)
+    for (int c = lane; c < ncols; c += 64) hcol[c] = h1[c];
+  if (lane != 0) return;
+  if (one_pass) {
     const double hn = sqrt(r2);
     hcol[ncols] = hn;
     inv[0] = hn > 0 ? 1.0 / hn : 0.0;
@@ -1247,12 +1252,15 @@ __global__ void k_cgs_decide(int ncols, const double* h1, double* hcol, double* 
 
 __global__ void k_cgs2_combine(int ncols, const double* h1, const double* h2, double* hcol,
                                double* inv, int* flag, const int* skip) {
-  if (threadIdx.x != 0 || (skip && *skip)) return;
-  double q = 0;
-  for (int c = 0; c < ncols; ++c) {
+  if (skip && *skip) return;
+  const int lane = threadIdx.x;
+  double ql = 0;
+  for (int c = lane; c < ncols; c += 64) {
     hcol[c] = h1[c] + h2[c];
-    q += h2[c] * h2[c];
+    ql += h2[c] * h2[c];
   }
+  const double q = wave_sum(ql);
+  if (lane != 0) return;
   const double nrm2 = h2[ncols];
   double hn2 = nrm2 - q;
   int f = 0;
@@ -1403,11 +1411,13 @@ __device__ __forceinline__ void finish_cols(const T* partials, int nblk, int nco
                                             double* out, double* sh) {
   constexpr int NW = kThreads / 64, NJ = kFinishCols / NW;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // wave w takes columns w, w + NW, ...; each lane's loads for all of them
-  // are issued together
+  // wave w takes columns w, w + NW, ...; each lane's loads for all of them,
+  // over four of its partials, are issued together (one grid of partials is
+  // read in a few round trips; each lane still adds its partials in order)
   double acc[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) acc[j] = 0;
+#pragma unroll 4
   for (int b = lane; b < nblk; b += 64) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
@@ -1492,8 +1502,8 @@ __global__ __launch_bounds__(kThreads) void k_bicg_exit_vec(const T* __restrict_
                                                             const double* sc, int64_t n) {
   if (sc[kDone] != (double)kConvHalf) return;
   const T alpha = (T)sc[kAlpha];
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i < n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
     y[i] += alpha * p[i];
     r[i] = sv[i];
   }
@@ -1969,7 +1979,8 @@ hipError_t bicg_finish_half(hipStream_t s, const T* partials, int nblk, double* 
 template <class T>
 hipError_t bicg_exit_vec(hipStream_t s, const T* p, T* y, const T* sv, T* r, const double* sc,
                          int64_t n) {
-  if (n > 0) k_bicg_exit_vec<T><<<grid_for(n), kThreads, 0, s>>>(p, y, sv, r, sc, n);
+  // a small grid: the kernel usually returns at once, and runs at most once per solve
+  if (n > 0) k_bicg_exit_vec<T><<<std::min(grid_for(n), 512), kThreads, 0, s>>>(p, y, sv, r, sc, n);
   return hipGetLastError();
 }
 template <class T>
