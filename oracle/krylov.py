@@ -241,6 +241,125 @@ def harmonic_ritz_update(rec: Recycle, V, Hbar, B, k):
     return ties
 
 
+@dataclasses.dataclass
+class GcrotParams:
+    """Parameters of the GCROT rule for line 14a (Sec. 3 lists them with
+    their values): kt outer vectors kept at a truncation (k - 10 there), s
+    latest inner vectors to select from (m / 2), p inner vectors selected per
+    cycle (1 or 2).  The fourth parameter, latest inner vectors kept, is 0
+    in every run of the paper and is not modelled."""
+    kt: int
+    s: int
+    p: int
+
+
+def _small_gs(H, G, drop=1e-10):
+    """Orthonormalise the columns of H G ((j+1) x q) in order, classical
+    Gram-Schmidt applied twice, dropping a column whose remainder is at most
+    `drop` times its norm.  Returns (Q, Gc) with H Gc = Q, Q^T Q = I."""
+    Q, Gc = [], []
+    for i in range(G.shape[1]):
+        g = G[:, i].copy()
+        h = H @ g
+        h0 = _norm(h)
+        if h0 == 0.0:
+            continue
+        for _ in range(2):
+            for q, gc in zip(Q, Gc):
+                t = q @ h
+                h = h - t * q
+                g = g - t * gc
+        nrm = _norm(h)
+        if nrm <= drop * h0:
+            continue
+        Q.append(h / nrm)
+        Gc.append(g / nrm)
+    if not Q:
+        return np.zeros((H.shape[0], 0)), np.zeros((G.shape[0], 0))
+    return np.column_stack(Q), np.column_stack(Gc)
+
+
+def gcrot_update(rec: Recycle, V, Hbar, B, y, k, par: GcrotParams, prev):
+    """Line 14a of Alg. 3 by the GCROT rule, which takes the recycle space
+    from angles between successive search spaces (Sec. 2.3; the details are
+    in the GCROT references, so this is a reading).
+
+    The cycle's search space is range(V_j) + range(U) with images
+    A~ (V_j g - U B g) = V_{j+1} Hbar g, orthogonal to C.
+      1. The cycle's own correction g = y (its image is r_old - r_new) joins
+         the outer space.
+      2. Selection space of this cycle: the images of the last s inner
+         vectors, S = V_{j+1} Hbar[:, j-s:j] with orthonormal basis V Qs.
+         With `prev` the previous cycle's selection space (orthonormal
+         columns), the p principal vectors of S making the smallest angles
+         with `prev` (largest singular values of prev^T V Qs, each vector's
+         largest component made positive) join the outer space too.
+      3. The new images are orthonormalised in order (Gram-Schmidt twice,
+         dropping dependent ones): q new pairs u = (V_j - U B) g,
+         c = V_{j+1} Hbar g.
+      4. If kc + q > k, the outer space is first cut to kt' = min(kt, k - q)
+         of its columns: those making the smallest angles with the cycle's
+         search space A~ range(V_j) (largest ||Q_K[i, :]||, Q_K an
+         orthonormal basis of [B; Hbar], the coefficients of A~ V_j in
+         [C, V_{j+1}]); on equal cosines the newer column wins.
+      5. The new C is orthogonal to the kept one only as far as the Arnoldi
+         basis is; two Cholesky-QR passes (C <- C R^-1, U <- U R^-1) keep
+         C^T C = I over many cycles.
+    Returns (new prev, ties), ties counting near-equal singular values or
+    cosines at a cut."""
+    kc = rec.dim
+    j = Hbar.shape[1]
+    if j == 0:
+        return prev, 0
+    ties = 0
+    sj = min(par.s, j)
+    # 2. selection space of this cycle
+    Qs, Rs = np.linalg.qr(Hbar[:, j - sj:])
+    sg = np.sign(np.diag(Rs))
+    sg[sg == 0] = 1.0
+    Qs = Qs * sg[None, :]
+    Rs = Rs * sg[:, None]
+    cand = [y.copy()]
+    if prev is not None and prev.shape[1] and par.p > 0:
+        M = (prev.T @ V) @ Qs                         # cosines: singular values
+        _, sig, Vt = np.linalg.svd(M)
+        npick = min(par.p, sj)
+        if npick < len(sig) and sig[npick - 1] > 0 and \
+                (sig[npick - 1] - sig[npick]) / sig[npick - 1] < 1e-8:
+            ties += 1
+        for i in range(npick):
+            r = Vt[i].copy()
+            if r[np.argmax(np.abs(r))] < 0:
+                r = -r
+            g = np.zeros(j)
+            g[j - sj:] = scipy.linalg.solve_triangular(Rs, r, lower=False)
+            cand.append(g)
+    Qn, Gc = _small_gs(Hbar, np.column_stack(cand))
+    q = Qn.shape[1]
+    new_prev = V @ Qs
+    # 4. truncation of the outer space
+    keep = list(range(kc))
+    if kc + q > k:
+        ktp = max(0, min(par.kt, k - q))
+        Qk, _ = np.linalg.qr(np.vstack([B, Hbar]))
+        cos = np.sqrt(np.sum(Qk[:kc] ** 2, axis=1))
+        order = sorted(range(kc), key=lambda i: (-cos[i], -i))
+        if 0 < ktp < kc and cos[order[ktp - 1]] > 0 and \
+                (cos[order[ktp - 1]] - cos[order[ktp]]) / cos[order[ktp - 1]] < 1e-8:
+            ties += 1
+        keep = sorted(order[:ktp])
+    # 3. new pairs, appended after the kept columns
+    Unew = V[:, :j] @ Gc - rec.U @ (B @ Gc)
+    Cnew = V @ Qn
+    rec.U = np.hstack([rec.U[:, keep], Unew])
+    rec.C = np.hstack([rec.C[:, keep], Cnew])
+    for _ in range(2):
+        R = np.linalg.cholesky(rec.C.T @ rec.C).T
+        rec.C = scipy.linalg.solve_triangular(R, rec.C.T, trans="T", lower=False).T
+        rec.U = scipy.linalg.solve_triangular(R, rec.U.T, trans="T", lower=False).T
+    return new_prev, ties
+
+
 def recycle_setup(op, rec: Recycle):
     """Alg. 3 line 1a: C~ = A~ U, thin QR C~ = C R, U <- U R^-1."""
     if rec.dim == 0:
@@ -256,7 +375,7 @@ def recycle_setup(op, rec: Recycle):
 
 
 def rgcrot(op, minv, b, m, k, tol, rec: Recycle, update=True, max_its=2000, orth="cgs2",
-           trace=None):
+           trace=None, gcrot: GcrotParams | None = None):
     """rGCROT(m,k), Alg. 3, right-preconditioned, x^ = 0, R absorbed in U.
 
     Line 1b projects b against C; lines 6a-6c orthogonalise each new Arnoldi
@@ -266,7 +385,9 @@ def rgcrot(op, minv, b, m, k, tol, rec: Recycle, update=True, max_its=2000, orth
     printed in line 13a would add +U B y instead).  Line 14 takes the true
     residual, line 14a updates (U, C) when `update`, and the residual is then
     re-projected against the new C so that the next cycle starts with
-    r, v_1 orthogonal to C.  `rec` is updated in place."""
+    r, v_1 orthogonal to C.  `rec` is updated in place.  gcrot: the update
+    follows the GCROT rule (gcrot_update) instead of the harmonic-Ritz one;
+    the previous cycle's selection space is kept within one solve."""
     b = np.asarray(b, dtype=np.float64)
     n = b.size
     nb = _norm(b)
@@ -280,6 +401,7 @@ def rgcrot(op, minv, b, m, k, tol, rec: Recycle, update=True, max_its=2000, orth
         r = b.copy()
         y_acc = np.zeros(n)
     rho = _norm(r)
+    prev = None
     while rho > tol * nb and its < max_its:
         kc = rec.dim
         V = np.zeros((n, m + 1))
@@ -310,8 +432,13 @@ def rgcrot(op, minv, b, m, k, tol, rec: Recycle, update=True, max_its=2000, orth
         cycles += 1
         if trace is not None:
             trace(dict(V=V[:, :jj + 1].copy(), H=H[:jj + 1, :jj].copy(), B=Bm[:, :jj].copy(),
-                       U=rec.U.copy(), C=rec.C.copy(), y_acc=y_acc.copy(), r=r.copy()))
-        if update:                                        # line 14a
+                       U=rec.U.copy(), C=rec.C.copy(), y_acc=y_acc.copy(), r=r.copy(),
+                       y=y.copy(), prev=None if prev is None else prev.copy()))
+        if update and gcrot is not None:                 # line 14a
+            prev, t = gcrot_update(rec, V[:, :jj + 1], H[:jj + 1, :jj], Bm[:, :jj], y, k,
+                                   gcrot, prev)
+            ties += t
+        elif update:
             ties += harmonic_ritz_update(rec, V[:, :jj + 1], H[:jj + 1, :jj], Bm[:, :jj], k)
         if rec.dim:
             xi = rec.C.T @ r

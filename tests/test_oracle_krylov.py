@@ -402,3 +402,123 @@ def test_hybrid_switches_back_after_poor_convergence():
     # the new matrix with the old (re-formed) space converged poorly, and the
     # policy reacted within the sequence
     assert "rgcrot" in seq[5:], (seq, mvs)
+
+
+# ---------------------------------------------------------------------------
+# GCROT rule of line 14a (selection by angles between successive search
+# spaces, truncation of the outer space).  Every check below rebuilds the
+# spaces with applications of A~, not from the Hessenberg relation the
+# update itself uses.
+# ---------------------------------------------------------------------------
+
+def _gcrot_run(m=10, k=8, par=K.GcrotParams(kt=5, s=5, p=1), n_sys=3, extra=21):
+    prob = W.grf_problem(10, extra=extra)
+    _, Mi, op = _ops(prob)
+    rec = K.Recycle.empty(prob.n)
+    runs = []
+    for b in W.rhs_perturbed(prob, n_sys, extra=extra):
+        traces = []
+        res = K.rgcrot(op, Mi, b, m, k, 1e-10, rec, trace=traces.append, gcrot=par)
+        # rec after each cycle: the next trace's (U, C), or the final rec
+        afters = [(t["U"], t["C"]) for t in traces[1:]] + [(rec.U.copy(), rec.C.copy())]
+        runs.append((b, res, traces, afters))
+    return prob, op, rec, runs
+
+
+def _in_range(C, v):
+    return np.linalg.norm(v - C @ (C.T @ v)) / np.linalg.norm(v)
+
+
+def test_gcrot_rule_invariants_and_cycle_correction():
+    """After every update: A~ U = C, C^T C = I, dim <= k; the cycle's
+    residual decrease A~ (V_j y - U B y) lies in the new range(C)."""
+    prob, op, rec, runs = _gcrot_run()
+    ncycles = 0
+    for b, res, traces, afters in runs:
+        assert res.status == K.CONVERGED and res.eig_ties == 0
+        for tr, (U, C) in zip(traces, afters):
+            ncycles += 1
+            assert C.shape[1] <= 8
+            AU = np.column_stack([op(U[:, i]) for i in range(U.shape[1])])
+            assert np.linalg.norm(AU - C) <= 1e-11 * np.linalg.norm(C)
+            assert np.linalg.norm(C.T @ C - np.eye(C.shape[1])) <= 1e-13
+            j = tr["H"].shape[1]
+            corr = tr["V"][:, :j] @ tr["y"] - tr["U"] @ (tr["B"] @ tr["y"])
+            dec = op(corr)
+            assert _in_range(C, dec) <= 1e-9
+    assert ncycles >= 6
+
+
+def test_gcrot_rule_selects_smallest_angle_with_previous_cycle():
+    """p = 1: the principal vector of this cycle's selection space (images of
+    the last s inner vectors) closest to the previous cycle's selection space
+    lies in the new range(C); both spaces rebuilt from A~ applications."""
+    prob, op, rec, runs = _gcrot_run(par=K.GcrotParams(kt=5, s=5, p=1))
+    checked = 0
+    for b, res, traces, afters in runs:
+        for tr, (U, C) in zip(traces, afters):
+            if tr["prev"] is None:
+                continue
+            V, B, Uo = tr["V"], tr["B"], tr["U"]
+            j = tr["H"].shape[1]
+            sj = min(5, j)
+            # images of the last sj inner vectors: A~ (v_i - U B e_i)
+            S = np.column_stack([op(V[:, i] - Uo @ B[:, i]) for i in range(j - sj, j)])
+            Qs, _ = np.linalg.qr(S)
+            Ql, _ = np.linalg.qr(tr["prev"])
+            _, sig, Vt = np.linalg.svd(Ql.T @ Qs)
+            w = Qs @ Vt[0]
+            assert _in_range(C, w) <= 1e-8
+            checked += 1
+    assert checked >= 3
+
+
+def test_gcrot_rule_truncation_keeps_smallest_angles():
+    """When the outer space is cut, the kept old columns are those making the
+    smallest angles with A~ range(V_j) (cosines from A~ applications); the
+    dropped ones leave the space."""
+    prob, op, rec, runs = _gcrot_run(m=6, k=6, par=K.GcrotParams(kt=3, s=3, p=1), n_sys=3)
+    cuts = 0
+    for b, res, traces, afters in runs:
+        for tr, (U, C) in zip(traces, afters):
+            Co = tr["C"]
+            kc = Co.shape[1]
+            j = tr["H"].shape[1]
+            if kc == 0:
+                continue
+            AV = np.column_stack([op(tr["V"][:, i]) for i in range(j)])
+            Qa, _ = np.linalg.qr(AV)
+            cos = np.linalg.norm(Qa.T @ Co, axis=0)
+            q = 1 + (tr["prev"] is not None)      # the cycle's correction (+ one selected)
+            if kc + q <= 6:
+                continue                  # no cut in this update
+            ktp = min(3, 6 - q)
+            assert C.shape[1] == ktp + q
+            order = sorted(range(kc), key=lambda i: (-cos[i], -i))
+            for i in order[:ktp]:
+                assert _in_range(C, Co[:, i]) <= 1e-9
+            for i in order[ktp:]:
+                assert _in_range(C, Co[:, i]) > 1e-3
+            cuts += 1
+    assert cuts >= 2
+
+
+def test_gcrot_rule_without_selection_is_gcro():
+    """p = 0 and k above the number of cycles: no selection and no cut, so
+    range(C) is spanned by the residual decreases of all cycles (GCRO with
+    the full outer space), rebuilt from true residuals."""
+    prob = W.grf_problem(10, extra=23)
+    _, Mi, op = _ops(prob)
+    b = W.rhs_perturbed(prob, 1, extra=23)[0]
+    rec = K.Recycle.empty(prob.n)
+    traces = []
+    res = K.rgcrot(op, Mi, b, 5, 60, 1e-10, rec, trace=traces.append,
+                   gcrot=K.GcrotParams(kt=50, s=3, p=0))
+    assert res.status == K.CONVERGED
+    decs = []
+    for tr in traces:
+        j = tr["H"].shape[1]
+        decs.append(op(tr["V"][:, :j] @ tr["y"] - tr["U"] @ (tr["B"] @ tr["y"])))
+    D = np.column_stack(decs)
+    assert rec.dim == D.shape[1] == len(traces) >= 5
+    assert scipy.linalg.subspace_angles(rec.C, D).max() <= 1e-7
