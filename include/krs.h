@@ -72,8 +72,27 @@ typedef enum krs_solver {
   KRS_SOLVER_GMRES = 0,     /* Alg. 1 */
   KRS_SOLVER_RGCROT = 1,    /* Alg. 3 */
   KRS_SOLVER_RBICGSTAB = 2, /* Alg. 4 (Alg. 2 with an empty recycle space) */
-  KRS_SOLVER_IR = 3         /* FP32 inner solver inside FP64 refinement: extra FP64/FP32 vectors */
+  KRS_SOLVER_IR = 3,        /* FP32 inner solver inside FP64 refinement: extra FP64/FP32 vectors */
+  KRS_SOLVER_RGCROT_T = 4   /* workspace size only: rGCROT with the GCROT rule
+                               (opts.recycle_rule = KRS_RECYCLE_GCROT), m vectors more */
 } krs_solver;
+
+/* How rGCROT updates (U, C) at a cycle end (Alg. 3 line 14a; the paper
+ * leaves the details to its references, Sec. 2.3).
+ * KRS_RECYCLE_HARMONIC: the GCRODR rule - the k harmonic Ritz vectors of the
+ *   search space range(U) + range(V_j) with the smallest |theta|.
+ * KRS_RECYCLE_GCROT: a reading of the GCROT rule, which measures angles
+ *   between successive search spaces.  The outer space gains the cycle's
+ *   own correction and gcrot_p directions of this cycle's selection space
+ *   (the images of its last gcrot_s inner vectors) that make the smallest
+ *   angles with the previous cycle's selection space (within one solve);
+ *   when it would exceed k it is first cut to gcrot_kt columns, those making
+ *   the smallest angles with the cycle's search space; two Cholesky-QR
+ *   passes then restore C^T C = I.  Sec. 3 uses kt = k - 10, s = m / 2 and
+ *   p = 1 or 2 (its fourth parameter, latest inner vectors kept, is 0 and
+ *   not modelled).  Needs the KRS_SOLVER_RGCROT_T workspace; rGCROT only
+ *   (the hybrid and refinement drivers reject it). */
+typedef enum krs_recycle_rule { KRS_RECYCLE_HARMONIC = 0, KRS_RECYCLE_GCROT = 1 } krs_recycle_rule;
 
 typedef enum krs_pc_type {
   KRS_PC_NONE = 0,
@@ -163,6 +182,10 @@ typedef struct krs_opts {
                               switch_back times the matvecs of the first rBiCGStab system
                               since the last rGCROT one, the next system runs rGCROT
                               (recycle space refreshed); 0 = off */
+  int32_t recycle_rule;    /* krs_recycle_rule (rGCROT only) */
+  int32_t gcrot_kt;        /* GCROT rule: outer vectors kept at a cut, 1..k-1 (<= 0: max(1, k-10)) */
+  int32_t gcrot_s;         /* GCROT rule: inner vectors to select from, 1..m (<= 0: max(1, m/2)) */
+  int32_t gcrot_p;         /* GCROT rule: inner vectors selected per cycle, 0..4 */
 } krs_opts;
 
 typedef struct krs_stats {

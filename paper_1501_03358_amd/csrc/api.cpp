@@ -20,6 +20,15 @@ int check_opts(krs_ctx* ctx, const krs_opts* o, bool needs_m) {
   if (!(o->tol >= 0)) return set_err(ctx, KRS_ERR_ARG, "opts.tol must be >= 0");
   if (o->history_cap < 0 || (o->history_cap > 0 && !o->history))
     return set_err(ctx, KRS_ERR_ARG, "history buffer inconsistent");
+  if (o->recycle_rule != KRS_RECYCLE_HARMONIC && o->recycle_rule != KRS_RECYCLE_GCROT)
+    return set_err(ctx, KRS_ERR_ARG, "unknown opts.recycle_rule");
+  if (o->recycle_rule == KRS_RECYCLE_GCROT) {
+    if (o->gcrot_p < 0 || o->gcrot_p > 4)
+      return set_err(ctx, KRS_ERR_ARG, "opts.gcrot_p must be in 0..4");
+    if (o->gcrot_s > o->m) return set_err(ctx, KRS_ERR_ARG, "opts.gcrot_s must not exceed opts.m");
+    if (o->gcrot_kt > 0 && o->gcrot_kt >= o->k)
+      return set_err(ctx, KRS_ERR_ARG, "opts.gcrot_kt must be below opts.k");
+  }
   return KRS_OK;
 }
 
@@ -303,6 +312,8 @@ int krs_hybrid_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, kr
   if (rc) return rc;
   if (opts->flags & KRS_FLAG_LEFT_PRECOND)
     return set_err(ctx, KRS_ERR_ARG, "the hybrid is right-preconditioned");
+  if (opts->recycle_rule != KRS_RECYCLE_HARMONIC)
+    return set_err(ctx, KRS_ERR_ARG, "the hybrid updates (U, C) by the harmonic-Ritz rule");
   if ((rc = check_precond(ctx, A, M))) return rc;
   if ((rc = check_rec(ctx, A, rec, opts, true))) return rc;
   if (opts->switch_back < 0 || !std::isfinite(opts->switch_back))
@@ -360,6 +371,8 @@ int krs_ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32,
   if (rc) return rc;
   if (opts->flags & KRS_FLAG_LEFT_PRECOND)
     return set_err(ctx, KRS_ERR_ARG, "refinement runs right-preconditioned inner solves");
+  if (opts->recycle_rule != KRS_RECYCLE_HARMONIC)
+    return set_err(ctx, KRS_ERR_ARG, "refinement updates (U, C) by the harmonic-Ritz rule");
   if (A64->dt != KRS_F64 || A32->dt != KRS_F32)
     return set_err(ctx, KRS_ERR_STATE, "IR needs an FP64 and an FP32 matrix");
   if (A64->n != A32->n) return set_err(ctx, KRS_ERR_STATE, "IR matrices differ in size");

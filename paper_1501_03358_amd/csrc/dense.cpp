@@ -57,6 +57,62 @@ void qr_thin(int m, int n, const double* A, double* Q, double* R) {
   }
 }
 
+bool sym_eig(int n, const double* A, std::vector<double>& w, std::vector<double>& Z) {
+  std::vector<double> M(A, A + (size_t)n * n);
+  auto m = [&](int i, int j) -> double& { return M[i + (size_t)n * j]; };
+  Z.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Z[i + (size_t)n * i] = 1.0;
+  bool ok = false;
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0, tot = 0;
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        tot += m(i, j) * m(i, j);
+        if (i != j) off += m(i, j) * m(i, j);
+      }
+    if (off <= (n * kEps) * (n * kEps) * tot || off == 0) {
+      ok = true;
+      break;
+    }
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = m(p, q);
+        if (apq == 0) continue;
+        // rotation that zeroes (p, q): tan of the angle from the classical formula
+        const double theta = (m(q, q) - m(p, p)) / (2 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1));
+        const double c = 1 / std::sqrt(t * t + 1), sn = t * c;
+        for (int k = 0; k < n; ++k) {   // columns p, q
+          const double mkp = m(k, p), mkq = m(k, q);
+          m(k, p) = c * mkp - sn * mkq;
+          m(k, q) = sn * mkp + c * mkq;
+        }
+        for (int k = 0; k < n; ++k) {   // rows p, q
+          const double mpk = m(p, k), mqk = m(q, k);
+          m(p, k) = c * mpk - sn * mqk;
+          m(q, k) = sn * mpk + c * mqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double zkp = Z[k + (size_t)n * p], zkq = Z[k + (size_t)n * q];
+          Z[k + (size_t)n * p] = c * zkp - sn * zkq;
+          Z[k + (size_t)n * q] = sn * zkp + c * zkq;
+        }
+      }
+  }
+  // sort descending
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return m(a, a) > m(b, b); });
+  std::vector<double> Zs((size_t)n * n);
+  w.assign(n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    w[c] = m(idx[c], idx[c]);
+    for (int i = 0; i < n; ++i) Zs[i + (size_t)n * c] = Z[i + (size_t)n * idx[c]];
+  }
+  Z.swap(Zs);
+  return ok;
+}
+
 bool cholesky_upper(int n, const double* A, double* R) {
   for (int j = 0; j < n; ++j)
     for (int i = 0; i < n; ++i) R[i + (size_t)n * j] = 0;

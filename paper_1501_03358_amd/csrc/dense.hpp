@@ -35,6 +35,11 @@ bool eigenvalues(int n, const double* A, std::vector<cplx>& lam);
 void eigenvector(int n, const double* A, cplx mu, const std::vector<cplx>& start,
                  const std::vector<cplx>& against, int na, std::vector<cplx>& v);
 
+// Eigen-decomposition of a symmetric n x n matrix by the cyclic Jacobi
+// method: eigenvalues w descending, eigenvectors the columns of Z (n x n).
+// Returns false if the sweeps do not converge.
+bool sym_eig(int n, const double* A, std::vector<double>& w, std::vector<double>& Z);
+
 // Harmonic-Ritz selection for the recycle-space update.
 //   G: mg x ng (= ng+1 rows), F: mg x ng, both column-major.
 // Solves G^T G z = theta G^T F z, keeps the k pairs of smallest |theta|

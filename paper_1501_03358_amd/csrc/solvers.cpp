@@ -300,6 +300,205 @@ int harmonic_update(krs_ctx* ctx, krs_recycle* rec, const T* V, int64_t ld, int 
   return 0;
 }
 
+template <class T>
+int cholqr2(krs_ctx* ctx, krs_recycle* rec, T* part, double* sc, const char* fail);
+
+struct GcrotPar {
+  int kt, s, p;
+};
+
+// ---------------------------------------------------------------------------
+// recycle-space update, Alg. 3 line 14a (GCROT rule; a reading, since the
+// paper names the rule and its parameters only): the outer space gains the
+// cycle's correction y and the p directions of this cycle's selection space
+// (images of the last s inner vectors) closest to the previous cycle's one
+// (prevQ, prev_dim columns, kept within a solve); above k it is first cut
+// to kt columns, those closest to A~ range(V_j); Cholesky-QR twice.
+// ---------------------------------------------------------------------------
+template <class T>
+int gcrot_update(krs_ctx* ctx, krs_recycle* rec, const T* V, int64_t ld, int jj,
+                 const std::vector<double>& Hbar, int ldh, const std::vector<double>& Bm,
+                 int ldb, const std::vector<double>& yv, int k, const GcrotPar& par, T* prevQ,
+                 int& prev_dim, T* part, double* sc, krs_stats* st) {
+  hipStream_t s = ctx->stream;
+  const int64_t n = rec->n;
+  const int kc = rec->dim;
+  if (jj == 0) return 0;
+  T* U = (T*)rec->U;
+  T* C = (T*)rec->C;
+  const int64_t ldr = rec->ld;
+  const int mg = jj + 1;
+  const int sj = std::min(par.s, jj);
+  const double NW = (double)n * sizeof(T);
+  const bool select = prev_dim > 0 && par.p > 0;
+  std::vector<double> PV;
+  if (select) {
+    // prev^T V_{j+1}: prev_dim x (jj + 1)
+    const int gb = gram_blocks(prev_dim, mg, n);
+    KRS_LAUNCH(ctx, KRS_K_GRAM, NW * (prev_dim + mg),
+               gram<T>(s, cols<T>(prevQ, ld, prev_dim), cols<T>(V, ld, mg), n, part, gb));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
+               finish_sum<T>(s, part, gb, prev_dim * mg, sc + Ws<T>::kGram1));
+    int rc = read_dev(ctx, sc + Ws<T>::kGram1, prev_dim * mg);
+    if (rc) return rc;
+    PV.assign(ctx->pin, ctx->pin + (size_t)prev_dim * mg);   // PV[a * mg + b]
+  }
+  Timer te;
+  int ties = 0;
+  auto hb = [&](int i, int j) { return Hbar[i + (size_t)ldh * j]; };
+  // selection space of this cycle: Hbar[:, jj-sj:jj] = Qs Rs
+  std::vector<double> S((size_t)mg * sj), Qs((size_t)mg * sj), Rs((size_t)sj * sj);
+  for (int c = 0; c < sj; ++c)
+    for (int i = 0; i < mg; ++i) S[i + (size_t)mg * c] = hb(i, jj - sj + c);
+  dense::qr_thin(mg, sj, S.data(), Qs.data(), Rs.data());
+  // candidate coefficient vectors (length jj): y, then the selected ones
+  std::vector<std::vector<double>> cand;
+  cand.push_back(std::vector<double>(yv.begin(), yv.begin() + jj));
+  if (select) {
+    // cosines: singular values of Mx = (prev^T V) Qs; right singular vectors
+    // from the eigenvectors of Mx^T Mx
+    std::vector<double> Mx((size_t)prev_dim * sj, 0.0), MtM((size_t)sj * sj, 0.0), w, Z;
+    for (int a = 0; a < prev_dim; ++a)
+      for (int c = 0; c < sj; ++c) {
+        double sum = 0;
+        for (int b = 0; b < mg; ++b) sum += PV[(size_t)a * mg + b] * Qs[b + (size_t)mg * c];
+        Mx[a + (size_t)prev_dim * c] = sum;
+      }
+    for (int c1 = 0; c1 < sj; ++c1)
+      for (int c2 = 0; c2 < sj; ++c2) {
+        double sum = 0;
+        for (int a = 0; a < prev_dim; ++a)
+          sum += Mx[a + (size_t)prev_dim * c1] * Mx[a + (size_t)prev_dim * c2];
+        MtM[c1 + (size_t)sj * c2] = sum;
+      }
+    if (!dense::sym_eig(sj, MtM.data(), w, Z)) {
+      if (st) st->host_eig_ms += te.ms();
+      return set_err(ctx, KRS_ERR_EIG, "GCROT selection: eigen-solver failed");
+    }
+    // only directions with a nonzero cosine are defined
+    auto sv = [&](int i) { return i < std::min(prev_dim, sj) ? std::sqrt(std::max(w[i], 0.0)) : 0.0; };
+    int npick = std::min(std::min(par.p, sj), prev_dim);
+    while (npick > 0 && sv(npick - 1) <= 1e-12) --npick;
+    if (npick > 0 && npick < std::min(prev_dim, sj) &&
+        (sv(npick - 1) - sv(npick)) / sv(npick - 1) < 1e-8)
+      ++ties;
+    for (int i = 0; i < npick; ++i) {
+      std::vector<double> r(Z.begin() + (size_t)sj * i, Z.begin() + (size_t)sj * (i + 1));
+      int big = 0;
+      for (int t = 1; t < sj; ++t)
+        if (std::fabs(r[t]) > std::fabs(r[big])) big = t;
+      if (r[big] < 0)
+        for (double& v : r) v = -v;
+      std::vector<double> g(jj, 0.0), sol(sj);
+      dense::upper_solve(sj, Rs.data(), sj, r.data(), sol.data());
+      for (int t = 0; t < sj; ++t) g[jj - sj + t] = sol[t];
+      cand.push_back(g);
+    }
+  }
+  // orthonormalise the images Hbar g in order (Gram-Schmidt twice, dropping
+  // dependent ones): Hbar Gc = Qn
+  std::vector<std::vector<double>> Qn, Gc;
+  for (const auto& g0 : cand) {
+    std::vector<double> g = g0, h(mg, 0.0);
+    for (int i = 0; i < mg; ++i) {
+      double sum = 0;
+      for (int j = 0; j < jj; ++j) sum += hb(i, j) * g[j];
+      h[i] = sum;
+    }
+    double h0 = 0;
+    for (double v : h) h0 += v * v;
+    h0 = std::sqrt(h0);
+    if (h0 == 0) continue;
+    for (int pass = 0; pass < 2; ++pass)
+      for (size_t l = 0; l < Qn.size(); ++l) {
+        double t = 0;
+        for (int i = 0; i < mg; ++i) t += Qn[l][i] * h[i];
+        for (int i = 0; i < mg; ++i) h[i] -= t * Qn[l][i];
+        for (int j = 0; j < jj; ++j) g[j] -= t * Gc[l][j];
+      }
+    double nrm = 0;
+    for (double v : h) nrm += v * v;
+    nrm = std::sqrt(nrm);
+    if (nrm <= 1e-10 * h0) continue;
+    for (double& v : h) v /= nrm;
+    for (double& v : g) v /= nrm;
+    Qn.push_back(h);
+    Gc.push_back(g);
+  }
+  const int q = (int)Qn.size();
+  // cut of the outer space: keep the columns closest to A~ range(V_j)
+  std::vector<int> keep;
+  for (int i = 0; i < kc; ++i) keep.push_back(i);
+  if (kc + q > k) {
+    const int ktp = std::max(0, std::min(par.kt, k - q));
+    const int mk = kc + mg;
+    std::vector<double> K((size_t)mk * jj), Qk((size_t)mk * jj), Rk((size_t)jj * jj);
+    for (int j = 0; j < jj; ++j) {
+      for (int i = 0; i < kc; ++i) K[i + (size_t)mk * j] = Bm[i + (size_t)ldb * j];
+      for (int i = 0; i < mg; ++i) K[kc + i + (size_t)mk * j] = hb(i, j);
+    }
+    dense::qr_thin(mk, jj, K.data(), Qk.data(), Rk.data());
+    std::vector<double> cosv(kc);
+    for (int i = 0; i < kc; ++i) {
+      double sum = 0;
+      for (int j = 0; j < jj; ++j) sum += Qk[i + (size_t)mk * j] * Qk[i + (size_t)mk * j];
+      cosv[i] = std::sqrt(sum);
+    }
+    std::vector<int> order(kc);
+    for (int i = 0; i < kc; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+      return cosv[a] != cosv[b] ? cosv[a] > cosv[b] : a > b;
+    });
+    if (ktp > 0 && ktp < kc && cosv[order[ktp - 1]] > 0 &&
+        (cosv[order[ktp - 1]] - cosv[order[ktp]]) / cosv[order[ktp - 1]] < 1e-8)
+      ++ties;
+    keep.assign(order.begin(), order.begin() + ktp);
+    std::sort(keep.begin(), keep.end());
+  }
+  const int nk = (int)keep.size(), nout = nk + q;
+  // U <- [U_keep, (V_j - U B) Gc] from In = [U, V_j]; C <- [C_keep, V_{j+1} Qn]
+  // from In = [C, V_{j+1}]; the next selection basis V_{j+1} Qs into prevQ
+  const int nu = kc + jj, ncin = kc + mg;
+  std::vector<double> Mu((size_t)nu * nout, 0.0), Mc((size_t)ncin * nout, 0.0);
+  for (int o = 0; o < nk; ++o) {
+    Mu[keep[o] + (size_t)nu * o] = 1.0;
+    Mc[keep[o] + (size_t)ncin * o] = 1.0;
+  }
+  for (int l = 0; l < q; ++l) {
+    const int o = nk + l;
+    for (int c = 0; c < kc; ++c) {
+      double sum = 0;
+      for (int j = 0; j < jj; ++j) sum += Bm[c + (size_t)ldb * j] * Gc[l][j];
+      Mu[c + (size_t)nu * o] = -sum;
+    }
+    for (int j = 0; j < jj; ++j) Mu[kc + j + (size_t)nu * o] = Gc[l][j];
+    for (int i = 0; i < mg; ++i) Mc[kc + i + (size_t)ncin * o] = Qn[l][i];
+  }
+  if (st) {
+    st->host_eig_ms += te.ms();
+    st->eig_ties += ties;
+  }
+  std::vector<double> all(Mu);
+  all.insert(all.end(), Mc.begin(), Mc.end());
+  all.insert(all.end(), Qs.begin(), Qs.end());
+  int rc = upload(ctx, sc + Ws<T>::kM, all.data(), (int)all.size());
+  if (rc) return rc;
+  const double* dMu = sc + Ws<T>::kM;
+  const double* dMc = dMu + Mu.size();
+  const double* dQs = dMc + Mc.size();
+  KRS_LAUNCH(ctx, KRS_K_ROW_TRANSFORM, NW * (mg + sj),
+             row_transform<T>(s, cols<T>(V, ld, mg), dQs, sj, prevQ, ld, n));
+  if (nout > 0) {
+    KRS_LAUNCH(ctx, KRS_K_ROW_TRANSFORM, NW * (nu + nout),
+               row_transform<T>(s, cols<T>(U, ldr, kc, V, ld, jj), dMu, nout, U, ldr, n));
+    KRS_LAUNCH(ctx, KRS_K_ROW_TRANSFORM, NW * (ncin + nout),
+               row_transform<T>(s, cols<T>(C, ldr, kc, V, ld, mg), dMc, nout, C, ldr, n));
+  }
+  prev_dim = sj;
+  rec->dim = nout;
+  return cholqr2<T>(ctx, rec, part, sc, "GCROT update: C is rank deficient");
+}
+
 // ---------------------------------------------------------------------------
 // GMRES(m) and rGCROT(m,k)
 // ---------------------------------------------------------------------------
@@ -324,6 +523,12 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
   const bool left = (o->flags & KRS_FLAG_LEFT_PRECOND) != 0 && M && M->d.type != KRS_PC_NONE;
   T* bl = left ? cv.vec<T>(ld) : nullptr;     // M^-1 b
   T* ptmp = left ? cv.vec<T>(ld) : nullptr;   // preconditioner temporary
+  // GCROT rule: the previous cycle's selection space (up to m columns)
+  const bool gcrot = update && rec && o->recycle_rule == KRS_RECYCLE_GCROT;
+  T* prevQ = gcrot ? cv.vec<T>(ld * m) : nullptr;
+  int prev_dim = 0;
+  const GcrotPar gpar{o->gcrot_kt > 0 ? o->gcrot_kt : std::max(1, o->k - 10),
+                      o->gcrot_s > 0 ? o->gcrot_s : std::max(1, m / 2), o->gcrot_p};
   if (!ws || !cv.ok) return set_err(ctx, KRS_ERR_WORKSPACE, "workspace missing or too small");
   double* d_h1 = sc + Ws<T>::kH1;
   double* d_h2 = sc + Ws<T>::kH2;
@@ -506,7 +711,11 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
                                0, part, nblk));
     ++cycles;
     // line 14a: recycle-space update
-    if (update && rec) {
+    if (gcrot) {
+      rc = gcrot_update<T>(ctx, rec, V, ld, jj, Hbar, ldh, Bm, ldb, yv, o->k, gpar, prevQ,
+                           prev_dim, part, sc, st);
+      if (rc) return rc;
+    } else if (update && rec) {
       rc = harmonic_update<T>(ctx, rec, V, ld, jj, Hbar, ldh, Bm, ldb, o->k, part, sc, st);
       if (rc) return rc;
     }
@@ -585,6 +794,41 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
 // ---------------------------------------------------------------------------
 // Alg. 3 line 1a: C~ = A~ U, C~ = C R (Cholesky QR, twice), U <- U R^-1
 // ---------------------------------------------------------------------------
+// Two Cholesky-QR passes over C (U alongside): G = C^T C = R^T R,
+// C <- C R^-1, U <- U R^-1, so C^T C = I and A~ U = C are kept.
+template <class T>
+int cholqr2(krs_ctx* ctx, krs_recycle* rec, T* part, double* sc, const char* fail) {
+  hipStream_t s = ctx->stream;
+  const int64_t n = rec->n;
+  const int kc = rec->dim;
+  if (kc == 0) return 0;
+  T* U = (T*)rec->U;
+  T* C = (T*)rec->C;
+  const int64_t ldr = rec->ld;
+  std::vector<double> G((size_t)kc * kc), R((size_t)kc * kc), Ri((size_t)kc * kc);
+  const double NW = (double)n * sizeof(T);
+  for (int pass = 0; pass < 2; ++pass) {
+    const int gb = gram_blocks(kc, kc, n);
+    KRS_LAUNCH(ctx, KRS_K_GRAM, NW * kc,
+               gram<T>(s, cols<T>(C, ldr, kc), cols<T>(C, ldr, kc), n, part, gb));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, gb, kc * kc, sc + Ws<T>::kGram1));
+    int rc = read_dev(ctx, sc + Ws<T>::kGram1, kc * kc);
+    if (rc) return rc;
+    for (int a = 0; a < kc; ++a)
+      for (int b = 0; b < kc; ++b) G[a + (size_t)kc * b] = ctx->pin[a * kc + b];
+    if (!dense::cholesky_upper(kc, G.data(), R.data()) ||
+        !dense::upper_inverse(kc, R.data(), Ri.data()))
+      return set_err(ctx, KRS_ERR_STATE, fail);
+    rc = upload(ctx, sc + Ws<T>::kM, Ri.data(), kc * kc);
+    if (rc) return rc;
+    KRS_LAUNCH(ctx, KRS_K_ROW_TRANSFORM, NW * 2 * kc,
+               row_transform<T>(s, cols<T>(C, ldr, kc), sc + Ws<T>::kM, kc, C, ldr, n));
+    KRS_LAUNCH(ctx, KRS_K_ROW_TRANSFORM, NW * 2 * kc,
+               row_transform<T>(s, cols<T>(U, ldr, kc), sc + Ws<T>::kM, kc, U, ldr, n));
+  }
+  return 0;
+}
+
 template <class T>
 int recycle_setup_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
                     void* ws, size_t wsb) {
@@ -606,27 +850,8 @@ int recycle_setup_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs
     int rc = op.apply(U + (int64_t)c * ldr, C + (int64_t)c * ldr);
     if (rc) return rc;
   }
-  std::vector<double> G((size_t)kc * kc), R((size_t)kc * kc), Ri((size_t)kc * kc);
-  const double NW = (double)n * sizeof(T);
-  for (int pass = 0; pass < 2; ++pass) {
-    const int gb = gram_blocks(kc, kc, n);
-    KRS_LAUNCH(ctx, KRS_K_GRAM, NW * kc,
-               gram<T>(s, cols<T>(C, ldr, kc), cols<T>(C, ldr, kc), n, part, gb));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, gb, kc * kc, sc + Ws<T>::kGram1));
-    int rc = read_dev(ctx, sc + Ws<T>::kGram1, kc * kc);
-    if (rc) return rc;
-    for (int a = 0; a < kc; ++a)
-      for (int b = 0; b < kc; ++b) G[a + (size_t)kc * b] = ctx->pin[a * kc + b];
-    if (!dense::cholesky_upper(kc, G.data(), R.data()) ||
-        !dense::upper_inverse(kc, R.data(), Ri.data()))
-      return set_err(ctx, KRS_ERR_STATE, "recycle setup: A~ U is rank deficient");
-    rc = upload(ctx, sc + Ws<T>::kM, Ri.data(), kc * kc);
-    if (rc) return rc;
-    KRS_LAUNCH(ctx, KRS_K_ROW_TRANSFORM, NW * 2 * kc,
-               row_transform<T>(s, cols<T>(C, ldr, kc), sc + Ws<T>::kM, kc, C, ldr, n));
-    KRS_LAUNCH(ctx, KRS_K_ROW_TRANSFORM, NW * 2 * kc,
-               row_transform<T>(s, cols<T>(U, ldr, kc), sc + Ws<T>::kM, kc, U, ldr, n));
-  }
+  int rc = cholqr2<T>(ctx, rec, part, sc, "recycle setup: A~ U is rank deficient");
+  if (rc) return rc;
   KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
   timing_flush(ctx);
   return 0;
@@ -984,6 +1209,12 @@ int workspace_bytes(krs_solver solver, int64_t n, int m, int k, krs_dtype dt, si
       v = f64 ? std::max(ws_gmres<double>(n, m), ws_bicg<double>(n))
               : std::max(ws_gmres<float>(n, m), ws_bicg<float>(n));
       break;
+    case KRS_SOLVER_RGCROT_T: {
+      const size_t extra = (size_t)vec_ld(n) * m * (f64 ? sizeof(double) : sizeof(float));
+      v = f64 ? std::max(ws_gmres<double>(n, m) + extra + 256, ws_bicg<double>(n))
+              : std::max(ws_gmres<float>(n, m) + extra + 256, ws_bicg<float>(n));
+      break;
+    }
     case KRS_SOLVER_RBICGSTAB:
       v = f64 ? ws_bicg<double>(n) : ws_bicg<float>(n);
       break;

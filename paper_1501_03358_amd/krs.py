@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libkrs.so")
 OK, NOT_CONVERGED, BREAKDOWN, DIVERGED = 0, 1, 2, 3
 ERR_ARG, ERR_HIP, ERR_WORKSPACE, ERR_STATE, ERR_EIG = -1, -2, -3, -4, -5
 F64, F32 = 0, 1
-SOLVER_GMRES, SOLVER_RGCROT, SOLVER_RBICGSTAB, SOLVER_IR = 0, 1, 2, 3
+SOLVER_GMRES, SOLVER_RGCROT, SOLVER_RBICGSTAB, SOLVER_IR, SOLVER_RGCROT_T = 0, 1, 2, 3, 4
+RECYCLE_HARMONIC, RECYCLE_GCROT = 0, 1
 PC_NONE, PC_JACOBI, PC_SCHWARZ_JACOBI = 0, 1, 2
 LOCAL_JACOBI, LOCAL_SSOR = 0, 1
 FLAG_TRUST_ESTIMATE = 1
@@ -56,7 +57,9 @@ class Opts(ctypes.Structure):
                 ("max_matvecs", ctypes.c_int64), ("div_factor", ctypes.c_double),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("history", ctypes.POINTER(ctypes.c_double)),
-                ("history_cap", ctypes.c_int64), ("switch_back", ctypes.c_double)]
+                ("history_cap", ctypes.c_int64), ("switch_back", ctypes.c_double),
+                ("recycle_rule", ctypes.c_int32), ("gcrot_kt", ctypes.c_int32),
+                ("gcrot_s", ctypes.c_int32), ("gcrot_p", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -301,9 +304,10 @@ class Workspace:
 
 def make_opts(m=30, k=20, tol=1e-8, max_matvecs=2000, update_recycle=True, inner_solver=None,
               div_factor=1e2, inner_tol=1e-5, max_outer=20, history=None, flags=0,
-              switch_back=0.0):
+              switch_back=0.0, recycle_rule=RECYCLE_HARMONIC, gcrot_kt=0, gcrot_s=0, gcrot_p=1):
     o = Opts()
     o.switch_back = switch_back
+    o.recycle_rule, o.gcrot_kt, o.gcrot_s, o.gcrot_p = recycle_rule, gcrot_kt, gcrot_s, gcrot_p
     o.flags = flags
     o.m, o.k, o.update_recycle = m, k, 1 if update_recycle else 0
     o.inner_solver = SOLVER_RGCROT if inner_solver is None else inner_solver

@@ -20,7 +20,7 @@ class Dev:
     """A problem's matrix, preconditioner and workspace on the GPU."""
 
     def __init__(self, krs, prob, pc="jacobi", params=None, dtype=torch.float64, ctx=None,
-                 m=30, k=20):
+                 m=30, k=20, solver=None):
         self.krs = krs
         self.prob = prob
         self.dev = torch.device("cuda:0")
@@ -30,7 +30,8 @@ class Dev:
         self.A = krs.Matrix(self.ctx, prob.shape, prob.periodic, self.bands)
         p = dict(params or {})
         self.M = krs.Precond(self.ctx, self.A, pc, **p) if pc != "none" else None
-        self.wsb = krs.workspace_size(krs.SOLVER_RGCROT, prob.n, m, k, dtype)
+        self.wsb = krs.workspace_size(krs.SOLVER_RGCROT if solver is None else solver, prob.n,
+                                      m, k, dtype)
         self.ws = torch.empty(self.wsb, dtype=torch.uint8, device=self.dev)
 
     def vec(self, a):

@@ -48,13 +48,18 @@ def test_gmres_matches_oracle_grf24(gpu_lib):
     assert st.rel_res_true <= 1e-8
 
 
-def _rgcrot_sequence(krs, prob, pc, params, m, k, steps, bs, tol=1e-8, stepwise=True):
+def _rgcrot_sequence(krs, prob, pc, params, m, k, steps, bs, tol=1e-8, stepwise=True,
+                     gcrot=None):
     """Runs the GPU rGCROT over a sequence of right-hand sides next to the
     oracle.  stepwise: before every system the oracle receives a copy of the
     GPU's recycle space, so that both sides solve the same problem and only
     the step's own rounding differs; otherwise each side keeps its own space
-    (recycle updates then amplify rounding through the eigenvector step)."""
-    d = Dev(krs, prob, pc, params, m=m, k=k)
+    (recycle updates then amplify rounding through the eigenvector step).
+    gcrot: oracle GcrotParams; both sides then update by the GCROT rule."""
+    d = Dev(krs, prob, pc, params, m=m, k=k,
+            solver=krs.SOLVER_RGCROT_T if gcrot is not None else None)
+    extra = {} if gcrot is None else dict(recycle_rule=krs.RECYCLE_GCROT, gcrot_kt=gcrot.kt,
+                                          gcrot_s=gcrot.s, gcrot_p=gcrot.p)
     _, Mi, op = oracle_ops(prob, pc, params)
     rec = krs.Recycle(d.ctx, prob.n, k, torch.float64)
     orec = K.Recycle.empty(prob.n)
@@ -66,8 +71,8 @@ def _rgcrot_sequence(krs, prob, pc, params, m, k, steps, bs, tol=1e-8, stepwise=
         h = _hist()
         x = d.empty()
         rc, st = krs.rgcrot_solve(d.ctx, d.A, d.M, rec, d.vec(b), x,
-                                  krs.make_opts(m=m, k=k, tol=tol, history=h), d.ws)
-        ref = K.rgcrot(op, Mi, b, m, k, tol, orec)
+                                  krs.make_opts(m=m, k=k, tol=tol, history=h, **extra), d.ws)
+        ref = K.rgcrot(op, Mi, b, m, k, tol, orec, gcrot=gcrot)
         out.append((rc, st, h[:st.history_len].copy(), x.cpu().numpy(), ref))
     return d, rec, orec, op, out
 
@@ -534,3 +539,59 @@ def test_rgcrot_large_recycle_space(gpu_lib):
                          krs.make_opts(m=11, k=53, tol=1e-8), d2.ws)
     with pytest.raises(krs.KrsError):
         krs.Recycle(d2.ctx, prob.n, 63, torch.float64)
+
+
+@pytest.mark.parametrize("kind,m,k,par", [
+    ("grf", 20, 10, (5, 10, 1)),       # Jacobi: cuts and one selected vector per cycle
+    ("porous", 30, 20, (10, 15, 2)),   # Schwarz, the channel parameters of Sec. 3 with p = 2
+    ("channel", 10, 40, (30, 5, 2)),   # the porous-media parameters rGCROT(10,40) of Sec. 3
+])
+def test_rgcrot_gcrot_rule_matches_oracle(gpu_lib, kind, m, k, par):
+    """The GCROT recycle-space rule, stepwise against the oracle: history
+    within 1e-10 over 20 steps, counts within 2, x within 1e-8; after the
+    last system the same outer space (subspace angles), A~ U = C, C^T C = I."""
+    krs = gpu_lib
+    gp = K.GcrotParams(*par)
+    if kind == "grf":
+        prob, pc, params = W.grf_problem(16, extra=81), "jacobi", None
+        bs = W.rhs_perturbed(prob, 4, extra=81)
+    else:
+        prob = W.porous_problem(24, extra=82) if kind == "porous" else W.channel_problem(24)
+        pc, params = "schwarz", dict(SMALL_SCHWARZ)
+        bs = list(W.rhs_ar1(prob, 4, extra=82))
+    d, rec, orec, op, out = _rgcrot_sequence(krs, prob, pc, params, m, k, 4, bs, gcrot=gp)
+    for t, (rc, st, h, x, ref) in enumerate(out):
+        assert rc == krs.OK and ref.status == K.CONVERGED, t
+        assert st.eig_ties == 0 and ref.eig_ties == 0
+        _check_history(h, ref.history)
+        assert abs(st.iterations - ref.iterations) <= 2, (t, st.iterations, ref.iterations)
+        _check_solution(prob, x, ref.x)
+    g = recycle_to_oracle(rec)
+    assert g.dim == orec.dim >= 1
+    assert scipy.linalg.subspace_angles(g.C, orec.C).max() < 1e-6
+    AU = np.column_stack([op(g.U[:, i]) for i in range(g.dim)])
+    assert np.linalg.norm(AU - g.C) / np.linalg.norm(g.C) <= 1e-10
+    assert np.linalg.norm(g.C.T @ g.C - np.eye(g.dim)) <= 1e-12
+
+
+def test_rgcrot_gcrot_rule_rejected_where_unsupported(gpu_lib):
+    krs = gpu_lib
+    prob = W.grf_problem(8, extra=83)
+    d = Dev(krs, prob, "jacobi", m=10, k=6)
+    dt = Dev(krs, prob, "jacobi", m=10, k=6, solver=krs.SOLVER_RGCROT_T, ctx=d.ctx)
+    assert dt.wsb > d.wsb
+    rec = krs.Recycle(d.ctx, prob.n, 6, torch.float64)
+    b = d.vec(W.random_vector(prob.n, 2))
+    o = krs.make_opts(m=10, k=6, recycle_rule=krs.RECYCLE_GCROT)
+    with pytest.raises(krs.KrsError, match="workspace"):   # no room for the selection space
+        krs.rgcrot_solve(d.ctx, d.A, d.M, rec, b, d.empty(), o, d.ws)
+    with pytest.raises(krs.KrsError, match="harmonic"):
+        krs.hybrid_solve(dt.ctx, dt.A, dt.M, rec, 0, 2, b, dt.empty(), o, dt.ws)
+    for bad in (dict(gcrot_p=5), dict(gcrot_s=11), dict(gcrot_kt=6)):
+        with pytest.raises(krs.KrsError, match="gcrot"):
+            krs.rgcrot_solve(dt.ctx, dt.A, dt.M, rec, b, dt.empty(),
+                             krs.make_opts(m=10, k=6, recycle_rule=krs.RECYCLE_GCROT, **bad),
+                             dt.ws)
+    rc, st = krs.rgcrot_solve(dt.ctx, dt.A, dt.M, rec, b, dt.empty(),
+                              krs.make_opts(m=10, k=6, recycle_rule=krs.RECYCLE_GCROT), dt.ws)
+    assert rc == krs.OK and 1 <= rec.dim <= 6

@@ -63,6 +63,10 @@ def test_workspace_within_paper_storage(lib, n):
     assert w <= 8 * ld * 8 + FIXED
     w32 = _ws(lib, 2, n, 30, 20, 1)
     assert w32 <= 4 * ld * 8 + FIXED
+    # rGCROT with the GCROT rule: m more vectors (the previous selection space)
+    for m, dt, wb in ((30, 0, 8), (10, 1, 4)):
+        extra = _ws(lib, 4, n, m, 20, dt) - _ws(lib, 1, n, m, 20, dt)
+        assert wb * ld * m <= extra <= wb * ld * m + 4096
 
 
 def test_invalid_arguments_are_rejected(lib):
