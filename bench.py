@@ -262,7 +262,9 @@ def seq_main(args):
     bands = torch.from_numpy(prob.bands).to(dev)
     A = krs.Matrix(ctx, prob.shape, prob.periodic, bands)
     Mp = krs.Precond(ctx, A, "schwarz", **local_params(args))
-    ws = torch.empty(krs.workspace_size(krs.SOLVER_RGCROT, prob.n, args.m, args.k, torch.float64),
+    gcrot = args.rule == "gcrot"
+    ws = torch.empty(krs.workspace_size(krs.SOLVER_RGCROT_T if gcrot else krs.SOLVER_RGCROT,
+                                        prob.n, args.m, args.k, torch.float64),
                      dtype=torch.uint8, device=dev)
     x = torch.zeros(prob.n, dtype=torch.float64, device=dev)
 
@@ -312,14 +314,22 @@ def seq_main(args):
                 "latency_ms": {"p50": float(np.percentile(lat, 50)),
                                "p99": float(np.percentile(lat, 99))}}, kt
 
-    def opts():
+    def opts(**kw):
         return krs.make_opts(m=args.m, k=args.k, tol=1e-8, max_matvecs=6000,
-                             flags=krs.FLAG_LEFT_PRECOND if args.left else 0)
+                             flags=krs.FLAG_LEFT_PRECOND if args.left else 0, **kw)
+
+    def run_gcrot():
+        """rGCROT with the GCROT recycle rule (kt = k - 10, s = m / 2)."""
+        if gcrot:
+            res["rgcrot_gcrot"], _ = run("rgcrot_gcrot", lambda rec, i, b: krs.rgcrot_solve(
+                ctx, A, Mp, rec, b, x, opts(recycle_rule=krs.RECYCLE_GCROT,
+                                            gcrot_p=args.gcrot_p), ws))
 
     res = {}
     if channel:
         res["rgcrot"], kt = run("rgcrot", lambda rec, i, b: krs.rgcrot_solve(
             ctx, A, Mp, rec, b, x, opts(), ws))
+        run_gcrot()
         res["gmres"], _ = run("gmres", lambda rec, i, b: krs.gmres(ctx, A, Mp, b, x, opts(), ws))
         main_name, other = "rgcrot", "gmres"
     else:
@@ -338,6 +348,7 @@ def seq_main(args):
                 ctx, A, Mp, None, b, x, opts(), ws))
             res["rgcrot"], _ = run("rgcrot", lambda rec, i, b: krs.rgcrot_solve(
                 ctx, A, Mp, rec, b, x, opts(), ws))
+            run_gcrot()
     dom = max(kt, key=lambda c: kt[c][1])
     n_l, ms_l, by_l = kt[dom]
     achieved = by_l / (ms_l * 1e-3) / 1e9 if ms_l > 0 else 0.0
@@ -355,6 +366,8 @@ def seq_main(args):
                    "preconditioning": "left" if args.left else "right",
                    "time_steps": steps, "m": args.m, "k": args.k, "tol": 1e-8,
                    "n_switch": None if channel else args.n_switch,
+                   "gcrot_rule": ({"kt": max(1, args.k - 10), "s": max(1, args.m // 2),
+                                   "p": args.gcrot_p} if gcrot else None),
                    "precond": f"Schwarz 8^3 tiles overlap 1, 5 local {args.local_solver} "
                               f"iterations + 1 global Jacobi sweep"},
         "methods": res,
@@ -395,6 +408,10 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="grid size per axis")
     ap.add_argument("--m", type=int, default=M, help="rGCROT cycle length")
     ap.add_argument("--k", type=int, default=K, help="recycle dimension")
+    ap.add_argument("--rule", choices=["harmonic", "gcrot"], default="harmonic",
+                    help="channel128/porous128: also run rGCROT with the GCROT recycle rule")
+    ap.add_argument("--gcrot-p", type=int, default=1,
+                    help="GCROT rule: inner vectors selected per cycle")
     ap.add_argument("--inner-tol", type=float, default=1e-5)
     ap.add_argument("--n-switch", type=int, default=N_SWITCH,
                     help="porous128: systems solved by rGCROT before rBiCGStab")
