@@ -56,6 +56,8 @@ def schwarz_jacobi(bands, shape, periodic, r, tile=8, overlap=1, local_sweeps=5,
     extended tile, restricted write-back, then global damped Jacobi sweeps."""
     if local_solver not in ("jacobi", "ssor"):
         raise ValueError(local_solver)
+    if local_solver == "ssor" and bands.shape[0] != 7:
+        raise ValueError("the two-colour SSOR ordering decouples 7-point bands only")
     nx, ny, nz = shape
     ix, vx = _axis_windows(nx, tile, overlap, periodic[0])
     iy, vy = _axis_windows(ny, tile, overlap, periodic[1])
@@ -77,20 +79,22 @@ def schwarz_jacobi(bands, shape, periodic, r, tile=8, overlap=1, local_sweeps=5,
     # local sweeps on every extended tile, starting from zero; neighbours
     # outside the extended tile count as zero
     z = np.zeros_like(rs)
-    nbrs = ((1, 5, -1), (2, 5, +1), (3, 4, -1), (4, 4, +1), (5, 3, -1), (6, 3, +1))
 
     def a_times(z):
         az = bs[0] * z
-        for band, ax, off in nbrs:
+        for band in range(1, bands.shape[0]):
+            # neighbour at offset (dx, dy, dz) inside the extended tile
+            # (axes 5, 4, 3 of z), zero beyond it
             nb = np.zeros_like(z)
             src = [slice(None)] * 6
             dst = [slice(None)] * 6
-            if off > 0:
-                dst[ax] = slice(0, E - 1)
-                src[ax] = slice(1, E)
-            else:
-                dst[ax] = slice(1, E)
-                src[ax] = slice(0, E - 1)
+            for ax, off in zip((5, 4, 3), stencil.OFFSETS19[band - 1]):
+                if off > 0:
+                    dst[ax] = slice(0, E - 1)
+                    src[ax] = slice(1, E)
+                elif off < 0:
+                    dst[ax] = slice(1, E)
+                    src[ax] = slice(0, E - 1)
             nb[tuple(dst)] = z[tuple(src)]
             az = az + bs[band] * nb
         return az

@@ -197,3 +197,37 @@ def test_ssor_single_tile_converges_to_inverse():
     zj = precond.schwarz_jacobi(bands, shape, periodic, r, tile=8, overlap=0, local_sweeps=10,
                                 omega_local=1.0, global_sweeps=0)
     assert np.linalg.norm(zs - ref) < np.linalg.norm(zj - ref)
+
+
+def _random_19pt(shape, periodic, seed):
+    """A 7-point random operator plus small random edge couplings (19 bands),
+    and its dense matrix built by explicit loops."""
+    from oracle import stencil
+    from tests.test_oracle_stencil import _dense19_by_loops
+    bc = {a: ('periodic' if periodic[i] else ('dirichlet', 'neumann')) for i, a in enumerate('xyz')}
+    b7, _, _ = _random_problem(shape, bc, seed)
+    rng = np.random.default_rng(seed + 1)
+    bands = np.zeros((19, b7.shape[1]))
+    bands[:7] = b7
+    bands[7:] = 0.05 * rng.standard_normal((12, b7.shape[1])) * np.abs(b7[0])[None]
+    return bands, _dense19_by_loops(bands, shape, periodic), stencil
+
+
+@pytest.mark.parametrize("case", [((8, 8, 8), (False, False, False), 4, 1),
+                                  ((8, 12, 8), (True, False, True), 4, 1)])
+def test_19pt_schwarz_matches_dense_construction(case):
+    shape, periodic, tile, overlap = case
+    bands, A, _ = _random_19pt(shape, periodic, 31)
+    r = np.random.default_rng(12).standard_normal(A.shape[0])
+    z = precond.schwarz_jacobi(bands, shape, periodic, r, tile=tile, overlap=overlap,
+                               local_sweeps=5, omega_local=6 / 7, global_sweeps=1,
+                               omega_global=6 / 7)
+    ref = _dense_schwarz(A, shape, periodic, r, tile, overlap, 5, 6 / 7, 1, 6 / 7)
+    assert np.linalg.norm(z - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_19pt_ssor_local_solver_rejected():
+    bands, _, _ = _random_19pt((8, 8, 8), (False, False, False), 5)
+    with pytest.raises(ValueError):
+        precond.schwarz_jacobi(bands, (8, 8, 8), (False, False, False), np.ones(512),
+                               tile=4, local_solver="ssor")

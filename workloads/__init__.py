@@ -218,6 +218,42 @@ def grf_problem(n=24, seed_cfg=1, extra=0, ell=4.0):
                    vol.reshape(-1), False)
 
 
+def skewed_problem(n=32, seed_cfg=5, extra=0, shear=(0.2, 0.15, 0.1), ell=4.0):
+    """19-point operator of a non-orthogonal (sheared) grid: k = exp(g) on a
+    uniform n^3 grid with unit volumes, Dirichlet on both x faces, Neumann
+    elsewhere, plus the cross-derivative terms of a constant metric whose
+    off-diagonal entries are `shear` = (xy, xz, yz).  The term
+    -d_p(s k d_q u) - d_q(s k d_p u) by central differences couples a cell to
+    its four edge neighbours (c + a e_p + b e_q, a, b = +-1) with -s a b k_e / 2,
+    k_e the harmonic mean of the two cells' k (symmetric); beyond a boundary
+    the edge neighbour is dropped.  Bands in the 19-point layout."""
+    s_coef, _, _, _ = _seeds(seed_cfg, extra)
+    g = gaussian_random_field((n, n, n), ell, np.random.default_rng(s_coef))
+    kcell = np.exp(g)
+    vol = np.ones((n, n, n))
+    bc = {'x': ('dirichlet', 'dirichlet'), 'y': ('neumann', 'neumann'),
+          'z': ('neumann', 'neumann')}
+    ones = np.ones(n)
+    b7 = assemble(kcell, vol, (ones, ones, ones), bc)
+    bands = np.zeros((19, n ** 3))
+    bands[:7] = b7
+    # edge bands 7..18: (dx, dy, dz) as in the 19-point layout
+    edges = ((-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 1, 0),
+             (-1, 0, -1), (1, 0, -1), (-1, 0, 1), (1, 0, 1),
+             (0, -1, -1), (0, 1, -1), (0, -1, 1), (0, 1, 1))
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    for e, (dx, dy, dz) in enumerate(edges):
+        gam = shear[0] if dz == 0 else (shear[1] if dy == 0 else shear[2])
+        sign = (dx or 1) * (dy or 1) * (dz or 1)      # product of the two nonzero offsets
+        xn, yn, zn = x + dx, y + dy, z + dz
+        ok = (xn >= 0) & (xn < n) & (yn >= 0) & (yn < n) & (zn >= 0) & (zn < n)
+        kn = kcell[np.clip(zn, 0, n - 1), np.clip(yn, 0, n - 1), np.clip(xn, 0, n - 1)]
+        ke = 2.0 * kcell * kn / (kcell + kn)
+        bands[7 + e] = np.where(ok, -gam * sign * ke / 2.0, 0.0).reshape(-1)
+    return Problem(f"skewed{n}", (n, n, n), (False, False, False), np.ascontiguousarray(bands),
+                   vol.reshape(-1), False)
+
+
 # tanh clustering strength of the 128^3 channel grid with adjacent width
 # ratio 1.1; the same wall clustering at other resolutions (largest/smallest
 # width ~ 94..112 for 32^3..192^3)
@@ -326,4 +362,6 @@ def build_problem(kind, n, extra=0):
         return channel_problem(n)
     if kind == "porous":
         return porous_problem(n, extra=extra)
+    if kind == "skewed":
+        return skewed_problem(n, extra=extra)
     raise ValueError(kind)
