@@ -222,6 +222,19 @@ int krs_set_stream(krs_ctx* ctx, void* hip_stream);
 /* Matrix: borrows `bands` (7*N device values of `dt`). */
 int krs_matrix_create(krs_ctx* ctx, const krs_grid* g, krs_dtype dt, const void* bands,
                       krs_matrix** out);
+/* Matrix of a 19-point stencil (non-orthogonal grids, Sec. 2.1 "Data
+ * Layout"): borrows `bands`, 19*N device values of `dt`, band-major.  Band 0
+ * couples a cell to itself, bands 1-6 to its face neighbours in the order
+ * of the 7-point layout (x-1, x+1, y-1, y+1, z-1, z+1), bands 7-18 to its
+ * edge neighbours (dx, dy, dz): (-1,-1,0) (1,-1,0) (-1,1,0) (1,1,0),
+ * (-1,0,-1) (1,0,-1) (-1,0,1) (1,0,1), (0,-1,-1) (0,1,-1) (0,-1,1) (0,1,1).
+ * Periodic axes wrap; a neighbour beyond a non-periodic face contributes
+ * nothing.  Every solver takes it; the Schwarz preconditioner then reads the
+ * bands in its local solves (no coefficient pack) and runs the global sweep
+ * and the matvec as separate passes; SSOR local solves are refused (the two
+ * colours do not decouple edge neighbours). */
+int krs_matrix_create_19pt(krs_ctx* ctx, const krs_grid* g, krs_dtype dt, const void* bands,
+                           krs_matrix** out);
 void krs_matrix_destroy(krs_matrix* A);
 
 /* Preconditioner for A; `ws` is a device buffer of at least

@@ -102,6 +102,18 @@ int krs_set_stream(krs_ctx* ctx, void* hip_stream) {
 
 int krs_matrix_create(krs_ctx* ctx, const krs_grid* g, krs_dtype dt, const void* bands,
                       krs_matrix** out) {
+  return krs::matrix_create(ctx, g, dt, bands, 7, out);
+}
+
+int krs_matrix_create_19pt(krs_ctx* ctx, const krs_grid* g, krs_dtype dt, const void* bands,
+                           krs_matrix** out) {
+  return krs::matrix_create(ctx, g, dt, bands, 19, out);
+}
+}  // extern "C"
+
+namespace krs {
+int matrix_create(krs_ctx* ctx, const krs_grid* g, krs_dtype dt, const void* bands, int pts,
+                  krs_matrix** out) {
   if (!ctx || !g || !out) return KRS_ERR_ARG;
   *out = nullptr;
   if (!valid_dtype(dt)) return set_err(ctx, KRS_ERR_ARG, "unknown dtype");
@@ -121,9 +133,13 @@ int krs_matrix_create(krs_ctx* ctx, const krs_grid* g, krs_dtype dt, const void*
   A->dt = dt;
   A->bands = bands;
   A->n = n;
+  A->pts = pts;
   *out = A;
   return KRS_OK;
 }
+}  // namespace krs
+
+extern "C" {
 
 void krs_matrix_destroy(krs_matrix* A) { delete A; }
 
@@ -152,6 +168,9 @@ int krs_precond_create(krs_ctx* ctx, const krs_matrix* A, const krs_precond_desc
       return set_err(ctx, KRS_ERR_ARG, "sweep counts must be >= 0");
     if (d->local_solver != KRS_LOCAL_JACOBI && d->local_solver != KRS_LOCAL_SSOR)
       return set_err(ctx, KRS_ERR_ARG, "unknown local solver");
+    if (d->local_solver == KRS_LOCAL_SSOR && A->pts != 7)
+      return set_err(ctx, KRS_ERR_ARG,
+                     "SSOR local solves need 7-point bands (two colours decouple only those)");
     const int64_t dims[3] = {A->g.nx, A->g.ny, A->g.nz};
     for (int a = 0; a < 3; ++a) {
       if (dims[a] % d->tile)
@@ -169,7 +188,9 @@ int krs_precond_create(krs_ctx* ctx, const krs_matrix* A, const krs_precond_desc
   M->d = *d;
   if (d->type == KRS_PC_SCHWARZ_JACOBI) {
     M->tmp = ws;
-    M->pack = (char*)ws + krs::align_up((size_t)krs::vec_ld(A->n) * dsize(A->dt));
+    M->pack = krs::precond_pack_bytes(A, d) > 0
+                  ? (char*)ws + krs::align_up((size_t)krs::vec_ld(A->n) * dsize(A->dt))
+                  : nullptr;
     const int rc = krs::precond_pack(ctx, M);
     if (rc) {
       delete M;
@@ -376,6 +397,7 @@ int krs_ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32,
   if (A64->dt != KRS_F64 || A32->dt != KRS_F32)
     return set_err(ctx, KRS_ERR_STATE, "IR needs an FP64 and an FP32 matrix");
   if (A64->n != A32->n) return set_err(ctx, KRS_ERR_STATE, "IR matrices differ in size");
+  if (A64->pts != A32->pts) return set_err(ctx, KRS_ERR_STATE, "IR matrices differ in stencil");
   if ((rc = check_precond(ctx, A32, M32))) return rc;
   if (opts->inner_solver != KRS_SOLVER_RGCROT && opts->inner_solver != KRS_SOLVER_RBICGSTAB)
     return set_err(ctx, KRS_ERR_ARG, "inner solver must be RGCROT or RBICGSTAB");

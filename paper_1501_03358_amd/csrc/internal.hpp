@@ -48,6 +48,7 @@ struct krs_matrix {
   krs_dtype dt = KRS_F64;
   const void* bands = nullptr;
   int64_t n = 0;
+  int pts = 7;        // 7 or 19 bands
 };
 
 struct krs_precond {
@@ -131,6 +132,7 @@ inline Grid3 grid3(const krs_matrix* A) {
   g.py = A->g.periodic[1] ? 1 : 0;
   g.pz = A->g.periodic[2] ? 1 : 0;
   g.n = A->n;
+  g.pts = A->pts;
   return g;
 }
 
@@ -182,6 +184,9 @@ void timing_add_bytes(krs_ctx* ctx, int cls, double bytes);
 namespace krs {
 int workspace_bytes(krs_solver solver, int64_t n, int m, int k, krs_dtype dt, size_t* bytes);
 int precond_apply(krs_ctx* ctx, const krs_precond* M, const void* r, void* z, void* tmp);
+// krs_matrix_create / krs_matrix_create_19pt (pts = 7 or 19 bands)
+int matrix_create(krs_ctx* ctx, const krs_grid* g, krs_dtype dt, const void* bands, int pts,
+                  krs_matrix** out);
 int operator_apply(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const void* v, void* w,
                    void* tmp);
 int precond_pack(krs_ctx* ctx, const krs_precond* M);

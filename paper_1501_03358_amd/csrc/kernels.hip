@@ -96,6 +96,67 @@ __device__ __forceinline__ T apply_row(const Grid3& g, const T* __restrict__ A,
   return ax;
 }
 
+// ---------------------------------------------------------------------------
+// 19-point stencil of non-orthogonal grids: band 0 the cell, bands 1-6 the
+// face neighbours in the 7-point order, bands 7-18 the edge neighbours
+// (dx, dy, dz) listed in kNb19[6..17]; periodic wrap per axis, a neighbour
+// beyond a non-periodic face contributes nothing
+// ---------------------------------------------------------------------------
+constexpr int kNb19[18][3] = {{-1, 0, 0}, {1, 0, 0},  {0, -1, 0}, {0, 1, 0},   {0, 0, -1},
+                              {0, 0, 1},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 1, 0},
+                              {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1}, {1, 0, 1},  {0, -1, -1},
+                              {0, 1, -1}, {0, -1, 1}, {0, 1, 1}};
+
+__device__ __forceinline__ bool wrap_coord(int& c, int n, int periodic);
+
+template <class T>
+__device__ __forceinline__ T apply_row19(const Grid3& g, const T* __restrict__ A,
+                                         const T* __restrict__ x, int64_t i) {
+  const int64_t N = g.n;
+  const int ii = (int)i;
+  const int ix = ii % g.nx, t = ii / g.nx;
+  const int iy = t % g.ny, iz = t / g.ny;
+  T ax = A[i] * x[i];
+#pragma unroll
+  for (int k = 0; k < 18; ++k) {
+    int jx = ix + kNb19[k][0], jy = iy + kNb19[k][1], jz = iz + kNb19[k][2];
+    if (wrap_coord(jx, g.nx, g.px) && wrap_coord(jy, g.ny, g.py) && wrap_coord(jz, g.nz, g.pz))
+      ax += A[(k + 1) * N + i] * x[jx + (int64_t)g.nx * (jy + (int64_t)g.ny * jz)];
+  }
+  return ax;
+}
+
+template <class T, int MODE>
+__global__ __launch_bounds__(kThreads) void k_stencil19(Grid3 g, const T* __restrict__ A,
+                                                         const T* __restrict__ x, T* y, T alpha,
+                                                         T beta, const T* __restrict__ bv) {
+  const int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+  if (i >= g.n) return;
+  const T ax = apply_row19(g, A, x, i);
+  T out;
+  if constexpr (MODE == 0) out = alpha * ax;
+  else if constexpr (MODE == 1) out = alpha * ax + beta * bv[i];
+  else if constexpr (MODE == 2) out = alpha * ax + beta * y[i];
+  else out = x[i] + alpha * (bv[i] - ax) / A[i];
+  y[i] = out;
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_residual_norm19(Grid3 g, const T* __restrict__ A,
+                                                              const T* __restrict__ x,
+                                                              const T* __restrict__ b,
+                                                              T* __restrict__ y, T* partials) {
+  T acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const T v = b[i] - apply_row19(g, A, x, i);
+    y[i] = v;
+    acc += v * v;
+  }
+  const T s = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
 // MODE 0: y = a*Ax; 1: y = a*Ax + b0*bv; 2: y = a*Ax + b0*y; 3: y = x + a*(bv - Ax)/C
 template <class T, int MODE>
 __global__ __launch_bounds__(kThreads) void k_stencil(Grid3 g, const T* __restrict__ A,
@@ -358,7 +419,9 @@ __device__ __forceinline__ bool wrap_coord(int& c, int n, int periodic) {
   return true;
 }
 
-template <class T, int TILE>
+// NN neighbours per cell: 6 (7-point bands) or 18 (19-point bands), in the
+// order of kNb19.
+template <class T, int TILE, int NN>
 __global__ __launch_bounds__(kThreads) void k_schwarz_local(Grid3 g, const T* __restrict__ A,
                                                             const T* __restrict__ r,
                                                             T* __restrict__ z, T omega,
@@ -382,7 +445,7 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local(Grid3 g, const T* __
 
   // per cell: d0 = omega r / a_C and c_k = omega a_k / a_C, so that one damped
   // Jacobi sweep is z <- (1 - omega) z + d0 - sum_k c_k z_k
-  T cf[PER][6];
+  T cf[PER][NN];
   T d0[PER];
   int li[PER];
   int gi[PER];
@@ -391,7 +454,7 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local(Grid3 g, const T* __
   for (int q = 0; q < PER; ++q) {
     const int e = tid + kThreads * q;
 #pragma unroll
-    for (int d = 0; d < 6; ++d) cf[q][d] = 0;
+    for (int d = 0; d < NN; ++d) cf[q][d] = 0;
     d0[q] = 0;
     gi[q] = -1;
     li[q] = 0;
@@ -408,7 +471,7 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local(Grid3 g, const T* __
         gi[q] = (int)i;
         const T s = omega / A[i];
 #pragma unroll
-        for (int d = 0; d < 6; ++d) cf[q][d] = s * A[(d + 1) * N + i];
+        for (int d = 0; d < NN; ++d) cf[q][d] = s * A[(d + 1) * N + i];
         d0[q] = s * r[i];
       }
     }
@@ -432,12 +495,9 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local(Grid3 g, const T* __
       if (e < NE) {
         const int l = li[q];
         T v = keep * zc[l] + d0[q];
-        v -= cf[q][0] * zc[l - 1];
-        v -= cf[q][1] * zc[l + 1];
-        v -= cf[q][2] * zc[l - P];
-        v -= cf[q][3] * zc[l + P];
-        v -= cf[q][4] * zc[l - P * P];
-        v -= cf[q][5] * zc[l + P * P];
+#pragma unroll
+        for (int d = 0; d < NN; ++d)
+          v -= cf[q][d] * zc[l + kNb19[d][0] + P * kNb19[d][1] + P * P * kNb19[d][2]];
         zn[l] = v;
       }
     }
@@ -1620,6 +1680,14 @@ hipError_t stencil(hipStream_t s, const Grid3& g, const T* bands, const T* x, T*
                    double beta, const T* b, int mode) {
   const int grid = grid_for(g.n);
   if (g.n == 0) return hipSuccess;
+  if (g.pts == 19) {
+    switch (mode) {
+      case 0: k_stencil19<T, 0><<<grid, kThreads, 0, s>>>(g, bands, x, y, (T)alpha, (T)beta, b); break;
+      case 1: k_stencil19<T, 1><<<grid, kThreads, 0, s>>>(g, bands, x, y, (T)alpha, (T)beta, b); break;
+      default: k_stencil19<T, 2><<<grid, kThreads, 0, s>>>(g, bands, x, y, (T)alpha, (T)beta, b); break;
+    }
+    return hipGetLastError();
+  }
   constexpr int W = 16 / sizeof(T);
   if (stencil_vec_ok(g, bands, x, y, b)) {
     const int gv = grid_for(g.n / W);
@@ -1642,7 +1710,9 @@ template <class T>
 hipError_t residual_norm(hipStream_t s, const Grid3& g, const T* bands, const T* x, const T* b,
                          T* y, T* partials) {
   constexpr int W = 16 / sizeof(T);
-  if (stencil_vec_ok(g, bands, x, (const T*)y, b))
+  if (g.pts == 19)
+    k_residual_norm19<T><<<red_blocks(g.n), kThreads, 0, s>>>(g, bands, x, b, y, partials);
+  else if (stencil_vec_ok(g, bands, x, (const T*)y, b))
     k_residual_norm_v<T, W><<<red_blocks(g.n), kThreads, 0, s>>>(g, bands, x, b, y, partials);
   else
     k_residual_norm<T><<<red_blocks(g.n), kThreads, 0, s>>>(g, bands, x, b, y, partials);
@@ -1654,7 +1724,9 @@ hipError_t jacobi_sweep(hipStream_t s, const Grid3& g, const T* bands, const T* 
                         T* zout, double omega) {
   if (g.n == 0) return hipSuccess;
   constexpr int W = 16 / sizeof(T);
-  if (stencil_vec_ok(g, bands, zin, (const T*)zout, r))
+  if (g.pts == 19)
+    k_stencil19<T, 3><<<grid_for(g.n), kThreads, 0, s>>>(g, bands, zin, zout, (T)omega, T(0), r);
+  else if (stencil_vec_ok(g, bands, zin, (const T*)zout, r))
     k_stencil_v<T, W, 3><<<grid_for(g.n / W), kThreads, 0, s>>>(g, bands, zin, zout, (T)omega,
                                                                 T(0), r);
   else
@@ -1666,6 +1738,7 @@ template <class T>
 hipError_t sweep_stencil(hipStream_t s, const Grid3& g, const T* bands, const T* r, const T* zl,
                          T* w, double omega) {
   if (g.n == 0) return hipSuccess;
+  if (g.pts != 7) return hipErrorInvalidValue;   // fused form for 7-point bands only
   const bool wide = g.nx > 32;
   const int TX = wide ? 64 : 32, TY = wide ? 8 : 16;
   const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY;
@@ -1696,6 +1769,7 @@ hipError_t point_jacobi(hipStream_t s, const Grid3& g, const T* bands, const T* 
 template <class T>
 hipError_t schwarz_pack(hipStream_t s, const Grid3& g, int tile, const T* bands, T* pk,
                         double omega) {
+  if (g.pts != 7) return hipErrorInvalidValue;   // packed form for 7-point bands only
   const int ntx = g.nx / tile, nty = g.ny / tile, ntz = g.nz / tile;
   const int br = schwarz_brick(g, tile);
   const int nbx = ntx / br, nby = nty / br, nb = nbx * nby * (ntz / br);
@@ -1714,6 +1788,7 @@ hipError_t schwarz_pack(hipStream_t s, const Grid3& g, int tile, const T* bands,
 template <class T>
 hipError_t schwarz_local_packed(hipStream_t s, const Grid3& g, int tile, const T* pk, const T* r,
                                 T* z, double omega, int sweeps, bool ssor) {
+  if (g.pts != 7) return hipErrorInvalidValue;   // packed form for 7-point bands only
   const int ntx = g.nx / tile, nty = g.ny / tile, ntz = g.nz / tile;
   const int nt = ntx * nty * ntz;
   if (nt == 0) return hipSuccess;
@@ -1745,12 +1820,15 @@ hipError_t schwarz_local(hipStream_t s, const Grid3& g, int tile, const T* bands
   const int nt = ntx * nty * ntz;
   if (nt == 0) return hipSuccess;
   if (sweeps < 1) return hipErrorInvalidValue;
-  if (tile == 8)
-    k_schwarz_local<T, 8><<<nt, kThreads, 0, s>>>(g, bands, r, z, (T)omega, sweeps, ntx, nty);
-  else if (tile == 4)
-    k_schwarz_local<T, 4><<<nt, kThreads, 0, s>>>(g, bands, r, z, (T)omega, sweeps, ntx, nty);
-  else
-    return hipErrorInvalidValue;
+#define KRS_SL(TL, NN) \
+  k_schwarz_local<T, TL, NN><<<nt, kThreads, 0, s>>>(g, bands, r, z, (T)omega, sweeps, ntx, nty)
+  const bool p19 = g.pts == 19;
+  if (tile == 8 && p19) KRS_SL(8, 18);
+  else if (tile == 8) KRS_SL(8, 6);
+  else if (tile == 4 && p19) KRS_SL(4, 18);
+  else if (tile == 4) KRS_SL(4, 6);
+  else return hipErrorInvalidValue;
+#undef KRS_SL
   return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@ struct Grid3 {
   int nx, ny, nz;
   int px, py, pz;
   int64_t n;
+  int pts = 7;   // stencil points: 7 (orthogonal grids) or 19 (non-orthogonal)
 };
 
 // A column set [P1 (n1 columns, ld1) | P2 (n2 columns, ld2)].

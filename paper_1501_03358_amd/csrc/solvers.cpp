@@ -55,13 +55,14 @@ struct Op {
     }
     const int gs = M->d.global_sweeps;
     T* first = (gs % 2 == 0) ? out : tmp;
+    const double PW = (double)(g.pts + 2) * NW;   // bands, input and output
     if (M->d.local_sweeps > 0 && M->pack) {
-      KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, 9 * NW,
+      KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, PW,
                  schwarz_local_packed<T>(s, g, M->d.tile, (const T*)M->pack, r, first,
                                          M->d.omega_local, M->d.local_sweeps,
                                          M->d.local_solver == KRS_LOCAL_SSOR));
     } else if (M->d.local_sweeps > 0) {
-      KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, 9 * NW,
+      KRS_LAUNCH(ctx, KRS_K_SCHWARZ_LOCAL, PW,
                  schwarz_local<T>(s, g, M->d.tile, bands(), r, first, M->d.omega_local,
                                   M->d.local_sweeps));
     } else {
@@ -70,7 +71,7 @@ struct Op {
     T* cur = first;
     for (int i = 0; i < gs; ++i) {
       T* nxt = (cur == out) ? tmp : out;
-      KRS_LAUNCH(ctx, KRS_K_JACOBI_SWEEP, 10 * NW,
+      KRS_LAUNCH(ctx, KRS_K_JACOBI_SWEEP, PW + NW,
                  jacobi_sweep<T>(s, g, bands(), r, cur, nxt, M->d.omega_global));
       cur = nxt;
     }
@@ -80,7 +81,7 @@ struct Op {
   // (w, not yet written, is the preconditioner's temporary)
   int apply(const T* v, T* w) {
     if (M && M->d.type == KRS_PC_SCHWARZ_JACOBI && M->d.global_sweeps == 1 &&
-        g.n >= kFuseMinN) {
+        g.n >= kFuseMinN && g.pts == 7) {
       // local solves into z, then the global sweep and the matvec in one pass
       // (on smaller grids the two streaming kernels are as fast: the fused
       // pass recomputes two halo planes per column chunk)
@@ -104,7 +105,7 @@ struct Op {
     }
     int rc = minv_s(v, z, w);
     if (rc) return rc;
-    KRS_LAUNCH(ctx, KRS_K_STENCIL, 9.0 * g.n * sizeof(T),
+    KRS_LAUNCH(ctx, KRS_K_STENCIL, (g.pts + 2.0) * g.n * sizeof(T),
                stencil<T>(ctx->stream, g, bands(), z, w, 1.0, 0.0, nullptr, 0));
     return 0;
   }
@@ -547,7 +548,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
   // through z, with ptmp as the preconditioner's temporary)
   auto apply = [&](const T* v, T* out) -> int {
     if (!left) return op.apply(v, out);
-    KRS_LAUNCH(ctx, KRS_K_STENCIL, 9 * NW,
+    KRS_LAUNCH(ctx, KRS_K_STENCIL, (op.g.pts + 2) * NW,
                stencil<T>(s, op.g, op.bands(), v, z, 1.0, 0.0, nullptr, 0));
     return op.minv_s(z, out, ptmp);
   };
@@ -722,7 +723,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
     // line 14: true residual r = b - A~ y (into the first basis column)
     if (left) {
       // r = M^-1 (b - A x) = M^-1 b - M^-1 A x
-      KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 10 * NW,
+      KRS_LAUNCH(ctx, KRS_K_RESIDUAL, (op.g.pts + 3) * NW,
                  residual_norm<T>(s, op.g, op.bands(), x, b_orig, z, part));
       rc = op.minv_s(z, r0, ptmp);
       if (rc) return rc;
@@ -730,7 +731,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
     } else {
       rc = op.minv(x, z);
       if (rc) return rc;
-      KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 10 * NW,
+      KRS_LAUNCH(ctx, KRS_K_RESIDUAL, (op.g.pts + 3) * NW,
                  residual_norm<T>(s, op.g, op.bands(), z, b, r0, part));
     }
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, d_nrm));
@@ -761,7 +762,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
   double rel_true = rho / nb;
   if (left) {
     // x is the iterate itself; report the unpreconditioned residual
-    KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 10 * NW,
+    KRS_LAUNCH(ctx, KRS_K_RESIDUAL, (op.g.pts + 3) * NW,
                residual_norm<T>(s, op.g, op.bands(), x, b_orig, z, part));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, d_nrm));
     rc = read_dev(ctx, d_nrm, 1);
@@ -1176,7 +1177,8 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   rc = op.minv_s(y, x, z);
   if (rc) return rc;
   // true residual of x
-  KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 10 * NW, residual_norm<T>(s, op.g, op.bands(), x, b, t, part));
+  KRS_LAUNCH(ctx, KRS_K_RESIDUAL, (op.g.pts + 3) * NW,
+             residual_norm<T>(s, op.g, op.bands(), x, b, t, part));
   KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, sc + kNrm));
   rc = read_dev(ctx, sc + kNrm, 1);
   if (rc) return rc;
@@ -1229,7 +1231,8 @@ int workspace_bytes(krs_solver solver, int64_t n, int m, int k, krs_dtype dt, si
 }
 
 size_t precond_pack_bytes(const krs_matrix* A, const krs_precond_desc* d) {
-  if (!d || d->type != KRS_PC_SCHWARZ_JACOBI || d->tile <= 0) return 0;
+  // the packed coefficients serve 7-point bands; 19-point local solves read the bands
+  if (!d || d->type != KRS_PC_SCHWARZ_JACOBI || d->tile <= 0 || A->pts != 7) return 0;
   return (size_t)schwarz_pack_values(grid3(A), d->tile) *
          (A->dt == KRS_F64 ? sizeof(double) : sizeof(float));
 }
@@ -1382,7 +1385,7 @@ int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const k
     // x += ||r|| d ; r = b - A x in FP64
     ctx->bytes = 0;
     KRS_LAUNCH(ctx, KRS_K_OTHER, 20.0 * n, axpy_f32_into_f64(s, d32, x, n, sc + 17));
-    KRS_LAUNCH(ctx, KRS_K_RESIDUAL, 80.0 * n,
+    KRS_LAUNCH(ctx, KRS_K_RESIDUAL, (8.0 * g.pts + 24.0) * n,
                residual_norm<double>(s, g, (const double*)A64->bands, x, b, r64, part));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<double>(s, part, nblk, 1, sc));
     total_bytes += ctx->bytes;

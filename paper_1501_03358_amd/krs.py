@@ -30,6 +30,7 @@ FLAG_LEFT_PRECOND = 8
 
 EXPORTS = (
     "krs_create", "krs_destroy", "krs_last_error", "krs_set_stream", "krs_matrix_create",
+    "krs_matrix_create_19pt",
     "krs_matrix_destroy", "krs_precond_create", "krs_precond_workspace_size",
     "krs_precond_refresh", "krs_precond_destroy", "krs_recycle_create", "krs_recycle_destroy", "krs_recycle_dim",
     "krs_recycle_set_dim", "krs_recycle_mark_stale", "krs_workspace_size", "krs_stencil_apply", "krs_precond_apply",
@@ -88,6 +89,7 @@ def _declare(L):
         "krs_last_error": (ctypes.c_char_p, [P]),
         "krs_set_stream": (i32, [P, P]),
         "krs_matrix_create": (i32, [P, ctypes.POINTER(Grid), i32, P, ctypes.POINTER(P)]),
+        "krs_matrix_create_19pt": (i32, [P, ctypes.POINTER(Grid), i32, P, ctypes.POINTER(P)]),
         "krs_matrix_destroy": (None, [P]),
         "krs_precond_create": (i32, [P, P, ctypes.POINTER(PrecondDesc), P, sz, ctypes.POINTER(P)]),
         "krs_precond_workspace_size": (sz, [P, ctypes.POINTER(PrecondDesc)]),
@@ -190,11 +192,12 @@ class Context:
 
 
 class Matrix:
-    """7-band operator on an (nx, ny, nz) grid; `bands` is a [7, N] device tensor."""
+    """7- or 19-band operator on an (nx, ny, nz) grid; `bands` is a [7, N] or
+    [19, N] device tensor (krs_matrix_create / krs_matrix_create_19pt)."""
 
     def __init__(self, ctx, shape, periodic, bands):
-        if not bands.is_cuda or not bands.is_contiguous() or bands.shape[0] != 7:
-            raise ValueError("bands must be a contiguous [7, N] device tensor")
+        if not bands.is_cuda or not bands.is_contiguous() or bands.shape[0] not in (7, 19):
+            raise ValueError("bands must be a contiguous [7, N] or [19, N] device tensor")
         self.ctx, self.bands = ctx, bands
         self.shape = tuple(int(s) for s in shape)
         self.n = self.shape[0] * self.shape[1] * self.shape[2]
@@ -202,8 +205,8 @@ class Matrix:
         g = Grid(self.shape[0], self.shape[1], self.shape[2],
                  (ctypes.c_int32 * 3)(*[1 if p else 0 for p in periodic]))
         h = P()
-        ctx.check(lib().krs_matrix_create(ctx.h, ctypes.byref(g), _dt(bands), _ptr(bands),
-                                          ctypes.byref(h)))
+        create = lib().krs_matrix_create if bands.shape[0] == 7 else lib().krs_matrix_create_19pt
+        ctx.check(create(ctx.h, ctypes.byref(g), _dt(bands), _ptr(bands), ctypes.byref(h)))
         self.h = h
 
     def __del__(self):

@@ -24,6 +24,16 @@ def _ragged(shape, periodic, seed):
     return W.Problem("ragged", shape, periodic, bands, vol.reshape(-1), False)
 
 
+def _ragged19(shape, periodic, seed):
+    """A ragged 7-point problem plus random edge couplings (19 bands)."""
+    p7 = _ragged(shape, periodic, seed)
+    rng = np.random.default_rng(seed + 50)
+    bands = np.zeros((19, p7.n))
+    bands[:7] = p7.bands
+    bands[7:] = 0.05 * rng.standard_normal((12, p7.n)) * np.abs(p7.bands[0])[None]
+    return W.Problem("ragged19", shape, periodic, np.ascontiguousarray(bands), p7.vol, False)
+
+
 STENCIL_CASES = [
     lambda: W.grf_problem(24),
     lambda: W.channel_problem(16),
@@ -31,6 +41,11 @@ STENCIL_CASES = [
     lambda: _ragged((1, 1, 1), (False, False, False), 2),
     lambda: _ragged((67, 3, 9), (True, True, True), 3),
     lambda: _ragged((5, 300, 2), (False, False, False), 4),
+    # 19-point operators (non-orthogonal grids)
+    lambda: W.skewed_problem(16),
+    lambda: _ragged19((13, 7, 5), (False, True, False), 11),
+    lambda: _ragged19((3, 3, 3), (True, True, True), 12),
+    lambda: _ragged19((67, 3, 9), (True, False, True), 13),
 ]
 
 
@@ -79,6 +94,11 @@ PC_CASES = [
      dict(tile=8, local_solver="ssor", omega_local=1.3)),
     ("porous32_t4_ssor", lambda: W.porous_problem(32, extra=5),
      dict(tile=4, local_solver="ssor", omega_local=1.0, local_sweeps=3)),
+    # 19-point operators: local solves over the 18 neighbours (bands read directly)
+    ("skewed16_t8", lambda: W.skewed_problem(16), dict(tile=8)),
+    ("skewed16_t4", lambda: W.skewed_problem(16), SMALL_SCHWARZ),
+    ("ragged19_24x16x16_t8", lambda: _ragged19((24, 16, 16), (True, False, True), 14),
+     dict(tile=8, global_sweeps=2)),
 ]
 
 
@@ -166,6 +186,9 @@ OP_CASES = PC_CASES + [
     ("fused40x40x2624", lambda: _ragged((40, 40, 2624), (False, True, False), 9), dict(tile=8)),
     ("fused24x24x7296_px", lambda: _ragged((24, 24, 7296), (True, False, False), 10),
      dict(tile=8)),
+    # a 19-point operator of that size runs the sweep and the matvec separately
+    ("ragged19_72x24x2432_periodic", lambda: _ragged19((72, 24, 2432), (True, True, True), 15),
+     dict(tile=8)),
 ]
 
 
@@ -231,3 +254,10 @@ def test_operator_apply_full_size_porous256_fp32(gpu_lib):
         got = a.reshape(256, 256, 256)[sl][16:24, 16:24, 16:24]
         refw = ws[16:24, 16:24, 16:24]
         assert np.abs(got - refw).max() <= 1e-4 * np.abs(refw).max()
+
+
+def test_19pt_ssor_local_solver_rejected(gpu_lib):
+    krs = gpu_lib
+    prob = W.skewed_problem(8)
+    with pytest.raises(krs.KrsError, match="SSOR"):
+        Dev(krs, prob, "schwarz", dict(tile=4, local_solver="ssor", omega_local=1.0))

@@ -595,3 +595,51 @@ def test_rgcrot_gcrot_rule_rejected_where_unsupported(gpu_lib):
     rc, st = krs.rgcrot_solve(dt.ctx, dt.A, dt.M, rec, b, dt.empty(),
                               krs.make_opts(m=10, k=6, recycle_rule=krs.RECYCLE_GCROT), dt.ws)
     assert rc == krs.OK and 1 <= rec.dim <= 6
+
+
+def test_19pt_operator_solvers_match_oracle(gpu_lib):
+    """Sheared-grid 19-point operator (Schwarz local solves over the 18
+    neighbours): rGCROT stepwise against the oracle, rBiCGStab with the
+    resulting space, and FP32 inner solves in FP64 refinement to a 1e-8 true
+    residual."""
+    krs = gpu_lib
+    prob = W.skewed_problem(24, extra=91)
+    params = dict(SMALL_SCHWARZ)
+    bs = list(W.rhs_ar1(prob, 4, extra=91))
+    d, rec, orec, op, out = _rgcrot_sequence(krs, prob, "schwarz", params, 20, 10, 3, bs)
+    for t, (rc, st, h, x, ref) in enumerate(out):
+        assert rc == krs.OK and ref.status == K.CONVERGED, t
+        _check_history(h, ref.history)
+        assert abs(st.iterations - ref.iterations) <= 2, (t, st.iterations, ref.iterations)
+        _check_solution(prob, x, ref.x)
+    _, Mi, _ = oracle_ops(prob, "schwarz", params)
+    g = recycle_to_oracle(rec)
+    h = _hist()
+    x = d.empty()
+    rc, st = krs.rbicgstab_solve(d.ctx, d.A, d.M, rec, d.vec(bs[3]), x,
+                                 krs.make_opts(tol=1e-8, history=h), d.ws)
+    ref = K.rbicgstab(op, Mi, bs[3], 1e-8, g)
+    assert rc == krs.OK and ref.status == K.CONVERGED
+    _check_history(h[:st.history_len], ref.history)
+    assert abs(st.iterations - ref.iterations) <= 2
+    _check_solution(prob, x.cpu().numpy(), ref.x)
+    # FP32 inner solves in FP64 refinement
+    dev = torch.device("cuda:0")
+    ctx = d.ctx
+    b64 = torch.from_numpy(prob.bands).to(dev)
+    b32 = b64.float()
+    A64 = krs.Matrix(ctx, prob.shape, prob.periodic, b64)
+    A32 = krs.Matrix(ctx, prob.shape, prob.periodic, b32)
+    M32 = krs.Precond(ctx, A32, "schwarz", **params)
+    rec32 = krs.Recycle(ctx, prob.n, 10, torch.float32)
+    ws = torch.empty(krs.workspace_size(krs.SOLVER_IR, prob.n, 20, 10, torch.float32),
+                     dtype=torch.uint8, device=dev)
+    A = lambda v: stencil.apply(prob.bands, prob.shape, prob.periodic, v)
+    for t, b in enumerate(bs):
+        x = torch.empty(prob.n, dtype=torch.float64, device=dev)
+        inner = krs.SOLVER_RGCROT if t < 2 else krs.SOLVER_RBICGSTAB
+        rc, st = krs.ir_solve(ctx, A64, A32, M32, rec32, torch.from_numpy(b).to(dev), x,
+                              krs.make_opts(m=20, k=10, tol=1e-8, inner_solver=inner,
+                                            inner_tol=1e-5), ws)
+        assert rc == krs.OK, (t, rc)
+        assert np.linalg.norm(b - A(x.cpu().numpy())) <= 1e-8 * np.linalg.norm(b)
