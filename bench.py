@@ -235,8 +235,9 @@ def serve_main(args):
 
 def seq_main(args):
     """FP64 sequences on the GPU: the 128^3 channel (rGCROT(30,20) against
-    GMRES(30), 50 systems) or the 128^3 porous medium (hybrid against plain
-    BiCGStab and rGCROT(30,20) throughout, 100 systems)."""
+    GMRES(30), 50 systems), or the 128^3 porous medium or sheared grid
+    (19-point operator) with the hybrid against plain BiCGStab and
+    rGCROT(30,20) throughout, 100 systems."""
     import torch
 
     import workloads as W
@@ -248,7 +249,10 @@ def seq_main(args):
     n = args.n if args.n != 256 else 128
     steps = args.steps if args.steps is not None else (50 if channel else 100)
     t0 = time.time()
-    prob = W.channel_problem(n) if channel else W.porous_problem(n, seed_cfg=3)
+    if args.workload == "skewed128":     # 19-point operator of a sheared grid
+        prob = W.skewed_problem(n)
+    else:
+        prob = W.channel_problem(n) if channel else W.porous_problem(n, seed_cfg=3)
     # changing matrix: the solid conductivity drifts by 10% every
     # `change_every` systems (same pore geometry)
     probs_t = None
@@ -384,7 +388,7 @@ def seq_main(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["porous_ir", "serve", "channel128", "porous128",
-                                           "porous128_changing"],
+                                           "porous128_changing", "skewed128"],
                     default="porous_ir")
     ap.add_argument("--local-solver", choices=["jacobi", "ssor"], default="jacobi",
                     help="local smoother of the Schwarz preconditioner")
@@ -436,7 +440,7 @@ def main():
     if args.workload == "serve":
         serve_main(args)
         return
-    if args.workload in ("channel128", "porous128", "porous128_changing"):
+    if args.workload in ("channel128", "porous128", "porous128_changing", "skewed128"):
         if args.left and args.workload != "channel128":
             print("--left applies to channel128 (GMRES and rGCROT); the hybrid and BiCGStab "
                   "are right-preconditioned", file=sys.stderr)
