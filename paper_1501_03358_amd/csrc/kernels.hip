@@ -447,15 +447,19 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local(Grid3 g, const T* __
   // Jacobi sweep is z <- (1 - omega) z + d0 - sum_k c_k z_k
   T cf[PER][NN];
   T d0[PER];
+  T ac[PER], rv[PER];
   int li[PER];
   int gi[PER];
   unsigned ownm = 0;
+  // the raw bands and r of all slots are loaded before any is used (scaling
+  // inside the per-slot branch would wait for each slot's loads in turn)
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = tid + kThreads * q;
 #pragma unroll
     for (int d = 0; d < NN; ++d) cf[q][d] = 0;
-    d0[q] = 0;
+    ac[q] = 1;
+    rv[q] = 0;
     gi[q] = -1;
     li[q] = 0;
     if (e < NE) {
@@ -469,11 +473,21 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local(Grid3 g, const T* __
       if (ok) {
         const int64_t i = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
         gi[q] = (int)i;
-        const T s = omega / A[i];
+        ac[q] = A[i];
 #pragma unroll
-        for (int d = 0; d < NN; ++d) cf[q][d] = s * A[(d + 1) * N + i];
-        d0[q] = s * r[i];
+        for (int d = 0; d < NN; ++d) cf[q][d] = A[(d + 1) * N + i];
+        rv[q] = r[i];
       }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    d0[q] = 0;
+    if (gi[q] >= 0) {
+      const T s = omega / ac[q];
+#pragma unroll
+      for (int d = 0; d < NN; ++d) cf[q][d] = s * cf[q][d];
+      d0[q] = s * rv[q];
     }
   }
   __syncthreads();
@@ -594,15 +608,19 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T*
   const T* tp = pk + (int64_t)brick * 7 * NB;
   T cf[PER][6];
   T d0[PER];
+  T sc[PER], rv[PER];
   int li[PER];
   int gi[PER];
   unsigned ownm = 0;
+  // all loads of all slots are issued before any is used (a product inside
+  // the per-slot branch would wait for each slot's loads in turn)
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = cell(q);
 #pragma unroll
     for (int d = 0; d < 6; ++d) cf[q][d] = 0;
-    d0[q] = 0;
+    sc[q] = 0;
+    rv[q] = 0;
     gi[q] = -1;
     li[q] = 0;
     if (e < NE) {
@@ -614,16 +632,18 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T*
       if (ex >= 1 && ex <= TILE && ey >= 1 && ey <= TILE && ez >= 1 && ez <= TILE)
         ownm |= 1u << q;
       const int be = ((sz * TILE + ez) * EB + sy * TILE + ey) * EB + sx * TILE + ex;
-      const T sc = tp[be];
+      sc[q] = tp[be];
 #pragma unroll
       for (int d = 0; d < 6; ++d) cf[q][d] = tp[(d + 1) * NB + be];
       if (ok) {
         const int64_t i = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
         gi[q] = (int)i;
-        d0[q] = sc * r[i];
+        rv[q] = r[i];
       }
     }
   }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) d0[q] = gi[q] >= 0 ? sc[q] * rv[q] : T(0);
   __syncthreads();
   const T keep = T(1) - omega;
   if constexpr (SSOR) {
