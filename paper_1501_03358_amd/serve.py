@@ -132,7 +132,7 @@ class MatrixSpec:
     mid: int
     shape: tuple
     periodic: tuple
-    bands: np.ndarray        # [7, N] FP64 host
+    bands: np.ndarray        # [7, N] or [19, N] FP64 host
     k: Optional[int] = None  # recycle dimension (None: the server's default)
 
 
@@ -152,13 +152,15 @@ class _State:
         self.steps_done = 0
 
 
-def state_bytes(shape, k, tile=8):
-    """Device bytes of a resident matrix: FP64 + FP32 bands, the preconditioner
-    (one FP32 vector + packed coefficients) and the FP32 recycle space."""
+def state_bytes(shape, k, tile=8, npts=7):
+    """Device bytes of a resident matrix: FP64 + FP32 bands (7 or 19), the
+    preconditioner (one FP32 vector, plus packed coefficients for 7-point
+    bands: at most 7 values per extended-tile cell) and the FP32 recycle space."""
     n = shape[0] * shape[1] * shape[2]
     e = tile + 2
     ntile = (shape[0] // tile) * (shape[1] // tile) * (shape[2] // tile)
-    return 7 * n * 12 + 4 * n + 4 * 7 * e ** 3 * ntile + 2 * k * 4 * n
+    pack = 4 * 7 * e ** 3 * ntile if npts == 7 else 0
+    return npts * n * 12 + 4 * n + pack + 2 * k * 4 * n
 
 
 class Server:
@@ -182,7 +184,8 @@ class Server:
         budget = mem_budget - n_slots * slot_bytes
         self.sched = Scheduler(n_slots, budget,
                                lambda mid: state_bytes(self.specs[mid].shape, self.k_of[mid],
-                                                       self.pc["tile"]))
+                                                       self.pc["tile"],
+                                                       len(self.specs[mid].bands)))
         self.states = {}
         self.states_lock = threading.Lock()
         self.completed = []

@@ -151,3 +151,13 @@ def test_poisson_arrivals_and_latency_summary():
     s = latency_summary(reqs)
     assert s["p50"] == pytest.approx(50.5, rel=1e-6)
     assert s["p99"] == pytest.approx(99.01, rel=1e-3)
+
+
+def test_state_bytes_counts_bands_and_pack():
+    from paper_1501_03358_amd.serve import state_bytes
+    n = 32 ** 3
+    b7 = state_bytes((32, 32, 32), 10)
+    b19 = state_bytes((32, 32, 32), 10, npts=19)
+    pack7 = 4 * 7 * 10 ** 3 * 64
+    assert b7 == 7 * 12 * n + 4 * n + pack7 + 80 * n
+    assert b19 == 19 * 12 * n + 4 * n + 80 * n      # no coefficient pack for 19 bands
