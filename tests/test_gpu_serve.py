@@ -72,3 +72,22 @@ def test_memory_budget_evicts_and_still_serves(gpu_lib):
         p = probs[r.mid]
         res = rhs[r.mid][r.step] - stencil.apply(p.bands, p.shape, p.periodic, r.x)
         assert np.linalg.norm(res) <= 1e-8 * np.linalg.norm(rhs[r.mid][r.step])
+
+
+def test_serving_mixes_7_and_19_point_matrices(gpu_lib):
+    """A 19-band (sheared-grid) matrix served next to 7-band ones: every
+    request meets the tolerance, and the 19-band state is admitted with its
+    own size."""
+    from paper_1501_03358_amd.serve import MatrixSpec, state_bytes
+    probs = [W.skewed_problem(16, extra=35), W.grf_problem(16, extra=36)]
+    specs = [MatrixSpec(i, p.shape, p.periodic, p.bands) for i, p in enumerate(probs)]
+    rhs = {i: list(W.rhs_ar1(p, 3, seed_cfg=5, extra=50 + i)) for i, p in enumerate(probs)}
+    order = [(mid, step) for step in range(3) for mid in range(2)]
+    reqs, srv = _run(dict(m=20, k=10, n_switch=2, mem_budget=8e9, n_slots=2), specs, rhs, order)
+    for r in reqs:
+        assert r.status == 0
+        p = probs[r.mid]
+        res = rhs[r.mid][r.step] - stencil.apply(p.bands, p.shape, p.periodic, r.x)
+        assert np.linalg.norm(res) <= 1e-8 * np.linalg.norm(rhs[r.mid][r.step])
+    assert srv.sched.resident[0] == state_bytes((16, 16, 16), 10, 8, 19)
+    assert srv.sched.resident[1] == state_bytes((16, 16, 16), 10, 8, 7)
