@@ -122,7 +122,10 @@ def serve_main(args):
         else:
             p = W.porous_problem(n, seed_cfg=5, extra=i)
         probs.append(p)
-        specs.append(MatrixSpec(i, p.shape, p.periodic, p.bands, k=10 if n <= 64 else 20))
+        # channel matrices: rGCROT throughout with --channel-rgcrot
+        ns = 10 ** 9 if (args.channel_rgcrot and i % 2 == 0) else None
+        specs.append(MatrixSpec(i, p.shape, p.periodic, p.bands, k=10 if n <= 64 else 20,
+                                n_switch=ns))
     log(f"[serve] {len(specs)} matrices, {sum(p.n for p in probs) / 1e6:.1f}M cells "
         f"({time.time() - t0:.1f}s)")
 
@@ -400,6 +403,8 @@ def main():
     ap.add_argument("--grids", default="32,64,96,128,192", help="serve: grid sizes per axis")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent solves")
     ap.add_argument("--mem-gb", type=float, default=200.0, help="serve: HBM budget")
+    ap.add_argument("--channel-rgcrot", action="store_true",
+                    help="serve: channel matrices run rGCROT throughout (no switch)")
     ap.add_argument("--capacity-steps", type=int, default=2,
                     help="serve: closed-loop requests per matrix for the capacity figure")
     ap.add_argument("--rate", type=float, default=0.0,

@@ -134,6 +134,7 @@ class MatrixSpec:
     periodic: tuple
     bands: np.ndarray        # [7, N] or [19, N] FP64 host
     k: Optional[int] = None  # recycle dimension (None: the server's default)
+    n_switch: Optional[int] = None  # rGCROT steps before rBiCGStab (None: the server's)
 
 
 class _State:
@@ -234,7 +235,9 @@ class Server:
                     n = st.A32.n
                     b = torch.from_numpy(req.b).to(self.device, non_blocking=False)
                     x = torch.empty(n, dtype=torch.float64, device=self.device)
-                    inner = (krs.SOLVER_RGCROT if st.steps_done < self.n_switch
+                    spec_ns = self.specs[req.mid].n_switch
+                    ns = self.n_switch if spec_ns is None else spec_ns
+                    inner = (krs.SOLVER_RGCROT if st.steps_done < ns
                              else krs.SOLVER_RBICGSTAB)
                     o = krs.make_opts(m=self.m, k=st.k, tol=self.tol, inner_solver=inner,
                                       inner_tol=self.inner_tol, max_matvecs=4000)
