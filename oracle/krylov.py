@@ -293,8 +293,8 @@ def gcrot_update(rec: Recycle, V, Hbar, B, y, k, par: GcrotParams, prev):
          With `prev` the previous cycle's selection space (orthonormal
          columns), the p principal vectors of S making the smallest angles
          with `prev` (largest singular values of prev^T V Qs, each vector's
-         largest component made positive; at most dim(prev) of them, and none
-         with a zero cosine) join the outer space too.
+         largest component made positive; at most dim(prev) and k - 1 of
+         them, and none with a zero cosine) join the outer space too.
       3. The new images are orthonormalised in order (Gram-Schmidt twice,
          dropping dependent ones): q new pairs u = (V_j - U B) g,
          c = V_{j+1} Hbar g.
@@ -325,7 +325,7 @@ def gcrot_update(rec: Recycle, V, Hbar, B, y, k, par: GcrotParams, prev):
         M = (prev.T @ V) @ Qs                         # cosines: singular values
         _, sig, Vt = np.linalg.svd(M)
         # only directions with a nonzero cosine are defined
-        npick = min(par.p, sj, prev.shape[1])
+        npick = min(par.p, sj, prev.shape[1], k - 1)      # with y, at most k new columns
         while npick > 0 and sig[npick - 1] <= 1e-12:
             npick -= 1
         if 0 < npick < len(sig) and (sig[npick - 1] - sig[npick]) / sig[npick - 1] < 1e-8:

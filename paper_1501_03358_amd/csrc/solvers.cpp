@@ -378,7 +378,8 @@ int gcrot_update(krs_ctx* ctx, krs_recycle* rec, const T* V, int64_t ld, int jj,
     }
     // only directions with a nonzero cosine are defined
     auto sv = [&](int i) { return i < std::min(prev_dim, sj) ? std::sqrt(std::max(w[i], 0.0)) : 0.0; };
-    int npick = std::min(std::min(par.p, sj), prev_dim);
+    // with the cycle's correction, at most k new columns
+    int npick = std::min(std::min(par.p, sj), std::min(prev_dim, k - 1));
     while (npick > 0 && sv(npick - 1) <= 1e-12) --npick;
     if (npick > 0 && npick < std::min(prev_dim, sj) &&
         (sv(npick - 1) - sv(npick)) / sv(npick - 1) < 1e-8)
@@ -457,6 +458,8 @@ int gcrot_update(krs_ctx* ctx, krs_recycle* rec, const T* V, int64_t ld, int jj,
     std::sort(keep.begin(), keep.end());
   }
   const int nk = (int)keep.size(), nout = nk + q;
+  if (nout > k || nout > rec->kmax)
+    return set_err(ctx, KRS_ERR_STATE, "GCROT update: outer space above k");
   // U <- [U_keep, (V_j - U B) Gc] from In = [U, V_j]; C <- [C_keep, V_{j+1} Qn]
   // from In = [C, V_{j+1}]; the next selection basis V_{j+1} Qs into prevQ
   const int nu = kc + jj, ncin = kc + mg;

@@ -545,6 +545,7 @@ def test_rgcrot_large_recycle_space(gpu_lib):
     ("grf", 20, 10, (5, 10, 1)),       # Jacobi: cuts and one selected vector per cycle
     ("porous", 30, 20, (10, 15, 2)),   # Schwarz, the channel parameters of Sec. 3 with p = 2
     ("channel", 10, 40, (30, 5, 2)),   # the porous-media parameters rGCROT(10,40) of Sec. 3
+    ("grf", 8, 2, (1, 4, 2)),          # k = 2 < 1 + p: the selection is capped at k - 1
 ])
 def test_rgcrot_gcrot_rule_matches_oracle(gpu_lib, kind, m, k, par):
     """The GCROT recycle-space rule, stepwise against the oracle: history

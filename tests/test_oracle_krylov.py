@@ -522,3 +522,14 @@ def test_gcrot_rule_without_selection_is_gcro():
     D = np.column_stack(decs)
     assert rec.dim == D.shape[1] == len(traces) >= 5
     assert scipy.linalg.subspace_angles(rec.C, D).max() <= 1e-7
+
+
+def test_gcrot_rule_small_k_never_exceeds_k():
+    """k = 2 with p = 2: the cycle's correction plus at most k - 1 selected
+    vectors, so the outer space never holds more than k columns."""
+    prob, op, rec, runs = _gcrot_run(m=8, k=2, par=K.GcrotParams(kt=1, s=4, p=2), n_sys=2)
+    for b, res, traces, afters in runs:
+        assert res.status == K.CONVERGED
+        for U, C in afters:
+            assert 1 <= C.shape[1] <= 2
+            assert np.linalg.norm(C.T @ C - np.eye(C.shape[1])) <= 1e-13
