@@ -1476,9 +1476,8 @@ __device__ inline void hist_push(double* sc, double v) {
 
 // ---------------------------------------------------------------------------
 // BiCGStab finishing reductions fused with the scalar step that consumes them
-// (one launch instead of two).  One block: wave w sums columns w, w+4, ...
-// of the per-block partials (lane-strided, fixed order, FP64) into out[];
-// then thread 0 runs the scalar step.  Every kernel returns at once when the
+// (one launch instead of two).  One block sums the columns of the per-block
+// partials (FP64, fixed order) into out[]; then thread 0 runs the scalar step.  Every kernel returns at once when the
 // device-side stop state is set.
 // ---------------------------------------------------------------------------
 // Column sums go to `out` (device memory, for the host) and to `sh` (LDS):
@@ -1489,32 +1488,86 @@ constexpr int kFinishCols = 72;
 template <class T>
 __device__ __forceinline__ void finish_cols(const T* partials, int nblk, int ncols,
                                             double* out, double* sh) {
-  constexpr int NW = kThreads / 64, NJ = kFinishCols / NW;
+  // Each thread issues the loads of 16 columns x 4 partials before the first
+  // is used (clamped addresses and a select instead of branches, so nothing
+  // splits the group): one round trip per group.  Fixed order throughout.
+  constexpr int NG = 16, U = 4, NWV = kThreads / 64;
+  __shared__ double wsum[NWV][kFinishCols];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // wave w takes columns w, w + NW, ...; each lane's loads for all of them,
-  // over four of its partials, are issued together (one grid of partials is
-  // read in a few round trips; each lane still adds its partials in order)
-  double acc[NJ];
+  if (nblk <= U * 64) {
+    // up to 256 partials: wave w owns columns w, w + 4, ..., w + 60 and lane l
+    // adds partials l, l + 64, l + 128, l + 192 (one group for all columns)
+    for (int c0 = wid; c0 < ncols; c0 += NWV * NG) {
+      double acc[NG];
+      T v[NG][U];
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) acc[j] = 0;
-#pragma unroll 4
-  for (int b = lane; b < nblk; b += 64) {
+      for (int j = 0; j < NG; ++j)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int c = wid + NW * j;
-      if (c < ncols) acc[j] += (double)partials[(int64_t)c * nblk + b];
-    }
-  }
+        for (int u = 0; u < U; ++u) {
+          const int b = lane + 64 * u, c = c0 + NWV * j;
+          const bool ok = b < nblk && c < ncols;
+          v[j][u] = partials[ok ? (int64_t)c * nblk + b : 0];
+        }
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int c = wid + NW * j;
-    if (c < ncols) {
-      const double v = wave_sum(acc[j]);
-      if (lane == 0) {
-        out[c] = v;
-        sh[c] = v;
+      for (int j = 0; j < NG; ++j) {
+        acc[j] = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int b = lane + 64 * u, c = c0 + NWV * j;
+          acc[j] += (b < nblk && c < ncols) ? (double)v[j][u] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NG; ++j) {
+        const int c = c0 + NWV * j;
+        const double w = wave_sum(acc[j]);
+        if (lane == 0 && c < ncols) {
+          out[c] = w;
+          sh[c] = w;
+        }
       }
     }
+    __syncthreads();
+    return;
+  }
+  // more partials: all threads take part in every column; thread t adds
+  // partials t, t + 256, t + 512, t + 768 (then the next 1024) of 16 columns
+  // at a time; wave sums, then the four wave results in wave order
+  for (int c0 = 0; c0 < ncols; c0 += NG) {
+    double acc[NG];
+#pragma unroll
+    for (int j = 0; j < NG; ++j) acc[j] = 0;
+    for (int b0 = 0; b0 < nblk; b0 += U * kThreads) {
+      T v[NG][U];
+#pragma unroll
+      for (int j = 0; j < NG; ++j)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int b = b0 + u * kThreads + (int)threadIdx.x, c = c0 + j;
+          const bool ok = b < nblk && c < ncols;
+          v[j][u] = partials[ok ? (int64_t)c * nblk + b : 0];
+        }
+#pragma unroll
+      for (int j = 0; j < NG; ++j)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int b = b0 + u * kThreads + (int)threadIdx.x, c = c0 + j;
+          acc[j] += (b < nblk && c < ncols) ? (double)v[j][u] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      const double w = wave_sum(acc[j]);
+      if (lane == 0 && c0 + j < ncols) wsum[wid][c0 + j] = w;
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncols; c += kThreads) {
+    double v = wsum[0][c];
+#pragma unroll
+    for (int w = 1; w < NWV; ++w) v += wsum[w][c];
+    out[c] = v;
+    sh[c] = v;
   }
   __syncthreads();
 }
@@ -1525,14 +1578,17 @@ __global__ __launch_bounds__(kThreads) void k_bicg_finish_alpha(const T* partial
                                                                 int kc, double* sums, double* sc,
                                                                 int off_eta1, int off_ctrt) {
   __shared__ double sh[kFinishCols];
+  __shared__ double ctrt[kFinishCols];
   if (sc[kDone] != 0.0) return;
+  // C^T r~ is staged in LDS by all threads at once: a serial loop over device
+  // memory interleaved with stores to the same array waits for one load per
+  // column (about 30 us per launch at k = 20)
+  for (int c = threadIdx.x; c < kc; c += kThreads) ctrt[c] = sc[off_ctrt + c];
   finish_cols<T>(partials, nblk, kc + 1, sums, sh);
+  for (int c = threadIdx.x; c < kc; c += kThreads) sc[off_eta1 + c] = sh[c];
   if (threadIdx.x != 0) return;
   double corr = 0;
-  for (int c = 0; c < kc; ++c) {
-    sc[off_eta1 + c] = sh[c];
-    corr += sc[off_ctrt + c] * sh[c];
-  }
+  for (int c = 0; c < kc; ++c) corr += ctrt[c] * sh[c];
   const double rtv = sh[kc] - corr;
   sc[kRtv] = rtv;
   if (rtv == 0.0 || !isfinite(rtv)) {
@@ -1596,6 +1652,8 @@ __global__ __launch_bounds__(kThreads) void k_bicg_finish_omega(const T* partial
                                                                 int off_eta1, int off_eta2,
                                                                 int off_xi) {
   __shared__ double sh[kFinishCols];
+  __shared__ double e1[kFinishCols];
+  __shared__ double om;
   // the pass after a half-step exit: mark the exit applied (so the vector
   // part runs once) and do nothing else
   if (sc[kDone] == (double)kConvHalf) {
@@ -1604,23 +1662,28 @@ __global__ __launch_bounds__(kThreads) void k_bicg_finish_omega(const T* partial
     return;
   }
   if (sc[kDone] != 0.0) return;
+  // eta1 staged in LDS by all threads (see k_bicg_finish_alpha)
+  for (int c = threadIdx.x; c < kc; c += kThreads) e1[c] = sc[off_eta1 + c];
   finish_cols<T>(partials, nblk, kc + 2, sums, sh);
-  if (threadIdx.x != 0) return;
-  double q = 0;
-  for (int c = 0; c < kc; ++c) {
-    sc[off_eta2 + c] = sh[c];
-    q += sh[c] * sh[c];
+  if (threadIdx.x == 0) {
+    double q = 0;
+    for (int c = 0; c < kc; ++c) q += sh[c] * sh[c];
+    const double ts = sh[kc];
+    const double tt = sh[kc + 1] - q;  // |t - C eta2|^2 with C^T C = I
+    sc[kTs] = ts;
+    sc[kTt] = tt;
+    double omega = 0.0;  // t = 0 (breakdown): y += alpha p, r = s; the stop state is set next
+    if (tt > 0.0 && isfinite(tt)) omega = ts / tt;
+    else sc[kFlag] = 2.0;
+    sc[kOmega] = omega;
+    om = omega;
   }
-  const double ts = sh[kc];
-  const double tt = sh[kc + 1] - q;  // |t - C eta2|^2 with C^T C = I
-  sc[kTs] = ts;
-  sc[kTt] = tt;
-  double omega = 0.0;  // t = 0 (breakdown): y += alpha p, r = s; the stop state is set next
-  if (tt > 0.0 && isfinite(tt)) omega = ts / tt;
-  else sc[kFlag] = 2.0;
-  sc[kOmega] = omega;
-  const double alpha = sc[kAlpha];
-  for (int c = 0; c < kc; ++c) sc[off_xi + c] += alpha * sc[off_eta1 + c] + omega * sc[off_eta2 + c];
+  __syncthreads();
+  const double alpha = sc[kAlpha], omega = om;
+  for (int c = threadIdx.x; c < kc; c += kThreads) {
+    sc[off_eta2 + c] = sh[c];
+    sc[off_xi + c] += alpha * e1[c] + omega * sh[c];
+  }
 }
 
 // rho = r~^T r, |r|^2, beta; then the full-step tests (line 3, breakdowns,
