@@ -23,6 +23,8 @@
  * Vectors: device arrays of N values of the handle's dtype (FP64 or FP32),
  *   except where an argument says otherwise.
  * Multi-vectors (U, C): column-major, column c at base + c*ld, ld >= N.
+ * An ld that is not a multiple of a large power of two streams faster (the
+ * library's own multi-vectors use N rounded up to 64, plus 1088).
  * Solvers are right-preconditioned: they iterate on A~ = A M^-1 and return
  *   x = M^-1 y; the initial guess is always x = 0 (Sec. 2.2), the stopping
  *   test is ||b - A x|| <= tol ||b|| (Alg. 1-4, line 3).

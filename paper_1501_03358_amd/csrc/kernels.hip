@@ -756,9 +756,18 @@ __device__ __forceinline__ Pk<T, W> ldn(const T* p, int64_t iv) {
   }
   return x;
 }
+// Nontemporal store of a pack: the streaming kernels write each output once.
 template <class T, int W>
 __device__ __forceinline__ void stp(T* p, int64_t iv, const Pk<T, W>& x) {
-  reinterpret_cast<Pk<T, W>*>(p)[iv] = x;
+  if constexpr (W == 1) {
+    __builtin_nontemporal_store(x.v[0], p + iv);
+  } else {
+    typedef T V __attribute__((ext_vector_type(W)));
+    V a;
+#pragma unroll
+    for (int e = 0; e < W; ++e) a[e] = x.v[e];
+    __builtin_nontemporal_store(a, reinterpret_cast<V*>(p) + iv);
+  }
 }
 
 constexpr int kGroup = 8;

@@ -156,8 +156,14 @@ def _dt(t):
     raise TypeError("tensors must be float64 or float32")
 
 
+LD_PAD = 1088
+
+
 def vec_ld(n):
-    return (n + 63) // 64 * 64
+    """Leading dimension of U and C (the library's rule for its own
+    multi-vectors): N rounded up to 64 values plus a pad, so that the columns
+    do not all start at the same offset modulo a large power of two."""
+    return (n + 63) // 64 * 64 + LD_PAD
 
 
 class Context:

@@ -161,7 +161,8 @@ def state_bytes(shape, k, tile=8, npts=7):
     e = tile + 2
     ntile = (shape[0] // tile) * (shape[1] // tile) * (shape[2] // tile)
     pack = 4 * 7 * e ** 3 * ntile if npts == 7 else 0
-    return npts * n * 12 + 4 * n + pack + 2 * k * 4 * n
+    ld = (n + 63) // 64 * 64 + 1088     # leading dimension of U and C
+    return npts * n * 12 + 4 * n + pack + 2 * k * 4 * ld
 
 
 class Server:

@@ -55,7 +55,7 @@ def test_workspace_within_paper_storage(lib, n):
     """GMRES(m): the paper counts (m+1)N + 4N; the library keeps V (m+1
     columns) and two temporaries (one vector of the iterate lives in x).
     rGCROT adds U, C (2kN, owned by the caller).  BiCGStab: 8N."""
-    ld = (n + 63) // 64 * 64
+    ld = (n + 63) // 64 * 64 + 1088  # rounded up to 64, plus the column pad
     for m in (20, 30, 50):
         w = _ws(lib, 1, n, m, 20, 0)
         assert w <= 8 * ld * (m + 5) + FIXED

@@ -159,5 +159,6 @@ def test_state_bytes_counts_bands_and_pack():
     b7 = state_bytes((32, 32, 32), 10)
     b19 = state_bytes((32, 32, 32), 10, npts=19)
     pack7 = 4 * 7 * 10 ** 3 * 64
-    assert b7 == 7 * 12 * n + 4 * n + pack7 + 80 * n
-    assert b19 == 19 * 12 * n + 4 * n + 80 * n      # no coefficient pack for 19 bands
+    rec = 2 * 10 * 4 * (n + 1088)                     # U and C, padded columns
+    assert b7 == 7 * 12 * n + 4 * n + pack7 + rec
+    assert b19 == 19 * 12 * n + 4 * n + rec          # no coefficient pack for 19 bands
