@@ -296,7 +296,7 @@ def seq_main(args):
             s0 = time.perf_counter()
             changed = set_matrix(i, rec if name.startswith("hybrid") else None)
             if changed and name == "rgcrot" and rec.dim > 0:
-                krs.recycle_update(ctx, A, Mp, rec, ws)   # line 1a for the new matrix
+                krs.recycle_update(ctx, A, Mp, rec, ws)   # re-form C = qr(A~ U) for the new matrix
             rc, st = solve(rec, i, bs[i])
             lat.append((time.perf_counter() - s0) * 1e3)
             mvs.append(st.matvecs)

@@ -27,9 +27,9 @@
  * library's own multi-vectors use N rounded up to 64, plus 1088).
  * Solvers are right-preconditioned: they iterate on A~ = A M^-1 and return
  *   x = M^-1 y; the initial guess is always x = 0 (Sec. 2.2), the stopping
- *   test is ||b - A x|| <= tol ||b|| (Alg. 1-4, line 3).
+ *   test is ||b - A x|| <= tol ||b|| (the loop test of Alg. 1-4).
  * Recycle space: (U, C) with A~ U = C and C^T C = I (the R factor of
- *   Alg. 3 line 1a is absorbed into U).
+ *   the recycle-space setup of Alg. 3 is absorbed into U).
  *
  * Ownership: every device pointer belongs to the caller and must stay valid
  *   while a handle that borrowed it is alive.  The library never allocates
@@ -60,7 +60,7 @@ extern "C" {
 /* status codes */
 #define KRS_OK 0
 #define KRS_NOT_CONVERGED 1   /* max_matvecs reached before tol */
-#define KRS_BREAKDOWN 2       /* rho = 0, r~^T v = 0 or t^T t = 0 (Alg. 2/4 line 5) */
+#define KRS_BREAKDOWN 2       /* rho = 0, r~^T v = 0 or t^T t = 0 (Alg. 2/4) */
 #define KRS_DIVERGED 3        /* non-finite residual or growth above div_factor */
 #define KRS_ERR_ARG (-1)      /* invalid argument or unsupported shape */
 #define KRS_ERR_HIP (-2)      /* HIP runtime error */
@@ -79,7 +79,7 @@ typedef enum krs_solver {
                                (opts.recycle_rule = KRS_RECYCLE_GCROT), m vectors more */
 } krs_solver;
 
-/* How rGCROT updates (U, C) at a cycle end (Alg. 3 line 14a; the paper
+/* How rGCROT updates (U, C) at a cycle end (the cycle-end step of Alg. 3; the paper
  * leaves the details to its references, Sec. 2.3).
  * KRS_RECYCLE_HARMONIC: the GCRODR rule - the k harmonic Ritz vectors of the
  *   search space range(U) + range(V_j) with the smallest |theta|.
@@ -170,7 +170,7 @@ typedef struct krs_opts {
   int32_t m;               /* Arnoldi steps per cycle (GMRES, rGCROT), 1..64 */
   int32_t k;               /* maximum recycle dimension (rGCROT update), <= recycle kmax;
                               rGCROT needs k + m + 1 <= 64 (one block pass over [C, V]) */
-  int32_t update_recycle;  /* rGCROT: update (U, C) at every cycle end (Alg. 3 line 14a) */
+  int32_t update_recycle;  /* rGCROT: update (U, C) at every cycle end (Alg. 3) */
   int32_t inner_solver;    /* IR only: KRS_SOLVER_RGCROT or KRS_SOLVER_RBICGSTAB */
   double tol;              /* relative tolerance on ||b - A x|| / ||b|| */
   int64_t max_matvecs;     /* cap on applications of A~ in the iteration */
@@ -205,9 +205,9 @@ typedef struct krs_stats {
   double bytes_model;      /* algorithmic HBM bytes of the call (byte model) */
   int64_t second_passes;   /* Arnoldi steps that needed a second Gram-Schmidt pass */
   int64_t solver;          /* krs_hybrid_solve: solver that produced x (KRS_SOLVER_*) */
-  int64_t refreshed;       /* krs_hybrid_solve: 1 if line 1a ran first (space marked stale) */
-  int64_t breakdown_site;  /* (r)BiCGStab: 0 none, 1 r~^T v = 0 (alpha, line 8), 2 t^T t = 0
-                              (omega, line 13), 3 rho = 0 (line 5) */
+  int64_t refreshed;       /* krs_hybrid_solve: 1 if C was re-formed first (space marked stale) */
+  int64_t breakdown_site;  /* (r)BiCGStab: 0 none, 1 r~^T v = 0 (alpha), 2 t^T t = 0
+                              (omega), 3 rho = 0 */
 } krs_stats;
 
 /* ---------------- context ---------------- */
@@ -266,7 +266,7 @@ int krs_recycle_dim(const krs_recycle* rec);
  * krs_recycle_update before solving if C does not hold A~ U. */
 int krs_recycle_set_dim(krs_recycle* rec, int k);
 /* Marks (U, C) stale: A or M changed since C = A~ U was formed.  The next
- * krs_hybrid_solve first re-forms C from U (Alg. 3 line 1a, which applies
+ * krs_hybrid_solve first re-forms C from U (the recycle-space setup of Alg. 3, which applies
  * whenever the matrix changes), keeping range(U).  Sec. 2.4 leaves the policy for changing
  * matrices open (intermittent rGCROT); this is the cheapest consistent one. */
 int krs_recycle_mark_stale(krs_recycle* rec);
@@ -300,12 +300,12 @@ int krs_operator_apply(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, 
 int krs_gmres(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const void* b, void* x,
               const krs_opts* opts, void* ws, size_t ws_bytes, krs_stats* stats);
 
-/* rGCROT(m,k)/GCRODR(m,k), Alg. 3.  Projects b against C (line 1b), runs
- * augmented Arnoldi cycles (lines 4-11, 6a-6c), updates x with V y - U B y
- * (lines 12-13a; the sign minimising the residual over range(U)+range(V)),
- * and, when opts.update_recycle, replaces (U, C) at every cycle end by the
- * k harmonic Ritz vectors of smallest |theta| of range(U)+range(V_j) (line 14a,
- * GCRODR rule; eigenproblem in FP64 on the host).  With an empty recycle
+/* rGCROT(m,k)/GCRODR(m,k), Alg. 3.  Projects b against C, runs augmented
+ * Arnoldi cycles (each new vector orthogonalised against C, then V), updates
+ * x with V y - U B y at each cycle end (the sign minimising the residual over
+ * range(U)+range(V)), and, when opts.update_recycle, replaces (U, C) at every
+ * cycle end by the k harmonic Ritz vectors of smallest |theta| of
+ * range(U)+range(V_j) (GCRODR rule; eigenproblem in FP64 on the host).  With an empty recycle
  * space and no update this is GMRES(m). */
 int krs_rgcrot_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
                      const void* b, void* x, const krs_opts* opts, void* ws, size_t ws_bytes,
@@ -313,12 +313,12 @@ int krs_rgcrot_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, kr
 
 /* rBiCGStab with one recycle space, Alg. 4 (rec may be NULL or of dimension
  * 0: BiCGStab, Alg. 2).  r~ = r_0 after projection; U-updates postponed to
- * the end (line 17a); rec is read only. */
+ * the end of the solve; rec is read only. */
 int krs_rbicgstab_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M,
                         const krs_recycle* rec, const void* b, void* x, const krs_opts* opts,
                         void* ws, size_t ws_bytes, krs_stats* stats);
 
-/* Alg. 3 line 1a / Alg. 4 line 1b: C~ = A~ U, thin QR C~ = C R (Cholesky QR,
+/* Recycle-space setup of Alg. 3 and 4: C~ = A~ U, thin QR C~ = C R (Cholesky QR,
  * twice), U <- U R^-1.  Call when A changed or U was set by the caller. */
 int krs_recycle_update(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
                        void* ws, size_t ws_bytes);
@@ -330,7 +330,7 @@ int krs_recycle_update(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, 
  * a system whose rBiCGStab solve needed more than switch_back times the
  * matvecs of the first rBiCGStab system since the last rGCROT one makes the
  * next system run rGCROT (Sec. 2.4: switch back when convergence becomes
- * poor).  A space marked stale is re-formed first (line 1a).  stats->solver
+ * poor).  A space marked stale is re-formed from U first.  stats->solver
  * and stats->refreshed tell what ran.  The policy state lives in rec.
  * ws: krs_workspace_size(KRS_SOLVER_RGCROT). */
 int krs_hybrid_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,

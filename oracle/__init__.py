@@ -13,7 +13,7 @@ Modules
               (Sec. 2.1, "Preconditioners in GenIDLEST").
   krylov   -- GMRES(m) (Alg. 1), BiCGStab (Alg. 2), rGCROT(m,k)/GCRODR(m,k)
               (Alg. 3) with the harmonic-Ritz recycle-space update, the
-              thin-QR recycle setup (Alg. 3 line 1a), rBiCGStab with one
+              thin-QR recycle setup (Alg. 3), rBiCGStab with one
               recycle space (Alg. 4) and the hybrid rGCROT -> rBiCGStab
               driver (Sec. 2.4).
 

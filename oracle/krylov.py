@@ -8,10 +8,10 @@ must see the same operator); Sec. 2.2 notes that the operator and right-hand
 side of Alg. 1 may be taken as the preconditioned ones.
 
 The initial guess is always zero, so r_0 = b (Sec. 2.2).  The stopping test
-is ||r|| <= tol * ||b|| (Alg. 1-4, line 3).
+is ||r|| <= tol * ||b|| (the loop test of Alg. 1-4).
 
 Recycle space convention: U, C with A~ U = C and C^T C = I, i.e. the factor R
-of Alg. 3 line 1a is absorbed into U (U R^-1 is stored as U).
+of the recycle-space setup of Alg. 3 is absorbed into U (U R^-1 is stored as U).
 """
 from __future__ import annotations
 
@@ -52,14 +52,14 @@ class Result:
     fallback: bool = False
     events: list = dataclasses.field(default_factory=list)
     solver: str = ""         # hybrid: "rgcrot" or "rbicgstab" (the one that produced x)
-    refreshed: bool = False  # hybrid: line 1a re-formed C first
+    refreshed: bool = False  # hybrid: C was re-formed from U first
 
 
 @dataclasses.dataclass
 class HybridState:
     """State of the hybrid policy across a sequence of systems.
 
-    stale: A or M changed since C = A~ U was formed (Alg. 3 line 1a: form C
+    stale: A or M changed since C = A~ U was formed (the recycle-space setup of Alg. 3: form C
     again when the matrix has changed); force_rgcrot: the next system runs
     rGCROT; ref_mv: matvecs of the first rBiCGStab system since the last
     rGCROT one (the reference for switching back, Sec. 2.4)."""
@@ -73,7 +73,7 @@ def _norm(v):
 
 
 def _ls(Hbar, rho):
-    """Line 12 of Alg. 1/3: y = argmin || e1 rho - Hbar y ||, and that minimum."""
+    """The least-squares step of Alg. 1/3: y = argmin || e1 rho - Hbar y ||, and that minimum."""
     rhs = np.zeros(Hbar.shape[0])
     rhs[0] = rho
     y = np.linalg.lstsq(Hbar, rhs, rcond=None)[0]
@@ -83,8 +83,8 @@ def _ls(Hbar, rho):
 def _orthogonalize(w, blocks, orth):
     """Orthogonalise w against the columns of each matrix in `blocks` (in order).
 
-    'mgs': one column at a time, as in the loops of Alg. 1 lines 7-9 and
-    Alg. 3 lines 6a-9.  'cgs2': classical Gram-Schmidt against all columns at
+    'mgs': one column at a time, as in the orthogonalisation loops of Alg. 1
+    and Alg. 3.  'cgs2': classical Gram-Schmidt against all columns at
     once, applied twice, coefficients summed.  Both give the same coefficients
     in exact arithmetic.  Returns (w, list of coefficient vectors per block)."""
     coefs = [np.zeros(Q.shape[1]) for Q in blocks]
@@ -118,7 +118,7 @@ def gmres(op, minv, b, m, tol, max_its=2000, orth="cgs2"):
 
     Convergence is tested inside the cycle on the least-squares residual
     (the estimate mentioned in the note to Alg. 1) and confirmed at the end of
-    the cycle with the true residual b - A~ y (line 14); if the confirmation
+    the cycle with the true residual b - A~ y; if the confirmation
     fails the next cycle starts."""
     b = np.asarray(b, dtype=np.float64)
     n = b.size
@@ -148,8 +148,8 @@ def gmres(op, minv, b, m, tol, max_its=2000, orth="cgs2"):
             if est <= tol * nb or H[j + 1, j] == 0.0 or its >= max_its:
                 break
         y, _ = _ls(H[:jj + 1, :jj], rho)
-        y_acc = y_acc + V[:, :jj] @ y                     # line 13
-        r = b - op(y_acc)                                 # line 14
+        y_acc = y_acc + V[:, :jj] @ y                     # solution update of the cycle
+        r = b - op(y_acc)                                 # true residual
         mv += 1
         rho = _norm(r)
         cycles += 1
@@ -162,7 +162,7 @@ def gmres(op, minv, b, m, tol, max_its=2000, orth="cgs2"):
 
 
 # ---------------------------------------------------------------------------
-# Alg. 3: rGCROT(m,k) / GCRODR(m,k) with the harmonic-Ritz update (line 14a)
+# Alg. 3: rGCROT(m,k) / GCRODR(m,k) with the harmonic-Ritz update at cycle ends
 # ---------------------------------------------------------------------------
 
 def harmonic_ritz_pairs(G, F):
@@ -172,7 +172,7 @@ def harmonic_ritz_pairs(G, F):
 
 
 def harmonic_ritz_update(rec: Recycle, V, Hbar, B, k):
-    """Line 14a of Alg. 3, by the GCRODR rule (the recycle space is spanned
+    """The recycle-space update at the end of a cycle of Alg. 3, by the GCRODR rule (the recycle space is spanned
     by harmonic Ritz vectors of the search space range(U) + range(V_j)).
 
     V: N x (j+1) Arnoldi basis, Hbar: (j+1) x j, B = C^T A~ V_j: kc x j.
@@ -243,7 +243,7 @@ def harmonic_ritz_update(rec: Recycle, V, Hbar, B, k):
 
 @dataclasses.dataclass
 class GcrotParams:
-    """Parameters of the GCROT rule for line 14a (Sec. 3 lists them with
+    """Parameters of the GCROT rule for the cycle-end recycle update (Sec. 3 lists them with
     their values): kt outer vectors kept at a truncation (k - 10 there), s
     latest inner vectors to select from (m / 2), p inner vectors selected per
     cycle (1 or 2).  The fourth parameter, latest inner vectors kept, is 0
@@ -280,7 +280,7 @@ def _small_gs(H, G, drop=1e-10):
 
 
 def gcrot_update(rec: Recycle, V, Hbar, B, y, k, par: GcrotParams, prev):
-    """Line 14a of Alg. 3 by the GCROT rule, which takes the recycle space
+    """The cycle-end recycle update of Alg. 3 by the GCROT rule, which takes the recycle space
     from angles between successive search spaces (Sec. 2.3; the details are
     in the GCROT references, so this is a reading).
 
@@ -364,7 +364,7 @@ def gcrot_update(rec: Recycle, V, Hbar, B, y, k, par: GcrotParams, prev):
 
 
 def recycle_setup(op, rec: Recycle):
-    """Alg. 3 line 1a: C~ = A~ U, thin QR C~ = C R, U <- U R^-1."""
+    """Recycle-space setup of Alg. 3: C~ = A~ U, thin QR C~ = C R, U <- U R^-1."""
     if rec.dim == 0:
         return
     Ct = np.column_stack([op(rec.U[:, i]) for i in range(rec.dim)])
@@ -381,12 +381,13 @@ def rgcrot(op, minv, b, m, k, tol, rec: Recycle, update=True, max_its=2000, orth
            trace=None, gcrot: GcrotParams | None = None):
     """rGCROT(m,k), Alg. 3, right-preconditioned, x^ = 0, R absorbed in U.
 
-    Line 1b projects b against C; lines 6a-6c orthogonalise each new Arnoldi
-    vector against C before V; line 12a takes z = -B y, and the update of the
-    solution uses V y + U z = V y - U B y (the form that minimises the
-    residual over range(U) + range(V_m), eq. for x_m and its argmin; the sign
-    printed in line 13a would add +U B y instead).  Line 14 takes the true
-    residual, line 14a updates (U, C) when `update`, and the residual is then
+    b is first projected against C; each new Arnoldi vector is
+    orthogonalised against C before V; the U-coefficients are z = -B y, and
+    the update of the solution uses V y + U z = V y - U B y (the form that
+    minimises the residual over range(U) + range(V_m), eq. for x_m and its
+    argmin; the sign printed in the U-term of the algorithm's solution update
+    would add +U B y instead).  Each cycle ends with the true residual, the
+    update of (U, C) when `update`, and the residual is then
     re-projected against the new C so that the next cycle starts with
     r, v_1 orthogonal to C.  `rec` is updated in place.  gcrot: the update
     follows the GCROT rule (gcrot_update) instead of the harmonic-Ritz one;
@@ -397,7 +398,7 @@ def rgcrot(op, minv, b, m, k, tol, rec: Recycle, update=True, max_its=2000, orth
     hist, its, mv, cycles, ties = [], 0, 0, 0, 0
     status = NOT_CONVERGED
     if rec.dim:
-        xi = rec.C.T @ b                                  # line 1b
+        xi = rec.C.T @ b                                  # project b against C
         r = b - rec.C @ xi
         y_acc = rec.U @ xi
     else:
@@ -410,16 +411,16 @@ def rgcrot(op, minv, b, m, k, tol, rec: Recycle, update=True, max_its=2000, orth
         V = np.zeros((n, m + 1))
         H = np.zeros((m + 1, m))
         Bm = np.zeros((kc, m))
-        V[:, 0] = r / rho                                 # line 4
+        V[:, 0] = r / rho
         jj = 0
         for j in range(m):
-            w = op(V[:, j])                               # line 6
+            w = op(V[:, j])
             its += 1
             mv += 1
             w, (bcol, h) = _orthogonalize(w, [rec.C, V[:, :j + 1]], orth)  # 6a-9
             Bm[:, j] = bcol
             H[:j + 1, j] = h
-            H[j + 1, j] = _norm(w)                        # line 10
+            H[j + 1, j] = _norm(w)
             jj = j + 1
             _, est = _ls(H[:j + 2, :j + 1], rho)
             hist.append(est / nb)
@@ -427,17 +428,17 @@ def rgcrot(op, minv, b, m, k, tol, rec: Recycle, update=True, max_its=2000, orth
                 V[:, j + 1] = w / H[j + 1, j]
             if est <= tol * nb or H[j + 1, j] == 0.0 or its >= max_its:
                 break
-        y, _ = _ls(H[:jj + 1, :jj], rho)                  # line 12
-        z = -Bm[:, :jj] @ y                               # line 12a
-        y_acc = y_acc + V[:, :jj] @ y + rec.U @ z         # lines 13, 13a
-        r = b - op(y_acc)                                 # line 14
+        y, _ = _ls(H[:jj + 1, :jj], rho)
+        z = -Bm[:, :jj] @ y                               # U-coefficients
+        y_acc = y_acc + V[:, :jj] @ y + rec.U @ z
+        r = b - op(y_acc)                                 # true residual
         mv += 1
         cycles += 1
         if trace is not None:
             trace(dict(V=V[:, :jj + 1].copy(), H=H[:jj + 1, :jj].copy(), B=Bm[:, :jj].copy(),
                        U=rec.U.copy(), C=rec.C.copy(), y_acc=y_acc.copy(), r=r.copy(),
                        y=y.copy(), prev=None if prev is None else prev.copy()))
-        if update and gcrot is not None:                 # line 14a
+        if update and gcrot is not None:                 # cycle-end recycle update
             prev, t = gcrot_update(rec, V[:, :jj + 1], H[:jj + 1, :jj], Bm[:, :jj], y, k,
                                    gcrot, prev)
             ties += t
@@ -467,10 +468,10 @@ def rbicgstab(op, minv, b, tol, rec: Recycle | None = None, max_matvecs=2000,
     """rBiCGStab with one recycle space, Alg. 4 (Alg. 2 when the space is empty).
 
     Runs BiCGStab on A~_C = (I - C C^T) A~ from r_0 = (I - C C^T) b
-    (lines 1c, 7a, 12a) with r~ = r_0; the U-parts of the solution updates are
-    accumulated in xi (lines 1c, 10a, 13a) and applied once at the end
-    (line 17a: y <- y - U xi).  The while test and line 9 use the updated
-    residual.  Breakdown (rho = 0, r~^T v = 0 or t^T t = 0) ends the
+    (projecting b, v and t against C) with r~ = r_0; the U-parts of the
+    solution updates are accumulated in xi (at the start, the half step and
+    the full step) and applied once at the end (y <- y - U xi).  The loop test
+    and the half-step test on s use the updated residual.  Breakdown (rho = 0, r~^T v = 0 or t^T t = 0) ends the
     iteration; so does a non-finite residual or one above div_factor*||b||
     (divergence guard for the hybrid solver)."""
     b = np.asarray(b, dtype=np.float64)
@@ -479,10 +480,10 @@ def rbicgstab(op, minv, b, tol, rec: Recycle | None = None, max_matvecs=2000,
     if rec is None:
         rec = Recycle.empty(n)
     C, U = rec.C, rec.U
-    eta1 = C.T @ b                                        # line 1c
+    eta1 = C.T @ b                                        # project b against C
     r = b - C @ eta1
     xi = -eta1
-    rt = r.copy()                                         # line 2: r~ = r_0
+    rt = r.copy()                                         # r~ = r_0
     y = np.zeros(n)
     p = np.zeros(n)
     v = np.zeros(n)
@@ -491,7 +492,7 @@ def rbicgstab(op, minv, b, tol, rec: Recycle | None = None, max_matvecs=2000,
     rho_old = alpha = omega = 0.0
     rnorm = _norm(r)
     while rnorm > tol * nb and mv < max_matvecs:
-        rho = rt @ r                                      # line 4
+        rho = rt @ r
         if rho == 0.0:
             status = BREAKDOWN
             break
@@ -499,29 +500,29 @@ def rbicgstab(op, minv, b, tol, rec: Recycle | None = None, max_matvecs=2000,
             p = r.copy()
         else:
             beta = (rho / rho_old) * (alpha / omega)
-            p = r + beta * (p - omega * v)                # line 6
-        v = op(p)                                         # line 7
+            p = r + beta * (p - omega * v)
+        v = op(p)
         mv += 1
-        eta1 = C.T @ v                                    # line 7a
+        eta1 = C.T @ v                                    # project v against C
         v = v - C @ eta1
         rtv = rt @ v
         if rtv == 0.0:
             status = BREAKDOWN
             break
-        alpha = rho / rtv                                 # line 8
+        alpha = rho / rtv
         s = r - alpha * v
         snorm = _norm(s)
         hist.append(snorm / nb)
         its += 1
-        if snorm <= tol * nb:                             # lines 9-10a
+        if snorm <= tol * nb:                             # half-step exit
             y = y + alpha * p
             r = s
             xi = xi + alpha * eta1
             rnorm = snorm
             break
-        t = op(s)                                         # line 12
+        t = op(s)
         mv += 1
-        eta2 = C.T @ t                                    # line 12a
+        eta2 = C.T @ t                                    # project t against C
         t = t - C @ eta2
         tt = t @ t
         if tt == 0.0:
@@ -531,11 +532,11 @@ def rbicgstab(op, minv, b, tol, rec: Recycle | None = None, max_matvecs=2000,
             r = s
             rnorm = snorm
             break
-        omega = (t @ s) / tt                              # line 13
-        xi = xi + alpha * eta1 + omega * eta2             # line 13a
-        y = y + alpha * p + omega * s                     # line 14
-        r = s - omega * t                                 # line 15
-        rho_old = rho                                     # line 16
+        omega = (t @ s) / tt
+        xi = xi + alpha * eta1 + omega * eta2             # U-part of the update
+        y = y + alpha * p + omega * s
+        r = s - omega * t
+        rho_old = rho
         rnorm = _norm(r)
         hist.append(rnorm / nb)
         if trace is not None:
@@ -543,7 +544,7 @@ def rbicgstab(op, minv, b, tol, rec: Recycle | None = None, max_matvecs=2000,
         if not np.isfinite(rnorm) or rnorm > div_factor * nb:
             status = DIVERGED
             break
-    y = y - U @ xi                                        # line 17a
+    y = y - U @ xi                                        # postponed U-update
     if status == NOT_CONVERGED and rnorm <= tol * nb:
         status = CONVERGED
     true = _norm(b - op(y)) / nb
@@ -563,7 +564,7 @@ def hybrid_step(step, n_switch, op, minv, b, m, k, tol, rec: Recycle,
     or fails to converge, the system is solved again by rGCROT.
 
     Readings for the two options Sec. 2.4 names without fixing them:
-    * a changing matrix (state.stale): C is formed again from U (line 1a)
+    * a changing matrix (state.stale): C is formed again from U (the recycle-space setup)
       before the system is solved;
     * switching back when convergence becomes poor (switch_back > 0): if a
       converged rBiCGStab system needed more than switch_back times the

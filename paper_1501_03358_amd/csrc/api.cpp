@@ -341,7 +341,7 @@ int krs_hybrid_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, kr
     return set_err(ctx, KRS_ERR_ARG, "switch_back must be >= 0");
   bool refreshed = false;
   if (rec->stale) {
-    // line 1a: the operator changed, so C = qr(A~ U).Q and U <- U R^-1
+    // the operator changed: C = qr(A~ U).Q and U <- U R^-1 again
     if (rec->dim > 0) {
       rc = krs::recycle_setup(ctx, A, M, rec, ws, ws_bytes);
       if (rc) return rc;

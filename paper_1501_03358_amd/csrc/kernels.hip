@@ -1695,8 +1695,8 @@ __global__ __launch_bounds__(kThreads) void k_bicg_finish_omega(const T* partial
   }
 }
 
-// rho = r~^T r, |r|^2, beta; then the full-step tests (line 3, breakdowns,
-// divergence guard, rho = 0 of line 5)
+// rho = r~^T r, |r|^2, beta; then the full-step tests (convergence,
+// breakdowns, divergence guard, rho = 0)
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_bicg_finish_full(const T* partials, int nblk,
                                                                double* sums, double* sc) {

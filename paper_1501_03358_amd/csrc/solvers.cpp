@@ -1,6 +1,6 @@
 // Host drivers of the Krylov solvers: GMRES(m) (Alg. 1), rGCROT(m,k)/GCRODR
 // (Alg. 3) with the harmonic-Ritz recycle update, the thin-QR recycle setup
-// (Alg. 3 line 1a), rBiCGStab with one recycle space (Alg. 4) and FP64
+// (Alg. 3), rBiCGStab with one recycle space (Alg. 4) and FP64
 // iterative refinement around an FP32 inner solver.
 //
 // All vector work runs in the device kernels of kernels.hip; the host keeps
@@ -198,7 +198,7 @@ size_t ws_ir(int64_t n, int m) {
 }
 
 // ---------------------------------------------------------------------------
-// recycle-space update, Alg. 3 line 14a (harmonic Ritz, GCRODR rule)
+// recycle-space update at a cycle end of Alg. 3 (harmonic Ritz, GCRODR rule)
 // ---------------------------------------------------------------------------
 template <class T>
 int harmonic_update(krs_ctx* ctx, krs_recycle* rec, const T* V, int64_t ld, int jj,
@@ -309,7 +309,7 @@ struct GcrotPar {
 };
 
 // ---------------------------------------------------------------------------
-// recycle-space update, Alg. 3 line 14a (GCROT rule; a reading, since the
+// recycle-space update at a cycle end of Alg. 3 (GCROT rule; a reading, since the
 // paper names the rule and its parameters only): the outer space gains the
 // cycle's correction y and the p directions of this cycle's selection space
 // (images of the last s inner vectors) closest to the previous cycle's one
@@ -589,7 +589,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
   int kc = rec ? rec->dim : 0;
   T* r0 = V;  // the residual lives in the first basis column
   double rho2 = 0;
-  // Alg. 3 line 1b: xi = C^T b, r = b - C xi, y = U xi
+  // project b against C: xi = C^T b, r = b - C xi, y = U xi
   if (kc > 0) {
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 1),
                block_dot<T>(s, cols<T>(C, ldr, kc), b, n, 0, part, nblk));
@@ -636,13 +636,13 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
     for (int j = 0; j < m; ++j) {
       T* vj = V + (int64_t)j * ld;
       T* vn = V + (int64_t)(j + 1) * ld;
-      rc = apply(vj, w);                                 // line 6
+      rc = apply(vj, w);
       if (rc) return rc;
       ++its;
       ++mv;
       const int ncols = kc + j + 1;
       const Cols<T> Q = cols<T>(C, ldr, kc, V, ld, j + 1);
-      // lines 6a-9 as classical Gram-Schmidt against [C, V_j]: a second
+      // orthogonalisation by classical Gram-Schmidt against [C, V_j]: a second
       // pass only when the first removed more than half of |w|^2
       KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (ncols + 1), block_dot<T>(s, Q, w, n, 1, part, nblk));
       KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, ncols + 1, d_h1));
@@ -651,7 +651,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
                  block_dot_after_update<T>(s, Q, d_h1, w, n, part, nblk, d_skip));
       KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
                  finish_cgs2<T>(s, part, nblk, ncols, d_h1, d_h2, d_hcol, d_inv, d_flag, d_skip));
-      // line 10: v_{j+1} = (w - Q h) / h_{j+1,j}
+      // v_{j+1} = (w - Q h) / h_{j+1,j}
       KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (ncols + 2),
                  block_update<T>(s, Q, d_hcol, -1.0, w, vn, n, d_inv, 0, part, nblk));
       rc = read_dev(ctx, sc, Ws<T>::kFlagOff + 1);
@@ -676,7 +676,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
       for (int i = 0; i < kc; ++i) Bm[i + (size_t)ldb * j] = hv[i];
       for (int i = 0; i <= j; ++i) Hbar[i + (size_t)ldh * j] = hv[kc + i];
       Hbar[(j + 1) + (size_t)ldh * j] = hv[ncols];
-      // Givens rotations for the least-squares problem of line 12
+      // Givens rotations for the least-squares problem of the cycle
       for (int i = 0; i <= j + 1; ++i) hc[i] = Hbar[i + (size_t)ldh * j];
       for (int i = 0; i < j; ++i) {
         const double a = hc[i], bb = hc[i + 1];
@@ -700,7 +700,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
       if (est <= tol * nb || hv[ncols] == 0.0 || its >= maxit) break;
     }
     est_converged = trust_est && est <= tol * nb;
-    // line 12: y = R^-1 g ; line 12a: z = -B y ; lines 13-13a: y_acc += V y + U z
+    // y = R^-1 g ; z = -B y ; y_acc += V y + U z
     dense::upper_solve(jj, Rr.data(), ldh, gv.data(), yv.data());
     for (int i = 0; i < jj; ++i) coef[i] = yv[i];
     for (int c = 0; c < kc; ++c) {
@@ -714,7 +714,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
                block_update<T>(s, cols<T>(V, ld, jj, U, ldr, kc), d_coef, 1.0, x, x, n, nullptr,
                                0, part, nblk));
     ++cycles;
-    // line 14a: recycle-space update
+    // recycle-space update
     if (gcrot) {
       rc = gcrot_update<T>(ctx, rec, V, ld, jj, Hbar, ldh, Bm, ldb, yv, o->k, gpar, prevQ,
                            prev_dim, part, sc, st);
@@ -723,7 +723,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
       rc = harmonic_update<T>(ctx, rec, V, ld, jj, Hbar, ldh, Bm, ldb, o->k, part, sc, st);
       if (rc) return rc;
     }
-    // line 14: true residual r = b - A~ y (into the first basis column)
+    // true residual r = b - A~ y (into the first basis column)
     if (left) {
       // r = M^-1 (b - A x) = M^-1 b - M^-1 A x
       KRS_LAUNCH(ctx, KRS_K_RESIDUAL, (op.g.pts + 3) * NW,
@@ -796,7 +796,7 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
 }
 
 // ---------------------------------------------------------------------------
-// Alg. 3 line 1a: C~ = A~ U, C~ = C R (Cholesky QR, twice), U <- U R^-1
+// recycle-space setup of Alg. 3: C~ = A~ U, C~ = C R (Cholesky QR, twice), U <- U R^-1
 // ---------------------------------------------------------------------------
 // Two Cholesky-QR passes over C (U alongside): G = C^T C = R^T R,
 // C <- C R^-1, U <- U R^-1, so C^T C = I and A~ U = C are kept.
@@ -912,7 +912,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   const Cols<T> Cc = cols<T>(C, ldr, kc);
   std::vector<double> slots(kSlots, 0.0);
   double rn2 = nb2;
-  // line 1c: eta1 = C^T b, r0 = b - C eta1, xi = -eta1
+  // project b: eta1 = C^T b, r0 = b - C eta1, xi = -eta1
   if (kc > 0) {
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 1), block_dot<T>(s, Cc, b, n, 0, part, nblk));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc, sc + kEta1));
@@ -931,7 +931,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   } else {
     KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, b, r, n));
   }
-  // line 2: r~ = r_0 ; C^T r~ for the alpha denominator
+  // r~ = r_0 ; C^T r~ for the alpha denominator
   KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, r, rt, n));
   if (kc > 0) {
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 1), block_dot<T>(s, Cc, rt, n, 0, part, nblk));
@@ -962,31 +962,31 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   // are charged to the byte model from the counts read back (dev = true).
   const double bytes_p = 4 * NW, bytes_sv = NW * (kc + (kc > 0 ? 4 : 3)), bytes_yr = NW * (kc + 7);
   auto first_half = [&](bool dev) -> int {
-    KRS_LAUNCH(ctx, KRS_K_BICG_P, dev ? 0 : bytes_p, bicg_p<T>(s, r, p, v, sc, n));   // line 6
-    int e = op.apply(p, v);                                  // line 7
+    KRS_LAUNCH(ctx, KRS_K_BICG_P, dev ? 0 : bytes_p, bicg_p<T>(s, r, p, v, sc, n));
+    int e = op.apply(p, v);
     if (e) return e;
-    // line 7a-8: eta1 = C^T v, v -= C eta1, alpha = rho / r~^T v, s = r - alpha v
+    // eta1 = C^T v, v -= C eta1, alpha = rho / r~^T v, s = r - alpha v
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 2),
                block_dot<T>(s, cols<T>(C, ldr, kc, rt, ld, 1), v, n, 0, part, nblk));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
                bicg_finish_alpha<T>(s, part, nblk, kc, sc + kSums, sc, kEta1, kCtrt));
     KRS_LAUNCH(ctx, KRS_K_BICG_SV, dev ? 0 : bytes_sv,
                bicg_sv<T>(s, Cc, r, v, sv, sc, kEta1, n, part, nblk));
-    // lines 9-10a: |s| tests; on convergence xi += alpha eta1 here and
+    // half-step |s| tests; on convergence xi += alpha eta1 here and
     // y += alpha p, r = s in the conditional pass that follows
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_finish_half<T>(s, part, nblk, sc, kEta1, kXi, kc));
     KRS_LAUNCH(ctx, KRS_K_BICG_P, 0, bicg_exit_vec<T>(s, p, y, sv, r, sc, n));
     return 0;
   };
   auto second_half = [&](bool dev) -> int {
-    int e = op.apply(sv, t);                                 // line 12
+    int e = op.apply(sv, t);
     if (e) return e;
-    // line 12a-13a: eta2 = C^T t, omega = t^T s / |t - C eta2|^2, xi update
+    // eta2 = C^T t, omega = t^T s / |t - C eta2|^2, xi update
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 2),
                block_dot<T>(s, cols<T>(C, ldr, kc, sv, ld, 1), t, n, 1, part, nblk));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
                bicg_finish_omega<T>(s, part, nblk, kc, sc + kSums, sc, kEta1, kEta2, kXi));
-    // lines 14-16 with the next rho = r~^T r, then the tests of line 3
+    // y and r updates with the next rho = r~^T r, then the loop tests
     KRS_LAUNCH(ctx, KRS_K_BICG_YR, dev ? 0 : bytes_yr,
                bicg_yr<T>(s, Cc, t, sv, p, y, r, rt, sc, kEta2, n, part, nblk));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_finish_full<T>(s, part, nblk, sc + kSums, sc));
@@ -994,7 +994,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   };
   if (o->flags & KRS_FLAG_HOST_LOOP) {
     while (rnorm > tol * nb && mv < maxmv) {
-      if (rho == 0.0) {                                      // line 5
+      if (rho == 0.0) {                                      // breakdown
         status = KRS_BREAKDOWN;
         break;
       }
@@ -1015,7 +1015,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
         status = KRS_DIVERGED;
         break;
       }
-      if (snorm <= tol * nb) {                              // lines 9-10a (applied)
+      if (snorm <= tol * nb) {                              // half-step exit (applied)
         timing_add_bytes(ctx, KRS_K_BICG_P, 5 * NW);
         rnorm = snorm;
         break;
@@ -1171,7 +1171,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     if (e) return e;
     site = ctx->pin[kFlag] != 0.0 ? (int64_t)ctx->pin[kFlag] : 3;
   }
-  // line 17a: y -= U xi ; then x = M^-1 y
+  // postponed U-update: y -= U xi ; then x = M^-1 y
   if (kc > 0) {
     KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (kc + 2),
                block_update<T>(s, cols<T>(U, ldr, kc), sc + kXi, -1.0, y, y, n, nullptr, 0, part,

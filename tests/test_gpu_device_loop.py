@@ -2,7 +2,7 @@
 between host reads, enqueued kernel by kernel or replayed as a captured HIP
 graph of one iteration) against the host-tested loop: bitwise the same
 iterate, history, status and counts, including exits at the half step
-(line 10), iteration caps and the FP32 path.  Graph replays are checked on
+(the test on s), iteration caps and the FP32 path.  Graph replays are checked on
 every solve, with eager solves of the other modes in between."""
 import numpy as np
 import pytest
@@ -98,7 +98,7 @@ def test_graph_cache_eviction_and_reuse(gpu_lib):
 
 def test_breakdown_site_reported_alike(gpu_lib):
     """A skew-symmetric operator (periodic central difference in x, zero
-    diagonal) gives r~^T A r~ = 0, so BiCGStab breaks down at alpha (line 8)
+    diagonal) gives r~^T A r~ = 0, so BiCGStab breaks down at alpha
     in the first pass: both loops report the breakdown and its site, like the
     oracle."""
     from oracle import krylov as K

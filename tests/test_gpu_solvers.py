@@ -189,7 +189,7 @@ def test_rbicgstab_plain_and_recycled_match_oracle(gpu_lib, pc):
 
 @pytest.mark.parametrize("kd", [6, 62])
 def test_recycle_update_cholqr(gpu_lib, kd):
-    """Line 1a: C = qr(A~ U).Q, U <- U R^-1: invariants and the oracle's range.
+    """Recycle-space setup: C = qr(A~ U).Q, U <- U R^-1: invariants and the oracle's range.
     kd = 62, the largest space: a 62 x 62 Gram matrix (256 4 x 4 tiles, one per
     thread, 32-row LDS staging in FP64).  Random U: the errors grow with the
     condition of A~ U, hence the looser bounds for the wide space."""
@@ -313,7 +313,7 @@ def test_edge_cases(gpu_lib):
 
 def test_hybrid_changing_matrix_and_switch_back(gpu_lib):
     """Sequence on two different 32^3 porous media (the matrix changes at
-    system 5): the space is marked stale and re-formed (line 1a) before the
+    system 5): the space is marked stale and re-formed from U before the
     next solve, the poor convergence that follows makes the next system run
     rGCROT (switch back, Sec. 2.4).  The solver chosen at every step, the
     re-forming, the iteration counts and x match the oracle."""

@@ -147,7 +147,7 @@ def test_rgcrot_cycle_minimises_over_recycle_plus_krylov():
         true = np.linalg.norm(b - op(res.y))
         assert abs(true - best) <= 1e-9 * best
         assert res.history[-1] * np.linalg.norm(b) == pytest.approx(best, rel=1e-8)
-        # the sign printed in line 13a (x - U z = x + U B y) does worse
+        # the sign printed in the algorithm's U-term (x - U z = x + U B y) does worse
         tr = traces[0]
         rho0 = np.linalg.norm(r0)
         e1 = np.zeros(j + 1)
@@ -304,7 +304,7 @@ def test_rbicgstab_residual_stays_orthogonal_to_c():
     for tr in traces:
         rn = np.linalg.norm(tr["r"])
         assert np.linalg.norm(rec.C.T @ tr["r"]) <= 1e-9 * rn + 1e-14 * np.linalg.norm(bs[2])
-    # updated vs true residual after the postponed U-update (line 17a)
+    # updated vs true residual after the postponed U-update
     assert res.rel_res_true <= 10 * 1e-10
 
 
@@ -357,7 +357,7 @@ def _two_porous(n=16):
 
 
 def test_hybrid_stale_space_is_reformed_for_the_new_matrix():
-    """Alg. 3 line 1a when the matrix changed: after the hybrid step on the
+    """The recycle-space setup of Alg. 3 when the matrix changed: after the hybrid step on the
     new operator, A~_new U = C and C^T C = I hold, and the system converges."""
     (p1, Mi1, op1), (p2, Mi2, op2) = _two_porous()
     bs = list(W.rhs_ar1(p1, 4, extra=61))
@@ -405,7 +405,7 @@ def test_hybrid_switches_back_after_poor_convergence():
 
 
 # ---------------------------------------------------------------------------
-# GCROT rule of line 14a (selection by angles between successive search
+# GCROT rule of the cycle-end update (selection by angles between successive search
 # spaces, truncation of the outer space).  Every check below rebuilds the
 # spaces with applications of A~, not from the Hessenberg relation the
 # update itself uses.
