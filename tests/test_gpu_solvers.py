@@ -644,3 +644,51 @@ def test_19pt_operator_solvers_match_oracle(gpu_lib):
                                             inner_tol=1e-5), ws)
         assert rc == krs.OK, (t, rc)
         assert np.linalg.norm(b - A(x.cpu().numpy())) <= 1e-8 * np.linalg.norm(b)
+
+
+def _shifted_grf(n):
+    """GRF operator with its diagonal scaled by 1.3 (nonsingular, strongly
+    diagonally dominant): BiCGStab converges in under 20 iterations, so the
+    oracle finishes in seconds at sizes with hundreds of per-block partials."""
+    import dataclasses
+    p0 = W.grf_problem(n, extra=5)
+    bands = p0.bands.copy()
+    bands[0] = 1.3 * bands[0]
+    return dataclasses.replace(p0, bands=bands, singular=False)
+
+
+@pytest.mark.parametrize("n,kd,dtype", [(66, 40, torch.float64), (66, 62, torch.float64),
+                                        (20, 62, torch.float64), (66, 40, torch.float32)])
+def test_rbicgstab_wide_space_finishing_paths(gpu_lib, n, kd, dtype):
+    """rBiCGStab with a wide recycle space (random U, set up on the device):
+    at 66^3 the passes leave 281 per-block partials, so the finishing
+    reductions of the alpha and omega steps take the all-threads path over
+    three or four 16-column groups (kd + 1, kd + 2 columns); at 20^3 (8
+    partials) the one-group path with up to 64 columns.  FP64: history and
+    iteration count against the oracle run with the device's space; FP32:
+    count within 2 and the FP64 true residual at the FP32 tolerance."""
+    krs = gpu_lib
+    prob = _shifted_grf(n)
+    d = Dev(krs, prob, "jacobi", m=1, k=kd, dtype=dtype)
+    _, Mi, op = oracle_ops(prob, "jacobi")
+    U0 = np.random.default_rng(4).standard_normal((prob.n, kd))
+    rec = krs.Recycle(d.ctx, prob.n, kd, dtype)
+    rec.U[:kd, :prob.n] = torch.from_numpy(U0.T.copy()).to(d.dev, dtype)
+    rec.set_dim(kd)
+    krs.recycle_update(d.ctx, d.A, d.M, rec, d.ws)
+    g = recycle_to_oracle(rec)
+    b = W.rhs_perturbed(prob, 1)[0]
+    tol = 1e-8 if dtype == torch.float64 else 1e-5
+    h = _hist()
+    x = d.empty()
+    rc, st = krs.rbicgstab_solve(d.ctx, d.A, d.M, rec, d.vec(b), x,
+                                 krs.make_opts(tol=tol, history=h), d.ws)
+    ref = K.rbicgstab(op, Mi, b, tol, g)
+    assert rc == krs.OK and ref.status == K.CONVERGED
+    assert abs(st.iterations - ref.iterations) <= 2, (st.iterations, ref.iterations)
+    xs = x.double().cpu().numpy()
+    res = b - stencil.apply(prob.bands, prob.shape, prob.periodic, xs)
+    assert np.linalg.norm(res) <= 2 * tol * np.linalg.norm(b)
+    if dtype == torch.float64:
+        _check_history(h[:st.history_len], ref.history)
+        assert rel(xs, ref.x) <= 1e-6
