@@ -1486,8 +1486,8 @@ __device__ inline void hist_push(double* sc, double v) {
 // ---------------------------------------------------------------------------
 // BiCGStab finishing reductions fused with the scalar step that consumes them
 // (one launch instead of two).  One block sums the columns of the per-block
-// partials (FP64, fixed order) into out[]; then thread 0 runs the scalar step.  Every kernel returns at once when the
-// device-side stop state is set.
+// partials (FP64, fixed order) into out[]; then thread 0 runs the scalar
+// step.  Every kernel returns at once when the device-side stop state is set.
 // ---------------------------------------------------------------------------
 // Column sums go to `out` (device memory, for the host) and to `sh` (LDS):
 // the scalar step reads them from LDS, never back from memory it wrote in
