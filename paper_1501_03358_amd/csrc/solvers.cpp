@@ -884,9 +884,9 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   double* sc = cv.vec<double>(kScalarDoubles);
   if (!ws || !cv.ok) return set_err(ctx, KRS_ERR_WORKSPACE, "workspace missing or too small");
   const int kSums = 32, kEta1 = 128, kEta2 = 192, kXi = 256, kCtrt = 320, kNrm = 384;
-  // the BiCGStab passes run on at most 512 blocks: at 2 waves per SIMD that
-  // is one wave slot per SIMD lane group for the whole chip, and the fused
-  // update passes stream 2-3% faster than on 1024 blocks (measured at 256^3)
+  // the BiCGStab passes run on at most 512 blocks (2048 waves: the whole grid
+  // is resident at once at the passes' 2 waves per SIMD); the fused update
+  // passes stream 2-3% faster than on 1024 blocks (measured at 256^3)
   const int nblk = std::min(red_blocks(n), 512);
   const double NW = (double)n * sizeof(T);
   const double tol = o->tol;
