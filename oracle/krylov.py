@@ -171,6 +171,47 @@ def harmonic_ritz_pairs(G, F):
     return scipy.linalg.eig(G.T @ G, G.T @ F)
 
 
+def harmonic_ritz_select(theta, Z, k):
+    """Selection step of the GCRODR rule: a real basis P of the eigenvectors
+    belonging to the k harmonic Ritz values of smallest |theta| (non-finite
+    values last).  A complex-conjugate pair contributes the real and the
+    imaginary part of one of its eigenvectors; when the cut at k falls
+    between the two members of a pair, both are left out (k - 1 columns).
+    Returns (P, number of near-ties at the cut)."""
+    ties = 0
+    mag = np.where(np.isfinite(theta), np.abs(theta), np.inf)
+    order = np.argsort(mag, kind="stable")
+    sel = list(order[:k])
+    if k < len(order) and np.isfinite(mag[order[k]]) and mag[order[k - 1]] > 0:
+        if (mag[order[k]] - mag[order[k - 1]]) / mag[order[k - 1]] < 1e-8:
+            ties += 1
+    # do not split a complex-conjugate pair
+    chosen = []
+    for i in sel:
+        if abs(theta[i].imag) > 0:
+            partner = [q for q in sel if q != i and np.isclose(theta[q], np.conj(theta[i]),
+                                                             rtol=1e-10, atol=0)]
+            if not partner:
+                continue
+        chosen.append(i)
+    cols = []
+    done = set()
+    for i in chosen:
+        if i in done:
+            continue
+        z = Z[:, i]
+        if abs(theta[i].imag) > 0:
+            cols.append(z.real)
+            cols.append(z.imag)
+            for q in chosen:
+                if q != i and np.isclose(theta[q], np.conj(theta[i]), rtol=1e-10, atol=0):
+                    done.add(q)
+        else:
+            cols.append(z.real)
+        done.add(i)
+    return np.array(cols).T, ties
+
+
 def harmonic_ritz_update(rec: Recycle, V, Hbar, B, k):
     """The recycle-space update at the end of a cycle of Alg. 3, by the GCRODR rule (the recycle space is spanned
     by harmonic Ritz vectors of the search space range(U) + range(V_j)).
@@ -200,37 +241,7 @@ def harmonic_ritz_update(rec: Recycle, V, Hbar, B, k):
         P = np.eye(kc + j)
     else:
         theta, Z = harmonic_ritz_pairs(G, What.T @ Vhat)
-        mag = np.where(np.isfinite(theta), np.abs(theta), np.inf)
-        order = np.argsort(mag, kind="stable")
-        sel = list(order[:k])
-        if k < len(order) and np.isfinite(mag[order[k]]) and mag[order[k - 1]] > 0:
-            if (mag[order[k]] - mag[order[k - 1]]) / mag[order[k - 1]] < 1e-8:
-                ties += 1
-        # do not split a complex-conjugate pair
-        chosen = []
-        for i in sel:
-            if abs(theta[i].imag) > 0:
-                partner = [q for q in sel if q != i and np.isclose(theta[q], np.conj(theta[i]),
-                                                                 rtol=1e-10, atol=0)]
-                if not partner:
-                    continue
-            chosen.append(i)
-        cols = []
-        done = set()
-        for i in chosen:
-            if i in done:
-                continue
-            z = Z[:, i]
-            if abs(theta[i].imag) > 0:
-                cols.append(z.real)
-                cols.append(z.imag)
-                for q in chosen:
-                    if q != i and np.isclose(theta[q], np.conj(theta[i]), rtol=1e-10, atol=0):
-                        done.add(q)
-            else:
-                cols.append(z.real)
-            done.add(i)
-        P = np.array(cols).T
+        P, ties = harmonic_ritz_select(theta, Z, k)
     Q, R = np.linalg.qr(G @ P)
     s = np.sign(np.diag(R))
     s[s == 0] = 1.0

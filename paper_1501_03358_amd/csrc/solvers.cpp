@@ -1182,10 +1182,11 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   }
   rc = op.minv_s(y, x, z);
   if (rc) return rc;
-  // true residual of x
+  // true residual of x (the residual kernel writes one partial per block of
+  // its own grid, red_blocks(n), which can exceed the passes' nblk)
   KRS_LAUNCH(ctx, KRS_K_RESIDUAL, (op.g.pts + 3) * NW,
              residual_norm<T>(s, op.g, op.bands(), x, b, t, part));
-  KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, sc + kNrm));
+  KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, red_blocks(n), 1, sc + kNrm));
   rc = read_dev(ctx, sc + kNrm, 1);
   if (rc) return rc;
   if (st) {

@@ -171,6 +171,8 @@ class Context:
         self.device = torch.device(device or "cuda:0")
         if self.device.type != "cuda":
             raise RuntimeError("krs needs a GPU device")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         torch.cuda.set_device(self.device)
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = s
@@ -333,14 +335,22 @@ def make_opts(m=30, k=20, tol=1e-8, max_matvecs=2000, update_recycle=True, inner
 # --------------------------------------------------------------------------
 
 def stencil_apply(ctx, A, x, y, alpha=1.0, beta=0.0, b=None):
+    check_vec(x, A.n, A.dtype, ctx.device, "x")
+    check_vec(y, A.n, A.dtype, ctx.device, "y")
+    if b is not None:
+        check_vec(b, A.n, A.dtype, ctx.device, "b")
     return ctx.check(lib().krs_stencil_apply(ctx.h, A.h, _ptr(x), _ptr(y), alpha, beta, _ptr(b)))
 
 
 def precond_apply(ctx, M, r, z):
+    check_vec(r, M.A.n, M.A.dtype, ctx.device, "r")
+    check_vec(z, M.A.n, M.A.dtype, ctx.device, "z")
     return ctx.check(lib().krs_precond_apply(ctx.h, M.h, _ptr(r), _ptr(z)))
 
 
 def operator_apply(ctx, A, M, v, w, tmp):
+    for t, name in ((v, "v"), (w, "w"), (tmp, "tmp")):
+        check_vec(t, A.n, A.dtype, ctx.device, name)
     return ctx.check(lib().krs_operator_apply(ctx.h, A.h, _h(M), _ptr(v), _ptr(w), _ptr(tmp)))
 
 
@@ -348,7 +358,42 @@ def _h(obj):
     return None if obj is None else obj.h
 
 
+def check_vec(t, n, dtype, device, name):
+    """Raises ValueError unless `t` is a contiguous tensor of `n` values of
+    `dtype` on `device` (the library reads and writes exactly n values
+    through the raw pointer, so anything else would be out of bounds)."""
+    if t is None:
+        raise ValueError(f"{name} is None")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, the matrix needs {dtype}")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} values, the matrix has {n} unknowns")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device != torch.device(device):
+        raise ValueError(f"{name} is on {t.device}, the context on {device}")
+
+
+def check_ws(ws, nbytes, device):
+    """Raises ValueError unless `ws` is a contiguous uint8 buffer of at least
+    `nbytes` bytes on `device`."""
+    if ws is None or ws.dtype != torch.uint8 or not ws.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 tensor")
+    if ws.numel() < nbytes:
+        raise ValueError(f"workspace has {ws.numel()} bytes, {nbytes} needed")
+    if ws.device != torch.device(device):
+        raise ValueError(f"workspace is on {ws.device}, the context on {device}")
+
+
+def _check_solve(ctx, A, b, x, ws, dtype=None):
+    dt = A.dtype if dtype is None else dtype
+    check_vec(b, A.n, dt, ctx.device, "b")
+    check_vec(x, A.n, dt, ctx.device, "x")
+    check_ws(ws, 1, ctx.device)
+
+
 def gmres(ctx, A, M, b, x, opts, ws, stats=None):
+    _check_solve(ctx, A, b, x, ws)
     st = stats or Stats()
     rc = lib().krs_gmres(ctx.h, A.h, _h(M), _ptr(b), _ptr(x), ctypes.byref(opts), _ptr(ws),
                          ws.numel(), ctypes.byref(st))
@@ -357,6 +402,7 @@ def gmres(ctx, A, M, b, x, opts, ws, stats=None):
 
 
 def rgcrot_solve(ctx, A, M, rec, b, x, opts, ws, stats=None):
+    _check_solve(ctx, A, b, x, ws)
     st = stats or Stats()
     rc = lib().krs_rgcrot_solve(ctx.h, A.h, _h(M), _h(rec), _ptr(b), _ptr(x), ctypes.byref(opts),
                                 _ptr(ws), ws.numel(), ctypes.byref(st))
@@ -365,6 +411,7 @@ def rgcrot_solve(ctx, A, M, rec, b, x, opts, ws, stats=None):
 
 
 def rbicgstab_solve(ctx, A, M, rec, b, x, opts, ws, stats=None):
+    _check_solve(ctx, A, b, x, ws)
     st = stats or Stats()
     rc = lib().krs_rbicgstab_solve(ctx.h, A.h, _h(M), _h(rec), _ptr(b), _ptr(x),
                                    ctypes.byref(opts), _ptr(ws), ws.numel(), ctypes.byref(st))
@@ -373,10 +420,12 @@ def rbicgstab_solve(ctx, A, M, rec, b, x, opts, ws, stats=None):
 
 
 def recycle_update(ctx, A, M, rec, ws):
+    check_ws(ws, 1, ctx.device)
     return ctx.check(lib().krs_recycle_update(ctx.h, A.h, _h(M), rec.h, _ptr(ws), ws.numel()))
 
 
 def hybrid_solve(ctx, A, M, rec, step, n_switch, b, x, opts, ws, stats=None):
+    _check_solve(ctx, A, b, x, ws)
     st = stats or Stats()
     rc = lib().krs_hybrid_solve(ctx.h, A.h, _h(M), rec.h, step, n_switch, _ptr(b), _ptr(x),
                                 ctypes.byref(opts), _ptr(ws), ws.numel(), ctypes.byref(st))
@@ -385,6 +434,7 @@ def hybrid_solve(ctx, A, M, rec, step, n_switch, b, x, opts, ws, stats=None):
 
 
 def ir_solve(ctx, A64, A32, M32, rec32, b, x, opts, ws, stats=None):
+    _check_solve(ctx, A64, b, x, ws, torch.float64)
     st = stats or Stats()
     rc = lib().krs_ir_solve(ctx.h, A64.h, A32.h, _h(M32), _h(rec32), _ptr(b), _ptr(x),
                             ctypes.byref(opts), _ptr(ws), ws.numel(), ctypes.byref(st))

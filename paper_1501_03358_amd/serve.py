@@ -28,6 +28,9 @@ from typing import Callable, Optional
 
 import numpy as np
 
+# status of a request whose matrix needs more device memory than the whole budget
+REJECTED = -101
+
 
 @dataclasses.dataclass
 class Request:
@@ -59,18 +62,30 @@ class Scheduler:
         self.free_slots = n_slots
         self.closed = False
         self.evicted = []                 # log of evictions (mid)
+        self.rejected = []                # requests refused at submission (too large)
 
-    def submit(self, req: Request):
+    def submit(self, req: Request) -> bool:
+        """Queues `req`; a request whose matrix cannot fit the whole memory
+        budget is completed at once with status REJECTED (its done event is
+        set) and False is returned, so it never blocks the queue."""
+        need = self.state_bytes(req.mid)
         with self.lock:
+            if need > self.budget:
+                req.status = REJECTED
+                req.t_start = req.t_done = time.perf_counter()
+                self.rejected.append(req)
+                req.done.set()
+                return False
             self.queues[req.mid].append(req)
             self.lock.notify_all()
+            return True
 
     def _admissible(self, mid):
         if mid in self.resident:
             return True, []
         need = self.state_bytes(mid)
-        if need > self.budget:
-            raise ValueError(f"matrix {mid} needs {need} bytes, over the whole budget")
+        if need > self.budget:   # never queued (submit rejects it)
+            return False, []
         free = self.budget - self.used
         victims = []
         for vid, vb in self.resident.items():     # least recently used first
@@ -197,8 +212,10 @@ class Server:
         for th in self.threads:
             th.start()
 
-    def submit(self, req: Request):
-        self.sched.submit(req)
+    def submit(self, req: Request) -> bool:
+        """False (and req.status == REJECTED, req.done set) when the
+        request's matrix cannot fit the memory budget."""
+        return self.sched.submit(req)
 
     def close(self, wait=True):
         self.sched.close()

@@ -249,6 +249,154 @@ def test_harmonic_ritz_standard_form_when_no_recycle_space():
         assert np.linalg.norm(res) <= 1e-10 * np.linalg.norm(Ga) * np.linalg.norm(Z[:, i])
 
 
+def _pair_at_cut_case(seed):
+    """A synthetic cycle with kc = 0 (random orthonormal V_{j+1}, random
+    upper Hessenberg Hbar) whose GMRES-DR matrix H + h^2 H^-T e_j e_j^T has
+    a complex-conjugate pair, well separated in |theta| from its neighbours,
+    at sorted positions i, i+1 with i >= 2.  Eigen-decomposition by
+    numpy.linalg.eig of that standard matrix (the oracle solves the
+    generalized pencil with QZ).  Returns (V, Hbar, eigenvalues and
+    eigenvectors sorted by |theta|, i) or None."""
+    rng = np.random.default_rng(seed)
+    j, n = 9, 60
+    Hb = np.triu(rng.standard_normal((j + 1, j)), -1)
+    V = np.linalg.qr(rng.standard_normal((n, j + 1)))[0]
+    H = Hb[:j, :]
+    e = np.zeros(j)
+    e[-1] = 1.0
+    T = H + Hb[j, j - 1] ** 2 * np.linalg.solve(H.T, np.outer(e, e))
+    ev, EV = np.linalg.eig(T)
+    order = np.argsort(np.abs(ev))
+    ev, EV = ev[order], EV[:, order]
+    mag = np.abs(ev)
+    if np.min(np.diff(mag)[np.abs(np.diff(mag)) > 1e-12] / mag[1:][np.abs(np.diff(mag)) > 1e-12],
+              initial=1.0) < 1e-3:
+        return None                               # near-ties other than a pair
+    for i in range(2, j - 1):
+        if abs(ev[i].imag) > 1e-3 * mag[i] and np.isclose(ev[i + 1], np.conj(ev[i])):
+            pairs_before = sum(1 for q in range(i) if abs(ev[q].imag) > 0)
+            if pairs_before % 2 == 0:            # no pair split before position i
+                return V, Hb, ev, EV, i
+    return None
+
+
+def _real_basis(ev, EV, count):
+    """Real basis of the eigenvectors of the first `count` sorted values
+    (a complex pair as the real and imaginary part of one member)."""
+    cols, q = [], 0
+    while q < count:
+        if abs(ev[q].imag) > 0:
+            cols += [EV[:, q].real, EV[:, q].imag]
+            q += 2
+        else:
+            cols.append(EV[:, q].real)
+            q += 1
+    return np.column_stack(cols)
+
+
+def _pair_cut_cases():
+    out = []
+    for seed in range(200):
+        c = _pair_at_cut_case(seed)
+        if c is not None:
+            out.append(c)
+        if len(out) == 3:
+            return out
+    raise AssertionError("no synthetic cycle with a well separated pair at the cut")
+
+
+def _check_pair_cut(cases):
+    """For each case: k = i + 1 puts the cut between the pair's members,
+    k = i + 2 keeps the pair.  The oracle's update must keep exactly k - 1
+    (resp. k) columns spanning V_j times the real invariant subspace of the
+    GMRES-DR matrix for the values before the cut (principal angles
+    < 1e-8).  Returns a list of failure descriptions (empty: pinned)."""
+    fails = []
+    for V, Hb, ev, EV, i in cases:
+        j = Hb.shape[1]
+        for k, want in ((i + 1, i), (i + 2, i + 2)):
+            rec = K.Recycle.empty(V.shape[0])
+            K.harmonic_ritz_update(rec, V, Hb, np.zeros((0, j)), k)
+            if rec.dim != want:
+                fails.append(("columns", k, rec.dim, want))
+                continue
+            expect = V[:, :j] @ _real_basis(ev, EV, want)
+            ang = scipy.linalg.subspace_angles(rec.U, expect).max()
+            if not ang < 1e-8:
+                fails.append(("angle", k, ang))
+    return fails
+
+
+def test_harmonic_ritz_cut_never_splits_a_conjugate_pair():
+    """The harmonic Ritz selection at a cycle end of Alg. 3 (GCRODR rule):
+    a complex-conjugate pair straddling the k-th smallest |theta| is left
+    out (k - 1 columns), a pair inside the first k is kept as the real and
+    imaginary parts of its eigenvector; checked against the eigenvectors of
+    the standard GMRES-DR matrix from numpy.linalg.eig."""
+    assert _check_pair_cut(_pair_cut_cases()) == []
+
+
+def _mistake_keep_real_part(theta, Z, k):
+    # a split pair keeps the real part of its member inside the cut
+    order = np.argsort(np.abs(theta), kind="stable")[:k]
+    cols, done = [], set()
+    for q in order:
+        if q in done:
+            continue
+        partner = [p for p in order if p != q and np.isclose(theta[p], np.conj(theta[q]))]
+        if abs(theta[q].imag) > 0 and partner:
+            cols += [Z[:, q].real, Z[:, q].imag]
+            done.add(partner[0])
+        else:
+            cols.append(Z[:, q].real)
+        done.add(q)
+    return np.array(cols).T, 0
+
+
+_SELECT = K.harmonic_ritz_select
+
+
+def _mistake_take_next(theta, Z, k):
+    # a split pair is replaced by the next value after it (k columns)
+    P, t = _SELECT(theta, Z, k)
+    if P.shape[1] == k - 1:
+        order = np.argsort(np.abs(theta), kind="stable")
+        P = np.column_stack([P, Z[:, order[k + 1]].real])
+    return P, t
+
+
+def _mistake_wrong_split(theta, Z, k):
+    # a kept pair contributes its real part and its modulus, not Re and Im
+    P, t = _SELECT(theta, Z, k)
+    order = np.argsort(np.abs(theta), kind="stable")
+    cols, done = [], set()
+    for a in order[:k]:
+        if a in done:
+            continue
+        partner = [p for p in order[:k] if p != a and np.isclose(theta[p], np.conj(theta[a]))]
+        if abs(theta[a].imag) > 0:
+            if not partner:
+                continue
+            cols += [Z[:, a].real, np.abs(Z[:, a])]
+            done.add(partner[0])
+        else:
+            cols.append(Z[:, a].real)
+        done.add(a)
+    return np.array(cols).T, t
+
+
+@pytest.mark.parametrize("mistake", [_mistake_keep_real_part, _mistake_take_next,
+                                     _mistake_wrong_split])
+def test_conjugate_pair_pin_detects_planted_mistakes(monkeypatch, mistake):
+    """The pin above fails for plausible mistakes in the selection (planted
+    in the oracle on the CPU): keeping the real part of a split pair's
+    member, replacing a split pair by the next value, and a wrong real basis
+    of a kept pair."""
+    cases = _pair_cut_cases()
+    monkeypatch.setattr(K, "harmonic_ritz_select", mistake)
+    assert _check_pair_cut(cases) != []
+
+
 def test_harmonic_ritz_values_real_for_symmetric_operator():
     shape = (8, 8, 8)
     bc = {'x': ('dirichlet', 'dirichlet'), 'y': ('neumann', 'neumann'),
@@ -402,6 +550,43 @@ def test_hybrid_switches_back_after_poor_convergence():
     # the new matrix with the old (re-formed) space converged poorly, and the
     # policy reacted within the sequence
     assert "rgcrot" in seq[5:], (seq, mvs)
+
+
+def test_hybrid_switch_back_policy_on_scripted_counts(monkeypatch):
+    """The switch-back reading of Sec. 2.4 on scripted solver outcomes (the
+    two solvers replaced by stubs): the expected sequence below is written
+    out by hand from the reading (n_switch = 2, factor 1.3: the first
+    rBiCGStab system after rGCROT sets the reference; a converged system
+    above 1.3 times it sends the next one to rGCROT; a failed rBiCGStab solve
+    is repeated by rGCROT and also resets the reference)."""
+    script = iter([(100, K.CONVERGED), (120, K.CONVERGED), (140, K.CONVERGED),
+                   (200, K.CONVERGED), (250, K.CONVERGED), (300, K.NOT_CONVERGED),
+                   (90, K.CONVERGED), (118, K.CONVERGED)])
+
+    def fake_bicg(op, minv, b, tol, rec, max_its=2000, div_factor=1e2):
+        mv, status = next(script)
+        return K.Result(b, b, status, [], mv // 2, mv)
+
+    def fake_rgcrot(op, minv, b, m, k, tol, rec, update=True, max_its=2000, orth="cgs2"):
+        return K.Result(b, b, K.CONVERGED, [], 30, 31)
+
+    monkeypatch.setattr(K, "rbicgstab", fake_bicg)
+    monkeypatch.setattr(K, "rgcrot", fake_rgcrot)
+    st, rec, b = K.HybridState(), K.Recycle.empty(4), np.ones(4)
+    seq = [K.hybrid_step(t, 2, None, None, b, 30, 20, 1e-8, rec, switch_back=1.3,
+                         state=st) for t in range(11)]
+    got = [(r.solver, r.fallback) for r in seq]
+    assert got == [("rgcrot", False), ("rgcrot", False),
+                   ("rbicgstab", False),   # 100: reference
+                   ("rbicgstab", False),   # 120 <= 130
+                   ("rbicgstab", False),   # 140 > 130: next runs rGCROT
+                   ("rgcrot", False),      # forced; reference reset
+                   ("rbicgstab", False),   # 200: new reference
+                   ("rbicgstab", False),   # 250 <= 260
+                   ("rgcrot", True),       # 300, not converged: solved again by rGCROT
+                   ("rbicgstab", False),   # 90: reference after the fallback
+                   ("rbicgstab", False)]   # 118 > 117 = 1.3 * 90: next would run rGCROT
+    assert st.force_rgcrot and st.ref_mv == 90
 
 
 # ---------------------------------------------------------------------------

@@ -116,10 +116,12 @@ def test_busy_matrix_is_never_evicted():
 
 
 def test_oversized_matrix_rejected():
+    from paper_1501_03358_amd.serve import REJECTED
     sched = Scheduler(1, 1.0, lambda mid: 2.0)
-    sched.submit(Request(0, 0, 0, np.zeros(1), 0.0))
-    with pytest.raises(ValueError):
-        sched.next(timeout=0.01)
+    r = Request(0, 0, 0, np.zeros(1), 0.0)
+    assert sched.submit(r) is False
+    assert r.done.is_set() and r.status == REJECTED
+    assert sched.next(timeout=0.01) == "timeout"
 
 
 def test_continuous_admission_while_running():
@@ -162,3 +164,31 @@ def test_state_bytes_counts_bands_and_pack():
     rec = 2 * 10 * 4 * (n + 1088)                     # U and C, padded columns
     assert b7 == 7 * 12 * n + 4 * n + pack7 + rec
     assert b19 == 19 * 12 * n + 4 * n + rec          # no coefficient pack for 19 bands
+
+
+def test_oversized_matrix_is_rejected_and_others_complete():
+    """A request whose matrix needs more than the whole memory budget is
+    completed at submission with status REJECTED; it does not stop the
+    workers, and every other request is still served."""
+    from paper_1501_03358_amd.serve import REJECTED
+    sizes = {0: 4.0, 1: 100.0, 2: 4.0}
+    sched = Scheduler(2, 10.0, lambda mid: sizes[mid])
+    log, lock = [], threading.Lock()
+    ths = _run_fake(sched, 2, lambda r: 0.001, log, lock)
+    reqs = []
+    for rid, (mid, step) in enumerate([(1, 0), (0, 0), (2, 0), (1, 1), (0, 1), (2, 1)]):
+        r = Request(rid, mid, step, np.zeros(1), time.perf_counter())
+        accepted = sched.submit(r)
+        assert accepted == (mid != 1)
+        reqs.append(r)
+    sched.close()
+    for t in ths:
+        t.join(timeout=10)
+        assert not t.is_alive()
+    for r in reqs:
+        assert r.done.wait(timeout=1)
+        if r.mid == 1:
+            assert r.status == REJECTED
+    served = [(e[1], e[2]) for e in log if e[0] == "start"]
+    assert sorted(served) == [(0, 0), (0, 1), (2, 0), (2, 1)]
+    assert [r.rid for r in sched.rejected] == [0, 3]
