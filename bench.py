@@ -84,19 +84,288 @@ def build_inputs(n, steps, warmup, dev, torch):
     return prob, bs
 
 
-def cpu_baseline(prob, mv_per_solve):
-    """Oracle (plain NumPy FP64) time of one preconditioned operator
-    application A M^-1 v on the same system, scaled by the matvecs per solve."""
+def host_info():
+    """Host cores as the oracle sample uses them: the CPU model, the logical
+    CPU count, and the BLAS thread pools NumPy runs its matrix products on
+    (elementwise and stencil work is single-threaded NumPy)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        import threadpoolctl
+        pools = [p for p in threadpoolctl.threadpool_info() if p.get("user_api") == "blas"]
+        if pools:
+            blas = max(int(p.get("num_threads", 1)) for p in pools)
+    except Exception:
+        blas = None
+    return {"cpu_model": model, "cpu_count": os.cpu_count(), "blas_threads": blas}
+
+
+def cpu_baseline(prob, U, C, counts):
+    """The oracle (plain NumPy/SciPy FP64, as it stands) timed on the host
+    for a bounded sample of the 256^3 workload, scaled to a whole sequence:
+
+      t_it   one rBiCGStab iteration with the k-dimensional recycle space
+             (Alg. 4: two applications of A M^-1, the C-projections and the
+             vector updates): the oracle's solve stopped after one iteration
+             less the same solve stopped before the first,
+      t_step one rGCROT Arnoldi step at j = 15 with k_c = k (Alg. 3: one
+             A M^-1, classical Gram-Schmidt twice against [C, V_16], the
+             least-squares update of the cycle),
+      t_op   one application of A M^-1 (the true residual at a cycle end).
+
+    counts: per system (solver, iterations, cycles) of the GPU's FP64
+    hybrid run of the same sequence (what the FP64 oracle would take).
+    Not timed (a lower bound on the oracle's time): the harmonic-Ritz update
+    at rGCROT cycle ends and the final x = M^-1 y."""
+    from oracle import krylov as K
     from oracle import precond, stencil
-    v = np.random.default_rng(1).standard_normal(prob.n)
+    Mi = lambda v: precond.schwarz_jacobi(prob.bands, prob.shape, prob.periodic, v, tile=8)
+    op = lambda v: stencil.apply(prob.bands, prob.shape, prob.periodic, Mi(v))
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal(prob.n)
+    rec = K.Recycle(U, C)
+    # one iteration: a solve stopped after its first iteration, less one
+    # stopped before it (both project b, form the true residual and M^-1 y)
     t0 = time.perf_counter()
-    z = precond.schwarz_jacobi(prob.bands, prob.shape, prob.periodic, v, tile=8)
-    stencil.apply(prob.bands, prob.shape, prob.periodic, z)
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / (dt * mv_per_solve), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one oracle application of A M^-1 (Schwarz-Jacobi + stencil) on the "
-                       f"{prob.shape[0]}^3 system took {dt:.2f} s on 1 host thread; scaled by the "
-                       f"GPU run's {mv_per_solve:.0f} operator applications per solve")}
+    K.rbicgstab(op, Mi, b, 1e-30, rec, max_matvecs=2)
+    t1 = time.perf_counter()
+    K.rbicgstab(op, Mi, b, 1e-30, rec, max_matvecs=0)
+    t_it = (t1 - t0) - (time.perf_counter() - t1)
+    j = 15
+    V = np.linalg.qr(rng.standard_normal((prob.n, j + 1)))[0]
+    H = np.triu(rng.standard_normal((j + 2, j + 1)), -1)
+    t0 = time.perf_counter()
+    w = op(V[:, j])
+    t_op = time.perf_counter() - t0
+    w, _ = K._orthogonalize(w, [C, V], "cgs2")
+    K._norm(w)
+    K._ls(H, 1.0)
+    t_step = time.perf_counter() - t0
+    total = 0.0
+    n_it = n_step = n_cyc = 0
+    for solver, its, cycles in counts:
+        if solver == "rgcrot":
+            total += its * t_step + cycles * t_op
+            n_step += its
+            n_cyc += cycles
+        else:
+            total += its * t_it
+            n_it += its
+    info = host_info()
+    return {"value": len(counts) / total, "unit": "solves/s",
+            "cores": info["blas_threads"] or 1, "kind": "oracle",
+            "sample": (f"oracle on the {prob.shape[0]}^3 system, FP64 NumPy on the host "
+                       f"({info['cpu_model']}, {info['cpu_count']} logical CPUs; BLAS products on "
+                       f"{info['blas_threads']} threads, stencil and preconditioner on 1): one "
+                       f"rBiCGStab iteration with k={C.shape[1]} took {t_it:.2f} s, one rGCROT "
+                       f"Arnoldi step at j=15 with k_c={C.shape[1]} {t_step:.2f} s (of which "
+                       f"A M^-1 {t_op:.2f} s); scaled by the GPU FP64 run's counts over "
+                       f"{len(counts)} systems: {n_it} rBiCGStab iterations x t_it + {n_step} "
+                       f"Arnoldi steps x t_step + {n_cyc} cycle-end residuals x t_op; "
+                       f"harmonic-Ritz updates and the final M^-1 not included"),
+            "t_iteration_s": t_it, "t_arnoldi_step_s": t_step, "t_operator_s": t_op,
+            "host": info}
+
+
+def grf24_main(args):
+    """The CPU-oracle-size case: 24^3 Gaussian-random-field medium (13,824
+    unknowns, random cell volumes, so A is nonsymmetric), point Jacobi, FP64,
+    5 right-hand sides b_t = b_0 + 0.05 t eta_t.  GMRES(20) (Alg. 1) against
+    rGCROT(20,10) (Alg. 3) on the GPU, with the oracle's full solves of the
+    same sequence timed on the host beside it."""
+    import torch
+
+    import workloads as W
+    from oracle import krylov as K
+    from oracle import precond, stencil
+    from paper_1501_03358_amd import krs
+
+    dev = torch.device("cuda:0")
+    prob = W.grf_problem(24)
+    bs_h = W.rhs_perturbed(prob, 5)
+    bs = [torch.from_numpy(b).to(dev) for b in bs_h]
+    m, k = 20, 10
+    reps = args.steps if args.steps is not None else 20
+    ctx = krs.Context(dev)
+    A = krs.Matrix(ctx, prob.shape, prob.periodic, torch.from_numpy(prob.bands).to(dev))
+    Mp = krs.Precond(ctx, A, "jacobi")
+    ws = torch.empty(krs.workspace_size(krs.SOLVER_RGCROT, prob.n, m, k, torch.float64),
+                     dtype=torch.uint8, device=dev)
+    x = torch.zeros(prob.n, dtype=torch.float64, device=dev)
+    opts = krs.make_opts(m=m, k=k, tol=1e-8)
+    Mi = lambda v: precond.jacobi(prob.bands, v)
+    op = lambda v: stencil.apply(prob.bands, prob.shape, prob.periodic, Mi(v))
+
+    def gpu_seq(name):
+        rec = krs.Recycle(ctx, prob.n, k, torch.float64)
+        out = []
+        for b in bs:
+            if name == "rgcrot":
+                rc, st = krs.rgcrot_solve(ctx, A, Mp, rec, b, x, opts, ws)
+            else:
+                rc, st = krs.gmres(ctx, A, Mp, b, x, opts, ws)
+            out.append((rc, st.iterations, x.cpu().numpy().copy()))
+        return out
+
+    res = {}
+    for name in ("rgcrot", "gmres"):
+        first = gpu_seq(name)          # also the warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            gpu_seq(name)
+        torch.cuda.synchronize()
+        t_gpu = time.perf_counter() - t
+        t = time.perf_counter()
+        orec = K.Recycle.empty(prob.n)
+        refs = [K.rgcrot(op, Mi, b, m, k, 1e-8, orec) if name == "rgcrot"
+                else K.gmres(op, Mi, b, m, 1e-8) for b in bs_h]
+        t_cpu = time.perf_counter() - t
+        res[name] = {
+            "gpu_solves_per_s": 5 * reps / t_gpu,
+            "oracle_solves_per_s": 5 / t_cpu,
+            "iterations_gpu": [f[1] for f in first],
+            "iterations_oracle": [r.iterations for r in refs],
+            "max_rel_x_diff_vs_oracle": max(float(np.linalg.norm(f[2] - r.x) /
+                                                  np.linalg.norm(r.x))
+                                            for f, r in zip(first, refs)),
+            "all_converged": all(f[0] == 0 for f in first) and
+            all(r.status == K.CONVERGED for r in refs),
+        }
+        log(f"[bench] grf24 {name}: GPU {res[name]['gpu_solves_per_s']:.1f} solves/s, oracle "
+            f"{res[name]['oracle_solves_per_s']:.2f} solves/s, iterations "
+            f"{res[name]['iterations_gpu']} (oracle {res[name]['iterations_oracle']})")
+    info = host_info()
+    r0 = res["rgcrot"]
+    out = {
+        "metric": "solves/s to 1e-8 relative residual (FP64, rGCROT(20,10) vs GMRES(20))",
+        "value": r0["gpu_solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 5 * reps,
+        "warmup": 5, "ms_per_step": 1e3 / r0["gpu_solves_per_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "grf24", "grid": "24^3", "unknowns": prob.n, "time_steps": 5,
+                   "m": m, "k": k, "precond": "point Jacobi", "tol": 1e-8,
+                   "note": "13,824 unknowns: launch-latency bound on the GPU, not a bandwidth "
+                           "configuration"},
+        "methods": res,
+        "speedup_vs_gmres": r0["gpu_solves_per_s"] / res["gmres"]["gpu_solves_per_s"],
+        "cpu_baseline": {"value": r0["oracle_solves_per_s"], "unit": "solves/s",
+                         "cores": info["blas_threads"] or 1, "kind": "oracle",
+                         "sample": "the oracle's full rGCROT(20,10) solves of the 5-system "
+                                   "sequence, timed on the host (whole workload, not sampled)",
+                         "host": info},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_leg(n_matrices=16, grids=(32, 64), per_matrix=4, duration=8.0, batch_max=8):
+    """A short serving run for the default benchmark line: n_matrices small
+    resident matrices (channel and porous coefficients alternating, grids
+    drawn from `grids`), the hybrid per matrix (rGCROT steps first), FP32
+    inner solves in FP64 refinement to 1e-8.  Closed-loop capacity with and
+    without the batch worker (grouped rBiCGStab launches), then Poisson
+    arrivals at half the batched capacity and at the capacity itself, with
+    p50/p99 latency (arrival to result on the host, including the upload of
+    b and the download of x)."""
+    import threading
+
+    import workloads as W
+    from paper_1501_03358_amd.serve import (MatrixSpec, Request, Server, latency_summary,
+                                            poisson_arrivals)
+
+    rng = np.random.default_rng(np.random.SeedSequence(W.SEED_BASE + 55))
+    probs, specs = [], []
+    for i in range(n_matrices):
+        n = int(rng.choice(grids))
+        p = (W.channel_problem(n, g=W.CHANNEL_G128 * float(rng.uniform(0.9, 1.0)))
+             if i % 2 == 0 else W.porous_problem(n, seed_cfg=5, extra=100 + i))
+        probs.append(p)
+        specs.append(MatrixSpec(i, p.shape, p.periodic, p.bands, k=10))
+    state = []
+    for i, p in enumerate(probs):
+        g = np.random.default_rng(np.random.SeedSequence([W.SEED_BASE + 55, i]))
+        xis = [W.make_compatible(g.standard_normal(p.n), p) for _ in range(2)]
+        state.append({"b": W.make_compatible(g.standard_normal(p.n), p), "xi": xis, "t": 0})
+
+    def next_rhs(mid):
+        st = state[mid]
+        if st["t"] > 0:
+            st["b"] = 0.98 * st["b"] + 0.02 * st["xi"][st["t"] % 2]
+        st["t"] += 1
+        return st["t"] - 1, st["b"].copy()
+
+    out = {"matrices": n_matrices, "grids": list(grids), "slots": 2, "batch_max": batch_max}
+    rid = [0]
+
+    def closed(srv, rounds):
+        reqs = []
+        t = time.perf_counter()
+        for _ in range(rounds):
+            for mid in range(n_matrices):
+                step, b = next_rhs(mid)
+                r = Request(rid[0], mid, step, b, t)
+                rid[0] += 1
+                srv.submit(r)
+                reqs.append(r)
+        for r in reqs:
+            r.done.wait()
+        return reqs, time.perf_counter() - t
+
+    def open_loop(srv, rate):
+        arrivals = poisson_arrivals(rate, duration, n_matrices, seed=W.SEED_BASE + 56)
+        load = []
+
+        def feeder():
+            t0 = time.perf_counter()
+            for ta, mid in arrivals:
+                now = time.perf_counter() - t0
+                if ta > now:
+                    time.sleep(ta - now)
+                step, b = next_rhs(mid)
+                r = Request(rid[0], mid, step, b, t0 + ta)
+                rid[0] += 1
+                srv.submit(r)
+                load.append(r)
+        th = threading.Thread(target=feeder)
+        t = time.perf_counter()
+        th.start()
+        th.join()
+        for r in load:
+            r.done.wait()
+        dt = time.perf_counter() - t
+        lat = latency_summary(load)
+        return {"rate_req_s": rate, "requests": len(load), "solves_per_s": len(load) / dt,
+                "latency_ms": lat,
+                "all_converged": all(r.status == 0 for r in load)}
+
+    for bm in (0, batch_max):
+        srv = Server(specs, "cuda:0", n_slots=2, mem_budget=100e9, m=M, k=10, n_switch=N_SWITCH,
+                     tol=1e-8, batch_max=bm)
+        warm, t_warm = closed(srv, N_SWITCH)
+        cap, t_cap = closed(srv, per_matrix)
+        capacity = len(cap) / t_cap
+        key = "batched" if bm else "unbatched"
+        out[f"capacity_{key}_solves_per_s"] = capacity
+        out[f"closed_loop_{key}_latency_ms"] = latency_summary(cap)
+        ok = all(r.status == 0 for r in warm + cap)
+        if bm:
+            out["latency_under_load"] = {"half_capacity": open_loop(srv, 0.5 * capacity),
+                                         "at_capacity": open_loop(srv, capacity)}
+            out["mean_batch"] = float(np.mean(srv.batches)) if srv.batches else None
+        srv.close()
+        if srv.errors:
+            raise RuntimeError(f"serving errors: {srv.errors[:3]}")
+        out[f"all_converged_{key}"] = ok
+        log(f"[bench] serve leg {key}: capacity {capacity:.1f} solves/s "
+            f"(warm-up {t_warm:.1f}s)")
+    return out
 
 
 def serve_main(args):
@@ -146,7 +415,8 @@ def serve_main(args):
         return st["t"] - 1, st["b"].copy()
 
     srv = Server(specs, "cuda:0", n_slots=args.slots, mem_budget=args.mem_gb * 1e9, m=M, k=K,
-                 n_switch=N_SWITCH, tol=1e-8, inner_tol=args.inner_tol)
+                 n_switch=N_SWITCH, tol=1e-8, inner_tol=args.inner_tol,
+                 batch_max=args.batch_max)
     rid = [0]
 
     def submit(mid, t_arr):
@@ -391,7 +661,7 @@ def seq_main(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["porous_ir", "serve", "channel128", "porous128",
-                                           "porous128_changing", "skewed128"],
+                                           "porous128_changing", "skewed128", "grf24"],
                     default="porous_ir")
     ap.add_argument("--local-solver", choices=["jacobi", "ssor"], default="jacobi",
                     help="local smoother of the Schwarz preconditioner")
@@ -428,6 +698,10 @@ def main():
                     help="porous128: time only the hybrid (switch-point sweeps)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the short serving leg of the default benchmark")
+    ap.add_argument("--batch-max", type=int, default=8,
+                    help="serve: requests the batch worker solves together (0: none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -444,6 +718,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "serve":
         serve_main(args)
+        return
+    if args.workload == "grf24":
+        grf24_main(args)
         return
     if args.workload in ("channel128", "porous128", "porous128_changing", "skewed128"):
         if args.left and args.workload != "channel128":
@@ -524,6 +801,7 @@ def main():
     if not args.no_fp64:
         rec64 = krs.Recycle(ctx, prob.n, args.k, torch.float64)
         its64 = 0
+        counts64 = []
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for t in range(args.steps):
@@ -531,6 +809,8 @@ def main():
             rc, st = krs.hybrid_solve(ctx, A64, M64, rec64, t, args.n_switch, bs[args.warmup + t],
                                       x64s[t], o, ws64)
             its64 += st.iterations
+            counts64.append(("rgcrot" if st.solver == krs.SOLVER_RGCROT else "rbicgstab",
+                             int(st.iterations), int(st.cycles)))
             log(f"[bench] fp64 step {t}: status {rc} its {st.iterations} "
                 f"rel_res {st.rel_res_true:.2e} {st.time_ms:.0f} ms")
         torch.cuda.synchronize()
@@ -538,8 +818,8 @@ def main():
         diffs = [float(torch.linalg.vector_norm(xs[t] - x64s[t]) /
                        torch.linalg.vector_norm(x64s[t])) for t in range(args.steps)]
         fp64 = {"solves_per_s": args.steps / t64, "ms_per_step": 1e3 * t64 / args.steps,
-                "iterations": its64, "max_rel_diff_fp32ir_vs_fp64": max(diffs)}
-        del rec64
+                "iterations": its64, "max_rel_diff_fp32ir_vs_fp64": max(diffs),
+                "rel_diff_fp32ir_vs_fp64": diffs}
 
     # ---- roofline of the dominant kernel class ------------------------------
     dom = max(kt, key=lambda c: kt[c][1])
@@ -551,9 +831,17 @@ def main():
 
     traffic, traffic_note = measured_traffic(dom)
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and fp64 is not None:
         log("[bench] timing the CPU oracle sample ...")
-        cpu = cpu_baseline(prob, mvs / args.steps)
+        U64, C64 = rec64.views()
+        cpu = cpu_baseline(prob, U64.cpu().numpy().copy(), C64.cpu().numpy().copy(), counts64)
+    if fp64 is not None:
+        del rec64
+
+    serve = None
+    if not args.no_serve:
+        log("[bench] serving leg ...")
+        serve = serve_leg()
 
     value = args.steps / t_ir
     out = {
@@ -584,6 +872,7 @@ def main():
                      "launches": n_l, "avg_launch_us": 1e3 * ms_l / max(n_l, 1)},
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "serve_leg": serve,
     }
     print(json.dumps(out), flush=True)
 

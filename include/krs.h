@@ -142,11 +142,15 @@ typedef struct krs_precond_desc {
  * meets tol, without confirming it with the true residual (used for the
  * inner solves of iterative refinement, whose outer FP64 residual decides). */
 #define KRS_FLAG_TRUST_ESTIMATE 1
-/* rBiCGStab: test convergence on the host after every half step (two host
- * round trips per iteration).  By default the stopping tests of Alg. 4 run on
- * the device and the host enqueues several iterations between reads; passes
- * enqueued after the stop leave the iterate untouched, so both modes give
- * bitwise the same result, history and counts. */
+/* Test convergence on the host after every step: rBiCGStab after every half
+ * step (two host round trips per iteration), GMRES / rGCROT after every
+ * Arnoldi step (the host then applies the Givens rotations of Alg. 1 / 3 and
+ * tests the residual estimate).  By default these tests run on the device
+ * (the scalar steps of Alg. 4; the Givens rotations, estimate and stopping
+ * tests of an Arnoldi step, in FP64 with the host's operation order) and the
+ * host enqueues several iterations or steps between reads; work enqueued
+ * after the stop changes nothing that the result reads, so both modes give
+ * bitwise the same result, history, recycle space and counts. */
 #define KRS_FLAG_HOST_LOOP 2
 /* rBiCGStab, device-driven loop: replay a captured HIP graph of one
  * iteration instead of enqueuing its kernels one by one (grids of at most
@@ -351,6 +355,43 @@ int krs_hybrid_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, kr
 int krs_ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32,
                  const krs_precond* M32, krs_recycle* rec32, const void* b, void* x,
                  const krs_opts* opts, void* ws, size_t ws_bytes, krs_stats* stats);
+
+/* One system of krs_ir_solve_batched: the arguments of krs_ir_solve for
+ * it (ws: krs_workspace_size(KRS_SOLVER_IR, N, opts.m, k, KRS_F32) bytes of
+ * its own) and where its statistics go (may be NULL). */
+typedef struct krs_ir_system {
+  const krs_matrix* A64;
+  const krs_matrix* A32;
+  const krs_precond* M32;
+  krs_recycle* rec32;
+  const void* b;
+  void* x;
+  void* ws;
+  size_t ws_bytes;
+  krs_stats* stats;
+} krs_ir_system;
+
+/* Bytes of the shared workspace of krs_ir_solve_batched (the table of the
+ * grouped launches). */
+#define KRS_BATCH_WORKSPACE_BYTES ((size_t)64 << 10)
+
+/* FP64 iterative refinement of nsys independent systems at once, each with
+ * rBiCGStab inner solves (opts.inner_solver must be KRS_SOLVER_RBICGSTAB;
+ * Sec. 2.4: the later systems of a sequence, once a recycle space exists),
+ * for many small systems whose solves alone would be bound by kernel launch
+ * latency.  Each inner rBiCGStab pass runs as one launch per step for all
+ * systems (a block range of the grid per system), with a fixed per-system
+ * reduction tree: every system's result, statistics and iteration counts
+ * are bitwise those of krs_ir_solve on it alone.  Grouped: FP32 7-point
+ * systems with the Schwarz-Jacobi preconditioner (8^3 tiles in bricks of
+ * 2^3, Jacobi local sweeps, one global sweep) whose recycle spaces have the
+ * same dimension as the first such system, up to 32 of them; every other
+ * system is solved alone after them.  Systems converge and leave the group
+ * independently.  Returns KRS_OK when every system converged, else the
+ * largest per-system status (each in its stats->status), or a negative
+ * error.  ws: KRS_BATCH_WORKSPACE_BYTES of device memory.  Synchronous. */
+int krs_ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys,
+                         const krs_opts* opts, void* ws, size_t ws_bytes);
 
 /* ---------------- measurement ---------------- */
 

@@ -2,6 +2,7 @@
 #include <climits>
 #include <cmath>
 #include <new>
+#include <string>
 
 #include "internal.hpp"
 
@@ -404,6 +405,39 @@ int krs_ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32,
   const bool upd = rec32 && (opts->update_recycle || opts->inner_solver == KRS_SOLVER_RBICGSTAB);
   if ((rc = check_rec(ctx, A32, rec32, opts, upd))) return rc;
   return krs::ir_solve(ctx, A64, A32, M32, rec32, b, x, opts, ws, ws_bytes, stats);
+}
+
+
+int krs_ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys, const krs_opts* opts,
+                         void* ws, size_t ws_bytes) {
+  if (!ctx || nsys < 0 || (nsys > 0 && !sys)) return KRS_ERR_ARG;
+  int rc = check_opts(ctx, opts, true);
+  if (rc) return rc;
+  if (opts->flags & KRS_FLAG_LEFT_PRECOND)
+    return set_err(ctx, KRS_ERR_ARG, "refinement runs right-preconditioned inner solves");
+  if (opts->inner_solver != KRS_SOLVER_RBICGSTAB)
+    return set_err(ctx, KRS_ERR_ARG, "batched refinement runs rBiCGStab inner solves");
+  if (!ws || ws_bytes < KRS_BATCH_WORKSPACE_BYTES)
+    return set_err(ctx, KRS_ERR_WORKSPACE, "batch workspace missing or too small");
+  for (int i = 0; i < nsys; ++i) {
+    const krs_ir_system& q = sys[i];
+    if (!q.A64 || !q.A32 || !q.b || !q.x || !q.ws)
+      return set_err(ctx, KRS_ERR_ARG, "system " + std::to_string(i) + ": missing argument");
+    if (q.A64->dt != KRS_F64 || q.A32->dt != KRS_F32)
+      return set_err(ctx, KRS_ERR_STATE, "IR needs an FP64 and an FP32 matrix");
+    if (q.A64->n != q.A32->n || q.A64->pts != q.A32->pts)
+      return set_err(ctx, KRS_ERR_STATE, "IR matrices differ");
+    if ((rc = check_precond(ctx, q.A32, q.M32))) return rc;
+    if ((rc = check_rec(ctx, q.A32, q.rec32, opts, q.rec32 != nullptr))) return rc;
+    size_t need = 0;
+    krs::workspace_bytes(KRS_SOLVER_IR, q.A64->n, opts->m, opts->k, KRS_F32, &need);
+    if (q.ws_bytes < need)
+      return set_err(ctx, KRS_ERR_WORKSPACE, "system " + std::to_string(i) + ": workspace too small");
+    for (int j = 0; j < i; ++j)
+      if (sys[j].x == q.x || sys[j].ws == q.ws || (q.rec32 && sys[j].rec32 == q.rec32))
+        return set_err(ctx, KRS_ERR_ARG, "systems share x, a workspace or a recycle space");
+  }
+  return krs::ir_solve_batched(ctx, nsys, sys, opts, ws, ws_bytes);
 }
 
 }  // extern "C"

@@ -97,6 +97,7 @@ constexpr int64_t kGraphMaxN = int64_t(1) << 20;   // larger grids keep the GPU 
 constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+static_assert(sizeof(BatchTable) <= KRS_BATCH_WORKSPACE_BYTES, "batch workspace");
 // Leading dimension of multi-vectors: N rounded up to 64 values, plus a pad
 // of 1088 values (4 KiB + 256 B in FP32), so that the columns of a block
 // product do not all start at the same offset modulo a large power of two
@@ -204,6 +205,9 @@ int rbicgstab(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const krs
               const void* b, void* x, const krs_opts* o, void* ws, size_t wsb, krs_stats* st);
 int recycle_setup(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
                   void* ws, size_t wsb);
+// krs_ir_solve_batched (grouped rBiCGStab inner passes; bitwise as alone)
+int ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys, const krs_opts* o,
+                     void* ws, size_t wsb);
 int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const krs_precond* M32,
              krs_recycle* rec32, const void* b, void* x, const krs_opts* o, void* ws, size_t wsb,
              krs_stats* st);

@@ -18,6 +18,16 @@ namespace {
 
 constexpr int kXcd = 8;
 
+// Block coordinates of a launch: the hardware ones, or, in a grouped launch
+// over several independent systems, the block's place within its system's
+// share of the grid.  Kernel bodies take them explicitly, so that one system
+// computes the same values (same rows per block, same partial-sum slots) in
+// either kind of launch.
+struct Blk {
+  int b, G;
+};
+__device__ __forceinline__ Blk hw_blk() { return Blk{(int)blockIdx.x, (int)gridDim.x}; }
+
 // Block b runs on XCD b % 8; give every XCD a contiguous range of work ids.
 __device__ __forceinline__ int xcd_remap(int b, int G) {
   const int q = G / kXcd, r = G % kXcd;
@@ -51,7 +61,8 @@ __device__ __forceinline__ T block_sum(T v) {
 
 // Block-reduce nv (<= NV) accumulators and store partials[c*nblk + blockIdx.x].
 template <class T, int NV>
-__device__ __forceinline__ void reduce_store(T (&acc)[NV], int nv, T* partials, int nblk) {
+__device__ __forceinline__ void reduce_store(T (&acc)[NV], int nv, T* partials, int nblk,
+                                             Blk k = hw_blk()) {
   __shared__ T sh[NV][kThreads / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -63,7 +74,7 @@ __device__ __forceinline__ void reduce_store(T (&acc)[NV], int nv, T* partials, 
   }
   __syncthreads();
   for (int c = threadIdx.x; c < nv; c += kThreads)
-    partials[(int64_t)c * nblk + blockIdx.x] = (sh[c][0] + sh[c][1]) + (sh[c][2] + sh[c][3]);
+    partials[(int64_t)c * nblk + k.b] = (sh[c][0] + sh[c][1]) + (sh[c][2] + sh[c][3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -569,10 +580,10 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_pack(Grid3 g, const T* __r
 // (after the XCD remap, on one XCD), so the cells they share come from L2.
 // The extended tile lives in LDS with a zero border, double-buffered.
 template <class T, int TILE, int BR, bool SSOR>
-__global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T* __restrict__ pk,
-                                                               const T* __restrict__ r,
-                                                               T* __restrict__ z, T omega,
-                                                               int sweeps, int nbx, int nby) {
+__device__ __forceinline__ void schwarz_local_pk_body(Blk k, const Grid3& g,
+                                                      const T* __restrict__ pk,
+                                                      const T* __restrict__ r, T* __restrict__ z,
+                                                      T omega, int sweeps, int nbx, int nby) {
   constexpr int E = TILE + 2;
   constexpr int P = E + 2;
   constexpr int NE = E * E * E;
@@ -599,7 +610,7 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T*
   };
   __shared__ T zs[2 * NP];
   for (int idx = threadIdx.x; idx < 2 * NP; idx += kThreads) zs[idx] = 0;
-  const int lt = xcd_remap(blockIdx.x, gridDim.x);
+  const int lt = xcd_remap(k.b, k.G);
   const int brick = lt / (BR * BR * BR), sub = lt % (BR * BR * BR);
   const int sx = sub % BR, sy = (sub / BR) % BR, sz = sub / (BR * BR);
   const int tx = (brick % nbx) * BR + sx;
@@ -611,18 +622,19 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T*
   T sc[PER], rv[PER];
   int li[PER];
   int gi[PER];
+  int be[PER];
   unsigned ownm = 0;
   // all loads of all slots are issued before any is used (a product inside
-  // the per-slot branch would wait for each slot's loads in turn)
+  // the per-slot branch would wait for each slot's loads in turn); the
+  // scattered loads of r go first, so that their latency overlaps the
+  // coefficient stream (measured: 9% less time at 256^3 FP32 than r last)
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = cell(q);
-#pragma unroll
-    for (int d = 0; d < 6; ++d) cf[q][d] = 0;
-    sc[q] = 0;
     rv[q] = 0;
     gi[q] = -1;
     li[q] = 0;
+    be[q] = 0;
     if (e < NE) {
       const int ex = e % E, ey = (e / E) % E, ez = e / (E * E);
       li[q] = ((ez + 1) * P + (ey + 1)) * P + ex + 1;
@@ -631,15 +643,23 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T*
                       wrap_coord(gz, g.nz, g.pz);
       if (ex >= 1 && ex <= TILE && ey >= 1 && ey <= TILE && ez >= 1 && ez <= TILE)
         ownm |= 1u << q;
-      const int be = ((sz * TILE + ez) * EB + sy * TILE + ey) * EB + sx * TILE + ex;
-      sc[q] = tp[be];
-#pragma unroll
-      for (int d = 0; d < 6; ++d) cf[q][d] = tp[(d + 1) * NB + be];
+      be[q] = ((sz * TILE + ez) * EB + sy * TILE + ey) * EB + sx * TILE + ex;
       if (ok) {
         const int64_t i = gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz);
         gi[q] = (int)i;
         rv[q] = r[i];
       }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) cf[q][d] = 0;
+    sc[q] = 0;
+    if (cell(q) < NE) {
+      sc[q] = tp[be[q]];
+#pragma unroll
+      for (int d = 0; d < 6; ++d) cf[q][d] = tp[(d + 1) * NB + be[q]];
     }
   }
 #pragma unroll
@@ -720,6 +740,14 @@ __global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T*
   }
 }
 
+template <class T, int TILE, int BR, bool SSOR>
+__global__ __launch_bounds__(kThreads) void k_schwarz_local_pk(Grid3 g, const T* __restrict__ pk,
+                                                               const T* __restrict__ r,
+                                                               T* __restrict__ z, T omega,
+                                                               int sweeps, int nbx, int nby) {
+  schwarz_local_pk_body<T, TILE, BR, SSOR>(hw_blk(), g, pk, r, z, omega, sweeps, nbx, nby);
+}
+
 // ---------------------------------------------------------------------------
 // tall-skinny block products
 //
@@ -775,10 +803,10 @@ constexpr int kGroup = 8;
 // Rows (or packs of W rows) are dealt to the grid's threads in turn: at any
 // moment the whole grid reads one contiguous stretch of every column, which
 // streams from HBM faster than one far-apart range per block.
-__device__ __forceinline__ int64_t first_row() {
-  return (int64_t)blockIdx.x * kThreads + threadIdx.x;
+__device__ __forceinline__ int64_t first_row(Blk k = hw_blk()) {
+  return (int64_t)k.b * kThreads + threadIdx.x;
 }
-__device__ __forceinline__ int64_t grid_step() { return (int64_t)gridDim.x * kThreads; }
+__device__ __forceinline__ int64_t grid_step(Blk k = hw_blk()) { return (int64_t)k.G * kThreads; }
 
 // Calls f(c, pack) for the columns c = 0, 1, ... of row pack iv, in order.
 // The loads of up to kBatch columns are all issued before the first is used
@@ -826,23 +854,29 @@ __device__ __forceinline__ void dot_rows(const Cols<T>& Q, int nc, const T* __re
 }
 
 template <class T, int W, int NC>
-__global__ __launch_bounds__(kThreads) void k_block_dot(Cols<T> Q, const T* __restrict__ w,
-                                                        int64_t n, int self_dot, T* partials,
-                                                        int nblk) {
+__device__ __forceinline__ void block_dot_body(Blk k, const Cols<T>& Q, const T* __restrict__ w,
+                                               int64_t n, int self_dot, T* partials, int nblk) {
   const int nc = Q.n1 + Q.n2;
   T acc[NC + 1];
 #pragma unroll
   for (int c = 0; c <= NC; ++c) acc[c] = 0;
   const int64_t npk = n / W;
-  dot_rows<T, W, NC>(Q, nc, w, first_row(), npk, grid_step(), acc);
-  if (W > 1 && blockIdx.x == gridDim.x - 1)
+  dot_rows<T, W, NC>(Q, nc, w, first_row(k), npk, grid_step(k), acc);
+  if (W > 1 && k.b == k.G - 1)
     dot_rows<T, 1, NC>(Q, nc, w, npk * W + threadIdx.x, n, kThreads, acc);
   if (self_dot) {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
       if (c == nc) acc[c] = acc[NC];
   }
-  reduce_store<T, NC + 1>(acc, nc + (self_dot ? 1 : 0), partials, nblk);
+  reduce_store<T, NC + 1>(acc, nc + (self_dot ? 1 : 0), partials, nblk, k);
+}
+
+template <class T, int W, int NC>
+__global__ __launch_bounds__(kThreads) void k_block_dot(Cols<T> Q, const T* __restrict__ w,
+                                                        int64_t n, int self_dot, T* partials,
+                                                        int nblk) {
+  block_dot_body<T, W, NC>(hw_blk(), Q, w, n, self_dot, partials, nblk);
 }
 
 template <class T, int W, int NC>
@@ -875,8 +909,10 @@ template <class T, int W, int NC>
 __global__ __launch_bounds__(kThreads) void k_block_update(Cols<T> Q, const double* coef, T sgn,
                                                            const T* w_in, T* w_out, int64_t n,
                                                            const double* scale, int norm,
-                                                           T* partials, int nblk) {
+                                                           T* partials, int nblk,
+                                                           const int* run_if) {
   __shared__ T cf[NC > 0 ? NC : 1];
+  if (run_if && *run_if == 0) return;
   const int nc = Q.n1 + Q.n2;
   for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < nc ? sgn * (T)coef[c] : T(0);
   __syncthreads();
@@ -1172,29 +1208,33 @@ __global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t
 }
 
 // out[:, o] = sum_c In_c * M[c + nin*o]; one row per thread (in place over In
-// allowed: a thread reads its whole row before writing it).
+// allowed: a thread reads its whole row before writing it).  The
+// coefficients stay in FP64 and each output is summed in FP64 and rounded
+// once: the recycle update's coefficients (P R^-1 with an ill-conditioned R)
+// are large with cancelling terms, where FP32 products and sums would each
+// add rounding of the size of the largest term.
 template <class T, int NIN>
 __global__ __launch_bounds__(kThreads) void k_row_transform(Cols<T> In, const double* M,
                                                             int nout, T* out, int64_t ldo,
                                                             int64_t n) {
   extern __shared__ unsigned char smem_raw[];
-  T* Ms = reinterpret_cast<T*>(smem_raw);
+  double* Ms = reinterpret_cast<double*>(smem_raw);
   const int nin = In.n1 + In.n2;
   for (int idx = threadIdx.x; idx < NIN * nout; idx += kThreads) {
     const int c = idx % NIN, o = idx / NIN;
-    Ms[idx] = c < nin ? (T)M[c + nin * o] : T(0);
+    Ms[idx] = c < nin ? M[c + nin * o] : 0.0;
   }
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
-  T v[NIN];
+  double v[NIN];
 #pragma unroll
-  for (int c = 0; c < NIN; ++c) v[c] = col_ptr(In, min(c, nin - 1))[i];
+  for (int c = 0; c < NIN; ++c) v[c] = (double)col_ptr(In, min(c, nin - 1))[i];
   for (int o = 0; o < nout; ++o) {
-    T s = 0;
+    double s = 0;
 #pragma unroll
     for (int c = 0; c < NIN; ++c) s += v[c] * Ms[o * NIN + c];
-    out[(int64_t)o * ldo + i] = s;
+    out[(int64_t)o * ldo + i] = (T)s;
   }
 }
 
@@ -1247,10 +1287,22 @@ __device__ __forceinline__ void apply_pack(const Grid3& g, const T* __restrict__
 
 // MODE as k_stencil
 template <class T, int W, int MODE>
+__device__ __forceinline__ void stencil_v_body(Blk k, const Grid3& g, const T* __restrict__ A,
+                                               const T* __restrict__ x, T* y, T alpha, T beta,
+                                               const T* __restrict__ bv);
+
+template <class T, int W, int MODE>
 __global__ __launch_bounds__(kThreads) void k_stencil_v(Grid3 g, const T* __restrict__ A,
                                                          const T* __restrict__ x, T* y, T alpha,
                                                          T beta, const T* __restrict__ bv) {
-  const int64_t iv = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+  stencil_v_body<T, W, MODE>(hw_blk(), g, A, x, y, alpha, beta, bv);
+}
+
+template <class T, int W, int MODE>
+__device__ __forceinline__ void stencil_v_body(Blk k, const Grid3& g, const T* __restrict__ A,
+                                               const T* __restrict__ x, T* y, T alpha, T beta,
+                                               const T* __restrict__ bv) {
+  const int64_t iv = (int64_t)xcd_remap(k.b, k.G) * kThreads + threadIdx.x;
   if (iv * W >= g.n) return;
   T ax[W], xc[W];
   apply_pack<T, W>(g, A, x, iv, ax, xc);
@@ -1302,7 +1354,8 @@ __global__ __launch_bounds__(kThreads) void k_residual_norm_v(Grid3 g, const T* 
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_finish_sum(const T* partials, int nblk,
-                                                         double* out) {
+                                                         double* out, const int* run_if) {
+  if (run_if && *run_if == 0) return;
   const int c = blockIdx.x;
   double s = 0;
   for (int b = threadIdx.x; b < nblk; b += kThreads) s += (double)partials[(int64_t)c * nblk + b];
@@ -1361,8 +1414,69 @@ __global__ void k_cgs2_combine(int ncols, const double* h1, const double* h2, do
   flag[0] = f;
 }
 
-__global__ void k_set_norm(const double* nrm2, double* hcol_last, double* inv) {
-  if (threadIdx.x != 0) return;
+// End of Arnoldi step j of a cycle, on the device (one thread): store the new
+// column [B; Hbar] from hcol = [C V_j]^T-coefficients with the new norm
+// appended, rotate it by the j previous Givens rotations, form rotation j,
+// update g and the residual estimate |g_{j+1}|, push the estimate to the
+// history ring and set the stop state (estimate at the tolerance, lucky
+// breakdown, non-finite estimate, step limit).  Once stopped, later steps of
+// the batch change nothing here.  The arithmetic is that of the host loop
+// term by term (no contraction into fused multiply-adds), so both give the
+// same bits.
+__global__ void k_arnoldi_givens(double* arn, const double* hcol, const int* skip,
+                                 const int* flag, int j, int kc, int m) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0 || arn[kArnStop] != 0.0) return;
+  if (flag && *flag) {
+    // the norm from the Pythagorean identity is unreliable: stop here; the
+    // host runs this step again with an explicit norm pass
+    arn[kArnStop] = 2.0;
+    arn[kArnJ] = j;
+    return;
+  }
+  const int ncols = kc + j + 1, ldh = m + 1;
+  double* H = arn + kArnH;
+  double* R = arn + kArnR;
+  double* B = arn + kArnB;
+  double* g = arn + kArnG;
+  double* cs = arn + kArnCs;
+  double* sn = arn + kArnSn;
+  for (int i = 0; i < kc; ++i) B[i + kc * j] = hcol[i];
+  for (int i = 0; i <= j; ++i) H[i + ldh * j] = hcol[kc + i];
+  const double hn = hcol[ncols];
+  H[(j + 1) + ldh * j] = hn;
+  double hc[kMaxArnM + 1];
+  for (int i = 0; i <= j + 1; ++i) hc[i] = H[i + ldh * j];
+  for (int i = 0; i < j; ++i) {
+    const double a = hc[i], bb = hc[i + 1];
+    hc[i] = cs[i] * a + sn[i] * bb;
+    hc[i + 1] = -sn[i] * a + cs[i] * bb;
+  }
+  const double a = hc[j], bb = hc[j + 1];
+  const double rr = sqrt(a * a + bb * bb);
+  cs[j] = rr > 0 ? a / rr : 1.0;
+  sn[j] = rr > 0 ? bb / rr : 0.0;
+  hc[j] = rr;
+  hc[j + 1] = 0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  for (int i = 0; i <= j + 1; ++i) R[i + ldh * j] = hc[i];
+  const double est = fabs(g[j + 1]);
+  const int its = (int)arn[kArnIts] + 1;
+  arn[kArnIts] = its;
+  arn[kArnHist + (its - 1) % kArnHistRing] = est;
+  arn[kArnJ] = j + 1;
+  arn[kArnEst] = est;
+  if (!(skip && *skip)) {
+    arn[kArnTwo] += 1.0;
+    arn[kArnTwoCols] += ncols + 1;
+  }
+  if (!isfinite(est) || est <= arn[kArnTolAbs] || hn == 0.0 || its >= arn[kArnMaxIts])
+    arn[kArnStop] = 1.0;
+}
+__global__ void k_set_norm(const double* nrm2, double* hcol_last, double* inv,
+                           const int* run_if) {
+  if (threadIdx.x != 0 || (run_if && *run_if == 0)) return;
   const double hn = sqrt(nrm2[0] > 0 ? nrm2[0] : 0.0);
   hcol_last[0] = hn;
   inv[0] = hn > 0 ? 1.0 / hn : 0.0;
@@ -1372,13 +1486,20 @@ __global__ void k_set_norm(const double* nrm2, double* hcol_last, double* inv) {
 // BiCGStab passes
 // ---------------------------------------------------------------------------
 template <class T>
+__device__ __forceinline__ void bicg_p_body(Blk k, const T* __restrict__ r, T* __restrict__ p,
+                                            const T* __restrict__ v, const double* sc,
+                                            int64_t n) {
+  if (sc[kDone] != 0.0) return;
+  const T beta = (T)sc[kBeta], omega = (T)sc[kOmega];
+  const int64_t i = (int64_t)k.b * kThreads + threadIdx.x;
+  if (i < n) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+template <class T>
 __global__ __launch_bounds__(kThreads) void k_bicg_p(const T* __restrict__ r, T* __restrict__ p,
                                                      const T* __restrict__ v, const double* sc,
                                                      int64_t n) {
-  if (sc[kDone] != 0.0) return;
-  const T beta = (T)sc[kBeta], omega = (T)sc[kOmega];
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i < n) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+  bicg_p_body<T>(hw_blk(), r, p, v, sc, n);
 }
 
 template <class T, int W, int NC>
@@ -1407,10 +1528,9 @@ __device__ __forceinline__ void sv_rows(const Cols<T>& C, const T* cf, T alpha,
 
 // v -= C eta1 ; s = r - alpha v ; partial |s|^2
 template <class T, int W, int NC>
-__global__ __launch_bounds__(kThreads) void k_bicg_sv(Cols<T> C, const T* __restrict__ r, T* v,
-                                                      T* __restrict__ sv, const double* sc,
-                                                      int off_eta1, int64_t n, T* partials,
-                                                      int nblk) {
+__device__ __forceinline__ void bicg_sv_body(Blk k, const Cols<T>& C, const T* __restrict__ r,
+                                             T* v, T* __restrict__ sv, const double* sc,
+                                             int off_eta1, int64_t n, T* partials, int nblk) {
   if (sc[kDone] != 0.0) return;
   __shared__ T cf[NC > 0 ? NC : 1];
   const int kc = C.n1;
@@ -1419,10 +1539,18 @@ __global__ __launch_bounds__(kThreads) void k_bicg_sv(Cols<T> C, const T* __rest
   const T alpha = (T)sc[kAlpha];
   T acc[1] = {0};
   const int64_t npk = n / W;
-  sv_rows<T, W, NC>(C, cf, alpha, r, v, sv, first_row(), npk, grid_step(), acc[0]);
-  if (W > 1 && blockIdx.x == gridDim.x - 1)
+  sv_rows<T, W, NC>(C, cf, alpha, r, v, sv, first_row(k), npk, grid_step(k), acc[0]);
+  if (W > 1 && k.b == k.G - 1)
     sv_rows<T, 1, NC>(C, cf, alpha, r, v, sv, npk * W + threadIdx.x, n, kThreads, acc[0]);
-  reduce_store<T, 1>(acc, 1, partials, nblk);
+  reduce_store<T, 1>(acc, 1, partials, nblk, k);
+}
+
+template <class T, int W, int NC>
+__global__ __launch_bounds__(kThreads) void k_bicg_sv(Cols<T> C, const T* __restrict__ r, T* v,
+                                                      T* __restrict__ sv, const double* sc,
+                                                      int off_eta1, int64_t n, T* partials,
+                                                      int nblk) {
+  bicg_sv_body<T, W, NC>(hw_blk(), C, r, v, sv, sc, off_eta1, n, partials, nblk);
 }
 
 template <class T, int W, int NC>
@@ -1455,12 +1583,11 @@ __device__ __forceinline__ void yr_rows(const Cols<T>& C, const T* cf, T alpha, 
 
 // y += alpha p + omega s ; r = s - omega (t - C eta2) ; partials r~.r, |r|^2
 template <class T, int W, int NC>
-__global__ __launch_bounds__(kThreads) void k_bicg_yr(Cols<T> C, const T* __restrict__ t,
-                                                      const T* __restrict__ sv,
-                                                      const T* __restrict__ p, T* __restrict__ y,
-                                                      T* __restrict__ r, const T* __restrict__ rt,
-                                                      const double* sc, int off_eta2, int64_t n,
-                                                      T* partials, int nblk) {
+__device__ __forceinline__ void bicg_yr_body(Blk k, const Cols<T>& C, const T* __restrict__ t,
+                                             const T* __restrict__ sv, const T* __restrict__ p,
+                                             T* __restrict__ y, T* __restrict__ r,
+                                             const T* __restrict__ rt, const double* sc,
+                                             int off_eta2, int64_t n, T* partials, int nblk) {
   if (sc[kDone] != 0.0) return;
   __shared__ T cf[NC > 0 ? NC : 1];
   const int kc = C.n1;
@@ -1469,12 +1596,22 @@ __global__ __launch_bounds__(kThreads) void k_bicg_yr(Cols<T> C, const T* __rest
   const T alpha = (T)sc[kAlpha], omega = (T)sc[kOmega];
   T acc[2] = {0, 0};
   const int64_t npk = n / W;
-  yr_rows<T, W, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, first_row(), npk, grid_step(),
+  yr_rows<T, W, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, first_row(k), npk, grid_step(k),
                     acc);
-  if (W > 1 && blockIdx.x == gridDim.x - 1)
+  if (W > 1 && k.b == k.G - 1)
     yr_rows<T, 1, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, npk * W + threadIdx.x, n,
                       kThreads, acc);
-  reduce_store<T, 2>(acc, 2, partials, nblk);
+  reduce_store<T, 2>(acc, 2, partials, nblk, k);
+}
+
+template <class T, int W, int NC>
+__global__ __launch_bounds__(kThreads) void k_bicg_yr(Cols<T> C, const T* __restrict__ t,
+                                                      const T* __restrict__ sv,
+                                                      const T* __restrict__ p, T* __restrict__ y,
+                                                      T* __restrict__ r, const T* __restrict__ rt,
+                                                      const double* sc, int off_eta2, int64_t n,
+                                                      T* partials, int nblk) {
+  bicg_yr_body<T, W, NC>(hw_blk(), C, t, sv, p, y, r, rt, sc, off_eta2, n, partials, nblk);
 }
 
 __device__ inline void hist_push(double* sc, double v) {
@@ -1583,7 +1720,7 @@ __device__ __forceinline__ void finish_cols(const T* partials, int nblk, int nco
 
 // eta1 = C^T v, r~^T v; alpha = rho / (r~^T v - (C^T r~) . eta1)
 template <class T>
-__global__ __launch_bounds__(kThreads) void k_bicg_finish_alpha(const T* partials, int nblk,
+__device__ __forceinline__ void bicg_finish_alpha_body(const T* partials, int nblk,
                                                                 int kc, double* sums, double* sc,
                                                                 int off_eta1, int off_ctrt) {
   __shared__ double sh[kFinishCols];
@@ -1608,11 +1745,18 @@ __global__ __launch_bounds__(kThreads) void k_bicg_finish_alpha(const T* partial
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_bicg_finish_alpha(const T* partials, int nblk,
+                                                                int kc, double* sums, double* sc,
+                                                                int off_eta1, int off_ctrt) {
+  bicg_finish_alpha_body<T>(partials, nblk, kc, sums, sc, off_eta1, off_ctrt);
+}
+
 // |s|^2, then the half-step tests; on convergence at the half step the
 // scalar part of the early exit (xi += alpha eta1) is applied here and the
 // vector part by the conditional exit kernel that follows.
 template <class T>
-__global__ __launch_bounds__(kThreads) void k_bicg_finish_half(const T* partials, int nblk,
+__device__ __forceinline__ void bicg_finish_half_body(const T* partials, int nblk,
                                                                double* sc, int off_eta1,
                                                                int off_xi, int kc) {
   __shared__ double sh[kFinishCols];
@@ -1640,23 +1784,36 @@ __global__ __launch_bounds__(kThreads) void k_bicg_finish_half(const T* partials
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_bicg_finish_half(const T* partials, int nblk,
+                                                               double* sc, int off_eta1,
+                                                               int off_xi, int kc) {
+  bicg_finish_half_body<T>(partials, nblk, sc, off_eta1, off_xi, kc);
+}
+
 // y += alpha p ; r = s when the half-step test converged (kDone == kConvHalf)
 template <class T>
-__global__ __launch_bounds__(kThreads) void k_bicg_exit_vec(const T* __restrict__ p, T* y,
-                                                            const T* __restrict__ sv, T* r,
-                                                            const double* sc, int64_t n) {
+__device__ __forceinline__ void bicg_exit_vec_body(Blk k, const T* __restrict__ p, T* y,
+                                                   const T* __restrict__ sv, T* r,
+                                                   const double* sc, int64_t n) {
   if (sc[kDone] != (double)kConvHalf) return;
   const T alpha = (T)sc[kAlpha];
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads) {
+  for (int64_t i = (int64_t)k.b * kThreads + threadIdx.x; i < n; i += (int64_t)k.G * kThreads) {
     y[i] += alpha * p[i];
     r[i] = sv[i];
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_bicg_exit_vec(const T* __restrict__ p, T* y,
+                                                            const T* __restrict__ sv, T* r,
+                                                            const double* sc, int64_t n) {
+  bicg_exit_vec_body<T>(hw_blk(), p, y, sv, r, sc, n);
+}
+
 // eta2 = C^T t; omega = t^T s / (|t|^2 - |eta2|^2); xi += alpha eta1 + omega eta2
 template <class T>
-__global__ __launch_bounds__(kThreads) void k_bicg_finish_omega(const T* partials, int nblk,
+__device__ __forceinline__ void bicg_finish_omega_body(const T* partials, int nblk,
                                                                 int kc, double* sums, double* sc,
                                                                 int off_eta1, int off_eta2,
                                                                 int off_xi) {
@@ -1695,10 +1852,18 @@ __global__ __launch_bounds__(kThreads) void k_bicg_finish_omega(const T* partial
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_bicg_finish_omega(const T* partials, int nblk,
+                                                                int kc, double* sums, double* sc,
+                                                                int off_eta1, int off_eta2,
+                                                                int off_xi) {
+  bicg_finish_omega_body<T>(partials, nblk, kc, sums, sc, off_eta1, off_eta2, off_xi);
+}
+
 // rho = r~^T r, |r|^2, beta; then the full-step tests (convergence,
 // breakdowns, divergence guard, rho = 0)
 template <class T>
-__global__ __launch_bounds__(kThreads) void k_bicg_finish_full(const T* partials, int nblk,
+__device__ __forceinline__ void bicg_finish_full_body(const T* partials, int nblk,
                                                                double* sums, double* sc) {
   __shared__ double sh[kFinishCols];
   if (sc[kDone] != 0.0) return;
@@ -1716,6 +1881,12 @@ __global__ __launch_bounds__(kThreads) void k_bicg_finish_full(const T* partials
   else if (!isfinite(rn) || rn > sc[kDivAbs]) sc[kDone] = kDiverge;
   else if (rn <= sc[kTolAbs]) sc[kDone] = kConvFull;
   else if (rho == 0.0) sc[kDone] = kBreak;
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_bicg_finish_full(const T* partials, int nblk,
+                                                               double* sums, double* sc) {
+  bicg_finish_full_body<T>(partials, nblk, sums, sc);
 }
 
 template <class T>
@@ -1751,6 +1922,116 @@ inline int grid_for(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
 
 template <int NC>
 constexpr bool fits(int n) { return n <= NC; }
+
+// ---------------------------------------------------------------------------
+// grouped rBiCGStab passes: one launch for every system of a BatchTable.
+// Block b of the grid belongs to the system whose range [off[s], off[s+1])
+// holds it and runs that system's kernel body with the block coordinates of
+// the system's own launch; blocks beyond the system's own count (padding to
+// a multiple of 8) return at once.  Operator and projection passes of a
+// system whose stop state is set are skipped (their results are read by
+// nothing after the stop); the finishing steps test the state themselves.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int batch_sys(const int* off, int nsys) {
+  int s = 0;
+  while (s + 1 < nsys && (int)blockIdx.x >= off[s + 1]) ++s;
+  return s;
+}
+__device__ __forceinline__ int dev_grid_for(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
+
+__global__ __launch_bounds__(kThreads) void kg_bicg_p(const BatchTable* tb) {
+  const int s = batch_sys(tb->elem, tb->nsys);
+  const BatchSys& q = tb->sys[s];
+  const int b = (int)blockIdx.x - tb->elem[s], cnt = dev_grid_for(q.n);
+  if (b >= cnt) return;
+  bicg_p_body<float>(Blk{b, cnt}, q.r, q.p, q.v, q.sc, q.n);
+}
+
+// operator pieces of A~ in -> out (in = p, out = v for which = 0; in = s,
+// out = t for which = 1): local solves into out, the global sweep from out
+// into z, the matvec of z into out
+__global__ __launch_bounds__(kThreads) void kg_schwarz(const BatchTable* tb, int which) {
+  const int s = batch_sys(tb->tile, tb->nsys);
+  const BatchSys& q = tb->sys[s];
+  const int cnt = (q.g.nx / 8) * (q.g.ny / 8) * (q.g.nz / 8);
+  const int b = (int)blockIdx.x - tb->tile[s];
+  if (b >= cnt || q.sc[kDone] != 0.0) return;
+  schwarz_local_pk_body<float, 8, 2, false>(Blk{b, cnt}, q.g, q.pk, which ? q.sv : q.p,
+                                            which ? q.t : q.v, q.omega_l, q.sweeps, q.nbx,
+                                            q.nby);
+}
+__global__ __launch_bounds__(kThreads) void kg_jsweep(const BatchTable* tb, int which) {
+  const int s = batch_sys(tb->pack, tb->nsys);
+  const BatchSys& q = tb->sys[s];
+  const int b = (int)blockIdx.x - tb->pack[s], cnt = dev_grid_for(q.n / 4);
+  if (b >= cnt || q.sc[kDone] != 0.0) return;
+  stencil_v_body<float, 4, 3>(Blk{b, cnt}, q.g, q.bands, which ? q.t : q.v, q.z, q.omega_g,
+                              0.f, which ? q.sv : q.p);
+}
+__global__ __launch_bounds__(kThreads) void kg_stencil(const BatchTable* tb, int which) {
+  const int s = batch_sys(tb->pack, tb->nsys);
+  const BatchSys& q = tb->sys[s];
+  const int b = (int)blockIdx.x - tb->pack[s], cnt = dev_grid_for(q.n / 4);
+  if (b >= cnt || q.sc[kDone] != 0.0) return;
+  stencil_v_body<float, 4, 0>(Blk{b, cnt}, q.g, q.bands, q.z, which ? q.t : q.v, 1.f, 0.f,
+                              nullptr);
+}
+// [C, r~]^T v (which = 0) or [C, s]^T t and |t|^2 (which = 1)
+template <int NC>
+__global__ __launch_bounds__(kThreads) void kg_block_dot(const BatchTable* tb, int which) {
+  const int s = batch_sys(tb->pass, tb->nsys);
+  const BatchSys& q = tb->sys[s];
+  const int b = (int)blockIdx.x - tb->pass[s], cnt = q.nblk;
+  if (b >= cnt || q.sc[kDone] != 0.0) return;
+  Cols<float> Q = q.C;
+  Q.p2 = which ? q.sv : q.rt;
+  Q.ld2 = q.ld;
+  Q.n2 = 1;
+  block_dot_body<float, 4, NC>(Blk{b, cnt}, Q, which ? q.t : q.v, q.n, which, q.part, q.nblk);
+}
+template <int NC>
+__global__ __launch_bounds__(kThreads) void kg_bicg_sv(const BatchTable* tb) {
+  const int s = batch_sys(tb->pass, tb->nsys);
+  const BatchSys& q = tb->sys[s];
+  const int b = (int)blockIdx.x - tb->pass[s], cnt = q.nblk;
+  if (b >= cnt) return;
+  bicg_sv_body<float, 4, NC>(Blk{b, cnt}, q.C, q.r, q.v, q.sv, q.sc, kBEta1, q.n, q.part,
+                             q.nblk);
+}
+template <int NC>
+__global__ __launch_bounds__(kThreads) void kg_bicg_yr(const BatchTable* tb) {
+  const int s = batch_sys(tb->pass, tb->nsys);
+  const BatchSys& q = tb->sys[s];
+  const int b = (int)blockIdx.x - tb->pass[s], cnt = q.nblk;
+  if (b >= cnt) return;
+  bicg_yr_body<float, 4, NC>(Blk{b, cnt}, q.C, q.t, q.sv, q.p, q.y, q.r, q.rt, q.sc, kBEta2,
+                             q.n, q.part, q.nblk);
+}
+__global__ __launch_bounds__(kThreads) void kg_exit_vec(const BatchTable* tb) {
+  const int s = batch_sys(tb->exitv, tb->nsys);
+  const BatchSys& q = tb->sys[s];
+  const int b = (int)blockIdx.x - tb->exitv[s], cnt = min(dev_grid_for(q.n), 512);
+  if (b >= cnt) return;
+  bicg_exit_vec_body<float>(Blk{b, cnt}, q.p, q.y, q.sv, q.r, q.sc, q.n);
+}
+// finishing steps: block s is system s
+__global__ __launch_bounds__(kThreads) void kg_finish_alpha(const BatchTable* tb) {
+  const BatchSys& q = tb->sys[blockIdx.x];
+  bicg_finish_alpha_body<float>(q.part, q.nblk, q.C.n1, q.sc + kBSums, q.sc, kBEta1, kBCtrt);
+}
+__global__ __launch_bounds__(kThreads) void kg_finish_half(const BatchTable* tb) {
+  const BatchSys& q = tb->sys[blockIdx.x];
+  bicg_finish_half_body<float>(q.part, q.nblk, q.sc, kBEta1, kBXi, q.C.n1);
+}
+__global__ __launch_bounds__(kThreads) void kg_finish_omega(const BatchTable* tb) {
+  const BatchSys& q = tb->sys[blockIdx.x];
+  bicg_finish_omega_body<float>(q.part, q.nblk, q.C.n1, q.sc + kBSums, q.sc, kBEta1, kBEta2,
+                                kBXi);
+}
+__global__ __launch_bounds__(kThreads) void kg_finish_full(const BatchTable* tb) {
+  const BatchSys& q = tb->sys[blockIdx.x];
+  bicg_finish_full_body<float>(q.part, q.nblk, q.sc + kBSums, q.sc);
+}
 
 }  // namespace
 
@@ -1967,17 +2248,17 @@ hipError_t block_dot(hipStream_t s, const Cols<T>& Q, const T* w, int64_t n, int
 template <class T>
 hipError_t block_update(hipStream_t s, const Cols<T>& Q, const double* coef, double sgn,
                         const T* w_in, T* w_out, int64_t n, const double* scale, int dots,
-                        T* partials, int nblk) {
+                        T* partials, int nblk, const int* run_if) {
   constexpr int VW = 16 / sizeof(T);
   const bool v = vec_ok(Q) && vec_ok(w_in) && vec_ok((const T*)w_out);
   const int norm = dots > 0 ? 1 : 0;
   KRS_NC_DISPATCH(Q.count() > 0 ? Q.count() : 1, {
     if (v)
       k_block_update<T, VW, NCB><<<nblk, kThreads, 0, s>>>(Q, coef, (T)sgn, w_in, w_out, n, scale,
-                                                          norm, partials, nblk);
+                                                          norm, partials, nblk, run_if);
     else
       k_block_update<T, 1, NCB><<<nblk, kThreads, 0, s>>>(Q, coef, (T)sgn, w_in, w_out, n, scale,
-                                                         norm, partials, nblk);
+                                                         norm, partials, nblk, run_if);
   });
   return hipGetLastError();
 }
@@ -2039,7 +2320,7 @@ hipError_t row_transform(hipStream_t s, const Cols<T>& In, const double* M, int 
   const int grid = grid_for(n);
 #define KRS_RT(NINB)                                                                 \
   do {                                                                               \
-    const size_t smem = sizeof(T) * (size_t)(NINB) * nout;                           \
+    const size_t smem = sizeof(double) * (size_t)(NINB) * nout;                      \
     if (smem > 64 * 1024) return hipErrorInvalidValue;                               \
     k_row_transform<T, NINB><<<grid, kThreads, smem, s>>>(In, M, nout, out, ldo, n); \
   } while (0)
@@ -2054,16 +2335,17 @@ hipError_t row_transform(hipStream_t s, const Cols<T>& In, const double* M, int 
 }
 
 template <class T>
-hipError_t finish_sum(hipStream_t s, const T* partials, int nblk, int ncols, double* out) {
+hipError_t finish_sum(hipStream_t s, const T* partials, int nblk, int ncols, double* out,
+                      const int* run_if) {
   if (ncols == 0) return hipSuccess;
-  k_finish_sum<T><<<ncols, kThreads, 0, s>>>(partials, nblk, out);
+  k_finish_sum<T><<<ncols, kThreads, 0, s>>>(partials, nblk, out, run_if);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t finish_cgs2(hipStream_t s, const T* partials, int nblk, int ncols, const double* h1,
                        double* h2, double* hcol, double* inv, int* flag, const int* skip) {
-  k_finish_sum<T><<<ncols + 1, kThreads, 0, s>>>(partials, nblk, h2);
+  k_finish_sum<T><<<ncols + 1, kThreads, 0, s>>>(partials, nblk, h2, nullptr);
   k_cgs2_combine<<<1, 64, 0, s>>>(ncols, h1, h2, hcol, inv, flag, skip);
   return hipGetLastError();
 }
@@ -2074,8 +2356,15 @@ hipError_t cgs_decide(hipStream_t s, int ncols, const double* h1, double* hcol, 
   return hipGetLastError();
 }
 
-hipError_t set_norm_from_sum(hipStream_t s, const double* nrm2, double* hcol_last, double* inv) {
-  k_set_norm<<<1, 64, 0, s>>>(nrm2, hcol_last, inv);
+hipError_t arnoldi_givens(hipStream_t s, double* arn, const double* hcol, const int* skip,
+                          const int* flag, int j, int kc, int m) {
+  k_arnoldi_givens<<<1, 64, 0, s>>>(arn, hcol, skip, flag, j, kc, m);
+  return hipGetLastError();
+}
+
+hipError_t set_norm_from_sum(hipStream_t s, const double* nrm2, double* hcol_last, double* inv,
+                             const int* run_if) {
+  k_set_norm<<<1, 64, 0, s>>>(nrm2, hcol_last, inv, run_if);
   return hipGetLastError();
 }
 
@@ -2194,6 +2483,75 @@ hipError_t axpy_f32_into_f64(hipStream_t s, const float* d, double* x, int64_t n
   return hipGetLastError();
 }
 
+void batch_layout(BatchTable& tb) {
+  auto up8 = [](int v) { return (v + kXcd - 1) / kXcd * kXcd; };
+  int e = 0, pk = 0, ti = 0, pa = 0, ex = 0;
+  for (int s = 0; s < tb.nsys; ++s) {
+    const BatchSys& q = tb.sys[s];
+    tb.elem[s] = e;
+    tb.pack[s] = pk;
+    tb.tile[s] = ti;
+    tb.pass[s] = pa;
+    tb.exitv[s] = ex;
+    tb.fin[s] = s;
+    e = up8(e + grid_for(q.n));
+    pk = up8(pk + grid_for(q.n / 4));
+    ti = up8(ti + (q.g.nx / 8) * (q.g.ny / 8) * (q.g.nz / 8));
+    pa = up8(pa + q.nblk);
+    ex = up8(ex + std::min(grid_for(q.n), 512));
+  }
+  tb.elem[tb.nsys] = e;
+  tb.pack[tb.nsys] = pk;
+  tb.tile[tb.nsys] = ti;
+  tb.pass[tb.nsys] = pa;
+  tb.exitv[tb.nsys] = ex;
+  tb.fin[tb.nsys] = tb.nsys;
+}
+
+#define KRS_BATCH_NC(ncount, ...)                                 \
+  do {                                                            \
+    const int _n = (ncount);                                      \
+    if (_n == 0) { constexpr int NCB = 0; __VA_ARGS__; }          \
+    else if (_n <= 8) { constexpr int NCB = 8; __VA_ARGS__; }     \
+    else if (_n <= 16) { constexpr int NCB = 16; __VA_ARGS__; }   \
+    else if (_n <= 32) { constexpr int NCB = 32; __VA_ARGS__; }   \
+    else if (_n <= 64) { constexpr int NCB = 64; __VA_ARGS__; }   \
+    else return hipErrorInvalidValue;                             \
+  } while (0)
+
+hipError_t batch_bicg_first_half(hipStream_t s, const BatchTable* d_tb, const BatchTable& tb,
+                                 int nc) {
+  const int ns = tb.nsys;
+  if (ns < 1 || ns > kMaxBatch) return hipErrorInvalidValue;
+  kg_bicg_p<<<tb.elem[ns], kThreads, 0, s>>>(d_tb);
+  kg_schwarz<<<tb.tile[ns], kThreads, 0, s>>>(d_tb, 0);
+  kg_jsweep<<<tb.pack[ns], kThreads, 0, s>>>(d_tb, 0);
+  kg_stencil<<<tb.pack[ns], kThreads, 0, s>>>(d_tb, 0);
+  // the block passes dispatch on their column count as the single-system
+  // launchers do: [C, r~] has nc + 1 columns, the C-updates nc
+  KRS_BATCH_NC(nc + 1, kg_block_dot<(NCB > 0 ? NCB : 8)><<<tb.pass[ns], kThreads, 0, s>>>(d_tb, 0));
+  kg_finish_alpha<<<ns, kThreads, 0, s>>>(d_tb);
+  KRS_BATCH_NC(nc, kg_bicg_sv<NCB><<<tb.pass[ns], kThreads, 0, s>>>(d_tb));
+  kg_finish_half<<<ns, kThreads, 0, s>>>(d_tb);
+  kg_exit_vec<<<tb.exitv[ns], kThreads, 0, s>>>(d_tb);
+  return hipGetLastError();
+}
+
+hipError_t batch_bicg_second_half(hipStream_t s, const BatchTable* d_tb, const BatchTable& tb,
+                                  int nc) {
+  const int ns = tb.nsys;
+  if (ns < 1 || ns > kMaxBatch) return hipErrorInvalidValue;
+  kg_schwarz<<<tb.tile[ns], kThreads, 0, s>>>(d_tb, 1);
+  kg_jsweep<<<tb.pack[ns], kThreads, 0, s>>>(d_tb, 1);
+  kg_stencil<<<tb.pack[ns], kThreads, 0, s>>>(d_tb, 1);
+  KRS_BATCH_NC(nc + 1, kg_block_dot<(NCB > 0 ? NCB : 8)><<<tb.pass[ns], kThreads, 0, s>>>(d_tb, 1));
+  kg_finish_omega<<<ns, kThreads, 0, s>>>(d_tb);
+  KRS_BATCH_NC(nc, kg_bicg_yr<NCB><<<tb.pass[ns], kThreads, 0, s>>>(d_tb));
+  kg_finish_full<<<ns, kThreads, 0, s>>>(d_tb);
+  return hipGetLastError();
+}
+#undef KRS_BATCH_NC
+
 #define KRS_INSTANTIATE(T)                                                                        \
   template hipError_t stencil<T>(hipStream_t, const Grid3&, const T*, const T*, T*, double,       \
                                  double, const T*, int);                                          \
@@ -2211,13 +2569,14 @@ hipError_t axpy_f32_into_f64(hipStream_t s, const float* d, double* x, int64_t n
                                               T*, double, int, bool);                             \
   template hipError_t block_dot<T>(hipStream_t, const Cols<T>&, const T*, int64_t, int, T*, int); \
   template hipError_t block_update<T>(hipStream_t, const Cols<T>&, const double*, double,         \
-                                      const T*, T*, int64_t, const double*, int, T*, int);        \
+                                      const T*, T*, int64_t, const double*, int, T*, int,         \
+                                      const int*);                                                \
   template hipError_t block_dot_after_update<T>(hipStream_t, const Cols<T>&, const double*,       \
                                                 const T*, int64_t, T*, int, const int*);          \
   template hipError_t gram<T>(hipStream_t, const Cols<T>&, const Cols<T>&, int64_t, T*, int);     \
   template hipError_t row_transform<T>(hipStream_t, const Cols<T>&, const double*, int, T*,       \
                                        int64_t, int64_t);                                         \
-  template hipError_t finish_sum<T>(hipStream_t, const T*, int, int, double*);                    \
+  template hipError_t finish_sum<T>(hipStream_t, const T*, int, int, double*, const int*);        \
   template hipError_t finish_cgs2<T>(hipStream_t, const T*, int, int, const double*, double*,     \
                                      double*, double*, int*, const int*);                         \
   template hipError_t bicg_p<T>(hipStream_t, const T*, T*, const T*, const double*, int64_t);     \

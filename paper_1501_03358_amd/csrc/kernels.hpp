@@ -95,10 +95,11 @@ hipError_t block_dot(hipStream_t s, const Cols<T>& Q, const T* w, int64_t n, int
                      T* partials, int nblk);
 // w_out = (w_in + sgn * Q coef) * (scale ? *scale : 1); w_in may be null (0).
 // dots: 0 none; 1 partial |w_out|^2; 2 partial Q^T w_out and |w_out|^2.
+// run_if: when not NULL, the launch does nothing unless *run_if != 0 (device flag).
 template <class T>
 hipError_t block_update(hipStream_t s, const Cols<T>& Q, const double* coef, double sgn,
                         const T* w_in, T* w_out, int64_t n, const double* scale, int dots,
-                        T* partials, int nblk);
+                        T* partials, int nblk, const int* run_if = nullptr);
 // partials of Q^T (w - Q coef) and |w - Q coef|^2 without writing anything;
 // returns at once when skip != NULL and *skip != 0 (device flag).
 template <class T>
@@ -116,7 +117,8 @@ hipError_t row_transform(hipStream_t s, const Cols<T>& In, const double* M, int 
 
 // out[c] = sum_blk partials[c*nblk + blk]   (fixed order, FP64)
 template <class T>
-hipError_t finish_sum(hipStream_t s, const T* partials, int nblk, int ncols, double* out);
+hipError_t finish_sum(hipStream_t s, const T* partials, int nblk, int ncols, double* out,
+                      const int* run_if = nullptr);
 // CGS2 end: h2 = sum(partials[0..ncols)), nrm2 = sum(partials[ncols]);
 // hcol[c] = h1[c] + h2[c]; hcol[ncols] = sqrt(nrm2 - |h2|^2) (flag = 1 when the
 // Pythagorean form is unreliable and an explicit norm is needed); inv = 1/hcol[ncols].
@@ -179,7 +181,82 @@ hipError_t bicg_finish_omega(hipStream_t s, const T* partials, int nblk, int kc,
 template <class T>
 hipError_t bicg_finish_full(hipStream_t s, const T* partials, int nblk, double* sums, double* sc);
 // hcol_last = sqrt(*nrm2), inv = 1/hcol_last
-hipError_t set_norm_from_sum(hipStream_t s, const double* nrm2, double* hcol_last, double* inv);
+hipError_t set_norm_from_sum(hipStream_t s, const double* nrm2, double* hcol_last, double* inv,
+                             const int* run_if = nullptr);
+
+// ---- device-side Arnoldi cycle state (GMRES / rGCROT), offsets in doubles ----
+// stop flag, steps done in the cycle, Arnoldi steps of the solve, last
+// estimate, absolute tolerance, step limit, second Gram-Schmidt passes and
+// their column count; then g, the rotations, the history ring, Hbar and its
+// rotated form R (leading dimension m + 1) and B (leading dimension k_c).
+constexpr int kMaxArnM = 64;
+enum ArnSlot {
+  kArnStop = 0, kArnJ, kArnIts, kArnEst, kArnTolAbs, kArnMaxIts, kArnTwo, kArnTwoCols,
+  kArnG = 16, kArnCs = kArnG + kMaxArnM + 16, kArnSn = kArnCs + kMaxArnM,
+  kArnHist = kArnSn + kMaxArnM, kArnHistRing = 64,
+  kArnH = kArnHist + kArnHistRing, kArnR = kArnH + (kMaxArnM + 1) * kMaxArnM,
+  kArnB = kArnR + (kMaxArnM + 1) * kMaxArnM, kArnSize = kArnB + 1024
+};
+// End of Arnoldi step j (k_c recycle columns, cycle length m) from hcol:
+// store the column, Givens rotations, estimate, history and stop state.
+// hcol holds k_c + j + 2 values; skip: the step took one Gram-Schmidt pass;
+// flag (may be NULL): when set, the step's norm needs an explicit pass, and
+// the kernel only records stop state 2 at step j for the host to redo it.
+hipError_t arnoldi_givens(hipStream_t s, double* arn, const double* hcol, const int* skip,
+                          const int* flag, int j, int kc, int m);
+
+// offsets (doubles) of the rBiCGStab scalar area beyond the BicgSlot slots:
+// finished sums, C^T v / C^T t (eta1, eta2), the postponed U-coefficients
+// xi, C^T r~, ||b||^2
+enum BicgOff { kBSums = 32, kBEta1 = 128, kBEta2 = 192, kBXi = 256, kBCtrt = 320, kBNrm = 384 };
+
+// ---- grouped rBiCGStab passes over several independent FP32 systems ----
+// Every launch covers all systems of a batch: system s owns the block range
+// [off[s], off[s+1]) of the grid (each range starts at a multiple of 8 blocks,
+// so the XCD mapping within a system is that of a launch of its own), and
+// its blocks compute exactly what the same launch of that system alone
+// computes (same rows per block, same partial-sum slots, same finishing
+// order): each result is bitwise that of the system solved alone.
+constexpr int kMaxBatch = 32;
+struct BatchSys {
+  Grid3 g;
+  const float* bands;     // 7 bands
+  const float* pk;        // Schwarz local-solve coefficients, bricks of 2^3 tiles of 8^3
+  int nbx, nby;           // bricks along x, y
+  float omega_l, omega_g;
+  int sweeps;             // local Jacobi sweeps
+  Cols<float> C;          // recycle space C (C.n1 = k_c columns)
+  const float* rt;        // shadow residual r~
+  float *r, *p, *v, *sv, *t, *z, *y;
+  float* part;            // per-block partial sums
+  double* sc;             // scalar area (BicgSlot, BicgOff)
+  int nblk;               // blocks of the streaming passes
+  int64_t n;
+  int64_t ld;             // leading dimension of the vectors
+};
+struct BatchTable {
+  int nsys;
+  int elem[kMaxBatch + 1];   // block ranges: one row per thread
+  int pack[kMaxBatch + 1];   //   four rows per thread (stencil packs)
+  int tile[kMaxBatch + 1];   //   one Schwarz tile per block
+  int pass[kMaxBatch + 1];   //   streaming passes (nblk blocks)
+  int exitv[kMaxBatch + 1];  //   the line-10 exit update (at most 512 blocks)
+  int fin[kMaxBatch + 1];    //   one block per system (finishing reductions)
+  BatchSys sys[kMaxBatch];
+};
+// Fills the block ranges of `tb` from its systems (host side).
+void batch_layout(BatchTable& tb);
+// One rBiCGStab pass sequence for all systems of the table (device copy
+// d_tb, host copy tb): the first half (p update, A~ p, C-projection, alpha,
+// s, half-step tests and exit) and the second half (A~ s, omega, y and r
+// updates, full-step tests).  The operator is Schwarz-Jacobi (packed Jacobi
+// local sweeps, one global sweep) followed by the matvec.  Systems whose stop
+// state is set skip every launch.  `nc` is the recycle dimension shared by
+// all systems of the table.
+hipError_t batch_bicg_first_half(hipStream_t s, const BatchTable* d_tb, const BatchTable& tb,
+                                 int nc);
+hipError_t batch_bicg_second_half(hipStream_t s, const BatchTable* d_tb, const BatchTable& tb,
+                                  int nc);
 
 // misc
 template <class T>

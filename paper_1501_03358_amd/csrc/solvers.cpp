@@ -26,6 +26,9 @@ struct Ws {
   // coefficient blocks, up to (63 + 64) x 62
   static constexpr int kCoef = 512, kXi = 768, kNrm = 832, kAux = 840;
   static constexpr int kGram1 = 4096, kGram2 = 8192, kM = 12288;
+  // device-side Arnoldi cycle state (ArnSlot offsets from here)
+  static constexpr int kArn = 20480;
+  static_assert(kArn + kArnSize <= kScalarDoubles, "scalar area");
 };
 
 // y-space operator A~ = A M^-1 and its pieces
@@ -619,6 +622,11 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
   int status = KRS_NOT_CONVERGED;
   double est = rho;
   const bool trust_est = (o->flags & KRS_FLAG_TRUST_ESTIMATE) != 0;
+  // host-tested loop (one read per step) or device-driven batches of steps
+  const bool host_loop = (o->flags & KRS_FLAG_HOST_LOOP) != 0;
+  double* d_arn = sc + Ws<T>::kArn;
+  const int bcap = n <= (int64_t(1) << 18) ? 32 : (n <= (int64_t(1) << 21) ? 8 : 4);
+  int batch = std::min(2, bcap);
   bool est_converged = false;
   while (rho > tol * nb && its < maxit && !est_converged) {
     kc = rec ? rec->dim : 0;
@@ -633,17 +641,18 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
     std::fill(Hbar.begin(), Hbar.end(), 0.0);
     std::fill(Bm.begin(), Bm.end(), 0.0);
     int jj = 0;
-    for (int j = 0; j < m; ++j) {
+    // one Arnoldi step: w = A~ v_j, Gram-Schmidt against [C, V_j] (second
+    // pass on the device's decision), v_{j+1} = (w - Q h) / h_{j+1,j}.  With
+    // `dev` the explicit-norm fallback is enqueued as launches that do
+    // nothing unless the device flag asks for them; otherwise the host reads
+    // the flag and launches them when needed.
+    auto step = [&](int j, bool dev) -> int {
       T* vj = V + (int64_t)j * ld;
       T* vn = V + (int64_t)(j + 1) * ld;
-      rc = apply(vj, w);
-      if (rc) return rc;
-      ++its;
-      ++mv;
+      int e = apply(vj, w);
+      if (e) return e;
       const int ncols = kc + j + 1;
       const Cols<T> Q = cols<T>(C, ldr, kc, V, ld, j + 1);
-      // orthogonalisation by classical Gram-Schmidt against [C, V_j]: a second
-      // pass only when the first removed more than half of |w|^2
       KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (ncols + 1), block_dot<T>(s, Q, w, n, 1, part, nblk));
       KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, ncols + 1, d_h1));
       KRS_LAUNCH(ctx, KRS_K_OTHER, 0, cgs_decide(s, ncols, d_h1, d_hcol, d_inv, d_flag, d_skip));
@@ -651,53 +660,175 @@ int gmres_rgcrot_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_
                  block_dot_after_update<T>(s, Q, d_h1, w, n, part, nblk, d_skip));
       KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
                  finish_cgs2<T>(s, part, nblk, ncols, d_h1, d_h2, d_hcol, d_inv, d_flag, d_skip));
-      // v_{j+1} = (w - Q h) / h_{j+1,j}
       KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (ncols + 2),
                  block_update<T>(s, Q, d_hcol, -1.0, w, vn, n, d_inv, 0, part, nblk));
-      rc = read_dev(ctx, sc, Ws<T>::kFlagOff + 1);
-      if (rc) return rc;
-      std::vector<double> hv(ctx->pin + Ws<T>::kHcol, ctx->pin + Ws<T>::kHcol + ncols + 1);
-      int flag = *(int*)(ctx->pin + Ws<T>::kFlagOff);
-      const int skipped = ((int*)(ctx->pin + Ws<T>::kFlagOff))[1];
-      if (!skipped) timing_add_bytes(ctx, KRS_K_BLOCK_DOT2, NW * (ncols + 1));
-      ++(skipped ? n_one_pass : n_two_pass);
-      if (flag) {
-        // norm from the Pythagorean identity unreliable: recompute explicitly
-        KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (ncols + 2),
-                   block_update<T>(s, Q, d_hcol, -1.0, w, vn, n, nullptr, 1, part, nblk));
-        KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, d_nrm));
-        KRS_LAUNCH(ctx, KRS_K_OTHER, 0, set_norm_from_sum(s, d_nrm, d_hcol + ncols, d_inv));
-        KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, 2 * NW,
-                   block_update<T>(s, Cols<T>{}, nullptr, 0.0, vn, vn, n, d_inv, 0, part, nblk));
-        rc = read_dev(ctx, d_hcol + ncols, 1);
+      if (dev)
+        KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
+                   arnoldi_givens(s, d_arn, d_hcol, d_skip, d_flag, j, kc, m));
+      return 0;
+    };
+    // the explicit norm of w - Q h and the rescale of v_{j+1}, for a step
+    // whose norm from the Pythagorean identity is unreliable (flag set)
+    auto explicit_norm = [&](int j) -> int {
+      const int ncols = kc + j + 1;
+      T* vn = V + (int64_t)(j + 1) * ld;
+      const Cols<T> Q = cols<T>(C, ldr, kc, V, ld, j + 1);
+      KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (ncols + 2),
+                 block_update<T>(s, Q, d_hcol, -1.0, w, vn, n, nullptr, 1, part, nblk));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, 1, d_nrm));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, set_norm_from_sum(s, d_nrm, d_hcol + ncols, d_inv));
+      KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, 2 * NW,
+                 block_update<T>(s, Cols<T>{}, nullptr, 0.0, vn, vn, n, d_inv, 0, part, nblk));
+      return 0;
+    };
+    if (host_loop) {
+      for (int j = 0; j < m; ++j) {
+        rc = step(j, false);
         if (rc) return rc;
-        hv[ncols] = ctx->pin[0];
+        ++its;
+        ++mv;
+        const int ncols = kc + j + 1;
+        rc = read_dev(ctx, sc, Ws<T>::kFlagOff + 1);
+        if (rc) return rc;
+        std::vector<double> hv(ctx->pin + Ws<T>::kHcol, ctx->pin + Ws<T>::kHcol + ncols + 1);
+        int flag = *(int*)(ctx->pin + Ws<T>::kFlagOff);
+        const int skipped = ((int*)(ctx->pin + Ws<T>::kFlagOff))[1];
+        if (!skipped) timing_add_bytes(ctx, KRS_K_BLOCK_DOT2, NW * (ncols + 1));
+        ++(skipped ? n_one_pass : n_two_pass);
+        if (flag) {
+          // norm from the Pythagorean identity unreliable: recompute explicitly
+          rc = explicit_norm(j);
+          if (rc) return rc;
+          rc = read_dev(ctx, d_hcol + ncols, 1);
+          if (rc) return rc;
+          hv[ncols] = ctx->pin[0];
+        }
+        for (int i = 0; i < kc; ++i) Bm[i + (size_t)ldb * j] = hv[i];
+        for (int i = 0; i <= j; ++i) Hbar[i + (size_t)ldh * j] = hv[kc + i];
+        Hbar[(j + 1) + (size_t)ldh * j] = hv[ncols];
+        // Givens rotations for the least-squares problem of the cycle (the
+        // same arithmetic, term by term, as the device-side step end)
+        for (int i = 0; i <= j + 1; ++i) hc[i] = Hbar[i + (size_t)ldh * j];
+        for (int i = 0; i < j; ++i) {
+          const double a = hc[i], bb = hc[i + 1];
+          hc[i] = cs[i] * a + sn[i] * bb;
+          hc[i + 1] = -sn[i] * a + cs[i] * bb;
+        }
+        const double a = hc[j], bb = hc[j + 1];
+        const double rr = std::sqrt(a * a + bb * bb);
+        cs[j] = rr > 0 ? a / rr : 1.0;
+        sn[j] = rr > 0 ? bb / rr : 0.0;
+        hc[j] = rr;
+        hc[j + 1] = 0;
+        gv[j + 1] = -sn[j] * gv[j];
+        gv[j] = cs[j] * gv[j];
+        for (int i = 0; i <= j + 1; ++i) Rr[i + (size_t)ldh * j] = hc[i];
+        est = std::fabs(gv[j + 1]);
+        if (o->history && hlen < o->history_cap) o->history[hlen] = est / nb;
+        ++hlen;
+        jj = j + 1;
+        if (!std::isfinite(est)) break;
+        if (est <= tol * nb || hv[ncols] == 0.0 || its >= maxit) break;
       }
-      for (int i = 0; i < kc; ++i) Bm[i + (size_t)ldb * j] = hv[i];
-      for (int i = 0; i <= j; ++i) Hbar[i + (size_t)ldh * j] = hv[kc + i];
-      Hbar[(j + 1) + (size_t)ldh * j] = hv[ncols];
-      // Givens rotations for the least-squares problem of the cycle
-      for (int i = 0; i <= j + 1; ++i) hc[i] = Hbar[i + (size_t)ldh * j];
-      for (int i = 0; i < j; ++i) {
-        const double a = hc[i], bb = hc[i + 1];
-        hc[i] = cs[i] * a + sn[i] * bb;
-        hc[i + 1] = -sn[i] * a + cs[i] * bb;
+    } else {
+      // Device-driven cycle: the step ends (Givens, estimate, stopping
+      // tests) run on the device; the host enqueues batches of steps and
+      // reads the cycle state once per batch.  Steps enqueued after the stop
+      // run on values nobody reads (the device state no longer changes), so
+      // the batch length follows the observed convergence rate.
+      std::vector<double> st0(kArnG + m + 1, 0.0);
+      st0[kArnTolAbs] = tol * nb;
+      st0[kArnMaxIts] = (double)maxit;
+      st0[kArnIts] = (double)its;
+      st0[kArnG] = rho;
+      rc = upload(ctx, d_arn, st0.data(), (int)st0.size());
+      if (rc) return rc;
+      int j = 0;
+      int64_t its0 = its;
+      double last = rho;
+      while (j < m) {
+        const int kb = std::min(batch, m - j);
+        for (int q = 0; q < kb; ++q) {
+          rc = step(j + q, true);
+          if (rc) return rc;
+        }
+        rc = read_dev(ctx, d_arn, kArnHist + kArnHistRing);
+        if (rc) return rc;
+        const double* d = ctx->pin;
+        const int jdone = (int)d[kArnJ];
+        for (int64_t h = its; h < (int64_t)d[kArnIts]; ++h) {
+          if (o->history && hlen < o->history_cap)
+            o->history[hlen] = d[kArnHist + h % kArnHistRing] / nb;
+          ++hlen;
+        }
+        its = (int64_t)d[kArnIts];
+        const double e_now = d[kArnEst];
+        j += kb;
+        if (d[kArnStop] == 2.0) {
+          // step jdone needs an explicit norm: the steps enqueued after it
+          // ran on a v_{j+1} that is about to change, so run the step again
+          // (same kernels, same inputs: V_{j+1} is intact), with the
+          // explicit norm pass, end it on the device and go on from there
+          const double zero = 0.0;
+          rc = upload(ctx, d_arn + kArnStop, &zero, 1);
+          if (rc) return rc;
+          rc = step(jdone, false);
+          if (rc) return rc;
+          rc = explicit_norm(jdone);
+          if (rc) return rc;
+          KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
+                     arnoldi_givens(s, d_arn, d_hcol, d_skip, nullptr, jdone, kc, m));
+          rc = read_dev(ctx, d_arn, kArnHist + kArnHistRing);
+          if (rc) return rc;
+          const double* d2 = ctx->pin;
+          for (int64_t h = its; h < (int64_t)d2[kArnIts]; ++h) {
+            if (o->history && hlen < o->history_cap)
+              o->history[hlen] = d2[kArnHist + h % kArnHistRing] / nb;
+            ++hlen;
+          }
+          its = (int64_t)d2[kArnIts];
+          j = jdone + 1;
+          if (d2[kArnStop] != 0.0) break;
+          its0 = its;
+          last = d2[kArnEst];
+          continue;
+        }
+        if (d[kArnStop] != 0.0) {
+          j = jdone;
+          break;
+        }
+        // next batch: about half the steps the recent rate still needs
+        const int64_t dj = its - its0;
+        if (dj > 0 && e_now > 0 && e_now < last) {
+          const double rate = std::pow(e_now / last, 1.0 / (double)dj);
+          const double need = std::log(tol * nb / e_now) / std::log(rate);
+          batch = (int)std::max(1.0, std::min((double)bcap, 0.5 * need));
+        }
+        its0 = its;
+        last = e_now;
       }
-      const double a = hc[j], bb = hc[j + 1];
-      const double rr = std::hypot(a, bb);
-      cs[j] = rr > 0 ? a / rr : 1.0;
-      sn[j] = rr > 0 ? bb / rr : 0.0;
-      hc[j] = rr;
-      hc[j + 1] = 0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = cs[j] * gv[j];
-      for (int i = 0; i <= j + 1; ++i) Rr[i + (size_t)ldh * j] = hc[i];
-      est = std::fabs(gv[j + 1]);
-      if (o->history && hlen < o->history_cap) o->history[hlen] = est / nb;
-      ++hlen;
-      jj = j + 1;
-      if (!std::isfinite(est)) break;
-      if (est <= tol * nb || hv[ncols] == 0.0 || its >= maxit) break;
+      jj = j;
+      mv += jj;
+      // the cycle's least-squares data and the recycle-update inputs
+      rc = read_dev(ctx, d_arn, kArnB + kc * jj);
+      if (rc) return rc;
+      const double* d = ctx->pin;
+      // column c holds rows 0..c+1 (the device never writes below the
+      // subdiagonal; those host entries stay zero)
+      for (int c = 0; c < jj; ++c) {
+        for (int i = 0; i <= c + 1; ++i) {
+          Hbar[i + (size_t)ldh * c] = d[kArnH + i + (m + 1) * c];
+          Rr[i + (size_t)ldh * c] = d[kArnR + i + (m + 1) * c];
+        }
+        for (int i = 0; i < kc; ++i) Bm[i + (size_t)ldb * c] = d[kArnB + i + kc * c];
+      }
+      for (int i = 0; i <= jj; ++i) gv[i] = d[kArnG + i];
+      est = jj > 0 ? std::fabs(gv[jj]) : rho;
+      // second Gram-Schmidt passes of the cycle (the state restarts per
+      // cycle); the Pythagorean-norm fallbacks that ran (rare: a norm pass
+      // and a rescale) are not in the byte model
+      n_two_pass += (int64_t)d[kArnTwo];
+      timing_add_bytes(ctx, KRS_K_BLOCK_DOT2, NW * d[kArnTwoCols]);
     }
     est_converged = trust_est && est <= tol * nb;
     // y = R^-1 g ; z = -B y ; y_acc += V y + U z
@@ -883,7 +1014,8 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   T* part = (T*)cv.take(partials_bytes(sizeof(T)));
   double* sc = cv.vec<double>(kScalarDoubles);
   if (!ws || !cv.ok) return set_err(ctx, KRS_ERR_WORKSPACE, "workspace missing or too small");
-  const int kSums = 32, kEta1 = 128, kEta2 = 192, kXi = 256, kCtrt = 320, kNrm = 384;
+  const int kSums = kBSums, kEta1 = kBEta1, kEta2 = kBEta2, kXi = kBXi, kCtrt = kBCtrt,
+            kNrm = kBNrm;
   // the BiCGStab passes run on at most 512 blocks (2048 waves: the whole grid
   // is resident at once at the passes' 2 waves per SIMD); the fused update
   // passes stream 2-3% faster than on 1024 blocks (measured at 256^3)
@@ -1427,6 +1559,447 @@ int ir_solve(krs_ctx* ctx, const krs_matrix* A64, const krs_matrix* A32, const k
     st->second_passes = second;
   }
   return status;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 iterative refinement of several independent systems at once, with the
+// inner rBiCGStab iterations of all of them in grouped launches
+// ---------------------------------------------------------------------------
+namespace {
+
+// Whether the grouped rBiCGStab passes can run system i exactly as its own
+// launches would: FP32 7-point bands, Schwarz-Jacobi with packed Jacobi local
+// sweeps on 8^3 tiles in bricks of 2^3, one global sweep, 16-byte packs.
+bool batchable(const krs_ir_system& q) {
+  const krs_matrix* A = q.A32;
+  const krs_precond* M = q.M32;
+  if (!A || !M || A->pts != 7 || A->dt != KRS_F32) return false;
+  if (M->d.type != KRS_PC_SCHWARZ_JACOBI || !M->pack || M->d.tile != 8 || M->d.overlap != 1 ||
+      M->d.local_sweeps < 1 || M->d.global_sweeps != 1 ||
+      M->d.local_solver != KRS_LOCAL_JACOBI)
+    return false;
+  const Grid3 g = grid3(A);
+  if (g.nx % 8 || g.ny % 8 || g.nz % 8 || schwarz_brick(g, 8) != 2 || g.nx % 4) return false;
+  auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  if (!al(A->bands) || !al(M->pack)) return false;
+  if (q.rec32 && q.rec32->dim > 0 && (!al(q.rec32->C) || q.rec32->ld % 4)) return false;
+  return true;
+}
+
+// Per-system state of the batched refinement: the layout of its workspace
+// (that of ir_solve, with rbicgstab_t's inside the inner part), its FP64
+// residual and the counters ir_solve keeps.
+struct IrSys {
+  const krs_ir_system* q;
+  int64_t n = 0, ld = 0;
+  void* inner = nullptr;
+  size_t inner_bytes = 0;
+  double* r64 = nullptr;
+  float* b32 = nullptr;
+  float* d32 = nullptr;
+  double* part = nullptr;
+  double* sc = nullptr;      // refinement scalars
+  // the inner rBiCGStab workspace
+  float *r = nullptr, *rt = nullptr, *p = nullptr, *v = nullptr, *sv = nullptr, *t = nullptr,
+        *z = nullptr, *y = nullptr, *ipart = nullptr;
+  double* isc = nullptr;
+  double nb = 0, rn = 0;
+  int status = KRS_NOT_CONVERGED;
+  bool active = false;
+  int64_t outer = 0, its = 0, mv = 0;
+  double bytes = 0;
+  // inner solve
+  double itol = 0, inb = 0, irnorm = 0;
+  int istatus = KRS_NOT_CONVERGED;
+  int64_t iits = 0, imv = 0;
+  bool inner_running = false;
+};
+
+}  // namespace
+
+int ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys, const krs_opts* o,
+                     void* ws, size_t wsb) {
+  hipStream_t s = ctx->stream;
+  if (nsys < 1) return KRS_OK;
+  if (!ws || wsb < align_up(sizeof(BatchTable)))
+    return set_err(ctx, KRS_ERR_WORKSPACE, "batch workspace missing or too small");
+  BatchTable* d_tb = (BatchTable*)ws;
+  const double inner_floor = o->inner_tol > 0 ? o->inner_tol : 1e-5;
+  const int max_outer = o->max_outer > 0 ? o->max_outer : 20;
+  const int64_t maxmv = o->max_matvecs > 0 ? o->max_matvecs : 2000;
+  const int64_t allowed = (maxmv + 1) / 2;
+  const bool use_graph = (o->flags & KRS_FLAG_GRAPH) != 0 && !ctx->timing;
+  krs_opts io = *o;
+  io.flags |= KRS_FLAG_TRUST_ESTIMATE;
+  io.flags &= ~(KRS_FLAG_GRAPH | KRS_FLAG_HOST_LOOP);
+  io.history = nullptr;
+  io.history_cap = 0;
+  // systems the grouped passes cannot run exactly as alone: solved alone
+  std::vector<IrSys> st;
+  std::vector<int> alone;
+  int kc_all = -1;
+  for (int i = 0; i < nsys; ++i) {
+    const krs_ir_system& q = sys[i];
+    const int kc = q.rec32 ? q.rec32->dim : 0;
+    if (batchable(q) && (kc_all < 0 || kc == kc_all) && (int)st.size() < kMaxBatch) {
+      kc_all = kc;
+      IrSys x;
+      x.q = &q;
+      st.push_back(x);
+    } else {
+      alone.push_back(i);
+    }
+  }
+  // refinement setup of every grouped system (as ir_solve)
+  for (IrSys& x : st) {
+    const krs_ir_system& q = *x.q;
+    x.n = q.A64->n;
+    x.ld = vec_ld(x.n);
+    x.inner_bytes = std::max(ws_gmres<float>(x.n, o->m), ws_bicg<float>(x.n));
+    Carver cv(q.ws, q.ws_bytes);
+    x.inner = cv.take(x.inner_bytes);
+    x.r64 = cv.vec<double>(x.ld);
+    x.b32 = cv.vec<float>(x.ld);
+    x.d32 = cv.vec<float>(x.ld);
+    x.part = (double*)cv.take(partials_bytes(sizeof(double)));
+    x.sc = cv.vec<double>(kScalarDoubles);
+    if (!q.ws || !cv.ok) return set_err(ctx, KRS_ERR_WORKSPACE, "system workspace too small");
+    Carver ci(x.inner, x.inner_bytes);
+    x.r = ci.vec<float>(x.ld);
+    x.rt = ci.vec<float>(x.ld);
+    x.p = ci.vec<float>(x.ld);
+    x.v = ci.vec<float>(x.ld);
+    x.sv = ci.vec<float>(x.ld);
+    x.t = ci.vec<float>(x.ld);
+    x.z = ci.vec<float>(x.ld);
+    x.y = ci.vec<float>(x.ld);
+    x.ipart = (float*)ci.take(partials_bytes(sizeof(float)));
+    x.isc = ci.vec<double>(kScalarDoubles);
+    init_stats(q.stats);
+    double nb2 = 0;
+    int rc = norm2<double>(ctx, (const double*)q.b, x.n, x.part, x.sc, nb2);
+    if (rc) return rc;
+    x.nb = std::sqrt(nb2);
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 8.0 * x.n, fill<double>(s, (double*)q.x, x.n, 0.0));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 16.0 * x.n, copy<double>(s, (const double*)q.b, x.r64, x.n));
+    x.rn = x.nb;
+    if (!(x.nb > 0)) {
+      x.status = std::isfinite(x.nb) ? KRS_OK : KRS_DIVERGED;
+      if (q.stats) {
+        q.stats->status = x.status;
+        q.stats->rel_res_true = 0;
+      }
+    } else {
+      x.active = x.rn > o->tol * x.nb;
+      if (!x.active) x.status = KRS_OK;
+    }
+  }
+  BatchTable tb;
+  std::vector<int> in_table;
+  // one device-driven batch of rBiCGStab inner solves of the active systems
+  auto inner_batch = [&](std::vector<IrSys*>& act) -> int {
+    // setup of each inner solve (as rbicgstab_t): ||b||, projection of b
+    // against C, r~, C^T r~, zero p v y, scalar slots
+    std::vector<IrSys*> run;
+    for (IrSys* x : act) {
+      const krs_recycle* rec = x->q->rec32;
+      const int kc = rec ? rec->dim : 0;
+      const Cols<float> Cc = cols<float>(rec ? (const float*)rec->C : nullptr, rec ? rec->ld : 0,
+                                         kc);
+      const int nblk = std::min(red_blocks(x->n), 512);
+      const double NW = (double)x->n * sizeof(float);
+      x->iits = 0;
+      x->imv = 0;
+      x->istatus = KRS_NOT_CONVERGED;
+      x->inner_running = false;
+      double nb2 = 0;
+      int rc = norm2<float>(ctx, x->b32, x->n, x->ipart, x->isc + kBNrm, nb2);
+      if (rc) return rc;
+      x->inb = std::sqrt(nb2);
+      if (x->inb == 0 || !std::isfinite(x->inb)) {
+        KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<float>(s, x->d32, x->n, 0.0));
+        x->istatus = std::isfinite(x->inb) ? KRS_OK : KRS_DIVERGED;
+        continue;
+      }
+      double rn2 = nb2;
+      if (kc > 0) {
+        KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 1),
+                   block_dot<float>(s, Cc, x->b32, x->n, 0, x->ipart, nblk));
+        KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
+                   finish_sum<float>(s, x->ipart, nblk, kc, x->isc + kBEta1));
+        KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (kc + 2),
+                   block_update<float>(s, Cc, x->isc + kBEta1, -1.0, x->b32, x->r, x->n, nullptr,
+                                       1, x->ipart, nblk));
+        KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<float>(s, x->ipart, nblk, 1, x->isc + kBNrm));
+        rc = read_dev(ctx, x->isc + kBEta1, kc);
+        if (rc) return rc;
+        std::vector<double> xi(kc);
+        for (int c = 0; c < kc; ++c) xi[c] = -ctx->pin[c];
+        rc = upload(ctx, x->isc + kBXi, xi.data(), kc);
+        if (rc) return rc;
+        rc = read_dev(ctx, x->isc + kBNrm, 1);
+        if (rc) return rc;
+        rn2 = ctx->pin[0];
+      } else {
+        KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<float>(s, x->b32, x->r, x->n));
+      }
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<float>(s, x->r, x->rt, x->n));
+      if (kc > 0) {
+        KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 1),
+                   block_dot<float>(s, Cc, x->rt, x->n, 0, x->ipart, nblk));
+        KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
+                   finish_sum<float>(s, x->ipart, nblk, kc, x->isc + kBCtrt));
+      }
+      KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<float>(s, x->p, x->n, 0.0));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<float>(s, x->v, x->n, 0.0));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<float>(s, x->y, x->n, 0.0));
+      std::vector<double> slots(kSlots, 0.0);
+      slots[kRho] = rn2;
+      slots[kOmega] = 1.0;
+      slots[kBeta] = 0.0;
+      slots[kRnorm2] = rn2;
+      slots[kTolAbs] = x->itol * x->inb;
+      slots[kDivAbs] = io.div_factor > 0 ? io.div_factor * x->inb : INFINITY;
+      rc = upload(ctx, x->isc, slots.data(), kSlots);
+      if (rc) return rc;
+      x->irnorm = std::sqrt(rn2);
+      if (x->irnorm > x->itol * x->inb) {
+        x->inner_running = true;
+        run.push_back(x);
+      }
+    }
+    // the grouped iterations
+    int64_t passes = 0;
+    int batch = 2;
+    double last = 0;
+    for (IrSys* x : run) last = std::max(last, x->irnorm / x->inb);
+    int64_t prev = 0;
+    while (!run.empty() && passes < allowed) {
+      tb.nsys = (int)run.size();
+      for (int i = 0; i < tb.nsys; ++i) {
+        IrSys* x = run[i];
+        const krs_ir_system& q = *x->q;
+        BatchSys& b = tb.sys[i];
+        b.g = grid3(q.A32);
+        b.bands = (const float*)q.A32->bands;
+        b.pk = (const float*)q.M32->pack;
+        b.nbx = b.g.nx / 16;
+        b.nby = b.g.ny / 16;
+        b.omega_l = (float)q.M32->d.omega_local;
+        b.omega_g = (float)q.M32->d.omega_global;
+        b.sweeps = q.M32->d.local_sweeps;
+        const krs_recycle* rec = q.rec32;
+        b.C = cols<float>(rec ? (const float*)rec->C : nullptr, rec ? rec->ld : 0,
+                          rec ? rec->dim : 0);
+        b.rt = x->rt;
+        b.r = x->r;
+        b.p = x->p;
+        b.v = x->v;
+        b.sv = x->sv;
+        b.t = x->t;
+        b.z = x->z;
+        b.y = x->y;
+        b.part = x->ipart;
+        b.sc = x->isc;
+        b.nblk = std::min(red_blocks(x->n), 512);
+        b.n = x->n;
+        b.ld = x->ld;
+      }
+      batch_layout(tb);
+      KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
+      std::memcpy(ctx->pin + kPinDoubles / 2, &tb, sizeof(BatchTable));
+      KRS_CHECK_HIP(ctx, hipMemcpyAsync(d_tb, ctx->pin + kPinDoubles / 2, sizeof(BatchTable),
+                                        hipMemcpyHostToDevice, s));
+      // optionally one pass of the table captured as a graph and replayed
+      // (its launches read everything from the table and the scalar areas)
+      hipGraphExec_t gexec = nullptr;
+      if (use_graph) {
+        if (!ctx->capture)
+          KRS_CHECK_HIP(ctx, hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+          hipError_t e1 = batch_bicg_first_half(ctx->capture, d_tb, tb, kc_all);
+          hipError_t e2 = batch_bicg_second_half(ctx->capture, d_tb, tb, kc_all);
+          e = hipStreamEndCapture(ctx->capture, &gr);
+          if (e == hipSuccess) e = e1 != hipSuccess ? e1 : e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&gexec, gr, nullptr, nullptr, 0);
+        if (gr) (void)hipGraphDestroy(gr);
+        if (e != hipSuccess)
+          return set_err(ctx, KRS_ERR_HIP, std::string("batched graph: ") + hipGetErrorString(e));
+      }
+      struct GraphGuard {
+        hipGraphExec_t& g;
+        ~GraphGuard() {
+          if (g) (void)hipGraphExecDestroy(g);
+        }
+      } guard{gexec};
+      // passes until the active set changes (read once per batch of passes)
+      while (passes < allowed) {
+        const int kb = (int)std::min<int64_t>(batch, allowed - passes);
+        for (int q = 0; q < kb; ++q) {
+          if (gexec) {
+            KRS_CHECK_HIP(ctx, hipGraphLaunch(gexec, s));
+          } else {
+            KRS_LAUNCH(ctx, KRS_K_OTHER, 0, batch_bicg_first_half(s, d_tb, tb, kc_all));
+            KRS_LAUNCH(ctx, KRS_K_OTHER, 0, batch_bicg_second_half(s, d_tb, tb, kc_all));
+          }
+        }
+        passes += kb;
+        // the state of every system of the table, one synchronisation
+        const int per = kHistOff + kHistRing;
+        for (int i = 0; i < tb.nsys; ++i)
+          KRS_CHECK_HIP(ctx, hipMemcpyAsync(ctx->pin + (size_t)i * per, run[i]->isc,
+                                            sizeof(double) * per, hipMemcpyDeviceToHost, s));
+        KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
+        timing_flush(ctx);
+        bool changed = false;
+        double worst = 0;
+        for (int i = 0; i < tb.nsys; ++i) {
+          IrSys* x = run[i];
+          const double* d = ctx->pin + (size_t)i * per;
+          x->iits = (int64_t)d[kIts];
+          const int done = (int)d[kDone];
+          x->irnorm = std::sqrt(d[kRnorm2]);
+          if (done != kRunning) {
+            x->imv = 2 * x->iits - (d[kEndHalf] != 0.0 ? 1 : 0);
+            if (done == kBreak) x->istatus = KRS_BREAKDOWN;
+            else if (done == kDiverge) x->istatus = KRS_DIVERGED;
+            x->inner_running = false;
+            changed = true;
+          } else {
+            x->imv = 2 * x->iits;
+            worst = std::max(worst, x->irnorm / x->inb);
+          }
+        }
+        if (changed) break;
+        // next batch: about half the iterations the slowest system still needs
+        const int64_t dits = passes - prev;
+        prev = passes;
+        if (dits > 0 && worst > 0 && worst < last) {
+          const double rate = std::pow(worst / last, 1.0 / (double)dits);
+          double tmin = 1.0;
+          for (IrSys* x : run) tmin = std::min(tmin, x->itol);
+          const double need = std::log(tmin / worst) / std::log(rate);
+          batch = (int)std::max(1.0, std::min(32.0, 0.5 * need));
+        }
+        last = worst;
+      }
+      std::vector<IrSys*> still;
+      for (IrSys* x : run)
+        if (x->inner_running) still.push_back(x);
+      run.swap(still);
+    }
+    // finish every inner solve (as rbicgstab_t): status, postponed U-update,
+    // x = M^-1 y
+    for (IrSys* x : act) {
+      if (x->inb == 0 || !std::isfinite(x->inb)) continue;
+      if (x->istatus == KRS_NOT_CONVERGED && x->irnorm <= x->itol * x->inb) x->istatus = KRS_OK;
+      const krs_recycle* rec = x->q->rec32;
+      const int kc = rec ? rec->dim : 0;
+      const int nblk = std::min(red_blocks(x->n), 512);
+      const double NW = (double)x->n * sizeof(float);
+      if (kc > 0) {
+        KRS_LAUNCH(ctx, KRS_K_BLOCK_UPDATE, NW * (kc + 2),
+                   block_update<float>(s, cols<float>((const float*)rec->U, rec->ld, kc),
+                                       x->isc + kBXi, -1.0, x->y, x->y, x->n, nullptr, 0,
+                                       x->ipart, nblk));
+      }
+      Op<float> op{ctx, x->q->A32, x->q->M32, grid3(x->q->A32), x->z, nullptr};
+      int rc = op.minv_s(x->y, x->d32, x->z);
+      if (rc) return rc;
+    }
+    return 0;
+  };
+  // refinement rounds over the systems still active
+  while (true) {
+    std::vector<IrSys*> act;
+    for (IrSys& x : st)
+      if (x.active) act.push_back(&x);
+    if (act.empty()) break;
+    for (IrSys* x : act) {
+      x->itol = std::max(inner_floor, 0.5 * o->tol * x->nb / x->rn);
+      const double sv[2] = {1.0 / x->rn, x->rn};
+      int rc = upload(ctx, x->sc + 16, sv, 2);
+      if (rc) return rc;
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 12.0 * x->n, cast_scale_f64_f32(s, x->r64, x->b32, x->n,
+                                                                   x->sc + 16));
+    }
+    int rc = inner_batch(act);
+    if (rc) return rc;
+    for (IrSys* x : act) {
+      x->its += x->iits;
+      x->mv += x->imv;
+      if (x->istatus == KRS_BREAKDOWN || x->istatus == KRS_DIVERGED) {
+        // switch back to rGCROT for this correction (Sec. 2.4), as ir_solve
+        krs_opts jo = io;
+        jo.tol = x->itol;
+        krs_stats ist;
+        const int irc = gmres_rgcrot(ctx, x->q->A32, x->q->M32, x->q->rec32, true, x->b32,
+                                     x->d32, &jo, x->inner, x->inner_bytes, &ist);
+        if (irc < 0) return irc;
+        x->its += ist.iterations;
+        x->mv += ist.matvecs;
+      }
+      const Grid3 g = grid3(x->q->A64);
+      const int nblk = red_blocks(x->n);
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 20.0 * x->n,
+                 axpy_f32_into_f64(s, x->d32, (double*)x->q->x, x->n, x->sc + 17));
+      KRS_LAUNCH(ctx, KRS_K_RESIDUAL, (8.0 * g.pts + 24.0) * x->n,
+                 residual_norm<double>(s, g, (const double*)x->q->A64->bands,
+                                       (const double*)x->q->x, (const double*)x->q->b, x->r64,
+                                       x->part));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<double>(s, x->part, nblk, 1, x->sc));
+    }
+    for (size_t i = 0; i < act.size(); ++i)
+      KRS_CHECK_HIP(ctx, hipMemcpyAsync(ctx->pin + i, act[i]->sc, sizeof(double),
+                                        hipMemcpyDeviceToHost, s));
+    KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
+    timing_flush(ctx);
+    for (size_t i = 0; i < act.size(); ++i) {
+      IrSys* x = act[i];
+      const double rn_new = std::sqrt(ctx->pin[i]);
+      ++x->outer;
+      if (!std::isfinite(rn_new)) {
+        x->status = KRS_DIVERGED;
+        x->rn = rn_new;
+        x->active = false;
+        continue;
+      }
+      const bool stalled = rn_new > 0.9 * x->rn;
+      x->rn = rn_new;
+      if (x->rn <= o->tol * x->nb) {
+        x->status = KRS_OK;
+        x->active = false;
+      } else if (stalled || x->outer >= max_outer) {
+        x->active = false;
+      }
+    }
+  }
+  int worst = KRS_OK;
+  for (IrSys& x : st) {
+    if (x.q->stats && x.nb > 0) {
+      krs_stats* so = x.q->stats;
+      so->status = x.status;
+      so->iterations = x.its;
+      so->matvecs = x.mv;
+      so->outer = x.outer;
+      so->history_len = 0;
+      so->rel_res_true = x.rn / x.nb;
+      so->rel_res_est = x.rn / x.nb;
+      so->solver = KRS_SOLVER_RBICGSTAB;
+    }
+    worst = std::max(worst, x.status);
+  }
+  for (int i : alone) {
+    const krs_ir_system& q = sys[i];
+    const int rc = ir_solve(ctx, q.A64, q.A32, q.M32, q.rec32, q.b, q.x, o, q.ws, q.ws_bytes,
+                            q.stats);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+  }
+  return worst;
 }
 
 }  // namespace krs

@@ -34,8 +34,9 @@ EXPORTS = (
     "krs_matrix_destroy", "krs_precond_create", "krs_precond_workspace_size",
     "krs_precond_refresh", "krs_precond_destroy", "krs_recycle_create", "krs_recycle_destroy", "krs_recycle_dim",
     "krs_recycle_set_dim", "krs_recycle_mark_stale", "krs_workspace_size", "krs_stencil_apply", "krs_precond_apply",
-    "krs_operator_apply", "krs_gmres", "krs_rgcrot_solve", "krs_rbicgstab_solve", "krs_recycle_update",
-    "krs_hybrid_solve", "krs_ir_solve", "krs_version", "krs_timing_enable", "krs_timing_reset",
+    "krs_operator_apply", "krs_gmres", "krs_rgcrot_solve", "krs_rbicgstab_solve",
+    "krs_recycle_update",
+    "krs_hybrid_solve", "krs_ir_solve", "krs_ir_solve_batched", "krs_version", "krs_timing_enable", "krs_timing_reset",
     "krs_timing_read",
 )
 
@@ -81,6 +82,16 @@ _LIB = None
 P = ctypes.c_void_p
 
 
+class IrSystem(ctypes.Structure):
+    _fields_ = [("A64", ctypes.c_void_p), ("A32", ctypes.c_void_p), ("M32", ctypes.c_void_p),
+                ("rec32", ctypes.c_void_p), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
+                ("stats", ctypes.POINTER(Stats))]
+
+
+BATCH_WORKSPACE_BYTES = 64 << 10
+
+
 def _declare(L):
     i32, i64, dbl, sz = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     sig = {
@@ -114,6 +125,8 @@ def _declare(L):
                                    ctypes.POINTER(Stats)]),
         "krs_ir_solve": (i32, [P, P, P, P, P, P, P, ctypes.POINTER(Opts), P, sz,
                                ctypes.POINTER(Stats)]),
+        "krs_ir_solve_batched": (i32, [P, i32, ctypes.POINTER(IrSystem), ctypes.POINTER(Opts), P,
+                                       sz]),
         "krs_version": (ctypes.c_char_p, []),
         "krs_timing_enable": (i32, [P, i32]),
         "krs_timing_reset": (i32, [P]),
@@ -440,6 +453,23 @@ def ir_solve(ctx, A64, A32, M32, rec32, b, x, opts, ws, stats=None):
                             ctypes.byref(opts), _ptr(ws), ws.numel(), ctypes.byref(st))
     ctx.check(rc, allow_outcome=True)
     return rc, st
+
+
+def ir_solve_batched(ctx, systems, opts, ws):
+    """krs_ir_solve_batched.  systems: list of (A64, A32, M32, rec32, b, x, ws)
+    tuples (the arguments of ir_solve for each system); ws: a device buffer of
+    BATCH_WORKSPACE_BYTES.  Returns (rc, [Stats per system])."""
+    check_ws(ws, BATCH_WORKSPACE_BYTES, ctx.device)
+    arr = (IrSystem * max(1, len(systems)))()
+    stats = [Stats() for _ in systems]
+    for i, (A64, A32, M32, rec32, b, x, wsi) in enumerate(systems):
+        _check_solve(ctx, A64, b, x, wsi, torch.float64)
+        arr[i] = IrSystem(A64.h, A32.h, _h(M32), _h(rec32), b.data_ptr(), x.data_ptr(),
+                          wsi.data_ptr(), wsi.numel(), ctypes.pointer(stats[i]))
+    rc = lib().krs_ir_solve_batched(ctx.h, len(systems), arr, ctypes.byref(opts), _ptr(ws),
+                                    ws.numel())
+    ctx.check(rc, allow_outcome=True)
+    return rc, stats
 
 
 KERNEL_CLASSES = ("stencil", "residual", "schwarz_local", "jacobi_sweep", "block_dot",

@@ -17,6 +17,16 @@ Scheduling (`Scheduler`, host logic only, no GPU):
 Execution (`Server`): `n_slots` worker threads, each with its own HIP stream
 and krs context, so the kernels of concurrently admitted solves overlap on the
 device; requests arriving meanwhile are admitted as slots and memory free up.
+With `batch_max` > 1 a batch worker takes up to `batch_max` admissible
+requests of small resident matrices past their rGCROT steps at once and
+solves them with krs_ir_solve_batched: every rBiCGStab pass of all of them
+runs as one launch per step (launch latency, not bandwidth, bounds such
+small solves), and each result is bitwise the one its solve alone gives.
+
+Stream ordering: a matrix's resident state is built on the stream of the
+worker that admits it and that stream is synchronised before the state is
+published; every solve returns only after its stream has drained, so the
+next request of the matrix, on whichever stream, sees all of its updates.
 """
 from __future__ import annotations
 
@@ -50,8 +60,10 @@ class Request:
 class Scheduler:
     """Admission and ordering (thread-safe; no device work)."""
 
-    def __init__(self, n_slots: int, mem_budget: float, state_bytes: Callable[[int], float]):
+    def __init__(self, n_slots: int, mem_budget: float, state_bytes: Callable[[int], float],
+                 classify: Optional[Callable[[int], str]] = None):
         self.n_slots = n_slots
+        self.classify = classify          # mid -> "single" | "batch" (None: all single)
         self.budget = float(mem_budget)
         self.state_bytes = state_bytes
         self.lock = threading.Condition()
@@ -97,34 +109,76 @@ class Scheduler:
             free += vb
         return free >= need, victims
 
+    def _kind(self, mid):
+        return "single" if self.classify is None else self.classify(mid)
+
+    def _take(self, mid):
+        """Admits the first request of `mid` if memory allows (lock held):
+        (request, evict_list, make_resident) or None."""
+        ok, victims = self._admissible(mid)
+        if not ok:
+            return None
+        for v in victims:
+            self.used -= self.resident.pop(v)
+            self.evicted.append(v)
+        new = mid not in self.resident
+        if new:
+            self.resident[mid] = self.state_bytes(mid)
+            self.used += self.resident[mid]
+        self.resident.move_to_end(mid)
+        req = self.queues[mid].popleft()
+        self.busy.add(mid)
+        return req, victims, new
+
+    def _cands(self, kind):
+        return sorted((q[0].t_arrival, mid) for mid, q in self.queues.items()
+                      if q and mid not in self.busy and self._kind(mid) == kind)
+
+    def _drained(self):
+        return self.closed and not any(self.queues.values()) and not self.busy
+
     def next(self, timeout=None):
-        """Blocks until a request can run; returns (request, evict_list,
-        make_resident) or None once closed and drained."""
+        """Blocks until a request of kind "single" can run; returns
+        (request, evict_list, make_resident) or None once closed and drained."""
         with self.lock:
             while True:
                 if self.free_slots > 0:
-                    cands = [(q[0].t_arrival, mid) for mid, q in self.queues.items()
-                             if q and mid not in self.busy]
-                    for _, mid in sorted(cands):
-                        ok, victims = self._admissible(mid)
-                        if not ok:
-                            continue
-                        for v in victims:
-                            self.used -= self.resident.pop(v)
-                            self.evicted.append(v)
-                        new = mid not in self.resident
-                        if new:
-                            self.resident[mid] = self.state_bytes(mid)
-                            self.used += self.resident[mid]
-                        self.resident.move_to_end(mid)
-                        req = self.queues[mid].popleft()
-                        self.busy.add(mid)
-                        self.free_slots -= 1
-                        return req, victims, new
-                if self.closed and not any(self.queues.values()) and not self.busy:
+                    for _, mid in self._cands("single"):
+                        got = self._take(mid)
+                        if got is not None:
+                            self.free_slots -= 1
+                            return got
+                if self._drained():
                     return None
                 if not self.lock.wait(timeout):
                     return "timeout"
+
+    def next_batch(self, max_n, timeout=None):
+        """Blocks until at least one request of kind "batch" can run; returns
+        a list of up to max_n (request, evict_list, make_resident) of
+        distinct matrices, oldest first, or None once closed and drained.
+        The batch runs in a slot of its own (not one of n_slots)."""
+        with self.lock:
+            while True:
+                out = []
+                for _, mid in self._cands("batch"):
+                    if len(out) == max_n:
+                        break
+                    got = self._take(mid)
+                    if got is not None:
+                        out.append(got)
+                if out:
+                    return out
+                if self._drained():
+                    return None
+                if not self.lock.wait(timeout):
+                    return "timeout"
+
+    def finish_batch(self, reqs):
+        with self.lock:
+            for r in reqs:
+                self.busy.discard(r.mid)
+            self.lock.notify_all()
 
     def finish(self, req: Request):
         with self.lock:
@@ -153,7 +207,9 @@ class MatrixSpec:
 
 
 class _State:
-    """Resident device state of one matrix."""
+    """Resident device state of one matrix, built on the current stream of
+    the admitting worker; that stream is drained before the state is used
+    anywhere else."""
 
     def __init__(self, krs, torch, ctx, spec: MatrixSpec, k, pc):
         dev = ctx.device
@@ -166,6 +222,7 @@ class _State:
         self.k = k
         self.rec = krs.Recycle(ctx, self.A32.n, k, torch.float32)
         self.steps_done = 0
+        torch.cuda.current_stream(dev).synchronize()
 
 
 def state_bytes(shape, k, tile=8, npts=7):
@@ -184,7 +241,8 @@ class Server:
     """Request loop over resident matrices with `n_slots` concurrent solves."""
 
     def __init__(self, specs, device="cuda:0", n_slots=4, mem_budget=64e9, m=30, k=20,
-                 n_switch=3, tol=1e-8, inner_tol=1e-5, pc=None):
+                 n_switch=3, tol=1e-8, inner_tol=1e-5, pc=None, batch_max=0,
+                 batch_cells=1 << 18):
         import torch
         from paper_1501_03358_amd import krs
         self.torch, self.krs = torch, krs
@@ -199,16 +257,27 @@ class Server:
                                            torch.float32)
         slot_bytes = self.ws_bytes + 3 * 8 * nmax
         budget = mem_budget - n_slots * slot_bytes
+        # batch worker: small matrices past their rGCROT steps, solved together
+        self.batch_max = batch_max if batch_max > 1 else 0
+        self.batch_cells = min(batch_cells, nmax)
+        if self.batch_max:
+            self.batch_ws_bytes = krs.workspace_size(krs.SOLVER_IR, self.batch_cells, m,
+                                                     max(self.k_of.values()), torch.float32)
+            budget -= self.batch_max * (self.batch_ws_bytes + 3 * 8 * self.batch_cells)
         self.sched = Scheduler(n_slots, budget,
                                lambda mid: state_bytes(self.specs[mid].shape, self.k_of[mid],
                                                        self.pc["tile"],
-                                                       len(self.specs[mid].bands)))
+                                                       len(self.specs[mid].bands)),
+                               classify=self._classify if self.batch_max else None)
         self.states = {}
         self.states_lock = threading.Lock()
         self.completed = []
         self.errors = []
         self.threads = [threading.Thread(target=self._worker, args=(i,), daemon=True)
                         for i in range(n_slots)]
+        if self.batch_max:
+            self.threads.append(threading.Thread(target=self._batch_worker, daemon=True))
+        self.batches = []                 # sizes of the batches run
         for th in self.threads:
             th.start()
 
@@ -216,6 +285,20 @@ class Server:
         """False (and req.status == REJECTED, req.done set) when the
         request's matrix cannot fit the memory budget."""
         return self.sched.submit(req)
+
+    def _n_switch(self, mid):
+        ns = self.specs[mid].n_switch
+        return self.n_switch if ns is None else ns
+
+    def _classify(self, mid):
+        """"batch": a resident 7-band matrix of at most batch_cells cells past
+        its rGCROT steps (the next solve is an rBiCGStab one); else "single"."""
+        spec = self.specs[mid]
+        if int(np.prod(spec.shape)) > self.batch_cells or len(spec.bands) != 7:
+            return "single"
+        with self.states_lock:
+            st = self.states.get(mid)
+            return "batch" if st is not None and st.steps_done >= self._n_switch(mid) else "single"
 
     def close(self, wait=True):
         self.sched.close()
@@ -253,9 +336,7 @@ class Server:
                     n = st.A32.n
                     b = torch.from_numpy(req.b).to(self.device, non_blocking=False)
                     x = torch.empty(n, dtype=torch.float64, device=self.device)
-                    spec_ns = self.specs[req.mid].n_switch
-                    ns = self.n_switch if spec_ns is None else spec_ns
-                    inner = (krs.SOLVER_RGCROT if st.steps_done < ns
+                    inner = (krs.SOLVER_RGCROT if st.steps_done < self._n_switch(req.mid)
                              else krs.SOLVER_RBICGSTAB)
                     o = krs.make_opts(m=self.m, k=st.k, tol=self.tol, inner_solver=inner,
                                       inner_tol=self.inner_tol, max_matvecs=4000)
@@ -273,6 +354,60 @@ class Server:
                     self.completed.append(req)
                     self.sched.finish(req)
                     req.done.set()
+            stream.synchronize()
+
+
+    def _batch_worker(self):
+        torch, krs = self.torch, self.krs
+        torch.cuda.set_device(self.device)
+        stream = torch.cuda.Stream(device=self.device)
+        with torch.cuda.stream(stream):
+            ctx = krs.Context(self.device, stream)
+            wss = [torch.empty(self.batch_ws_bytes, dtype=torch.uint8, device=self.device)
+                   for _ in range(self.batch_max)]
+            tws = torch.empty(krs.BATCH_WORKSPACE_BYTES, dtype=torch.uint8, device=self.device)
+            while True:
+                items = self.sched.next_batch(self.batch_max, timeout=0.5)
+                if items is None:
+                    break
+                if items == "timeout":
+                    continue
+                reqs = [it[0] for it in items]
+                try:
+                    t0 = time.perf_counter()
+                    systems, sts = [], []
+                    for (req, victims, new), ws in zip(items, wss):
+                        req.t_start = t0
+                        with self.states_lock:
+                            for v in victims:
+                                self.states.pop(v, None)
+                            st = self.states[req.mid]   # batch requests are resident
+                        b = torch.from_numpy(req.b).to(self.device)
+                        x = torch.empty(st.A32.n, dtype=torch.float64, device=self.device)
+                        systems.append((st.A64, st.A32, st.M32, st.rec, b, x, ws))
+                        sts.append(st)
+                    o = krs.make_opts(m=self.m, k=min(st.k for st in sts), tol=self.tol,
+                                      inner_solver=krs.SOLVER_RBICGSTAB,
+                                      inner_tol=self.inner_tol, max_matvecs=4000)
+                    rc, stats = krs.ir_solve_batched(ctx, systems, o, tws)
+                    self.batches.append(len(reqs))
+                    for req, sysd, sst, st in zip(reqs, systems, stats, sts):
+                        req.x = sysd[5].cpu().numpy()
+                        req.status = sst.status
+                        req.stats = sst.as_dict()
+                        st.steps_done += 1
+                except Exception as exc:  # surfaced to the caller via self.errors
+                    for req in reqs:
+                        req.status = -100
+                    self.errors.append((reqs[0].rid, repr(exc)))
+                finally:
+                    t1 = time.perf_counter()
+                    for req in reqs:
+                        req.t_done = t1
+                        self.completed.append(req)
+                    self.sched.finish_batch(reqs)
+                    for req in reqs:
+                        req.done.set()
             stream.synchronize()
 
 

@@ -123,3 +123,82 @@ def test_breakdown_site_reported_alike(gpu_lib):
                                      krs.make_opts(tol=1e-8, flags=flags), d.ws)
         assert rc == krs.BREAKDOWN and st.breakdown_site == 1, (flags, rc, st.breakdown_site)
         assert st.matvecs == ref.matvecs == 1
+
+
+# ---------------------------------------------------------------------------
+# GMRES / rGCROT: the Arnoldi step ends (Givens rotations, residual estimate,
+# stopping tests) on the device, read once per batch of steps, against the
+# host loop that reads every step and rotates on the host
+# ---------------------------------------------------------------------------
+
+def _arnoldi_seq(krs, d, prob, bs, m, k, tol, flags, gmres=False, maxmv=4000):
+    rec = krs.Recycle(d.ctx, prob.n, k, d.dtype)
+    out = []
+    for b in bs:
+        h = np.zeros(4000)
+        x = d.empty()
+        o = krs.make_opts(m=m, k=k, tol=tol, history=h, flags=flags, max_matvecs=maxmv)
+        if gmres:
+            rc, st = krs.gmres(d.ctx, d.A, d.M, d.vec(b), x, o, d.ws)
+        else:
+            rc, st = krs.rgcrot_solve(d.ctx, d.A, d.M, rec, d.vec(b), x, o, d.ws)
+        U, C = rec.views()
+        out.append((rc, st, h[:st.history_len].copy(), x.clone(), U.clone(), C.clone()))
+    return out
+
+
+def _same_arnoldi(a, c):
+    assert a[0] == c[0]
+    for f in ("iterations", "matvecs", "cycles", "history_len", "second_passes", "eig_ties"):
+        assert getattr(a[1], f) == getattr(c[1], f), (f, getattr(a[1], f), getattr(c[1], f))
+    for f in ("rel_res_est", "rel_res_true"):
+        assert np.array_equal(getattr(a[1], f), getattr(c[1], f), equal_nan=True), f
+    assert np.array_equal(a[2], c[2])
+    for i in (3, 4, 5):
+        assert torch.equal(a[i], c[i])
+
+
+@pytest.mark.parametrize("case", ["grf24_jacobi_f64", "porous32_schwarz_f64",
+                                  "porous32_schwarz_f32", "channel32_schwarz_f64"])
+def test_arnoldi_device_loop_equals_host_loop(gpu_lib, case):
+    """rGCROT(m,k) sequences with recycle updates, GMRES(m), a step cap in
+    the middle of a cycle, and a tolerance met inside a batch: x, U, C, the
+    history, counts and statuses bitwise equal in both modes."""
+    krs = gpu_lib
+    name, pc, dt = case.split("_")
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    if name == "grf24":
+        prob = W.grf_problem(24, extra=61)
+        bs = W.rhs_perturbed(prob, 3, extra=61)
+        params = None
+    else:
+        prob = (W.porous_problem(32, extra=62) if name.startswith("porous")
+                else W.channel_problem(32))
+        bs = list(W.rhs_ar1(prob, 3, extra=62))
+        params = dict(W.SCHWARZ_DEFAULT)
+    d = Dev(krs, prob, pc, params, dtype=dtype, m=20, k=10)
+    tol = 1e-8 if dtype == torch.float64 else 1e-5
+    for gm in (False, True):
+        a = _arnoldi_seq(krs, d, prob, bs, 20, 10, tol, krs.FLAG_HOST_LOOP, gmres=gm)
+        c = _arnoldi_seq(krs, d, prob, bs, 20, 10, tol, 0, gmres=gm)
+        for x, y in zip(a, c):
+            _same_arnoldi(x, y)
+        assert all(r[0] == krs.OK for r in a)
+    # step caps (inside the first and the second cycle): not converged, alike
+    for maxmv in (13, 27):
+        a = _arnoldi_seq(krs, d, prob, bs[:1], 20, 10, 1e-14, krs.FLAG_HOST_LOOP, maxmv=maxmv)
+        c = _arnoldi_seq(krs, d, prob, bs[:1], 20, 10, 1e-14, 0, maxmv=maxmv)
+        _same_arnoldi(a[0], c[0])
+        assert a[0][0] == krs.NOT_CONVERGED and a[0][1].iterations == maxmv
+
+
+def test_arnoldi_device_loop_zero_rhs(gpu_lib):
+    krs = gpu_lib
+    prob = W.grf_problem(8, extra=63)
+    d = Dev(krs, prob, "jacobi", m=10, k=4)
+    for flags in (krs.FLAG_HOST_LOOP, 0):
+        x = d.empty()
+        rc, st = krs.rgcrot_solve(d.ctx, d.A, d.M, krs.Recycle(d.ctx, prob.n, 4, torch.float64),
+                                  d.vec(np.zeros(prob.n)), x, krs.make_opts(m=10, k=4,
+                                                                            flags=flags), d.ws)
+        assert rc == krs.OK and st.iterations == 0 and float(x.abs().max()) == 0.0

@@ -278,20 +278,22 @@ def channel_problem(n=128, ratio=1.1, g=None):
 
 
 def porous_problem(n=128, seed_cfg=3, extra=0, solid_fraction=0.4,
-                   k_solid=1e-3, rmin=3.0, rmax=6.0):
-    """Sphere-pack porous medium on a uniform n^3 grid (unit volumes): k = 1 in
-    fluid and k_solid in solid cells; Dirichlet p = 0 on the x-max face,
-    Neumann elsewhere (nonsingular)."""
+                   k_solid=1e-3, rmin=3.0, rmax=6.0, shape=None):
+    """Sphere-pack porous medium on a uniform n^3 grid, or on an
+    nx x ny x nz grid when `shape` = (nx, ny, nz) is given (unit volumes):
+    k = 1 in fluid and k_solid in solid cells; Dirichlet p = 0 on the x-max
+    face, Neumann elsewhere (nonsingular)."""
+    nx, ny, nz = (n, n, n) if shape is None else tuple(int(v) for v in shape)
     s_coef, _, _, _ = _seeds(seed_cfg, extra)
-    solid = sphere_pack((n, n, n), rmin, rmax, solid_fraction,
+    solid = sphere_pack((nz, ny, nx), rmin, rmax, solid_fraction,
                         np.random.default_rng(s_coef))
     kcell = np.where(solid, k_solid, 1.0)
-    vol = np.ones((n, n, n))
+    vol = np.ones((nz, ny, nx))
     bc = {'x': ('neumann', 'dirichlet'), 'y': ('neumann', 'neumann'),
           'z': ('neumann', 'neumann')}
-    ones = np.ones(n)
-    bands = assemble(kcell, vol, (ones, ones, ones), bc)
-    return Problem(f"porous{n}", (n, n, n), (False, False, False), bands,
+    bands = assemble(kcell, vol, (np.ones(nx), np.ones(ny), np.ones(nz)), bc)
+    name = f"porous{n}" if shape is None else f"porous{nx}x{ny}x{nz}"
+    return Problem(name, (nx, ny, nz), (False, False, False), bands,
                    vol.reshape(-1), False)
 
 
