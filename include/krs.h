@@ -322,6 +322,27 @@ int krs_rbicgstab_solve(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M,
                         const krs_recycle* rec, const void* b, void* x, const krs_opts* opts,
                         void* ws, size_t ws_bytes, krs_stats* stats);
 
+/* Size (bytes) of the static device workspace of krs_rbicgstab_solve_noalloc,
+ * one per GPU the library runs on, held until the process ends. */
+#define KRS_NOALLOC_SCRATCH_BYTES ((size_t)48 << 20)
+
+/* krs_rbicgstab_solve without allocations, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): the same solve with its workspace in a static device
+ * array of KRS_NOALLOC_SCRATCH_BYTES (whose device address is looked up when
+ * a context is created on that GPU) instead of a caller buffer.  Arguments as
+ * for krs_rbicgstab_solve; the caller still provides b, x, the matrix,
+ * preconditioner and recycle space.  Returns KRS_ERR_WORKSPACE when
+ * krs_workspace_size(KRS_SOLVER_RBICGSTAB, N, ...) exceeds the static size
+ * (FP64 up to about 5.2e5 unknowns, FP32 up to about 1.3e6), KRS_ERR_ARG
+ * with KRS_FLAG_GRAPH and KRS_ERR_STATE while kernel timing is on (both
+ * create runtime objects).  Calls no allocating routine.  All calls on one
+ * GPU share the array: calls that overlap in time on one GPU (concurrent
+ * streams or threads) race and must be serialised by the caller. */
+int krs_rbicgstab_solve_noalloc(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M,
+                                const krs_recycle* rec, const void* b, void* x,
+                                const krs_opts* opts, krs_stats* stats);
+
 /* Recycle-space setup of Alg. 3 and 4: C~ = A~ U, thin QR C~ = C R (Cholesky QR,
  * twice), U <- U R^-1.  Call when A changed or U was set by the caller. */
 int krs_recycle_update(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,

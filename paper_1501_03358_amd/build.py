@@ -16,7 +16,7 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 SOURCES = [("kernels.hip", DEVICE_FLAGS), ("solvers.cpp", HOST_FLAGS),
            ("dense.cpp", HOST_FLAGS), ("api.cpp", HOST_FLAGS),
-           ("timing.cpp", HOST_FLAGS)]
+           ("timing.cpp", HOST_FLAGS), ("noalloc.hip", DEVICE_FLAGS)]
 
 
 def _compile(src, flags):

@@ -79,6 +79,12 @@ int krs_create(krs_ctx** out, void* hip_stream) {
     delete c;
     return KRS_ERR_HIP;
   }
+  // device address of this GPU's static workspace (krs_rbicgstab_solve_noalloc)
+  if (krs::noalloc_init(c) != KRS_OK) {
+    (void)hipHostFree(c->pin);
+    delete c;
+    return KRS_ERR_HIP;
+  }
   *out = c;
   return KRS_OK;
 }

@@ -205,6 +205,9 @@ int rbicgstab(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const krs
               const void* b, void* x, const krs_opts* o, void* ws, size_t wsb, krs_stats* st);
 int recycle_setup(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, krs_recycle* rec,
                   void* ws, size_t wsb);
+// per-device lookup of the static workspace of krs_rbicgstab_solve_noalloc
+// (noalloc.hip); the context's device must be current
+int noalloc_init(krs_ctx* ctx);
 // krs_ir_solve_batched (grouped rBiCGStab inner passes; bitwise as alone)
 int ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys, const krs_opts* o,
                      void* ws, size_t wsb);

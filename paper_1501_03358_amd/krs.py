@@ -35,7 +35,7 @@ EXPORTS = (
     "krs_precond_refresh", "krs_precond_destroy", "krs_recycle_create", "krs_recycle_destroy", "krs_recycle_dim",
     "krs_recycle_set_dim", "krs_recycle_mark_stale", "krs_workspace_size", "krs_stencil_apply", "krs_precond_apply",
     "krs_operator_apply", "krs_gmres", "krs_rgcrot_solve", "krs_rbicgstab_solve",
-    "krs_recycle_update",
+    "krs_rbicgstab_solve_noalloc", "krs_recycle_update",
     "krs_hybrid_solve", "krs_ir_solve", "krs_ir_solve_batched", "krs_version", "krs_timing_enable", "krs_timing_reset",
     "krs_timing_read",
 )
@@ -120,6 +120,8 @@ def _declare(L):
                                    ctypes.POINTER(Stats)]),
         "krs_rbicgstab_solve": (i32, [P, P, P, P, P, P, ctypes.POINTER(Opts), P, sz,
                                       ctypes.POINTER(Stats)]),
+        "krs_rbicgstab_solve_noalloc": (i32, [P, P, P, P, P, P, ctypes.POINTER(Opts),
+                                              ctypes.POINTER(Stats)]),
         "krs_recycle_update": (i32, [P, P, P, P, P, sz]),
         "krs_hybrid_solve": (i32, [P, P, P, P, i32, i32, P, P, ctypes.POINTER(Opts), P, sz,
                                    ctypes.POINTER(Stats)]),
@@ -428,6 +430,18 @@ def rbicgstab_solve(ctx, A, M, rec, b, x, opts, ws, stats=None):
     st = stats or Stats()
     rc = lib().krs_rbicgstab_solve(ctx.h, A.h, _h(M), _h(rec), _ptr(b), _ptr(x),
                                    ctypes.byref(opts), _ptr(ws), ws.numel(), ctypes.byref(st))
+    ctx.check(rc, allow_outcome=True)
+    return rc, st
+
+
+def rbicgstab_solve_noalloc(ctx, A, M, rec, b, x, opts, stats=None):
+    """krs_rbicgstab_solve with the library's static per-GPU workspace
+    (no workspace argument, no allocation)."""
+    check_vec(b, A.n, A.dtype, ctx.device, "b")
+    check_vec(x, A.n, A.dtype, ctx.device, "x")
+    st = stats or Stats()
+    rc = lib().krs_rbicgstab_solve_noalloc(ctx.h, A.h, _h(M), _h(rec), _ptr(b), _ptr(x),
+                                           ctypes.byref(opts), ctypes.byref(st))
     ctx.check(rc, allow_outcome=True)
     return rc, st
 
