@@ -1212,28 +1212,25 @@ __global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t
 // coefficients stay in FP64 and each output is summed in FP64 and rounded
 // once: the recycle update's coefficients (P R^-1 with an ill-conditioned R)
 // are large with cancelling terms, where FP32 products and sums would each
-// add rounding of the size of the largest term.
+// add rounding of the size of the largest term.  The coefficients are the
+// same for every lane, so they are read with scalar loads (no LDS traffic
+// per multiply-add).
 template <class T, int NIN>
 __global__ __launch_bounds__(kThreads) void k_row_transform(Cols<T> In, const double* M,
                                                             int nout, T* out, int64_t ldo,
                                                             int64_t n) {
-  extern __shared__ unsigned char smem_raw[];
-  double* Ms = reinterpret_cast<double*>(smem_raw);
   const int nin = In.n1 + In.n2;
-  for (int idx = threadIdx.x; idx < NIN * nout; idx += kThreads) {
-    const int c = idx % NIN, o = idx / NIN;
-    Ms[idx] = c < nin ? M[c + nin * o] : 0.0;
-  }
-  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
-  double v[NIN];
+  T v[NIN];
 #pragma unroll
-  for (int c = 0; c < NIN; ++c) v[c] = (double)col_ptr(In, min(c, nin - 1))[i];
+  for (int c = 0; c < NIN; ++c) v[c] = col_ptr(In, min(c, nin - 1))[i];
   for (int o = 0; o < nout; ++o) {
+    const double* mo = M + (int64_t)nin * o;
     double s = 0;
 #pragma unroll
-    for (int c = 0; c < NIN; ++c) s += v[c] * Ms[o * NIN + c];
+    for (int c = 0; c < NIN; ++c)
+      if (c < nin) s += (double)v[c] * mo[c];
     out[(int64_t)o * ldo + i] = (T)s;
   }
 }
@@ -2320,9 +2317,7 @@ hipError_t row_transform(hipStream_t s, const Cols<T>& In, const double* M, int 
   const int grid = grid_for(n);
 #define KRS_RT(NINB)                                                                 \
   do {                                                                               \
-    const size_t smem = sizeof(double) * (size_t)(NINB) * nout;                      \
-    if (smem > 64 * 1024) return hipErrorInvalidValue;                               \
-    k_row_transform<T, NINB><<<grid, kThreads, smem, s>>>(In, M, nout, out, ldo, n); \
+    k_row_transform<T, NINB><<<grid, kThreads, 0, s>>>(In, M, nout, out, ldo, n);    \
   } while (0)
   if (nin <= 8) KRS_RT(8);
   else if (nin <= 16) KRS_RT(16);
