@@ -265,7 +265,7 @@ def grf24_main(args):
     print(json.dumps(out), flush=True)
 
 
-def serve_leg(n_matrices=16, grids=(32, 64), per_matrix=4, duration=8.0, batch_max=8):
+def serve_leg(n_matrices=16, grids=(32, 64), per_matrix=4, duration=8.0, batch_max=16):
     """A short serving run for the default benchmark line: n_matrices small
     resident matrices (channel and porous coefficients alternating, grids
     drawn from `grids`), the hybrid per matrix (rGCROT steps first), FP32

@@ -1411,6 +1411,22 @@ __global__ void k_cgs2_combine(int ncols, const double* h1, const double* h2, do
   flag[0] = f;
 }
 
+__global__ void k_bicg_setup(double* sc, int kc, double tol, double div_factor) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0) return;
+  const double nb2 = sc[kBNb2];
+  const double rn2 = kc > 0 ? sc[kBNrm] : nb2;
+  for (int c = 0; c < kc; ++c) sc[kBXi + c] = -sc[kBEta1 + c];
+  for (int i = 0; i < kSlots; ++i) sc[i] = 0.0;
+  sc[kRho] = rn2;
+  sc[kOmega] = 1.0;
+  sc[kBeta] = 0.0;
+  sc[kRnorm2] = rn2;
+  const double nb = sqrt(nb2);
+  sc[kTolAbs] = tol * nb;
+  sc[kDivAbs] = div_factor > 0 ? div_factor * nb : INFINITY;
+}
+
 // End of Arnoldi step j of a cycle, on the device (one thread): store the new
 // column [B; Hbar] from hcol = [C V_j]^T-coefficients with the new norm
 // appended, rotate it by the j previous Givens rotations, form rotation j,
@@ -2348,6 +2364,11 @@ hipError_t finish_cgs2(hipStream_t s, const T* partials, int nblk, int ncols, co
 hipError_t cgs_decide(hipStream_t s, int ncols, const double* h1, double* hcol, double* inv,
                       int* flag, int* skip) {
   k_cgs_decide<<<1, 64, 0, s>>>(ncols, h1, hcol, inv, flag, skip);
+  return hipGetLastError();
+}
+
+hipError_t bicg_setup(hipStream_t s, double* sc, int kc, double tol, double div_factor) {
+  k_bicg_setup<<<1, 64, 0, s>>>(sc, kc, tol, div_factor);
   return hipGetLastError();
 }
 

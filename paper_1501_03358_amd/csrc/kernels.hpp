@@ -208,7 +208,15 @@ hipError_t arnoldi_givens(hipStream_t s, double* arn, const double* hcol, const 
 // offsets (doubles) of the rBiCGStab scalar area beyond the BicgSlot slots:
 // finished sums, C^T v / C^T t (eta1, eta2), the postponed U-coefficients
 // xi, C^T r~, ||b||^2
-enum BicgOff { kBSums = 32, kBEta1 = 128, kBEta2 = 192, kBXi = 256, kBCtrt = 320, kBNrm = 384 };
+enum BicgOff {
+  kBSums = 32, kBEta1 = 128, kBEta2 = 192, kBXi = 256, kBCtrt = 320, kBNrm = 384, kBNb2 = 385
+};
+// Starting state of an rBiCGStab solve from its setup sums: xi = -eta1, the
+// slots (rho = |r_0|^2, omega = 1, beta = 0, the absolute tolerance and
+// divergence thresholds from ||b|| = sqrt(sc[kBNb2])); |r_0|^2 is sc[kBNrm]
+// after the projection (kc > 0) or ||b||^2 (kc = 0).  The same values the
+// host forms and uploads in the single-system driver.
+hipError_t bicg_setup(hipStream_t s, double* sc, int kc, double tol, double div_factor);
 
 // ---- grouped rBiCGStab passes over several independent FP32 systems ----
 // Every launch covers all systems of a batch: system s owns the block range

@@ -1698,8 +1698,10 @@ int ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys, const krs
   std::vector<int> in_table;
   // one device-driven batch of rBiCGStab inner solves of the active systems
   auto inner_batch = [&](std::vector<IrSys*>& act) -> int {
-    // setup of each inner solve (as rbicgstab_t): ||b||, projection of b
-    // against C, r~, C^T r~, zero p v y, scalar slots
+    // setup of each inner solve, enqueued for all systems before one
+    // synchronisation: the kernels rbicgstab_t runs (||b||, projection of b
+    // against C, r~, C^T r~, zero p v y) and the starting state it forms on
+    // the host, formed on the device (same values)
     std::vector<IrSys*> run;
     for (IrSys* x : act) {
       const krs_recycle* rec = x->q->rec32;
@@ -1707,21 +1709,15 @@ int ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys, const krs
       const Cols<float> Cc = cols<float>(rec ? (const float*)rec->C : nullptr, rec ? rec->ld : 0,
                                          kc);
       const int nblk = std::min(red_blocks(x->n), 512);
+      const int nred = red_blocks(x->n);
       const double NW = (double)x->n * sizeof(float);
       x->iits = 0;
       x->imv = 0;
       x->istatus = KRS_NOT_CONVERGED;
       x->inner_running = false;
-      double nb2 = 0;
-      int rc = norm2<float>(ctx, x->b32, x->n, x->ipart, x->isc + kBNrm, nb2);
-      if (rc) return rc;
-      x->inb = std::sqrt(nb2);
-      if (x->inb == 0 || !std::isfinite(x->inb)) {
-        KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<float>(s, x->d32, x->n, 0.0));
-        x->istatus = std::isfinite(x->inb) ? KRS_OK : KRS_DIVERGED;
-        continue;
-      }
-      double rn2 = nb2;
+      KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW,
+                 block_dot<float>(s, Cols<float>{}, x->b32, x->n, 1, x->ipart, nred));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<float>(s, x->ipart, nred, 1, x->isc + kBNb2));
       if (kc > 0) {
         KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 1),
                    block_dot<float>(s, Cc, x->b32, x->n, 0, x->ipart, nblk));
@@ -1731,15 +1727,6 @@ int ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys, const krs
                    block_update<float>(s, Cc, x->isc + kBEta1, -1.0, x->b32, x->r, x->n, nullptr,
                                        1, x->ipart, nblk));
         KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<float>(s, x->ipart, nblk, 1, x->isc + kBNrm));
-        rc = read_dev(ctx, x->isc + kBEta1, kc);
-        if (rc) return rc;
-        std::vector<double> xi(kc);
-        for (int c = 0; c < kc; ++c) xi[c] = -ctx->pin[c];
-        rc = upload(ctx, x->isc + kBXi, xi.data(), kc);
-        if (rc) return rc;
-        rc = read_dev(ctx, x->isc + kBNrm, 1);
-        if (rc) return rc;
-        rn2 = ctx->pin[0];
       } else {
         KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<float>(s, x->b32, x->r, x->n));
       }
@@ -1753,15 +1740,26 @@ int ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys, const krs
       KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<float>(s, x->p, x->n, 0.0));
       KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<float>(s, x->v, x->n, 0.0));
       KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<float>(s, x->y, x->n, 0.0));
-      std::vector<double> slots(kSlots, 0.0);
-      slots[kRho] = rn2;
-      slots[kOmega] = 1.0;
-      slots[kBeta] = 0.0;
-      slots[kRnorm2] = rn2;
-      slots[kTolAbs] = x->itol * x->inb;
-      slots[kDivAbs] = io.div_factor > 0 ? io.div_factor * x->inb : INFINITY;
-      rc = upload(ctx, x->isc, slots.data(), kSlots);
-      if (rc) return rc;
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_setup(s, x->isc, kc, x->itol, io.div_factor));
+    }
+    for (size_t i = 0; i < act.size(); ++i)
+      KRS_CHECK_HIP(ctx, hipMemcpyAsync(ctx->pin + 2 * i, act[i]->isc + kBNrm,
+                                        2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    KRS_CHECK_HIP(ctx, hipStreamSynchronize(s));
+    timing_flush(ctx);
+    for (size_t i = 0; i < act.size(); ++i) {
+      IrSys* x = act[i];
+      const krs_recycle* rec = x->q->rec32;
+      const int kc = rec ? rec->dim : 0;
+      const double nb2 = ctx->pin[2 * i + 1];
+      const double rn2 = kc > 0 ? ctx->pin[2 * i] : nb2;
+      x->inb = std::sqrt(nb2);
+      if (x->inb == 0 || !std::isfinite(x->inb)) {
+        KRS_LAUNCH(ctx, KRS_K_OTHER, (double)x->n * sizeof(float),
+                   fill<float>(s, x->d32, x->n, 0.0));
+        x->istatus = std::isfinite(x->inb) ? KRS_OK : KRS_DIVERGED;
+        continue;
+      }
       x->irnorm = std::sqrt(rn2);
       if (x->irnorm > x->itol * x->inb) {
         x->inner_running = true;
