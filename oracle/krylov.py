@@ -428,7 +428,7 @@ def rgcrot(op, minv, b, m, k, tol, rec: Recycle, update=True, max_its=2000, orth
             w = op(V[:, j])
             its += 1
             mv += 1
-            w, (bcol, h) = _orthogonalize(w, [rec.C, V[:, :j + 1]], orth)  # 6a-9
+            w, (bcol, h) = _orthogonalize(w, [rec.C, V[:, :j + 1]], orth)  # against C, then V
             Bm[:, j] = bcol
             H[:j + 1, j] = h
             H[j + 1, j] = _norm(w)

@@ -164,7 +164,7 @@ hipError_t bicg_yr(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, con
                    int nblk);
 // Finishing reductions fused with the scalar step that uses them (one block):
 // finish + alpha; finish |s|^2 + half-step tests (with the scalar part of the
-// line-10 exit); the vector part of that exit (runs only when it fired);
+// early exit after the first half-step); the vector part of that exit (runs only when it fired);
 // finish + omega/xi; finish rho, |r|^2 + beta + full-step tests.
 template <class T>
 hipError_t bicg_finish_alpha(hipStream_t s, const T* partials, int nblk, int kc, double* sums,
@@ -246,9 +246,9 @@ struct BatchTable {
   int nsys;
   int elem[kMaxBatch + 1];   // block ranges: one row per thread
   int pack[kMaxBatch + 1];   //   four rows per thread (stencil packs)
-  int tile[kMaxBatch + 1];   //   one Schwarz tile per block
+  int tile[kMaxBatch + 1];   //   two Schwarz tiles (an x-pair) per block
   int pass[kMaxBatch + 1];   //   streaming passes (nblk blocks)
-  int exitv[kMaxBatch + 1];  //   the line-10 exit update (at most 512 blocks)
+  int exitv[kMaxBatch + 1];  //   the half-step exit update (at most 512 blocks)
   int fin[kMaxBatch + 1];    //   one block per system (finishing reductions)
   BatchSys sys[kMaxBatch];
 };

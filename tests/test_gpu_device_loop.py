@@ -61,7 +61,7 @@ def test_device_loop_equals_host_loop(gpu_lib, pc, dtype):
         for tol in tols:
             rc, st = _compare(krs, d, use_rec, bs[2], float(tol), 4000)
             half_exits += st.matvecs % 2 == 1 and rc == krs.OK
-    assert half_exits > 0          # the line-10 exit was exercised
+    assert half_exits > 0          # the exit after the first half-step was exercised
     # iteration caps, odd and even: not converged, same counts
     for maxmv in (7, 8):
         rc, st = _compare(krs, d, None, bs[2], 1e-14, maxmv)
