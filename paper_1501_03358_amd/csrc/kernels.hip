@@ -1335,24 +1335,53 @@ __global__ __launch_bounds__(kThreads) void k_gram(Cols<T> X, Cols<T> Y, int64_t
 // are large with cancelling terms, where FP32 products and sums would each
 // add rounding of the size of the largest term.  The coefficients are the
 // same for every lane, so they are read with scalar loads (no LDS traffic
-// per multiply-add).
+// per multiply-add).  Four outputs are summed together, so that each input
+// is widened to FP64 once per four products (each sum still runs over the
+// inputs in order, rounded once).  NIN is nin rounded up to a multiple of 8:
+// the loop over the inputs has no branch, so the coefficient loads of whole
+// groups of 8 inputs are issued together; in the last group, inputs past nin
+// are zero and read the coefficient of the last input (adding exact zeros).
 template <class T, int NIN>
 __global__ __launch_bounds__(kThreads) void k_row_transform(Cols<T> In, const double* M,
                                                             int nout, T* out, int64_t ldo,
                                                             int64_t n) {
+  constexpr int OG = 4;
+  static_assert(NIN % 8 == 0, "inputs in groups of 8");
   const int nin = In.n1 + In.n2;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
   T v[NIN];
 #pragma unroll
-  for (int c = 0; c < NIN; ++c) v[c] = col_ptr(In, min(c, nin - 1))[i];
-  for (int o = 0; o < nout; ++o) {
-    const double* mo = M + (int64_t)nin * o;
-    double s = 0;
+  for (int c = 0; c < NIN; ++c) v[c] = c < nin ? col_ptr(In, c)[i] : T(0);
+  if constexpr (sizeof(T) == 8) {
+    // FP64 data: one output at a time, each product behind its own branch
+    // (the grouped form below spills at this width)
+    for (int o = 0; o < nout; ++o) {
+      const double* m = M + (int64_t)nin * o;
+      double s = 0;
 #pragma unroll
-    for (int c = 0; c < NIN; ++c)
-      if (c < nin) s += (double)v[c] * mo[c];
-    out[(int64_t)o * ldo + i] = (T)s;
+      for (int c = 0; c < NIN; ++c)
+        if (c < nin) s += (double)v[c] * m[c];
+      out[(int64_t)o * ldo + i] = (T)s;
+    }
+    return;
+  }
+  for (int o0 = 0; o0 < nout; o0 += OG) {
+    // a short last group repeats the last output (computed, not stored)
+    const double* mo[OG];
+#pragma unroll
+    for (int j = 0; j < OG; ++j) mo[j] = M + (int64_t)nin * min(o0 + j, nout - 1);
+    double s[OG] = {};
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) {
+      const int cc = c < NIN - 8 ? c : min(c, nin - 1);
+      const double dv = (double)v[c];
+#pragma unroll
+      for (int j = 0; j < OG; ++j) s[j] += dv * mo[j][cc];
+    }
+#pragma unroll
+    for (int j = 0; j < OG; ++j)
+      if (o0 + j < nout) out[(int64_t)(o0 + j) * ldo + i] = (T)s[j];
   }
 }
 
@@ -2459,12 +2488,17 @@ hipError_t row_transform(hipStream_t s, const Cols<T>& In, const double* M, int 
   do {                                                                               \
     k_row_transform<T, NINB><<<grid, kThreads, 0, s>>>(In, M, nout, out, ldo, n);    \
   } while (0)
-  if (nin <= 8) KRS_RT(8);
-  else if (nin <= 16) KRS_RT(16);
-  else if (nin <= 32) KRS_RT(32);
-  else if (nin <= 48) KRS_RT(48);
-  else if (nin <= 64) KRS_RT(64);
-  else return hipErrorInvalidValue;
+  switch ((nin + 7) / 8) {
+    case 1: KRS_RT(8); break;
+    case 2: KRS_RT(16); break;
+    case 3: KRS_RT(24); break;
+    case 4: KRS_RT(32); break;
+    case 5: KRS_RT(40); break;
+    case 6: KRS_RT(48); break;
+    case 7: KRS_RT(56); break;
+    case 8: KRS_RT(64); break;
+    default: return hipErrorInvalidValue;
+  }
 #undef KRS_RT
   return hipGetLastError();
 }

@@ -85,6 +85,9 @@ PC_CASES = [
     ("grf16_t4", lambda: W.grf_problem(16, extra=3), SMALL_SCHWARZ),
     ("channel24_t8", lambda: W.channel_problem(24), dict(tile=8)),
     ("porous32_t8", lambda: W.porous_problem(32, extra=5), dict(tile=8)),
+    # even tile counts on every axis: FP32 runs the two-tiles-per-block form
+    ("pairs32x16x48_periodic", lambda: _ragged((32, 16, 48), (True, False, True), 16),
+     dict(tile=8)),
     ("grf8_t4_nosweep", lambda: W.grf_problem(8, extra=4), dict(tile=4, global_sweeps=0)),
     ("grf8_t4_2global", lambda: W.grf_problem(8, extra=4), dict(tile=4, global_sweeps=2)),
     # SSOR local smoother (colour-ordered forward and backward sweeps)
@@ -185,6 +188,8 @@ OP_CASES = PC_CASES + [
      dict(tile=8)),
     ("fused40x40x2624", lambda: _ragged((40, 40, 2624), (False, True, False), 9), dict(tile=8)),
     ("fused24x24x7296_px", lambda: _ragged((24, 24, 7296), (True, False, False), 10),
+     dict(tile=8)),
+    ("fused_pairs64x32x2048", lambda: _ragged((64, 32, 2048), (True, True, False), 17),
      dict(tile=8)),
     # a 19-point operator of that size runs the sweep and the matvec separately
     ("ragged19_72x24x2432_periodic", lambda: _ragged19((72, 24, 2432), (True, True, True), 15),
