@@ -191,6 +191,9 @@ OP_CASES = PC_CASES + [
      dict(tile=8)),
     ("fused_pairs64x32x2048", lambda: _ragged((64, 32, 2048), (True, True, False), 17),
      dict(tile=8)),
+    # rows of at least 128 cells: 128 x 8 columns (FP32), a ragged second one
+    ("fused136x16x1928_px", lambda: _ragged((136, 16, 1928), (True, False, True), 18),
+     dict(tile=8)),
     # a 19-point operator of that size runs the sweep and the matvec separately
     ("ragged19_72x24x2432_periodic", lambda: _ragged19((72, 24, 2432), (True, True, True), 15),
      dict(tile=8)),
