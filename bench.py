@@ -698,6 +698,9 @@ def main():
                     help="porous128: time only the hybrid (switch-point sweeps)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="no HIP events around the kernels of the timed region (no roofline; "
+                         "measures what the events cost)")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the short serving leg of the default benchmark")
     ap.add_argument("--batch-max", type=int, default=8,
@@ -775,7 +778,7 @@ def main():
     # ---- timed: FP32 inner solves inside FP64 refinement -------------------
     rec32 = krs.Recycle(ctx, prob.n, args.k, torch.float32)
     krs.timing_reset(ctx)
-    krs.timing_enable(ctx, True)
+    krs.timing_enable(ctx, not args.no_kernel_timing)
     lat, its, mvs, byt, outer, statuses, second = [], 0, 0, 0.0, [], [], 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -822,14 +825,21 @@ def main():
                 "rel_diff_fp32ir_vs_fp64": diffs}
 
     # ---- roofline of the dominant kernel class ------------------------------
-    dom = max(kt, key=lambda c: kt[c][1])
-    n_l, ms_l, by_l = kt[dom]
-    achieved = by_l / (ms_l * 1e-3) / 1e9 if ms_l > 0 else 0.0
-    kernels = {c: {"launches": v[0], "ms": round(v[1], 3),
-                   "GB_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
-               for c, v in kt.items() if v[0] > 0}
-
-    traffic, traffic_note = measured_traffic(dom)
+    roofline, kernels = None, {}
+    if not args.no_kernel_timing:
+        dom = max(kt, key=lambda c: kt[c][1])
+        n_l, ms_l, by_l = kt[dom]
+        achieved = by_l / (ms_l * 1e-3) / 1e9 if ms_l > 0 else 0.0
+        kernels = {c: {"launches": v[0], "ms": round(v[1], 3),
+                       "GB_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+                   for c, v in kt.items() if v[0] > 0}
+        traffic, traffic_note = measured_traffic(dom)
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                    "traffic_unit": "HBM bytes per launch (rocprofv3 counters)",
+                    "traffic_note": traffic_note,
+                    "algorithmic_bytes_per_launch": by_l / max(n_l, 1),
+                    "launches": n_l, "avg_launch_us": 1e3 * ms_l / max(n_l, 1)}
     cpu = None
     if not args.no_cpu and fp64 is not None:
         log("[bench] timing the CPU oracle sample ...")
@@ -864,12 +874,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "fp64": fp64,
         "speedup_vs_fp64": (value / fp64["solves_per_s"]) if fp64 else None,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 counters)",
-                     "traffic_note": traffic_note,
-                     "algorithmic_bytes_per_launch": by_l / max(n_l, 1),
-                     "launches": n_l, "avg_launch_us": 1e3 * ms_l / max(n_l, 1)},
+        "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
         "serve_leg": serve,

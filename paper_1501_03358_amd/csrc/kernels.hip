@@ -1689,6 +1689,18 @@ __device__ __forceinline__ void sv_rows(const Cols<T>& C, const T* cf, T alpha,
   }
 }
 
+template <class T, int W, int NC>
+__device__ __forceinline__ void bicg_sv_main(Blk k, const Cols<T>& C, const T* cf, T alpha,
+                                             const T* __restrict__ r, T* v, T* __restrict__ sv,
+                                             int64_t n, T* partials, int nblk) {
+  T acc[1] = {0};
+  const int64_t npk = n / W;
+  sv_rows<T, W, NC>(C, cf, alpha, r, v, sv, first_row(k), npk, grid_step(k), acc[0]);
+  if (W > 1 && k.b == k.G - 1)
+    sv_rows<T, 1, NC>(C, cf, alpha, r, v, sv, npk * W + threadIdx.x, n, kThreads, acc[0]);
+  reduce_store<T, 1>(acc, 1, partials, nblk, k);
+}
+
 // v -= C eta1 ; s = r - alpha v ; partial |s|^2
 template <class T, int W, int NC>
 __device__ __forceinline__ void bicg_sv_body(Blk k, const Cols<T>& C, const T* __restrict__ r,
@@ -1699,13 +1711,7 @@ __device__ __forceinline__ void bicg_sv_body(Blk k, const Cols<T>& C, const T* _
   const int kc = C.n1;
   for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (T)sc[off_eta1 + c] : T(0);
   __syncthreads();
-  const T alpha = (T)sc[kAlpha];
-  T acc[1] = {0};
-  const int64_t npk = n / W;
-  sv_rows<T, W, NC>(C, cf, alpha, r, v, sv, first_row(k), npk, grid_step(k), acc[0]);
-  if (W > 1 && k.b == k.G - 1)
-    sv_rows<T, 1, NC>(C, cf, alpha, r, v, sv, npk * W + threadIdx.x, n, kThreads, acc[0]);
-  reduce_store<T, 1>(acc, 1, partials, nblk, k);
+  bicg_sv_main<T, W, NC>(k, C, cf, (T)sc[kAlpha], r, v, sv, n, partials, nblk);
 }
 
 template <class T, int W, int NC>
@@ -1744,6 +1750,23 @@ __device__ __forceinline__ void yr_rows(const Cols<T>& C, const T* cf, T alpha, 
   }
 }
 
+template <class T, int W, int NC>
+__device__ __forceinline__ void bicg_yr_main(Blk k, const Cols<T>& C, const T* cf, T alpha,
+                                             T omega, const T* __restrict__ t,
+                                             const T* __restrict__ sv, const T* __restrict__ p,
+                                             T* __restrict__ y, T* __restrict__ r,
+                                             const T* __restrict__ rt, int64_t n, T* partials,
+                                             int nblk) {
+  T acc[2] = {0, 0};
+  const int64_t npk = n / W;
+  yr_rows<T, W, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, first_row(k), npk, grid_step(k),
+                    acc);
+  if (W > 1 && k.b == k.G - 1)
+    yr_rows<T, 1, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, npk * W + threadIdx.x, n,
+                      kThreads, acc);
+  reduce_store<T, 2>(acc, 2, partials, nblk, k);
+}
+
 // y += alpha p + omega s ; r = s - omega (t - C eta2) ; partials r~.r, |r|^2
 template <class T, int W, int NC>
 __device__ __forceinline__ void bicg_yr_body(Blk k, const Cols<T>& C, const T* __restrict__ t,
@@ -1756,15 +1779,8 @@ __device__ __forceinline__ void bicg_yr_body(Blk k, const Cols<T>& C, const T* _
   const int kc = C.n1;
   for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (T)sc[off_eta2 + c] : T(0);
   __syncthreads();
-  const T alpha = (T)sc[kAlpha], omega = (T)sc[kOmega];
-  T acc[2] = {0, 0};
-  const int64_t npk = n / W;
-  yr_rows<T, W, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, first_row(k), npk, grid_step(k),
-                    acc);
-  if (W > 1 && k.b == k.G - 1)
-    yr_rows<T, 1, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, npk * W + threadIdx.x, n,
-                      kThreads, acc);
-  reduce_store<T, 2>(acc, 2, partials, nblk, k);
+  bicg_yr_main<T, W, NC>(k, C, cf, (T)sc[kAlpha], (T)sc[kOmega], t, sv, p, y, r, rt, n, partials,
+                         nblk);
 }
 
 template <class T, int W, int NC>
@@ -1789,9 +1805,9 @@ __device__ inline void hist_push(double* sc, double v) {
 // partials (FP64, fixed order) into out[]; then thread 0 runs the scalar
 // step.  Every kernel returns at once when the device-side stop state is set.
 // ---------------------------------------------------------------------------
-// Column sums go to `out` (device memory, for the host) and to `sh` (LDS):
-// the scalar step reads them from LDS, never back from memory it wrote in
-// this kernel.
+// Column sums go to `out` (device memory, for the host; may be null) and to
+// `sh` (LDS): the scalar step reads them from LDS, never back from memory it
+// wrote in this kernel.
 constexpr int kFinishCols = 72;
 
 template <class T>
@@ -1831,7 +1847,7 @@ __device__ __forceinline__ void finish_cols(const T* partials, int nblk, int nco
         const int c = c0 + NWV * j;
         const double w = wave_sum(acc[j]);
         if (lane == 0 && c < ncols) {
-          out[c] = w;
+          if (out) out[c] = w;
           sh[c] = w;
         }
       }
@@ -1875,37 +1891,57 @@ __device__ __forceinline__ void finish_cols(const T* partials, int nblk, int nco
     double v = wsum[0][c];
 #pragma unroll
     for (int w = 1; w < NWV; ++w) v += wsum[w][c];
-    out[c] = v;
+    if (out) out[c] = v;
     sh[c] = v;
   }
   __syncthreads();
 }
 
-// eta1 = C^T v, r~^T v; alpha = rho / (r~^T v - (C^T r~) . eta1)
+// eta1 = C^T v, r~^T v; alpha = rho / (r~^T v - (C^T r~) . eta1).  Every
+// thread of the block gets eta1 in sh[] and alpha in *al; with `write` the
+// block also stores them (and the breakdown flag) in the scalar area.  Reads
+// no scalar-area slot it writes, so several blocks of one kernel can run it
+// with one of them writing.
+template <class T>
+__device__ __forceinline__ void alpha_step(const T* partials, int nblk, int kc, double* sums,
+                                           double* sc, int off_eta1, int off_ctrt, bool write,
+                                           double* sh, double* al) {
+  __shared__ double ctrt[kFinishCols];
+  // C^T r~ is staged in LDS by all threads at once: a serial loop over device
+  // memory interleaved with stores to the same array waits for one load per
+  // column (about 30 us per launch at k = 20)
+  for (int c = threadIdx.x; c < kc; c += kThreads) ctrt[c] = sc[off_ctrt + c];
+  finish_cols<T>(partials, nblk, kc + 1, write ? sums : nullptr, sh);
+  if (write)
+    for (int c = threadIdx.x; c < kc; c += kThreads) sc[off_eta1 + c] = sh[c];
+  if (threadIdx.x == 0) {
+    double corr = 0;
+    for (int c = 0; c < kc; ++c) corr += ctrt[c] * sh[c];
+    const double rtv = sh[kc] - corr;
+    double alpha;
+    if (rtv == 0.0 || !isfinite(rtv)) {
+      alpha = 0.0;   // breakdown: leave s = r; the stop state is set next
+      if (write) sc[kFlag] = 1.0;
+    } else {
+      alpha = sc[kRho] / rtv;
+    }
+    if (write) {
+      sc[kRtv] = rtv;
+      sc[kAlpha] = alpha;
+    }
+    *al = alpha;
+  }
+  __syncthreads();
+}
+
 template <class T>
 __device__ __forceinline__ void bicg_finish_alpha_body(const T* partials, int nblk,
                                                                 int kc, double* sums, double* sc,
                                                                 int off_eta1, int off_ctrt) {
   __shared__ double sh[kFinishCols];
-  __shared__ double ctrt[kFinishCols];
+  __shared__ double al;
   if (sc[kDone] != 0.0) return;
-  // C^T r~ is staged in LDS by all threads at once: a serial loop over device
-  // memory interleaved with stores to the same array waits for one load per
-  // column (about 30 us per launch at k = 20)
-  for (int c = threadIdx.x; c < kc; c += kThreads) ctrt[c] = sc[off_ctrt + c];
-  finish_cols<T>(partials, nblk, kc + 1, sums, sh);
-  for (int c = threadIdx.x; c < kc; c += kThreads) sc[off_eta1 + c] = sh[c];
-  if (threadIdx.x != 0) return;
-  double corr = 0;
-  for (int c = 0; c < kc; ++c) corr += ctrt[c] * sh[c];
-  const double rtv = sh[kc] - corr;
-  sc[kRtv] = rtv;
-  if (rtv == 0.0 || !isfinite(rtv)) {
-    sc[kAlpha] = 0.0;   // breakdown: leave s = r; the stop state is set next
-    sc[kFlag] = 1.0;
-  } else {
-    sc[kAlpha] = sc[kRho] / rtv;
-  }
+  alpha_step<T>(partials, nblk, kc, sums, sc, off_eta1, off_ctrt, true, sh, &al);
 }
 
 template <class T>
@@ -1917,34 +1953,51 @@ __global__ __launch_bounds__(kThreads) void k_bicg_finish_alpha(const T* partial
 
 // |s|^2, then the half-step tests; on convergence at the half step the
 // scalar part of the early exit (xi += alpha eta1) is applied here and the
-// vector part by the conditional exit kernel that follows.
+// vector part by the exit update that follows.  Returns the outcome to every
+// thread (0: go on, else the stop state); only with `write` is the state
+// stored.  Reads no scalar-area slot it writes except through `write`.
+template <class T>
+__device__ __forceinline__ int half_step(const T* partials, int nblk, double* sc, int off_eta1,
+                                         int off_xi, int kc, bool write) {
+  __shared__ double sh[kFinishCols];
+  __shared__ int dec;
+  finish_cols<T>(partials, nblk, 1, write ? sc + kSnorm2 : nullptr, sh);
+  if (threadIdx.x == 0) {
+    int d = 0;
+    if (write) sc[kIts] += 1.0;
+    if (sc[kFlag] != 0.0) {
+      d = kBreak;
+    } else {
+      const double sn2 = sh[0];
+      const double sn = sqrt(sn2);
+      if (write) hist_push(sc, sn);
+      if (!isfinite(sn)) {
+        d = kDiverge;
+      } else if (sn <= sc[kTolAbs]) {
+        d = kConvHalf;
+        if (write) {
+          const double alpha = sc[kAlpha];
+          for (int c = 0; c < kc; ++c) sc[off_xi + c] += alpha * sc[off_eta1 + c];
+          sc[kRnorm2] = sn2;
+        }
+      }
+    }
+    if (write && d != 0) {
+      sc[kDone] = d;
+      sc[kEndHalf] = 1.0;
+    }
+    dec = d;
+  }
+  __syncthreads();
+  return dec;
+}
+
 template <class T>
 __device__ __forceinline__ void bicg_finish_half_body(const T* partials, int nblk,
                                                                double* sc, int off_eta1,
                                                                int off_xi, int kc) {
-  __shared__ double sh[kFinishCols];
   if (sc[kDone] != 0.0) return;
-  finish_cols<T>(partials, nblk, 1, sc + kSnorm2, sh);
-  if (threadIdx.x != 0) return;
-  sc[kIts] += 1.0;
-  if (sc[kFlag] != 0.0) {
-    sc[kDone] = kBreak;
-    sc[kEndHalf] = 1.0;
-    return;
-  }
-  const double sn2 = sh[0];
-  const double sn = sqrt(sn2);
-  hist_push(sc, sn);
-  if (!isfinite(sn)) {
-    sc[kDone] = kDiverge;
-    sc[kEndHalf] = 1.0;
-  } else if (sn <= sc[kTolAbs]) {
-    const double alpha = sc[kAlpha];
-    for (int c = 0; c < kc; ++c) sc[off_xi + c] += alpha * sc[off_eta1 + c];
-    sc[kRnorm2] = sn2;
-    sc[kDone] = kConvHalf;
-    sc[kEndHalf] = 1.0;
-  }
+  (void)half_step<T>(partials, nblk, sc, off_eta1, off_xi, kc, true);
 }
 
 template <class T>
@@ -1974,14 +2027,49 @@ __global__ __launch_bounds__(kThreads) void k_bicg_exit_vec(const T* __restrict_
   bicg_exit_vec_body<T>(hw_blk(), p, y, sv, r, sc, n);
 }
 
-// eta2 = C^T t; omega = t^T s / (|t|^2 - |eta2|^2); xi += alpha eta1 + omega eta2
+// eta2 = C^T t; omega = t^T s / (|t|^2 - |eta2|^2); xi += alpha eta1 + omega
+// eta2.  Every thread gets eta2 in sh[] and omega in *om; with `write` the
+// block stores them, the breakdown flag and xi.  Reads no scalar-area slot it
+// writes except through `write`.
+template <class T>
+__device__ __forceinline__ void omega_step(const T* partials, int nblk, int kc, double* sums,
+                                           double* sc, int off_eta1, int off_eta2, int off_xi,
+                                           bool write, double* sh, double* om) {
+  __shared__ double e1[kFinishCols];
+  // eta1 staged in LDS by all threads (see alpha_step)
+  for (int c = threadIdx.x; c < kc; c += kThreads) e1[c] = sc[off_eta1 + c];
+  finish_cols<T>(partials, nblk, kc + 2, write ? sums : nullptr, sh);
+  if (threadIdx.x == 0) {
+    double q = 0;
+    for (int c = 0; c < kc; ++c) q += sh[c] * sh[c];
+    const double ts = sh[kc];
+    const double tt = sh[kc + 1] - q;  // |t - C eta2|^2 with C^T C = I
+    double omega = 0.0;  // t = 0 (breakdown): y += alpha p, r = s; the stop state is set next
+    if (tt > 0.0 && isfinite(tt)) omega = ts / tt;
+    else if (write) sc[kFlag] = 2.0;
+    if (write) {
+      sc[kTs] = ts;
+      sc[kTt] = tt;
+      sc[kOmega] = omega;
+    }
+    *om = omega;
+  }
+  __syncthreads();
+  if (write) {
+    const double alpha = sc[kAlpha], omega = *om;
+    for (int c = threadIdx.x; c < kc; c += kThreads) {
+      sc[off_eta2 + c] = sh[c];
+      sc[off_xi + c] += alpha * e1[c] + omega * sh[c];
+    }
+  }
+}
+
 template <class T>
 __device__ __forceinline__ void bicg_finish_omega_body(const T* partials, int nblk,
                                                                 int kc, double* sums, double* sc,
                                                                 int off_eta1, int off_eta2,
                                                                 int off_xi) {
   __shared__ double sh[kFinishCols];
-  __shared__ double e1[kFinishCols];
   __shared__ double om;
   // the pass after a half-step exit: mark the exit applied (so the vector
   // part runs once) and do nothing else
@@ -1991,28 +2079,7 @@ __device__ __forceinline__ void bicg_finish_omega_body(const T* partials, int nb
     return;
   }
   if (sc[kDone] != 0.0) return;
-  // eta1 staged in LDS by all threads (see k_bicg_finish_alpha)
-  for (int c = threadIdx.x; c < kc; c += kThreads) e1[c] = sc[off_eta1 + c];
-  finish_cols<T>(partials, nblk, kc + 2, sums, sh);
-  if (threadIdx.x == 0) {
-    double q = 0;
-    for (int c = 0; c < kc; ++c) q += sh[c] * sh[c];
-    const double ts = sh[kc];
-    const double tt = sh[kc + 1] - q;  // |t - C eta2|^2 with C^T C = I
-    sc[kTs] = ts;
-    sc[kTt] = tt;
-    double omega = 0.0;  // t = 0 (breakdown): y += alpha p, r = s; the stop state is set next
-    if (tt > 0.0 && isfinite(tt)) omega = ts / tt;
-    else sc[kFlag] = 2.0;
-    sc[kOmega] = omega;
-    om = omega;
-  }
-  __syncthreads();
-  const double alpha = sc[kAlpha], omega = om;
-  for (int c = threadIdx.x; c < kc; c += kThreads) {
-    sc[off_eta2 + c] = sh[c];
-    sc[off_xi + c] += alpha * e1[c] + omega * sh[c];
-  }
+  omega_step<T>(partials, nblk, kc, sums, sc, off_eta1, off_eta2, off_xi, true, sh, &om);
 }
 
 template <class T>
@@ -2050,6 +2117,76 @@ template <class T>
 __global__ __launch_bounds__(kThreads) void k_bicg_finish_full(const T* partials, int nblk,
                                                                double* sums, double* sc) {
   bicg_finish_full_body<T>(partials, nblk, sums, sc);
+}
+
+// The alpha step fused in front of the sv pass: every block sums the
+// partials of the dot pass itself (same code, same order, so the same
+// values) and block 0 stores the scalars; s's partials go to their own
+// buffer, since other blocks may still be reading the dot partials.
+template <class T, int W, int NC>
+__global__ __launch_bounds__(kThreads) void k_bicg_sv_fused(Cols<T> C, const T* __restrict__ r,
+                                                            T* v, T* __restrict__ sv, double* sc,
+                                                            int off_eta1, int off_ctrt,
+                                                            double* sums, int64_t n,
+                                                            const T* __restrict__ dot,
+                                                            T* partials, int nblk) {
+  const Blk k = hw_blk();
+  if (sc[kDone] != 0.0) return;
+  __shared__ double sh[kFinishCols];
+  __shared__ double al;
+  __shared__ T cf[NC > 0 ? NC : 1];
+  const int kc = C.n1;
+  alpha_step<T>(dot, nblk, kc, sums, sc, off_eta1, off_ctrt, k.b == 0, sh, &al);
+  for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (T)sh[c] : T(0);
+  __syncthreads();
+  bicg_sv_main<T, W, NC>(k, C, cf, (T)al, r, v, sv, n, partials, nblk);
+}
+
+// The omega step fused in front of the yr pass (as k_bicg_sv_fused); the
+// first pass after a half-step exit marks the exit applied and returns.
+template <class T, int W, int NC>
+__global__ __launch_bounds__(kThreads) void k_bicg_yr_fused(
+    Cols<T> C, const T* __restrict__ t, const T* __restrict__ sv, const T* __restrict__ p,
+    T* __restrict__ y, T* __restrict__ r, const T* __restrict__ rt, double* sc, int off_eta1,
+    int off_eta2, int off_xi, double* sums, int64_t n, const T* __restrict__ dot, T* partials,
+    int nblk) {
+  const Blk k = hw_blk();
+  const double d0 = sc[kDone];
+  if (d0 == (double)kConvHalf) {
+    if (k.b == 0 && threadIdx.x == 0) sc[kDone] = kExited;
+    return;
+  }
+  if (d0 != 0.0) return;
+  __shared__ double sh[kFinishCols];
+  __shared__ double om;
+  __shared__ T cf[NC > 0 ? NC : 1];
+  const int kc = C.n1;
+  omega_step<T>(dot, nblk, kc, sums, sc, off_eta1, off_eta2, off_xi, k.b == 0, sh, &om);
+  for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (T)sh[c] : T(0);
+  __syncthreads();
+  bicg_yr_main<T, W, NC>(k, C, cf, (T)sc[kAlpha], (T)om, t, sv, p, y, r, rt, n, partials, nblk);
+}
+
+// The half-step tests fused with the vector part of the early exit: every
+// block sums |s|^2 itself and takes the decision; block 0 stores the state.
+// A block that starts after block 0 stored kConvHalf goes on (it reaches the
+// same decision); kBreak or kDiverge from block 0 ends it, as intended.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_bicg_half_exit(const T* __restrict__ p, T* y,
+                                                             const T* __restrict__ sv, T* r,
+                                                             double* sc, int off_eta1,
+                                                             int off_xi, int kc,
+                                                             const T* __restrict__ partials,
+                                                             int nblk, int64_t n) {
+  const Blk k = hw_blk();
+  const double d0 = sc[kDone];
+  if (d0 != 0.0 && d0 != (double)kConvHalf) return;
+  if (half_step<T>(partials, nblk, sc, off_eta1, off_xi, kc, k.b == 0) != kConvHalf) return;
+  const T alpha = (T)sc[kAlpha];
+  for (int64_t i = (int64_t)k.b * kThreads + threadIdx.x; i < n; i += (int64_t)k.G * kThreads) {
+    y[i] += alpha * p[i];
+    r[i] = sv[i];
+  }
 }
 
 template <class T>
@@ -2609,6 +2746,74 @@ hipError_t bicg_yr(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, con
 }
 
 template <class T>
+hipError_t bicg_sv_fused(hipStream_t s, const Cols<T>& C, const T* r, T* v, T* sv, double* sc,
+                         int off_eta1, int off_ctrt, double* sums, int64_t n, const T* dot,
+                         T* partials, int nblk) {
+  constexpr int VW = 16 / sizeof(T);
+  const int kc = C.n1;
+  if (kc + 1 > kFinishCols) return hipErrorInvalidValue;
+  const bool vv = vec_ok(C) && vec_ok(r) && vec_ok((const T*)v) && vec_ok((const T*)sv);
+#define KRS_SVF(NCV)                                                                           \
+  do {                                                                                         \
+    if (vv) k_bicg_sv_fused<T, VW, NCV><<<nblk, kThreads, 0, s>>>(C, r, v, sv, sc, off_eta1,   \
+                                                                  off_ctrt, sums, n, dot,      \
+                                                                  partials, nblk);             \
+    else k_bicg_sv_fused<T, 1, NCV><<<nblk, kThreads, 0, s>>>(C, r, v, sv, sc, off_eta1,       \
+                                                              off_ctrt, sums, n, dot,          \
+                                                              partials, nblk);                 \
+  } while (0)
+  if (kc == 0) KRS_SVF(0);
+  else if (kc <= 8) KRS_SVF(8);
+  else if (kc <= 16) KRS_SVF(16);
+  else if (kc <= 32) KRS_SVF(32);
+  else if (kc <= 64) KRS_SVF(64);
+  else return hipErrorInvalidValue;
+#undef KRS_SVF
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t bicg_yr_fused(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, const T* p,
+                         T* y, T* r, const T* rt, double* sc, int off_eta1, int off_eta2,
+                         int off_xi, double* sums, int64_t n, const T* dot, T* partials,
+                         int nblk) {
+  constexpr int VW = 16 / sizeof(T);
+  const int kc = C.n1;
+  if (kc + 2 > kFinishCols) return hipErrorInvalidValue;
+  const bool vv = vec_ok(C) && vec_ok(t) && vec_ok(sv) && vec_ok(p) && vec_ok((const T*)y) &&
+                  vec_ok((const T*)r) && vec_ok(rt);
+#define KRS_YRF(NCV)                                                                           \
+  do {                                                                                         \
+    if (vv) k_bicg_yr_fused<T, VW, NCV><<<nblk, kThreads, 0, s>>>(C, t, sv, p, y, r, rt, sc,   \
+                                                                  off_eta1, off_eta2, off_xi,  \
+                                                                  sums, n, dot, partials,      \
+                                                                  nblk);                       \
+    else k_bicg_yr_fused<T, 1, NCV><<<nblk, kThreads, 0, s>>>(C, t, sv, p, y, r, rt, sc,       \
+                                                              off_eta1, off_eta2, off_xi,      \
+                                                              sums, n, dot, partials, nblk);   \
+  } while (0)
+  if (kc == 0) KRS_YRF(0);
+  else if (kc <= 8) KRS_YRF(8);
+  else if (kc <= 16) KRS_YRF(16);
+  else if (kc <= 32) KRS_YRF(32);
+  else if (kc <= 64) KRS_YRF(64);
+  else return hipErrorInvalidValue;
+#undef KRS_YRF
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t bicg_half_exit(hipStream_t s, const T* p, T* y, const T* sv, T* r, double* sc,
+                          int off_eta1, int off_xi, int kc, const T* partials, int nblk,
+                          int64_t n) {
+  if (n == 0) return hipSuccess;
+  k_bicg_half_exit<T><<<std::min(grid_for(n), 512), kThreads, 0, s>>>(p, y, sv, r, sc, off_eta1,
+                                                                       off_xi, kc, partials,
+                                                                       nblk, n);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t bicg_finish_alpha(hipStream_t s, const T* partials, int nblk, int kc, double* sums,
                              double* sc, int off_eta1, int off_ctrt) {
   k_bicg_finish_alpha<T><<<1, kThreads, 0, s>>>(partials, nblk, kc, sums, sc, off_eta1, off_ctrt);
@@ -2772,6 +2977,13 @@ hipError_t batch_bicg_second_half(hipStream_t s, const BatchTable* d_tb, const B
   template hipError_t bicg_finish_alpha<T>(hipStream_t, const T*, int, int, double*, double*, int, \
                                            int);                                                 \
   template hipError_t bicg_finish_half<T>(hipStream_t, const T*, int, double*, int, int, int);     \
+  template hipError_t bicg_sv_fused<T>(hipStream_t, const Cols<T>&, const T*, T*, T*, double*,   \
+                                       int, int, double*, int64_t, const T*, T*, int);           \
+  template hipError_t bicg_yr_fused<T>(hipStream_t, const Cols<T>&, const T*, const T*,         \
+                                       const T*, T*, T*, const T*, double*, int, int, int,       \
+                                       double*, int64_t, const T*, T*, int);                     \
+  template hipError_t bicg_half_exit<T>(hipStream_t, const T*, T*, const T*, T*, double*, int,  \
+                                        int, int, const T*, int, int64_t);                       \
   template hipError_t bicg_exit_vec<T>(hipStream_t, const T*, T*, const T*, T*, const double*,     \
                                        int64_t);                                                 \
   template hipError_t bicg_finish_omega<T>(hipStream_t, const T*, int, int, double*, double*, int, \

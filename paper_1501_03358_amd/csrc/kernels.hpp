@@ -162,6 +162,23 @@ template <class T>
 hipError_t bicg_yr(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, const T* p, T* y,
                    T* r, const T* rt, const double* sc, int off_eta2, int64_t n, T* partials,
                    int nblk);
+// The sv and yr passes with the alpha / omega step in front (every block
+// sums the dot pass's partials `dot` itself; block 0 stores the scalars);
+// their own partials go to `partials`, which must not overlap `dot`.
+template <class T>
+hipError_t bicg_sv_fused(hipStream_t s, const Cols<T>& C, const T* r, T* v, T* sv, double* sc,
+                         int off_eta1, int off_ctrt, double* sums, int64_t n, const T* dot,
+                         T* partials, int nblk);
+template <class T>
+hipError_t bicg_yr_fused(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, const T* p,
+                         T* y, T* r, const T* rt, double* sc, int off_eta1, int off_eta2,
+                         int off_xi, double* sums, int64_t n, const T* dot, T* partials,
+                         int nblk);
+// The half-step tests fused with the vector part of the early exit.
+template <class T>
+hipError_t bicg_half_exit(hipStream_t s, const T* p, T* y, const T* sv, T* r, double* sc,
+                          int off_eta1, int off_xi, int kc, const T* partials, int nblk,
+                          int64_t n);
 // Finishing reductions fused with the scalar step that uses them (one block):
 // finish + alpha; finish |s|^2 + half-step tests (with the scalar part of the
 // early exit after the first half-step); the vector part of that exit (runs only when it fired);

@@ -1041,6 +1041,8 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     return std::isfinite(nb) ? KRS_OK : KRS_DIVERGED;
   }
   const int kc = rec ? rec->dim : 0;
+  // partials of the fused sv / yr passes, after the dot pass's kc + 2 columns
+  T* const part2 = part + (size_t)nblk * (kc + 2);
   const T* U = rec ? (const T*)rec->U : nullptr;
   const T* C = rec ? (const T*)rec->C : nullptr;
   const int64_t ldr = rec ? rec->ld : 0;
@@ -1103,14 +1105,15 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     // eta1 = C^T v, v -= C eta1, alpha = rho / r~^T v, s = r - alpha v
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 2),
                block_dot<T>(s, cols<T>(C, ldr, kc, rt, ld, 1), v, n, 0, part, nblk));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
-               bicg_finish_alpha<T>(s, part, nblk, kc, sc + kSums, sc, kEta1, kCtrt));
+    // the alpha step runs in front of the sv pass (each block sums the dot
+    // partials itself), whose |s|^2 partials go to part2
     KRS_LAUNCH(ctx, KRS_K_BICG_SV, dev ? 0 : bytes_sv,
-               bicg_sv<T>(s, Cc, r, v, sv, sc, kEta1, n, part, nblk));
-    // half-step |s| tests; on convergence xi += alpha eta1 here and
-    // y += alpha p, r = s in the conditional pass that follows
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_finish_half<T>(s, part, nblk, sc, kEta1, kXi, kc));
-    KRS_LAUNCH(ctx, KRS_K_BICG_P, 0, bicg_exit_vec<T>(s, p, y, sv, r, sc, n));
+               bicg_sv_fused<T>(s, Cc, r, v, sv, sc, kEta1, kCtrt, sc + kSums, n, part, part2,
+                                nblk));
+    // half-step |s| tests; on convergence xi += alpha eta1 and, in the same
+    // launch, y += alpha p, r = s
+    KRS_LAUNCH(ctx, KRS_K_BICG_P, 0,
+               bicg_half_exit<T>(s, p, y, sv, r, sc, kEta1, kXi, kc, part2, nblk, n));
     return 0;
   };
   auto second_half = [&](bool dev) -> int {
@@ -1119,12 +1122,12 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     // eta2 = C^T t, omega = t^T s / |t - C eta2|^2, xi update
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 2),
                block_dot<T>(s, cols<T>(C, ldr, kc, sv, ld, 1), t, n, 1, part, nblk));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
-               bicg_finish_omega<T>(s, part, nblk, kc, sc + kSums, sc, kEta1, kEta2, kXi));
-    // y and r updates with the next rho = r~^T r, then the loop tests
+    // the omega step in front of the y and r updates (with the next
+    // rho = r~^T r), then the loop tests
     KRS_LAUNCH(ctx, KRS_K_BICG_YR, dev ? 0 : bytes_yr,
-               bicg_yr<T>(s, Cc, t, sv, p, y, r, rt, sc, kEta2, n, part, nblk));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_finish_full<T>(s, part, nblk, sc + kSums, sc));
+               bicg_yr_fused<T>(s, Cc, t, sv, p, y, r, rt, sc, kEta1, kEta2, kXi, sc + kSums, n,
+                                part, part2, nblk));
+    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_finish_full<T>(s, part2, nblk, sc + kSums, sc));
     return 0;
   };
   if (o->flags & KRS_FLAG_HOST_LOOP) {
