@@ -440,6 +440,11 @@ typedef enum krs_kernel_class {
  * (byte model: every array read once and written once) are accumulated per
  * class.  Adds two event records per launch. */
 int krs_timing_enable(krs_ctx* ctx, int on);
+/* Restricts the timing to the classes whose bit is set in `mask` (bit c for
+ * class c; every class by default): launches of other classes get no events
+ * and add nothing to the totals but their bytes.  Takes effect from the next
+ * launch.  KRS_ERR_ARG for a null context. */
+int krs_timing_classes(krs_ctx* ctx, unsigned int mask);
 int krs_timing_reset(krs_ctx* ctx);
 /* Totals of one class since the last reset: launches, milliseconds, bytes. */
 int krs_timing_read(krs_ctx* ctx, int kernel_class, int64_t* launches, double* ms,

@@ -24,6 +24,7 @@ struct krs_ctx {
     double bytes;
   };
   bool timing = false;
+  uint32_t timing_mask = 0xffffffffu;   // classes whose launches are timed
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   int64_t t_launches[KRS_K_COUNT] = {};
@@ -168,7 +169,7 @@ inline int set_err(krs_ctx* ctx, int code, const std::string& msg) {
 
 namespace krs {
 // kernel-launch bracketing for the timers and the byte model (timing.cpp)
-hipEvent_t launch_begin(krs_ctx* ctx);
+hipEvent_t launch_begin(krs_ctx* ctx, int cls);
 void launch_end(krs_ctx* ctx, int cls, double bytes, hipEvent_t a);
 // after a stream synchronisation: fold completed event pairs into the totals
 void timing_flush(krs_ctx* ctx);
@@ -180,7 +181,7 @@ void timing_add_bytes(krs_ctx* ctx, int cls, double bytes);
 // Launch `expr` (returning hipError_t) as kernel class `cls` moving `nbytes`.
 #define KRS_LAUNCH(ctx, cls, nbytes, expr)                                              \
   do {                                                                                 \
-    hipEvent_t _ev = krs::launch_begin(ctx);                                           \
+    hipEvent_t _ev = krs::launch_begin(ctx, (cls));                                    \
     hipError_t _e = (expr);                                                            \
     krs::launch_end(ctx, (cls), (nbytes), _ev);                                        \
     if (_e != hipSuccess)                                                              \

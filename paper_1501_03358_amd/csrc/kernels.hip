@@ -1897,6 +1897,58 @@ __device__ __forceinline__ void finish_cols(const T* partials, int nblk, int nco
   __syncthreads();
 }
 
+// finish_cols for at most 512 partials and NCOL columns: every thread issues
+// the loads of both its partials of all columns at once (one round trip; the
+// fused passes run this in front of every block).  Same sums in the same
+// order as finish_cols (the terms finish_cols adds past the 512th partial are
+// +0.0, and a sum that starts from +0.0 is never -0.0, so they change nothing).
+template <class T, int NCOL>
+__device__ __forceinline__ void finish_cols_512(const T* partials, int nblk, int ncols,
+                                                double* out, double* sh) {
+  constexpr int NWV = kThreads / 64;
+  __shared__ double wsum[NWV][kFinishCols];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  T v[NCOL][2];
+#pragma unroll
+  for (int j = 0; j < NCOL; ++j)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int b = u * kThreads + (int)threadIdx.x;
+      const bool ok = b < nblk && j < ncols;
+      v[j][u] = partials[ok ? (int64_t)j * nblk + b : 0];
+    }
+#pragma unroll
+  for (int j = 0; j < NCOL; ++j) {
+    double acc = 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int b = u * kThreads + (int)threadIdx.x;
+      acc += (b < nblk && j < ncols) ? (double)v[j][u] : 0.0;
+    }
+    const double w = wave_sum(acc);
+    if (lane == 0 && j < ncols) wsum[wid][j] = w;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncols; c += kThreads) {
+    double x = wsum[0][c];
+#pragma unroll
+    for (int w = 1; w < NWV; ++w) x += wsum[w][c];
+    if (out) out[c] = x;
+    sh[c] = x;
+  }
+  __syncthreads();
+}
+
+// column sums of the scalar steps: one round trip when it fits
+template <class T>
+__device__ __forceinline__ void step_cols(const T* partials, int nblk, int ncols, double* out,
+                                          double* sh) {
+  if (nblk <= 2 * kThreads && nblk > kThreads && ncols <= 32)
+    finish_cols_512<T, 32>(partials, nblk, ncols, out, sh);
+  else
+    finish_cols<T>(partials, nblk, ncols, out, sh);
+}
+
 // eta1 = C^T v, r~^T v; alpha = rho / (r~^T v - (C^T r~) . eta1).  Every
 // thread of the block gets eta1 in sh[] and alpha in *al; with `write` the
 // block also stores them (and the breakdown flag) in the scalar area.  Reads
@@ -1911,7 +1963,8 @@ __device__ __forceinline__ void alpha_step(const T* partials, int nblk, int kc, 
   // memory interleaved with stores to the same array waits for one load per
   // column (about 30 us per launch at k = 20)
   for (int c = threadIdx.x; c < kc; c += kThreads) ctrt[c] = sc[off_ctrt + c];
-  finish_cols<T>(partials, nblk, kc + 1, write ? sums : nullptr, sh);
+  const double rho = threadIdx.x == 0 ? sc[kRho] : 0.0;
+  step_cols<T>(partials, nblk, kc + 1, write ? sums : nullptr, sh);
   if (write)
     for (int c = threadIdx.x; c < kc; c += kThreads) sc[off_eta1 + c] = sh[c];
   if (threadIdx.x == 0) {
@@ -1923,7 +1976,7 @@ __device__ __forceinline__ void alpha_step(const T* partials, int nblk, int kc, 
       alpha = 0.0;   // breakdown: leave s = r; the stop state is set next
       if (write) sc[kFlag] = 1.0;
     } else {
-      alpha = sc[kRho] / rtv;
+      alpha = rho / rtv;
     }
     if (write) {
       sc[kRtv] = rtv;
@@ -1961,7 +2014,10 @@ __device__ __forceinline__ int half_step(const T* partials, int nblk, double* sc
                                          int off_xi, int kc, bool write) {
   __shared__ double sh[kFinishCols];
   __shared__ int dec;
-  finish_cols<T>(partials, nblk, 1, write ? sc + kSnorm2 : nullptr, sh);
+  if (nblk <= 2 * kThreads && nblk > kThreads)
+    finish_cols_512<T, 1>(partials, nblk, 1, write ? sc + kSnorm2 : nullptr, sh);
+  else
+    finish_cols<T>(partials, nblk, 1, write ? sc + kSnorm2 : nullptr, sh);
   if (threadIdx.x == 0) {
     int d = 0;
     if (write) sc[kIts] += 1.0;
@@ -2038,7 +2094,7 @@ __device__ __forceinline__ void omega_step(const T* partials, int nblk, int kc, 
   __shared__ double e1[kFinishCols];
   // eta1 staged in LDS by all threads (see alpha_step)
   for (int c = threadIdx.x; c < kc; c += kThreads) e1[c] = sc[off_eta1 + c];
-  finish_cols<T>(partials, nblk, kc + 2, write ? sums : nullptr, sh);
+  step_cols<T>(partials, nblk, kc + 2, write ? sums : nullptr, sh);
   if (threadIdx.x == 0) {
     double q = 0;
     for (int c = 0; c < kc; ++c) q += sh[c] * sh[c];

@@ -16,8 +16,8 @@ hipEvent_t take_event(krs_ctx* ctx) {
 }
 }  // namespace
 
-hipEvent_t launch_begin(krs_ctx* ctx) {
-  if (!ctx->timing) return nullptr;
+hipEvent_t launch_begin(krs_ctx* ctx, int cls) {
+  if (!ctx->timing || !((ctx->timing_mask >> cls) & 1u)) return nullptr;
   hipEvent_t a = take_event(ctx);
   if (a && hipEventRecord(a, ctx->stream) != hipSuccess) {
     ctx->pool.push_back(a);
@@ -72,6 +72,12 @@ int krs_timing_enable(krs_ctx* ctx, int on) {
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return KRS_ERR_HIP;
   krs::timing_flush(ctx);
   ctx->timing = on != 0;
+  return KRS_OK;
+}
+
+int krs_timing_classes(krs_ctx* ctx, unsigned int mask) {
+  if (!ctx) return KRS_ERR_ARG;
+  ctx->timing_mask = mask;
   return KRS_OK;
 }
 

@@ -36,7 +36,7 @@ EXPORTS = (
     "krs_recycle_set_dim", "krs_recycle_mark_stale", "krs_workspace_size", "krs_stencil_apply", "krs_precond_apply",
     "krs_operator_apply", "krs_gmres", "krs_rgcrot_solve", "krs_rbicgstab_solve",
     "krs_rbicgstab_solve_noalloc", "krs_recycle_update",
-    "krs_hybrid_solve", "krs_ir_solve", "krs_ir_solve_batched", "krs_version", "krs_timing_enable", "krs_timing_reset",
+    "krs_hybrid_solve", "krs_ir_solve", "krs_ir_solve_batched", "krs_version", "krs_timing_enable", "krs_timing_classes", "krs_timing_reset",
     "krs_timing_read",
 )
 
@@ -131,6 +131,7 @@ def _declare(L):
                                        sz]),
         "krs_version": (ctypes.c_char_p, []),
         "krs_timing_enable": (i32, [P, i32]),
+        "krs_timing_classes": (i32, [P, ctypes.c_uint]),
         "krs_timing_reset": (i32, [P]),
         "krs_timing_read": (i32, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                   ctypes.POINTER(dbl)]),
@@ -493,6 +494,12 @@ KERNEL_CLASSES = ("stencil", "residual", "schwarz_local", "jacobi_sweep", "block
 
 def timing_enable(ctx, on=True):
     return ctx.check(lib().krs_timing_enable(ctx.h, 1 if on else 0))
+
+
+def timing_classes(ctx, names=None):
+    """Time only the named kernel classes (None: every class)."""
+    mask = 0xFFFFFFFF if names is None else sum(1 << KERNEL_CLASSES.index(n) for n in names)
+    return ctx.check(lib().krs_timing_classes(ctx.h, mask))
 
 
 def timing_reset(ctx):

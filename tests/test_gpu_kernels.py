@@ -269,3 +269,28 @@ def test_19pt_ssor_local_solver_rejected(gpu_lib):
     prob = W.skewed_problem(8)
     with pytest.raises(krs.KrsError, match="SSOR"):
         Dev(krs, prob, "schwarz", dict(tile=4, local_solver="ssor", omega_local=1.0))
+
+
+def test_timing_restricted_to_classes(gpu_lib):
+    """Kernel timing of selected classes only: launches of other classes get
+    no events and no counts; None restores every class."""
+    krs = gpu_lib
+    prob = W.porous_problem(32, extra=5)
+    d = Dev(krs, prob, "schwarz", dict(W.SCHWARZ_DEFAULT), dtype=torch.float32)
+    v = d.vec(np.random.default_rng(3).standard_normal(prob.n))
+    w, tmp = d.empty(), d.empty()
+    krs.timing_reset(d.ctx)
+    krs.timing_classes(d.ctx, ["schwarz_local"])
+    krs.timing_enable(d.ctx, True)
+    krs.operator_apply(d.ctx, d.A, d.M, v, w, tmp)
+    krs.timing_enable(d.ctx, False)
+    kt = krs.timing_read(d.ctx)
+    assert kt["schwarz_local"][0] == 1 and kt["schwarz_local"][1] > 0
+    assert all(n == 0 for c, (n, ms, by) in kt.items() if c != "schwarz_local")
+    krs.timing_reset(d.ctx)
+    krs.timing_classes(d.ctx, None)
+    krs.timing_enable(d.ctx, True)
+    krs.operator_apply(d.ctx, d.A, d.M, v, w, tmp)
+    krs.timing_enable(d.ctx, False)
+    kt = krs.timing_read(d.ctx)
+    assert kt["schwarz_local"][0] == 1 and sum(n for n, _, _ in kt.values()) >= 3

@@ -78,3 +78,10 @@ def test_invalid_arguments_are_rejected(lib):
     assert fn(1, 100, 300, 20, 0, ctypes.byref(out)) == -1
     assert fn(9, 100, 30, 20, 0, ctypes.byref(out)) == -1
     assert fn(1, 100, 30, 20, 7, ctypes.byref(out)) == -1
+
+
+def test_timing_classes_rejects_null_context(lib):
+    fn = lib.krs_timing_classes
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_uint]
+    fn.restype = ctypes.c_int
+    assert fn(None, 1) == -1
