@@ -1560,43 +1560,64 @@ __global__ void k_bicg_setup(double* sc, int kc, double tol, double div_factor) 
   sc[kDivAbs] = div_factor > 0 ? div_factor * nb : INFINITY;
 }
 
-// End of Arnoldi step j of a cycle, on the device (one thread): store the new
-// column [B; Hbar] from hcol = [C V_j]^T-coefficients with the new norm
-// appended, rotate it by the j previous Givens rotations, form rotation j,
-// update g and the residual estimate |g_{j+1}|, push the estimate to the
-// history ring and set the stop state (estimate at the tolerance, lucky
-// breakdown, non-finite estimate, step limit).  Once stopped, later steps of
-// the batch change nothing here.  The arithmetic is that of the host loop
-// term by term (no contraction into fused multiply-adds), so both give the
-// same bits.
+// End of Arnoldi step j of a cycle, on the device: store the new column
+// [B; Hbar] from hcol = [C V_j]^T-coefficients with the new norm appended,
+// rotate it by the j previous Givens rotations, form rotation j, update g and
+// the residual estimate |g_{j+1}|, push the estimate to the history ring and
+// set the stop state (estimate at the tolerance, lucky breakdown, non-finite
+// estimate, step limit).  Once stopped, later steps of the batch change
+// nothing here.  The wave stages hcol and the earlier rotations in LDS and
+// stores the new column with all lanes (loads in parallel, where one thread
+// reading them in turn waited for each); then one thread does the rotations,
+// with the arithmetic of the host loop term by term (no contraction into
+// fused multiply-adds), so both give the same bits.
 __global__ void k_arnoldi_givens(double* arn, const double* hcol, const int* skip,
                                  const int* flag, int j, int kc, int m) {
 #pragma clang fp contract(off)
-  if (threadIdx.x != 0 || arn[kArnStop] != 0.0) return;
-  if (flag && *flag) {
-    // the norm from the Pythagorean identity is unreliable: stop here; the
-    // host runs this step again with an explicit norm pass
-    arn[kArnStop] = 2.0;
-    arn[kArnJ] = j;
-    return;
-  }
+  constexpr int kHs = 2 * kMaxArnM + 8;   // ncols + 1 <= 65 (block passes take <= 64 columns)
+  __shared__ double hs[kHs];
+  __shared__ double cs_s[kMaxArnM], sn_s[kMaxArnM];
+  __shared__ int go;
+  const int t = threadIdx.x;
   const int ncols = kc + j + 1, ldh = m + 1;
+  if (t == 0) {
+    go = 0;
+    if (arn[kArnStop] == 0.0) {
+      if (flag && *flag) {
+        // the norm from the Pythagorean identity is unreliable: stop here;
+        // the host runs this step again with an explicit norm pass
+        arn[kArnStop] = 2.0;
+        arn[kArnJ] = j;
+      } else {
+        go = 1;
+      }
+    }
+  }
+  for (int i = t; i <= ncols; i += 64) hs[i] = hcol[i];
+  for (int i = t; i < j; i += 64) {
+    cs_s[i] = arn[kArnCs + i];
+    sn_s[i] = arn[kArnSn + i];
+  }
+  __syncthreads();
+  if (!go) return;
   double* H = arn + kArnH;
   double* R = arn + kArnR;
   double* B = arn + kArnB;
   double* g = arn + kArnG;
   double* cs = arn + kArnCs;
   double* sn = arn + kArnSn;
-  for (int i = 0; i < kc; ++i) B[i + kc * j] = hcol[i];
-  for (int i = 0; i <= j; ++i) H[i + ldh * j] = hcol[kc + i];
-  const double hn = hcol[ncols];
+  for (int i = t; i < kc; i += 64) B[i + kc * j] = hs[i];
+  for (int i = t; i <= j; i += 64) H[i + ldh * j] = hs[kc + i];
+  if (t != 0) return;
+  const double hn = hs[ncols];
   H[(j + 1) + ldh * j] = hn;
   double hc[kMaxArnM + 1];
-  for (int i = 0; i <= j + 1; ++i) hc[i] = H[i + ldh * j];
+  for (int i = 0; i <= j; ++i) hc[i] = hs[kc + i];
+  hc[j + 1] = hn;
   for (int i = 0; i < j; ++i) {
     const double a = hc[i], bb = hc[i + 1];
-    hc[i] = cs[i] * a + sn[i] * bb;
-    hc[i + 1] = -sn[i] * a + cs[i] * bb;
+    hc[i] = cs_s[i] * a + sn_s[i] * bb;
+    hc[i + 1] = -sn_s[i] * a + cs_s[i] * bb;
   }
   const double a = hc[j], bb = hc[j + 1];
   const double rr = sqrt(a * a + bb * bb);
@@ -1604,8 +1625,9 @@ __global__ void k_arnoldi_givens(double* arn, const double* hcol, const int* ski
   sn[j] = rr > 0 ? bb / rr : 0.0;
   hc[j] = rr;
   hc[j + 1] = 0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
+  const double gj = g[j];
+  g[j + 1] = -sn[j] * gj;
+  g[j] = cs[j] * gj;
   for (int i = 0; i <= j + 1; ++i) R[i + ldh * j] = hc[i];
   const double est = fabs(g[j + 1]);
   const int its = (int)arn[kArnIts] + 1;
