@@ -1720,14 +1720,6 @@ __device__ __forceinline__ void bicg_sv_body(Blk k, const Cols<T>& C, const T* _
 }
 
 template <class T, int W, int NC>
-__global__ __launch_bounds__(kThreads) void k_bicg_sv(Cols<T> C, const T* __restrict__ r, T* v,
-                                                      T* __restrict__ sv, const double* sc,
-                                                      int off_eta1, int64_t n, T* partials,
-                                                      int nblk) {
-  bicg_sv_body<T, W, NC>(hw_blk(), C, r, v, sv, sc, off_eta1, n, partials, nblk);
-}
-
-template <class T, int W, int NC>
 __device__ __forceinline__ void yr_rows(const Cols<T>& C, const T* cf, T alpha, T omega,
                                         const T* __restrict__ t, const T* __restrict__ sv,
                                         const T* __restrict__ p, T* __restrict__ y,
@@ -1786,16 +1778,6 @@ __device__ __forceinline__ void bicg_yr_body(Blk k, const Cols<T>& C, const T* _
   __syncthreads();
   bicg_yr_main<T, W, NC>(k, C, cf, (T)sc[kAlpha], (T)sc[kOmega], t, sv, p, y, r, rt, n, partials,
                          nblk);
-}
-
-template <class T, int W, int NC>
-__global__ __launch_bounds__(kThreads) void k_bicg_yr(Cols<T> C, const T* __restrict__ t,
-                                                      const T* __restrict__ sv,
-                                                      const T* __restrict__ p, T* __restrict__ y,
-                                                      T* __restrict__ r, const T* __restrict__ rt,
-                                                      const double* sc, int off_eta2, int64_t n,
-                                                      T* partials, int nblk) {
-  bicg_yr_body<T, W, NC>(hw_blk(), C, t, sv, p, y, r, rt, sc, off_eta2, n, partials, nblk);
 }
 
 __device__ inline void hist_push(double* sc, double v) {
@@ -2002,13 +1984,6 @@ __device__ __forceinline__ void bicg_finish_alpha_body(const T* partials, int nb
   alpha_step<T>(partials, nblk, kc, sums, sc, off_eta1, off_ctrt, true, sh, &al);
 }
 
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_bicg_finish_alpha(const T* partials, int nblk,
-                                                                int kc, double* sums, double* sc,
-                                                                int off_eta1, int off_ctrt) {
-  bicg_finish_alpha_body<T>(partials, nblk, kc, sums, sc, off_eta1, off_ctrt);
-}
-
 // |s|^2, then the half-step tests; on convergence at the half step the
 // scalar part of the early exit (xi += alpha eta1) is applied here and the
 // vector part by the exit update that follows.  Returns the outcome to every
@@ -2061,13 +2036,6 @@ __device__ __forceinline__ void bicg_finish_half_body(const T* partials, int nbl
   (void)half_step<T>(partials, nblk, sc, off_eta1, off_xi, kc, true);
 }
 
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_bicg_finish_half(const T* partials, int nblk,
-                                                               double* sc, int off_eta1,
-                                                               int off_xi, int kc) {
-  bicg_finish_half_body<T>(partials, nblk, sc, off_eta1, off_xi, kc);
-}
-
 // y += alpha p ; r = s when the half-step test converged (kDone == kConvHalf)
 template <class T>
 __device__ __forceinline__ void bicg_exit_vec_body(Blk k, const T* __restrict__ p, T* y,
@@ -2079,13 +2047,6 @@ __device__ __forceinline__ void bicg_exit_vec_body(Blk k, const T* __restrict__ 
     y[i] += alpha * p[i];
     r[i] = sv[i];
   }
-}
-
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_bicg_exit_vec(const T* __restrict__ p, T* y,
-                                                            const T* __restrict__ sv, T* r,
-                                                            const double* sc, int64_t n) {
-  bicg_exit_vec_body<T>(hw_blk(), p, y, sv, r, sc, n);
 }
 
 // eta2 = C^T t; omega = t^T s / (|t|^2 - |eta2|^2); xi += alpha eta1 + omega
@@ -2141,14 +2102,6 @@ __device__ __forceinline__ void bicg_finish_omega_body(const T* partials, int nb
   }
   if (sc[kDone] != 0.0) return;
   omega_step<T>(partials, nblk, kc, sums, sc, off_eta1, off_eta2, off_xi, true, sh, &om);
-}
-
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_bicg_finish_omega(const T* partials, int nblk,
-                                                                int kc, double* sums, double* sc,
-                                                                int off_eta1, int off_eta2,
-                                                                int off_xi) {
-  bicg_finish_omega_body<T>(partials, nblk, kc, sums, sc, off_eta1, off_eta2, off_xi);
 }
 
 // rho = r~^T r, |r|^2, beta; then the full-step tests (convergence,
@@ -2761,54 +2714,6 @@ hipError_t bicg_p(hipStream_t s, const T* r, T* p, const T* v, const double* sc,
 }
 
 template <class T>
-hipError_t bicg_sv(hipStream_t s, const Cols<T>& C, const T* r, T* v, T* sv, const double* sc,
-                   int off_eta1, int64_t n, T* partials, int nblk) {
-  constexpr int VW = 16 / sizeof(T);
-  const int kc = C.n1;
-  const bool vv = vec_ok(C) && vec_ok(r) && vec_ok((const T*)v) && vec_ok((const T*)sv);
-#define KRS_SV(NCV)                                                                          \
-  do {                                                                                       \
-    if (vv) k_bicg_sv<T, VW, NCV><<<nblk, kThreads, 0, s>>>(C, r, v, sv, sc, off_eta1, n,    \
-                                                            partials, nblk);                 \
-    else k_bicg_sv<T, 1, NCV><<<nblk, kThreads, 0, s>>>(C, r, v, sv, sc, off_eta1, n,        \
-                                                        partials, nblk);                     \
-  } while (0)
-  if (kc == 0) KRS_SV(0);
-  else if (kc <= 8) KRS_SV(8);
-  else if (kc <= 16) KRS_SV(16);
-  else if (kc <= 32) KRS_SV(32);
-  else if (kc <= 64) KRS_SV(64);
-  else return hipErrorInvalidValue;
-#undef KRS_SV
-  return hipGetLastError();
-}
-
-template <class T>
-hipError_t bicg_yr(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, const T* p, T* y,
-                   T* r, const T* rt, const double* sc, int off_eta2, int64_t n, T* partials,
-                   int nblk) {
-  constexpr int VW = 16 / sizeof(T);
-  const int kc = C.n1;
-  const bool vv = vec_ok(C) && vec_ok(t) && vec_ok(sv) && vec_ok(p) && vec_ok((const T*)y) &&
-                  vec_ok((const T*)r) && vec_ok(rt);
-#define KRS_YR(NCV)                                                                          \
-  do {                                                                                       \
-    if (vv) k_bicg_yr<T, VW, NCV><<<nblk, kThreads, 0, s>>>(C, t, sv, p, y, r, rt, sc,       \
-                                                            off_eta2, n, partials, nblk);    \
-    else k_bicg_yr<T, 1, NCV><<<nblk, kThreads, 0, s>>>(C, t, sv, p, y, r, rt, sc, off_eta2, \
-                                                        n, partials, nblk);                  \
-  } while (0)
-  if (kc == 0) KRS_YR(0);
-  else if (kc <= 8) KRS_YR(8);
-  else if (kc <= 16) KRS_YR(16);
-  else if (kc <= 32) KRS_YR(32);
-  else if (kc <= 64) KRS_YR(64);
-  else return hipErrorInvalidValue;
-#undef KRS_YR
-  return hipGetLastError();
-}
-
-template <class T>
 hipError_t bicg_sv_fused(hipStream_t s, const Cols<T>& C, const T* r, T* v, T* sv, double* sc,
                          int off_eta1, int off_ctrt, double* sums, int64_t n, const T* dot,
                          T* partials, int nblk) {
@@ -2876,32 +2781,6 @@ hipError_t bicg_half_exit(hipStream_t s, const T* p, T* y, const T* sv, T* r, do
   return hipGetLastError();
 }
 
-template <class T>
-hipError_t bicg_finish_alpha(hipStream_t s, const T* partials, int nblk, int kc, double* sums,
-                             double* sc, int off_eta1, int off_ctrt) {
-  k_bicg_finish_alpha<T><<<1, kThreads, 0, s>>>(partials, nblk, kc, sums, sc, off_eta1, off_ctrt);
-  return hipGetLastError();
-}
-template <class T>
-hipError_t bicg_finish_half(hipStream_t s, const T* partials, int nblk, double* sc, int off_eta1,
-                            int off_xi, int kc) {
-  k_bicg_finish_half<T><<<1, kThreads, 0, s>>>(partials, nblk, sc, off_eta1, off_xi, kc);
-  return hipGetLastError();
-}
-template <class T>
-hipError_t bicg_exit_vec(hipStream_t s, const T* p, T* y, const T* sv, T* r, const double* sc,
-                         int64_t n) {
-  // a small grid: the kernel usually returns at once, and runs at most once per solve
-  if (n > 0) k_bicg_exit_vec<T><<<std::min(grid_for(n), 512), kThreads, 0, s>>>(p, y, sv, r, sc, n);
-  return hipGetLastError();
-}
-template <class T>
-hipError_t bicg_finish_omega(hipStream_t s, const T* partials, int nblk, int kc, double* sums,
-                             double* sc, int off_eta1, int off_eta2, int off_xi) {
-  k_bicg_finish_omega<T><<<1, kThreads, 0, s>>>(partials, nblk, kc, sums, sc, off_eta1, off_eta2,
-                                                off_xi);
-  return hipGetLastError();
-}
 template <class T>
 hipError_t bicg_finish_full(hipStream_t s, const T* partials, int nblk, double* sums, double* sc) {
   k_bicg_finish_full<T><<<1, kThreads, 0, s>>>(partials, nblk, sums, sc);
@@ -3033,13 +2912,6 @@ hipError_t batch_bicg_second_half(hipStream_t s, const BatchTable* d_tb, const B
   template hipError_t finish_cgs2<T>(hipStream_t, const T*, int, int, const double*, double*,     \
                                      double*, double*, int*, const int*);                         \
   template hipError_t bicg_p<T>(hipStream_t, const T*, T*, const T*, const double*, int64_t);     \
-  template hipError_t bicg_sv<T>(hipStream_t, const Cols<T>&, const T*, T*, T*, const double*,    \
-                                 int, int64_t, T*, int);                                          \
-  template hipError_t bicg_yr<T>(hipStream_t, const Cols<T>&, const T*, const T*, const T*, T*,   \
-                                 T*, const T*, const double*, int, int64_t, T*, int);             \
-  template hipError_t bicg_finish_alpha<T>(hipStream_t, const T*, int, int, double*, double*, int, \
-                                           int);                                                 \
-  template hipError_t bicg_finish_half<T>(hipStream_t, const T*, int, double*, int, int, int);     \
   template hipError_t bicg_sv_fused<T>(hipStream_t, const Cols<T>&, const T*, T*, T*, double*,   \
                                        int, int, double*, int64_t, const T*, T*, int);           \
   template hipError_t bicg_yr_fused<T>(hipStream_t, const Cols<T>&, const T*, const T*,         \
@@ -3047,10 +2919,6 @@ hipError_t batch_bicg_second_half(hipStream_t s, const BatchTable* d_tb, const B
                                        double*, int64_t, const T*, T*, int);                     \
   template hipError_t bicg_half_exit<T>(hipStream_t, const T*, T*, const T*, T*, double*, int,  \
                                         int, int, const T*, int, int64_t);                       \
-  template hipError_t bicg_exit_vec<T>(hipStream_t, const T*, T*, const T*, T*, const double*,     \
-                                       int64_t);                                                 \
-  template hipError_t bicg_finish_omega<T>(hipStream_t, const T*, int, int, double*, double*, int, \
-                                           int, int);                                            \
   template hipError_t bicg_finish_full<T>(hipStream_t, const T*, int, double*, double*);           \
   template hipError_t fill<T>(hipStream_t, T*, int64_t, double);                                  \
   template hipError_t copy<T>(hipStream_t, const T*, T*, int64_t);

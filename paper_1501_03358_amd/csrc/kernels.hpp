@@ -153,18 +153,12 @@ constexpr int kHistOff = 512, kHistRing = 128;
 // BiCGStab pieces; `sums` are finished FP64 dot products.
 template <class T>
 hipError_t bicg_p(hipStream_t s, const T* r, T* p, const T* v, const double* sc, int64_t n);
-// v -= C eta1 ; s = r - alpha v ; partial |s|^2
-template <class T>
-hipError_t bicg_sv(hipStream_t s, const Cols<T>& C, const T* r, T* v, T* sv, const double* sc,
-                   int off_eta1, int64_t n, T* partials, int nblk);
-// y += alpha p + omega s ; r = s - omega (t - C eta2) ; partials r~.r, |r|^2
-template <class T>
-hipError_t bicg_yr(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, const T* p, T* y,
-                   T* r, const T* rt, const double* sc, int off_eta2, int64_t n, T* partials,
-                   int nblk);
-// The sv and yr passes with the alpha / omega step in front (every block
-// sums the dot pass's partials `dot` itself; block 0 stores the scalars);
-// their own partials go to `partials`, which must not overlap `dot`.
+// The sv pass (v -= C eta1 ; s = r - alpha v ; partial |s|^2) and the yr pass
+// (y += alpha p + omega s ; r = s - omega (t - C eta2) ; partials r~.r,
+// |r|^2), each with its scalar step in front (alpha, resp. omega and xi):
+// every block sums the dot pass's partials `dot` itself and block 0 stores
+// the scalars; their own partials go to `partials`, which must not overlap
+// `dot`.
 template <class T>
 hipError_t bicg_sv_fused(hipStream_t s, const Cols<T>& C, const T* r, T* v, T* sv, double* sc,
                          int off_eta1, int off_ctrt, double* sums, int64_t n, const T* dot,
@@ -179,22 +173,7 @@ template <class T>
 hipError_t bicg_half_exit(hipStream_t s, const T* p, T* y, const T* sv, T* r, double* sc,
                           int off_eta1, int off_xi, int kc, const T* partials, int nblk,
                           int64_t n);
-// Finishing reductions fused with the scalar step that uses them (one block):
-// finish + alpha; finish |s|^2 + half-step tests (with the scalar part of the
-// early exit after the first half-step); the vector part of that exit (runs only when it fired);
-// finish + omega/xi; finish rho, |r|^2 + beta + full-step tests.
-template <class T>
-hipError_t bicg_finish_alpha(hipStream_t s, const T* partials, int nblk, int kc, double* sums,
-                             double* sc, int off_eta1, int off_ctrt);
-template <class T>
-hipError_t bicg_finish_half(hipStream_t s, const T* partials, int nblk, double* sc, int off_eta1,
-                            int off_xi, int kc);
-template <class T>
-hipError_t bicg_exit_vec(hipStream_t s, const T* p, T* y, const T* sv, T* r, const double* sc,
-                         int64_t n);
-template <class T>
-hipError_t bicg_finish_omega(hipStream_t s, const T* partials, int nblk, int kc, double* sums,
-                             double* sc, int off_eta1, int off_eta2, int off_xi);
+// One block: finish rho, |r|^2, then beta and the full-step tests.
 template <class T>
 hipError_t bicg_finish_full(hipStream_t s, const T* partials, int nblk, double* sums, double* sc);
 // hcol_last = sqrt(*nrm2), inv = 1/hcol_last
