@@ -1694,6 +1694,7 @@ __device__ __forceinline__ void sv_rows(const Cols<T>& C, const T* cf, T alpha,
   }
 }
 
+// v -= C eta1 ; s = r - alpha v ; partial |s|^2 (cf = eta1)
 template <class T, int W, int NC>
 __device__ __forceinline__ void bicg_sv_main(Blk k, const Cols<T>& C, const T* cf, T alpha,
                                              const T* __restrict__ r, T* v, T* __restrict__ sv,
@@ -1704,19 +1705,6 @@ __device__ __forceinline__ void bicg_sv_main(Blk k, const Cols<T>& C, const T* c
   if (W > 1 && k.b == k.G - 1)
     sv_rows<T, 1, NC>(C, cf, alpha, r, v, sv, npk * W + threadIdx.x, n, kThreads, acc[0]);
   reduce_store<T, 1>(acc, 1, partials, nblk, k);
-}
-
-// v -= C eta1 ; s = r - alpha v ; partial |s|^2
-template <class T, int W, int NC>
-__device__ __forceinline__ void bicg_sv_body(Blk k, const Cols<T>& C, const T* __restrict__ r,
-                                             T* v, T* __restrict__ sv, const double* sc,
-                                             int off_eta1, int64_t n, T* partials, int nblk) {
-  if (sc[kDone] != 0.0) return;
-  __shared__ T cf[NC > 0 ? NC : 1];
-  const int kc = C.n1;
-  for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (T)sc[off_eta1 + c] : T(0);
-  __syncthreads();
-  bicg_sv_main<T, W, NC>(k, C, cf, (T)sc[kAlpha], r, v, sv, n, partials, nblk);
 }
 
 template <class T, int W, int NC>
@@ -1747,6 +1735,8 @@ __device__ __forceinline__ void yr_rows(const Cols<T>& C, const T* cf, T alpha, 
   }
 }
 
+// y += alpha p + omega s ; r = s - omega (t - C eta2) ; partials r~.r, |r|^2
+// (cf = eta2)
 template <class T, int W, int NC>
 __device__ __forceinline__ void bicg_yr_main(Blk k, const Cols<T>& C, const T* cf, T alpha,
                                              T omega, const T* __restrict__ t,
@@ -1764,22 +1754,6 @@ __device__ __forceinline__ void bicg_yr_main(Blk k, const Cols<T>& C, const T* c
   reduce_store<T, 2>(acc, 2, partials, nblk, k);
 }
 
-// y += alpha p + omega s ; r = s - omega (t - C eta2) ; partials r~.r, |r|^2
-template <class T, int W, int NC>
-__device__ __forceinline__ void bicg_yr_body(Blk k, const Cols<T>& C, const T* __restrict__ t,
-                                             const T* __restrict__ sv, const T* __restrict__ p,
-                                             T* __restrict__ y, T* __restrict__ r,
-                                             const T* __restrict__ rt, const double* sc,
-                                             int off_eta2, int64_t n, T* partials, int nblk) {
-  if (sc[kDone] != 0.0) return;
-  __shared__ T cf[NC > 0 ? NC : 1];
-  const int kc = C.n1;
-  for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (T)sc[off_eta2 + c] : T(0);
-  __syncthreads();
-  bicg_yr_main<T, W, NC>(k, C, cf, (T)sc[kAlpha], (T)sc[kOmega], t, sv, p, y, r, rt, n, partials,
-                         nblk);
-}
-
 __device__ inline void hist_push(double* sc, double v) {
   const int h = (int)sc[kHlen];
   sc[kHistOff + h % kHistRing] = v;
@@ -1787,10 +1761,11 @@ __device__ inline void hist_push(double* sc, double v) {
 }
 
 // ---------------------------------------------------------------------------
-// BiCGStab finishing reductions fused with the scalar step that consumes them
-// (one launch instead of two).  One block sums the columns of the per-block
-// partials (FP64, fixed order) into out[]; then thread 0 runs the scalar
-// step.  Every kernel returns at once when the device-side stop state is set.
+// BiCGStab scalar steps: the columns of the per-block partials are summed
+// (FP64, fixed order), then one thread runs the scalar step.  The alpha and
+// omega steps run in front of the update passes that use them (every block),
+// the half-step tests with the early-exit update, the full-step tests in one
+// block.  Every kernel returns at once when the device-side stop state is set.
 // ---------------------------------------------------------------------------
 // Column sums go to `out` (device memory, for the host; may be null) and to
 // `sh` (LDS): the scalar step reads them from LDS, never back from memory it
@@ -1974,16 +1949,6 @@ __device__ __forceinline__ void alpha_step(const T* partials, int nblk, int kc, 
   __syncthreads();
 }
 
-template <class T>
-__device__ __forceinline__ void bicg_finish_alpha_body(const T* partials, int nblk,
-                                                                int kc, double* sums, double* sc,
-                                                                int off_eta1, int off_ctrt) {
-  __shared__ double sh[kFinishCols];
-  __shared__ double al;
-  if (sc[kDone] != 0.0) return;
-  alpha_step<T>(partials, nblk, kc, sums, sc, off_eta1, off_ctrt, true, sh, &al);
-}
-
 // |s|^2, then the half-step tests; on convergence at the half step the
 // scalar part of the early exit (xi += alpha eta1) is applied here and the
 // vector part by the exit update that follows.  Returns the outcome to every
@@ -2028,27 +1993,6 @@ __device__ __forceinline__ int half_step(const T* partials, int nblk, double* sc
   return dec;
 }
 
-template <class T>
-__device__ __forceinline__ void bicg_finish_half_body(const T* partials, int nblk,
-                                                               double* sc, int off_eta1,
-                                                               int off_xi, int kc) {
-  if (sc[kDone] != 0.0) return;
-  (void)half_step<T>(partials, nblk, sc, off_eta1, off_xi, kc, true);
-}
-
-// y += alpha p ; r = s when the half-step test converged (kDone == kConvHalf)
-template <class T>
-__device__ __forceinline__ void bicg_exit_vec_body(Blk k, const T* __restrict__ p, T* y,
-                                                   const T* __restrict__ sv, T* r,
-                                                   const double* sc, int64_t n) {
-  if (sc[kDone] != (double)kConvHalf) return;
-  const T alpha = (T)sc[kAlpha];
-  for (int64_t i = (int64_t)k.b * kThreads + threadIdx.x; i < n; i += (int64_t)k.G * kThreads) {
-    y[i] += alpha * p[i];
-    r[i] = sv[i];
-  }
-}
-
 // eta2 = C^T t; omega = t^T s / (|t|^2 - |eta2|^2); xi += alpha eta1 + omega
 // eta2.  Every thread gets eta2 in sh[] and omega in *om; with `write` the
 // block stores them, the breakdown flag and xi.  Reads no scalar-area slot it
@@ -2084,24 +2028,6 @@ __device__ __forceinline__ void omega_step(const T* partials, int nblk, int kc, 
       sc[off_xi + c] += alpha * e1[c] + omega * sh[c];
     }
   }
-}
-
-template <class T>
-__device__ __forceinline__ void bicg_finish_omega_body(const T* partials, int nblk,
-                                                                int kc, double* sums, double* sc,
-                                                                int off_eta1, int off_eta2,
-                                                                int off_xi) {
-  __shared__ double sh[kFinishCols];
-  __shared__ double om;
-  // the pass after a half-step exit: mark the exit applied (so the vector
-  // part runs once) and do nothing else
-  if (sc[kDone] == (double)kConvHalf) {
-    __syncthreads();
-    if (threadIdx.x == 0) sc[kDone] = kExited;
-    return;
-  }
-  if (sc[kDone] != 0.0) return;
-  omega_step<T>(partials, nblk, kc, sums, sc, off_eta1, off_eta2, off_xi, true, sh, &om);
 }
 
 // rho = r~^T r, |r|^2, beta; then the full-step tests (convergence,
@@ -2303,48 +2229,67 @@ __global__ __launch_bounds__(kThreads) void kg_block_dot(const BatchTable* tb, i
   Q.n2 = 1;
   block_dot_body<float, 4, NC>(Blk{b, cnt}, Q, which ? q.t : q.v, q.n, which, q.part, q.nblk);
 }
+// the alpha step in front of the sv pass (as k_bicg_sv_fused): every block
+// of a system sums that system's dot partials; its block 0 stores the scalars
 template <int NC>
 __global__ __launch_bounds__(kThreads) void kg_bicg_sv(const BatchTable* tb) {
   const int s = batch_sys(tb->pass, tb->nsys);
   const BatchSys& q = tb->sys[s];
   const int b = (int)blockIdx.x - tb->pass[s], cnt = q.nblk;
-  if (b >= cnt) return;
-  bicg_sv_body<float, 4, NC>(Blk{b, cnt}, q.C, q.r, q.v, q.sv, q.sc, kBEta1, q.n, q.part,
+  if (b >= cnt || q.sc[kDone] != 0.0) return;
+  __shared__ double sh[kFinishCols];
+  __shared__ double al;
+  __shared__ float cf[NC > 0 ? NC : 1];
+  const int kc = q.C.n1;
+  alpha_step<float>(q.part, q.nblk, kc, q.sc + kBSums, q.sc, kBEta1, kBCtrt, b == 0, sh, &al);
+  for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (float)sh[c] : 0.f;
+  __syncthreads();
+  bicg_sv_main<float, 4, NC>(Blk{b, cnt}, q.C, cf, (float)al, q.r, q.v, q.sv, q.n, q.part2,
                              q.nblk);
 }
+// the omega step in front of the yr pass (as k_bicg_yr_fused)
 template <int NC>
 __global__ __launch_bounds__(kThreads) void kg_bicg_yr(const BatchTable* tb) {
   const int s = batch_sys(tb->pass, tb->nsys);
   const BatchSys& q = tb->sys[s];
   const int b = (int)blockIdx.x - tb->pass[s], cnt = q.nblk;
   if (b >= cnt) return;
-  bicg_yr_body<float, 4, NC>(Blk{b, cnt}, q.C, q.t, q.sv, q.p, q.y, q.r, q.rt, q.sc, kBEta2,
-                             q.n, q.part, q.nblk);
+  const double d0 = q.sc[kDone];
+  if (d0 == (double)kConvHalf) {
+    if (b == 0 && threadIdx.x == 0) q.sc[kDone] = kExited;
+    return;
+  }
+  if (d0 != 0.0) return;
+  __shared__ double sh[kFinishCols];
+  __shared__ double om;
+  __shared__ float cf[NC > 0 ? NC : 1];
+  const int kc = q.C.n1;
+  omega_step<float>(q.part, q.nblk, kc, q.sc + kBSums, q.sc, kBEta1, kBEta2, kBXi, b == 0, sh,
+                    &om);
+  for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (float)sh[c] : 0.f;
+  __syncthreads();
+  bicg_yr_main<float, 4, NC>(Blk{b, cnt}, q.C, cf, (float)q.sc[kAlpha], (float)om, q.t, q.sv,
+                             q.p, q.y, q.r, q.rt, q.n, q.part2, q.nblk);
 }
-__global__ __launch_bounds__(kThreads) void kg_exit_vec(const BatchTable* tb) {
+// the half-step tests with the early-exit update (as k_bicg_half_exit)
+__global__ __launch_bounds__(kThreads) void kg_half_exit(const BatchTable* tb) {
   const int s = batch_sys(tb->exitv, tb->nsys);
   const BatchSys& q = tb->sys[s];
   const int b = (int)blockIdx.x - tb->exitv[s], cnt = min(dev_grid_for(q.n), 512);
   if (b >= cnt) return;
-  bicg_exit_vec_body<float>(Blk{b, cnt}, q.p, q.y, q.sv, q.r, q.sc, q.n);
+  const double d0 = q.sc[kDone];
+  if (d0 != 0.0 && d0 != (double)kConvHalf) return;
+  if (half_step<float>(q.part2, q.nblk, q.sc, kBEta1, kBXi, q.C.n1, b == 0) != kConvHalf) return;
+  const float alpha = (float)q.sc[kAlpha];
+  for (int64_t i = (int64_t)b * kThreads + threadIdx.x; i < q.n; i += (int64_t)cnt * kThreads) {
+    q.y[i] += alpha * q.p[i];
+    q.r[i] = q.sv[i];
+  }
 }
-// finishing steps: block s is system s
-__global__ __launch_bounds__(kThreads) void kg_finish_alpha(const BatchTable* tb) {
-  const BatchSys& q = tb->sys[blockIdx.x];
-  bicg_finish_alpha_body<float>(q.part, q.nblk, q.C.n1, q.sc + kBSums, q.sc, kBEta1, kBCtrt);
-}
-__global__ __launch_bounds__(kThreads) void kg_finish_half(const BatchTable* tb) {
-  const BatchSys& q = tb->sys[blockIdx.x];
-  bicg_finish_half_body<float>(q.part, q.nblk, q.sc, kBEta1, kBXi, q.C.n1);
-}
-__global__ __launch_bounds__(kThreads) void kg_finish_omega(const BatchTable* tb) {
-  const BatchSys& q = tb->sys[blockIdx.x];
-  bicg_finish_omega_body<float>(q.part, q.nblk, q.C.n1, q.sc + kBSums, q.sc, kBEta1, kBEta2,
-                                kBXi);
-}
+// one block per system: rho, |r|^2, beta and the full-step tests
 __global__ __launch_bounds__(kThreads) void kg_finish_full(const BatchTable* tb) {
   const BatchSys& q = tb->sys[blockIdx.x];
-  bicg_finish_full_body<float>(q.part, q.nblk, q.sc + kBSums, q.sc);
+  bicg_finish_full_body<float>(q.part2, q.nblk, q.sc + kBSums, q.sc);
 }
 
 }  // namespace
@@ -2862,10 +2807,8 @@ hipError_t batch_bicg_first_half(hipStream_t s, const BatchTable* d_tb, const Ba
   // the block passes dispatch on their column count as the single-system
   // launchers do: [C, r~] has nc + 1 columns, the C-updates nc
   KRS_BATCH_NC(nc + 1, kg_block_dot<(NCB > 0 ? NCB : 8)><<<tb.pass[ns], kThreads, 0, s>>>(d_tb, 0));
-  kg_finish_alpha<<<ns, kThreads, 0, s>>>(d_tb);
   KRS_BATCH_NC(nc, kg_bicg_sv<NCB><<<tb.pass[ns], kThreads, 0, s>>>(d_tb));
-  kg_finish_half<<<ns, kThreads, 0, s>>>(d_tb);
-  kg_exit_vec<<<tb.exitv[ns], kThreads, 0, s>>>(d_tb);
+  kg_half_exit<<<tb.exitv[ns], kThreads, 0, s>>>(d_tb);
   return hipGetLastError();
 }
 
@@ -2877,7 +2820,6 @@ hipError_t batch_bicg_second_half(hipStream_t s, const BatchTable* d_tb, const B
   kg_jsweep<<<tb.pack[ns], kThreads, 0, s>>>(d_tb, 1);
   kg_stencil<<<tb.pack[ns], kThreads, 0, s>>>(d_tb, 1);
   KRS_BATCH_NC(nc + 1, kg_block_dot<(NCB > 0 ? NCB : 8)><<<tb.pass[ns], kThreads, 0, s>>>(d_tb, 1));
-  kg_finish_omega<<<ns, kThreads, 0, s>>>(d_tb);
   KRS_BATCH_NC(nc, kg_bicg_yr<NCB><<<tb.pass[ns], kThreads, 0, s>>>(d_tb));
   kg_finish_full<<<ns, kThreads, 0, s>>>(d_tb);
   return hipGetLastError();

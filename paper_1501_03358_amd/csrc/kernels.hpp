@@ -232,7 +232,8 @@ struct BatchSys {
   Cols<float> C;          // recycle space C (C.n1 = k_c columns)
   const float* rt;        // shadow residual r~
   float *r, *p, *v, *sv, *t, *z, *y;
-  float* part;            // per-block partial sums
+  float* part;            // per-block partial sums of the dot passes
+  float* part2;           // those of the update passes (not overlapping part's)
   double* sc;             // scalar area (BicgSlot, BicgOff)
   int nblk;               // blocks of the streaming passes
   int64_t n;

@@ -1803,6 +1803,8 @@ int ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys, const krs
         b.part = x->ipart;
         b.sc = x->isc;
         b.nblk = std::min(red_blocks(x->n), 512);
+        // as in rbicgstab_t: after the dot passes' k_c + 2 columns
+        b.part2 = b.part + (size_t)b.nblk * (b.C.n1 + 2);
         b.n = x->n;
         b.ld = x->ld;
       }
