@@ -217,6 +217,33 @@ def test_rbicgstab_plain_and_recycled_match_oracle(gpu_lib, pc):
         assert rel(x2.cpu().numpy(), ref2.x) <= X_TOL
 
 
+def test_rbicgstab_history_on_a_512_block_grid(gpu_lib):
+    """Above 2^19 cells the BiCGStab passes run on 512 blocks and the alpha and
+    omega steps in front of the update passes sum 512 partials per column
+    (the path the benchmark's grids take): FP64 plain and recycled BiCGStab
+    with point Jacobi on a 96^3 random-field medium, the residual history
+    against the oracle's over the first 20 iterations (1e-10)."""
+    krs = gpu_lib
+    prob = W.grf_problem(96, extra=11)
+    d = Dev(krs, prob, "jacobi", m=1, k=6)
+    _, Mi, op = oracle_ops(prob, "jacobi")
+    b = next(W.rhs_ar1(prob, 1, extra=11))
+    rec = krs.Recycle(d.ctx, prob.n, 6, torch.float64)
+    U0 = np.random.default_rng(6).standard_normal((prob.n, 6))
+    rec.U[:6, :prob.n] = torch.from_numpy(U0.T.copy()).to(d.dev)
+    rec.set_dim(6)
+    krs.recycle_update(d.ctx, d.A, d.M, rec, d.ws)
+    g = recycle_to_oracle(rec)
+    for use_rec in (False, True):
+        h = _hist()
+        x = d.empty()
+        rc, st = krs.rbicgstab_solve(d.ctx, d.A, d.M, rec if use_rec else None, d.vec(b), x,
+                                     krs.make_opts(tol=1e-8, max_matvecs=80, history=h), d.ws)
+        ref = K.rbicgstab(op, Mi, b, 1e-8, g if use_rec else None, max_matvecs=80)
+        assert st.history_len >= 20 and len(ref.history) >= 20
+        _check_history(h[:st.history_len], ref.history)
+
+
 @pytest.mark.parametrize("n", [96, 128])
 def test_rbicgstab_true_residual_on_large_grids(gpu_lib, n):
     """On grids above 2^19 cells the residual kernel runs on more blocks
