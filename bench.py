@@ -41,9 +41,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_porous256_ir.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1501_03358_amd", "csrc", "kernels.hip")
 
 
-def measured_traffic(cls):
+def measured_traffic(cls, workload):
     """HBM bytes per launch of kernel class `cls` from the committed counter
-    summary, or None when absent or taken on other kernel code."""
+    summary, or None when absent, taken on other kernel code, or taken on
+    another workload than `workload` (None: a configuration no counters were
+    taken on)."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as f:
@@ -52,6 +54,8 @@ def measured_traffic(cls):
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, ValueError):
         return None, "no counter summary"
+    if workload is None or tr.get("workload", "").split(" ")[0] != workload:
+        return None, "the counters were taken on another workload"
     if tr.get("kernels_sha256") != sha:
         return None, "kernels changed since the counters were taken"
     c = tr.get("classes", {}).get(cls)
@@ -60,6 +64,16 @@ def measured_traffic(cls):
     return c["fetch_bytes"] + c["write_bytes"], None
 N_SWITCH = 3
 M, K = 30, 20
+INNER_TOL = 1e-5
+
+
+def counter_workload(args):
+    """Name of the default leg's workload as the counter summary records it,
+    or None when a parameter differs from those the counters were taken with."""
+    if (args.shape is not None or args.m != M or args.k != K or args.n_switch != N_SWITCH
+            or args.local_solver != "jacobi" or args.inner_tol != INNER_TOL):
+        return None
+    return f"porous{args.n}_ir"
 
 
 def local_params(args):
@@ -74,10 +88,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def build_inputs(n, steps, warmup, dev, torch):
+def build_inputs(n, steps, warmup, dev, torch, shape=None):
     import workloads as W
     t0 = time.time()
-    prob = W.porous_problem(n, seed_cfg=4)
+    prob = W.porous_problem(n, seed_cfg=4, shape=shape)
     gen = W.rhs_ar1(prob, warmup + steps, seed_cfg=4)
     bs = [torch.from_numpy(next(gen)).to(dev) for _ in range(warmup + steps)]
     log(f"[bench] inputs: {prob.name} N={prob.n} ({time.time() - t0:.1f}s)")
@@ -162,7 +176,7 @@ def cpu_baseline(prob, U, C, counts):
     info = host_info()
     return {"value": len(counts) / total, "unit": "solves/s",
             "cores": info["blas_threads"] or 1, "kind": "oracle",
-            "sample": (f"oracle on the {prob.shape[0]}^3 system, FP64 NumPy on the host "
+            "sample": (f"oracle on the {prob.name} system, FP64 NumPy on the host "
                        f"({info['cpu_model']}, {info['cpu_count']} logical CPUs; BLAS products on "
                        f"{info['blas_threads']} threads, stencil and preconditioner on 1): one "
                        f"rBiCGStab iteration with k={C.shape[1]} took {t_it:.2f} s, one rGCROT "
@@ -658,7 +672,7 @@ def seq_main(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
+def make_parser():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["porous_ir", "serve", "channel128", "porous128",
                                            "porous128_changing", "skewed128", "grf24"],
@@ -685,13 +699,16 @@ def main():
                     help="systems timed (default 20; 50 channel128, 100 porous128)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="grid size per axis")
+    ap.add_argument("--shape", type=int, nargs=3, metavar=("NX", "NY", "NZ"), default=None,
+                    help="default workload on an NX x NY x NZ box instead of n^3 (e.g. one "
+                         "rank's z-slab of a 256^3 grid split over 8 GPUs: 256 256 32)")
     ap.add_argument("--m", type=int, default=M, help="rGCROT cycle length")
     ap.add_argument("--k", type=int, default=K, help="recycle dimension")
     ap.add_argument("--rule", choices=["harmonic", "gcrot"], default="harmonic",
                     help="channel128/porous128: also run rGCROT with the GCROT recycle rule")
     ap.add_argument("--gcrot-p", type=int, default=1,
                     help="GCROT rule: inner vectors selected per cycle")
-    ap.add_argument("--inner-tol", type=float, default=1e-5)
+    ap.add_argument("--inner-tol", type=float, default=INNER_TOL)
     ap.add_argument("--n-switch", type=int, default=N_SWITCH,
                     help="porous128: systems solved by rGCROT before rBiCGStab")
     ap.add_argument("--hybrid-only", action="store_true",
@@ -708,7 +725,14 @@ def main():
                     help="serve: requests the batch worker solves together (0: none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM counters)")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = make_parser().parse_args()
+    if args.shape is not None and args.workload != "porous_ir":
+        print("--shape applies to the default workload (porous_ir)", file=sys.stderr)
+        sys.exit(2)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the method here runs on a single MI355X; "
@@ -745,7 +769,7 @@ def main():
         return
     if args.steps is None:
         args.steps = 20
-    prob, bs = build_inputs(args.n, args.steps, args.warmup, dev, torch)
+    prob, bs = build_inputs(args.n, args.steps, args.warmup, dev, torch, args.shape)
     ctx = krs.Context(dev)
     b64 = torch.from_numpy(prob.bands).to(dev)
     b32 = b64.float()
@@ -839,7 +863,7 @@ def main():
         kernels = {c: {"launches": v[0], "ms": round(v[1], 3),
                        "GB_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
                    for c, v in kt.items() if v[0] > 0}
-        traffic, traffic_note = measured_traffic(dom)
+        traffic, traffic_note = measured_traffic(dom, counter_workload(args))
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                     "traffic_unit": "HBM bytes per launch (rocprofv3 counters)",
@@ -866,7 +890,9 @@ def main():
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * t_ir / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"porous{args.n}_ir", "grid": f"{args.n}^3",
+        "config": {"workload": f"{prob.name}_ir",
+                   "grid": (f"{args.n}^3" if args.shape is None
+                            else "x".join(str(v) for v in args.shape)),
                    "unknowns": prob.n, "time_steps": args.steps,
                    "solver": (f"hybrid rGCROT({args.m},{args.k}) x{args.n_switch} -> "
                               f"rBiCGStab(k={args.k})"),
