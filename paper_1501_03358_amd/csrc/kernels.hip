@@ -1552,6 +1552,7 @@ __global__ void k_bicg_setup(double* sc, int kc, double tol, double div_factor) 
   for (int c = 0; c < kc; ++c) sc[kBXi + c] = -sc[kBEta1 + c];
   for (int i = 0; i < kSlots; ++i) sc[i] = 0.0;
   sc[kRho] = rn2;
+  sc[kRhoNew] = rn2;
   sc[kOmega] = 1.0;
   sc[kBeta] = 0.0;
   sc[kRnorm2] = rn2;
@@ -1653,23 +1654,6 @@ __global__ void k_set_norm(const double* nrm2, double* hcol_last, double* inv,
 // ---------------------------------------------------------------------------
 // BiCGStab passes
 // ---------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ void bicg_p_body(Blk k, const T* __restrict__ r, T* __restrict__ p,
-                                            const T* __restrict__ v, const double* sc,
-                                            int64_t n) {
-  if (sc[kDone] != 0.0) return;
-  const T beta = (T)sc[kBeta], omega = (T)sc[kOmega];
-  const int64_t i = (int64_t)k.b * kThreads + threadIdx.x;
-  if (i < n) p[i] = r[i] + beta * (p[i] - omega * v[i]);
-}
-
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_bicg_p(const T* __restrict__ r, T* __restrict__ p,
-                                                     const T* __restrict__ v, const double* sc,
-                                                     int64_t n) {
-  bicg_p_body<T>(hw_blk(), r, p, v, sc, n);
-}
-
 template <class T, int W, int NC>
 __device__ __forceinline__ void sv_rows(const Cols<T>& C, const T* cf, T alpha,
                                         const T* __restrict__ r, T* v, T* __restrict__ sv,
@@ -1752,6 +1736,20 @@ __device__ __forceinline__ void bicg_yr_main(Blk k, const Cols<T>& C, const T* c
     yr_rows<T, 1, NC>(C, cf, alpha, omega, t, sv, p, y, r, rt, npk * W + threadIdx.x, n,
                       kThreads, acc);
   reduce_store<T, 2>(acc, 2, partials, nblk, k);
+}
+
+// p = r + beta (p - omega v)
+template <class T, int W>
+__device__ __forceinline__ void p_rows(const T* __restrict__ r, T* __restrict__ p,
+                                       const T* __restrict__ v, T beta, T omega, int64_t i0,
+                                       int64_t i1, int64_t step) {
+  for (int64_t iv = i0; iv < i1; iv += step) {
+    const Pk<T, W> ri = ldn<T, W>(r, iv), vi = ldn<T, W>(v, iv);
+    Pk<T, W> pi = ldn<T, W>(p, iv);
+#pragma unroll
+    for (int e = 0; e < W; ++e) pi.v[e] = ri.v[e] + beta * (pi.v[e] - omega * vi.v[e]);
+    stp<T, W>(p, iv, pi);
+  }
 }
 
 __device__ inline void hist_push(double* sc, double v) {
@@ -1913,9 +1911,10 @@ __device__ __forceinline__ void step_cols(const T* partials, int nblk, int ncols
 
 // eta1 = C^T v, r~^T v; alpha = rho / (r~^T v - (C^T r~) . eta1).  Every
 // thread of the block gets eta1 in sh[] and alpha in *al; with `write` the
-// block also stores them (and the breakdown flag) in the scalar area.  Reads
-// no scalar-area slot it writes, so several blocks of one kernel can run it
-// with one of them writing.
+// block also stores them (and the breakdown flag) in the scalar area and
+// takes rho over from kRhoNew into kRho.  Reads no scalar-area slot it
+// writes, so several blocks of one kernel can run it with one of them
+// writing.
 template <class T>
 __device__ __forceinline__ void alpha_step(const T* partials, int nblk, int kc, double* sums,
                                            double* sc, int off_eta1, int off_ctrt, bool write,
@@ -1925,10 +1924,12 @@ __device__ __forceinline__ void alpha_step(const T* partials, int nblk, int kc, 
   // memory interleaved with stores to the same array waits for one load per
   // column (about 30 us per launch at k = 20)
   for (int c = threadIdx.x; c < kc; c += kThreads) ctrt[c] = sc[off_ctrt + c];
-  const double rho = threadIdx.x == 0 ? sc[kRho] : 0.0;
+  // rho of this iteration as the last full step formed it
+  const double rho = threadIdx.x == 0 ? sc[kRhoNew] : 0.0;
   step_cols<T>(partials, nblk, kc + 1, write ? sums : nullptr, sh);
   if (write)
     for (int c = threadIdx.x; c < kc; c += kThreads) sc[off_eta1 + c] = sh[c];
+  if (write && threadIdx.x == 0) sc[kRho] = rho;
   if (threadIdx.x == 0) {
     double corr = 0;
     for (int c = 0; c < kc; ++c) corr += ctrt[c] * sh[c];
@@ -2030,33 +2031,63 @@ __device__ __forceinline__ void omega_step(const T* partials, int nblk, int kc, 
   }
 }
 
-// rho = r~^T r, |r|^2, beta; then the full-step tests (convergence,
-// breakdowns, divergence guard, rho = 0)
-template <class T>
-__device__ __forceinline__ void bicg_finish_full_body(const T* partials, int nblk,
-                                                               double* sums, double* sc) {
+// The full step: rho = r~^T r, |r|^2, beta and the full-step tests
+// (convergence, breakdowns, divergence guard, rho = 0), then, unless the
+// iteration stops there, p = r + beta (p - omega v) for the next one.  Every
+// block sums the yr pass's partials itself (the same code in the same order,
+// so every block reaches the same beta and decision); block 0 stores the
+// state.  No block reads a slot block 0 writes here: the old rho is kRho, the
+// new one goes to kRhoNew.  A block that starts after block 0 stored a stop
+// returns at once, as it would have decided the same.
+template <class T, int W>
+__device__ __forceinline__ void bicg_finish_p_body(Blk k, const T* partials, int nblk,
+                                                   double* sums, double* sc,
+                                                   const T* __restrict__ r, T* __restrict__ p,
+                                                   const T* __restrict__ v, int64_t n) {
   __shared__ double sh[kFinishCols];
+  __shared__ double beta_s;
+  __shared__ int go;
   if (sc[kDone] != 0.0) return;
-  finish_cols<T>(partials, nblk, 2, sums, sh);
-  if (threadIdx.x != 0) return;
-  const double rho = sh[0], rn2 = sh[1];
-  const double rho_old = sc[kRho];
-  sc[kRnorm2] = rn2;
-  sc[kRhoOld] = rho_old;
-  sc[kBeta] = sc[kOmega] != 0.0 ? (rho / rho_old) * (sc[kAlpha] / sc[kOmega]) : 0.0;
-  sc[kRho] = rho;
-  const double rn = sqrt(rn2);
-  hist_push(sc, rn);
-  if (sc[kFlag] != 0.0) sc[kDone] = kBreak;
-  else if (!isfinite(rn) || rn > sc[kDivAbs]) sc[kDone] = kDiverge;
-  else if (rn <= sc[kTolAbs]) sc[kDone] = kConvFull;
-  else if (rho == 0.0) sc[kDone] = kBreak;
+  const bool write = k.b == 0;
+  if (nblk <= 2 * kThreads && nblk > kThreads)
+    finish_cols_512<T, 2>(partials, nblk, 2, write ? sums : nullptr, sh);
+  else
+    finish_cols<T>(partials, nblk, 2, write ? sums : nullptr, sh);
+  if (threadIdx.x == 0) {
+    const double rho = sh[0], rn2 = sh[1];
+    const double rho_old = sc[kRho];
+    const double beta = sc[kOmega] != 0.0 ? (rho / rho_old) * (sc[kAlpha] / sc[kOmega]) : 0.0;
+    const double rn = sqrt(rn2);
+    int d = 0;
+    if (sc[kFlag] != 0.0) d = kBreak;
+    else if (!isfinite(rn) || rn > sc[kDivAbs]) d = kDiverge;
+    else if (rn <= sc[kTolAbs]) d = kConvFull;
+    else if (rho == 0.0) d = kBreak;
+    if (write) {
+      sc[kRnorm2] = rn2;
+      sc[kRhoNew] = rho;
+      sc[kBeta] = beta;
+      hist_push(sc, rn);
+      if (d != 0) sc[kDone] = d;
+    }
+    beta_s = beta;
+    go = d == 0;
+  }
+  __syncthreads();
+  if (!go) return;
+  const T beta = (T)beta_s, omega = (T)sc[kOmega];
+  const int64_t npk = n / W;
+  p_rows<T, W>(r, p, v, beta, omega, first_row(k), npk, grid_step(k));
+  if (W > 1 && k.b == k.G - 1) p_rows<T, 1>(r, p, v, beta, omega, npk * W + threadIdx.x, n, kThreads);
 }
 
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_bicg_finish_full(const T* partials, int nblk,
-                                                               double* sums, double* sc) {
-  bicg_finish_full_body<T>(partials, nblk, sums, sc);
+template <class T, int W>
+__global__ __launch_bounds__(kThreads) void k_bicg_finish_p(const T* partials, int nblk,
+                                                            double* sums, double* sc,
+                                                            const T* __restrict__ r,
+                                                            T* __restrict__ p,
+                                                            const T* __restrict__ v, int64_t n) {
+  bicg_finish_p_body<T, W>(hw_blk(), partials, nblk, sums, sc, r, p, v, n);
 }
 
 // The alpha step fused in front of the sv pass: every block sums the
@@ -2179,14 +2210,6 @@ __device__ __forceinline__ int batch_sys(const int* off, int nsys) {
 }
 __device__ __forceinline__ int dev_grid_for(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
 
-__global__ __launch_bounds__(kThreads) void kg_bicg_p(const BatchTable* tb) {
-  const int s = batch_sys(tb->elem, tb->nsys);
-  const BatchSys& q = tb->sys[s];
-  const int b = (int)blockIdx.x - tb->elem[s], cnt = dev_grid_for(q.n);
-  if (b >= cnt) return;
-  bicg_p_body<float>(Blk{b, cnt}, q.r, q.p, q.v, q.sc, q.n);
-}
-
 // operator pieces of A~ in -> out (in = p, out = v for which = 0; in = s,
 // out = t for which = 1): local solves into out, the global sweep from out
 // into z, the matvec of z into out
@@ -2286,10 +2309,14 @@ __global__ __launch_bounds__(kThreads) void kg_half_exit(const BatchTable* tb) {
     q.r[i] = q.sv[i];
   }
 }
-// one block per system: rho, |r|^2, beta and the full-step tests
-__global__ __launch_bounds__(kThreads) void kg_finish_full(const BatchTable* tb) {
-  const BatchSys& q = tb->sys[blockIdx.x];
-  bicg_finish_full_body<float>(q.part2, q.nblk, q.sc + kBSums, q.sc);
+// the full step with the p update (as k_bicg_finish_p), nblk blocks per system
+__global__ __launch_bounds__(kThreads) void kg_finish_p(const BatchTable* tb) {
+  const int s = batch_sys(tb->pass, tb->nsys);
+  const BatchSys& q = tb->sys[s];
+  const int b = (int)blockIdx.x - tb->pass[s], cnt = q.nblk;
+  if (b >= cnt) return;
+  bicg_finish_p_body<float, 4>(Blk{b, cnt}, q.part2, q.nblk, q.sc + kBSums, q.sc, q.r, q.p, q.v,
+                               q.n);
 }
 
 }  // namespace
@@ -2652,13 +2679,6 @@ hipError_t set_norm_from_sum(hipStream_t s, const double* nrm2, double* hcol_las
 }
 
 template <class T>
-hipError_t bicg_p(hipStream_t s, const T* r, T* p, const T* v, const double* sc, int64_t n) {
-  if (n == 0) return hipSuccess;
-  k_bicg_p<T><<<grid_for(n), kThreads, 0, s>>>(r, p, v, sc, n);
-  return hipGetLastError();
-}
-
-template <class T>
 hipError_t bicg_sv_fused(hipStream_t s, const Cols<T>& C, const T* r, T* v, T* sv, double* sc,
                          int off_eta1, int off_ctrt, double* sums, int64_t n, const T* dot,
                          T* partials, int nblk) {
@@ -2727,8 +2747,14 @@ hipError_t bicg_half_exit(hipStream_t s, const T* p, T* y, const T* sv, T* r, do
 }
 
 template <class T>
-hipError_t bicg_finish_full(hipStream_t s, const T* partials, int nblk, double* sums, double* sc) {
-  k_bicg_finish_full<T><<<1, kThreads, 0, s>>>(partials, nblk, sums, sc);
+hipError_t bicg_finish_p(hipStream_t s, const T* partials, int nblk, double* sums, double* sc,
+                         const T* r, T* p, const T* v, int64_t n) {
+  constexpr int VW = 16 / sizeof(T);
+  const int grid = std::min(grid_for(n), 512);
+  if (vec_ok(r) && vec_ok((const T*)p) && vec_ok(v))
+    k_bicg_finish_p<T, VW><<<grid, kThreads, 0, s>>>(partials, nblk, sums, sc, r, p, v, n);
+  else
+    k_bicg_finish_p<T, 1><<<grid, kThreads, 0, s>>>(partials, nblk, sums, sc, r, p, v, n);
   return hipGetLastError();
 }
 
@@ -2762,27 +2788,22 @@ hipError_t axpy_f32_into_f64(hipStream_t s, const float* d, double* x, int64_t n
 
 void batch_layout(BatchTable& tb) {
   auto up8 = [](int v) { return (v + kXcd - 1) / kXcd * kXcd; };
-  int e = 0, pk = 0, ti = 0, pa = 0, ex = 0;
+  int pk = 0, ti = 0, pa = 0, ex = 0;
   for (int s = 0; s < tb.nsys; ++s) {
     const BatchSys& q = tb.sys[s];
-    tb.elem[s] = e;
     tb.pack[s] = pk;
     tb.tile[s] = ti;
     tb.pass[s] = pa;
     tb.exitv[s] = ex;
-    tb.fin[s] = s;
-    e = up8(e + grid_for(q.n));
     pk = up8(pk + grid_for(q.n / 4));
     ti = up8(ti + (q.g.nx / 8) * (q.g.ny / 8) * (q.g.nz / 8) / 2);   // tile pairs
     pa = up8(pa + q.nblk);
     ex = up8(ex + std::min(grid_for(q.n), 512));
   }
-  tb.elem[tb.nsys] = e;
   tb.pack[tb.nsys] = pk;
   tb.tile[tb.nsys] = ti;
   tb.pass[tb.nsys] = pa;
   tb.exitv[tb.nsys] = ex;
-  tb.fin[tb.nsys] = tb.nsys;
 }
 
 #define KRS_BATCH_NC(ncount, ...)                                 \
@@ -2800,7 +2821,6 @@ hipError_t batch_bicg_first_half(hipStream_t s, const BatchTable* d_tb, const Ba
                                  int nc) {
   const int ns = tb.nsys;
   if (ns < 1 || ns > kMaxBatch) return hipErrorInvalidValue;
-  kg_bicg_p<<<tb.elem[ns], kThreads, 0, s>>>(d_tb);
   kg_schwarz<<<tb.tile[ns], kPairThreads, 0, s>>>(d_tb, 0);
   kg_jsweep<<<tb.pack[ns], kThreads, 0, s>>>(d_tb, 0);
   kg_stencil<<<tb.pack[ns], kThreads, 0, s>>>(d_tb, 0);
@@ -2821,7 +2841,7 @@ hipError_t batch_bicg_second_half(hipStream_t s, const BatchTable* d_tb, const B
   kg_stencil<<<tb.pack[ns], kThreads, 0, s>>>(d_tb, 1);
   KRS_BATCH_NC(nc + 1, kg_block_dot<(NCB > 0 ? NCB : 8)><<<tb.pass[ns], kThreads, 0, s>>>(d_tb, 1));
   KRS_BATCH_NC(nc, kg_bicg_yr<NCB><<<tb.pass[ns], kThreads, 0, s>>>(d_tb));
-  kg_finish_full<<<ns, kThreads, 0, s>>>(d_tb);
+  kg_finish_p<<<tb.pass[ns], kThreads, 0, s>>>(d_tb);
   return hipGetLastError();
 }
 #undef KRS_BATCH_NC
@@ -2853,7 +2873,6 @@ hipError_t batch_bicg_second_half(hipStream_t s, const BatchTable* d_tb, const B
   template hipError_t finish_sum<T>(hipStream_t, const T*, int, int, double*, const int*);        \
   template hipError_t finish_cgs2<T>(hipStream_t, const T*, int, int, const double*, double*,     \
                                      double*, double*, int*, const int*);                         \
-  template hipError_t bicg_p<T>(hipStream_t, const T*, T*, const T*, const double*, int64_t);     \
   template hipError_t bicg_sv_fused<T>(hipStream_t, const Cols<T>&, const T*, T*, T*, double*,   \
                                        int, int, double*, int64_t, const T*, T*, int);           \
   template hipError_t bicg_yr_fused<T>(hipStream_t, const Cols<T>&, const T*, const T*,         \
@@ -2861,7 +2880,8 @@ hipError_t batch_bicg_second_half(hipStream_t s, const BatchTable* d_tb, const B
                                        double*, int64_t, const T*, T*, int);                     \
   template hipError_t bicg_half_exit<T>(hipStream_t, const T*, T*, const T*, T*, double*, int,  \
                                         int, int, const T*, int, int64_t);                       \
-  template hipError_t bicg_finish_full<T>(hipStream_t, const T*, int, double*, double*);           \
+  template hipError_t bicg_finish_p<T>(hipStream_t, const T*, int, double*, double*, const T*,    \
+                                       T*, const T*, int64_t);                                    \
   template hipError_t fill<T>(hipStream_t, T*, int64_t, double);                                  \
   template hipError_t copy<T>(hipStream_t, const T*, T*, int64_t);
 

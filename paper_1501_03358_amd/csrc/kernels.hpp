@@ -135,8 +135,11 @@ hipError_t cgs_decide(hipStream_t s, int ncols, const double* h1, double* hcol, 
 
 // ---- BiCGStab fused passes (all scalars in the FP64 array `sc`) ----
 // scalar slots
+// kRho is the rho of the current iteration; the full step stores the next
+// one in kRhoNew and the next alpha step takes it over into kRho (so that no
+// block of the full-step launch reads a slot that its block 0 writes).
 enum BicgSlot {
-  kRho = 0, kRhoOld, kAlpha, kOmega, kBeta, kRtv, kSnorm2, kRnorm2, kTs, kTt, kFlag,
+  kRho = 0, kRhoNew, kAlpha, kOmega, kBeta, kRtv, kSnorm2, kRnorm2, kTs, kTt, kFlag,
   // device-driven iteration: state (kDone), iterations started, history
   // entries written, absolute stopping and divergence thresholds, and whether
   // the stop came at the half step
@@ -151,8 +154,6 @@ enum BicgDone { kRunning = 0, kConvHalf = 1, kConvFull = 2, kBreak = 3, kDiverge
 // history ring of the device-driven loop (absolute norms, 2 per iteration)
 constexpr int kHistOff = 512, kHistRing = 128;
 // BiCGStab pieces; `sums` are finished FP64 dot products.
-template <class T>
-hipError_t bicg_p(hipStream_t s, const T* r, T* p, const T* v, const double* sc, int64_t n);
 // The sv pass (v -= C eta1 ; s = r - alpha v ; partial |s|^2) and the yr pass
 // (y += alpha p + omega s ; r = s - omega (t - C eta2) ; partials r~.r,
 // |r|^2), each with its scalar step in front (alpha, resp. omega and xi):
@@ -173,9 +174,13 @@ template <class T>
 hipError_t bicg_half_exit(hipStream_t s, const T* p, T* y, const T* sv, T* r, double* sc,
                           int off_eta1, int off_xi, int kc, const T* partials, int nblk,
                           int64_t n);
-// One block: finish rho, |r|^2, then beta and the full-step tests.
+// The full step: every block finishes rho = r~.r and |r|^2 from the yr
+// pass's partials, forms beta and takes the full-step tests; block 0 stores
+// the state; unless the iteration stops there, the blocks then update
+// p = r + beta (p - omega v) for the next iteration.
 template <class T>
-hipError_t bicg_finish_full(hipStream_t s, const T* partials, int nblk, double* sums, double* sc);
+hipError_t bicg_finish_p(hipStream_t s, const T* partials, int nblk, double* sums, double* sc,
+                         const T* r, T* p, const T* v, int64_t n);
 // hcol_last = sqrt(*nrm2), inv = 1/hcol_last
 hipError_t set_norm_from_sum(hipStream_t s, const double* nrm2, double* hcol_last, double* inv,
                              const int* run_if = nullptr);
@@ -208,7 +213,7 @@ enum BicgOff {
   kBSums = 32, kBEta1 = 128, kBEta2 = 192, kBXi = 256, kBCtrt = 320, kBNrm = 384, kBNb2 = 385
 };
 // Starting state of an rBiCGStab solve from its setup sums: xi = -eta1, the
-// slots (rho = |r_0|^2, omega = 1, beta = 0, the absolute tolerance and
+// slots (rho = rho_new = |r_0|^2, omega = 1, beta = 0, the absolute tolerance and
 // divergence thresholds from ||b|| = sqrt(sc[kBNb2])); |r_0|^2 is sc[kBNrm]
 // after the projection (kc > 0) or ||b||^2 (kc = 0).  The same values the
 // host forms and uploads in the single-system driver.
@@ -241,20 +246,18 @@ struct BatchSys {
 };
 struct BatchTable {
   int nsys;
-  int elem[kMaxBatch + 1];   // block ranges: one row per thread
-  int pack[kMaxBatch + 1];   //   four rows per thread (stencil packs)
+  int pack[kMaxBatch + 1];   // block ranges: four rows per thread (stencil packs)
   int tile[kMaxBatch + 1];   //   two Schwarz tiles (an x-pair) per block
   int pass[kMaxBatch + 1];   //   streaming passes (nblk blocks)
   int exitv[kMaxBatch + 1];  //   the half-step exit update (at most 512 blocks)
-  int fin[kMaxBatch + 1];    //   one block per system (finishing reductions)
   BatchSys sys[kMaxBatch];
 };
 // Fills the block ranges of `tb` from its systems (host side).
 void batch_layout(BatchTable& tb);
 // One rBiCGStab pass sequence for all systems of the table (device copy
-// d_tb, host copy tb): the first half (p update, A~ p, C-projection, alpha,
+// d_tb, host copy tb): the first half (A~ p, C-projection, alpha,
 // s, half-step tests and exit) and the second half (A~ s, omega, y and r
-// updates, full-step tests).  The operator is Schwarz-Jacobi (packed Jacobi
+// updates, full-step tests, next p).  The operator is Schwarz-Jacobi (packed Jacobi
 // local sweeps, one global sweep) followed by the matvec.  Systems whose stop
 // state is set skip every launch.  `nc` is the recycle dimension shared by
 // all systems of the table.

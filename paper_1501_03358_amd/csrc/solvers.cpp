@@ -1074,10 +1074,11 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 1), block_dot<T>(s, Cc, rt, n, 0, part, nblk));
     KRS_LAUNCH(ctx, KRS_K_OTHER, 0, finish_sum<T>(s, part, nblk, kc, sc + kCtrt));
   }
-  KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, p, n, 0.0));
-  KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, v, n, 0.0));
+  // p_0 = r_0 (the full step of each iteration forms the next p)
+  KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<T>(s, r, p, n));
   KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<T>(s, y, n, 0.0));
   slots[kRho] = rn2;  // r~ = r
+  slots[kRhoNew] = rn2;
   slots[kOmega] = 1.0;
   slots[kBeta] = 0.0;
   slots[kRnorm2] = rn2;
@@ -1099,7 +1100,6 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
   // are charged to the byte model from the counts read back (dev = true).
   const double bytes_p = 4 * NW, bytes_sv = NW * (kc + (kc > 0 ? 4 : 3)), bytes_yr = NW * (kc + 7);
   auto first_half = [&](bool dev) -> int {
-    KRS_LAUNCH(ctx, KRS_K_BICG_P, dev ? 0 : bytes_p, bicg_p<T>(s, r, p, v, sc, n));
     int e = op.apply(p, v);
     if (e) return e;
     // eta1 = C^T v, v -= C eta1, alpha = rho / r~^T v, s = r - alpha v
@@ -1122,12 +1122,14 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     // eta2 = C^T t, omega = t^T s / |t - C eta2|^2, xi update
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 2),
                block_dot<T>(s, cols<T>(C, ldr, kc, sv, ld, 1), t, n, 1, part, nblk));
-    // the omega step in front of the y and r updates (with the next
-    // rho = r~^T r), then the loop tests
+    // the omega step in front of the y and r updates (with the partials of
+    // the next rho = r~^T r), then the loop tests and the next p
     KRS_LAUNCH(ctx, KRS_K_BICG_YR, dev ? 0 : bytes_yr,
                bicg_yr_fused<T>(s, Cc, t, sv, p, y, r, rt, sc, kEta1, kEta2, kXi, sc + kSums, n,
                                 part, part2, nblk));
-    KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_finish_full<T>(s, part2, nblk, sc + kSums, sc));
+    // (its p update is charged once the state read back shows it ran)
+    KRS_LAUNCH(ctx, KRS_K_BICG_P, 0,
+               bicg_finish_p<T>(s, part2, nblk, sc + kSums, sc, r, p, v, n));
     return 0;
   };
   if (o->flags & KRS_FLAG_HOST_LOOP) {
@@ -1165,7 +1167,8 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
       if (rc) return rc;
       std::copy(ctx->pin, ctx->pin + kSlots, slots.begin());
       rnorm = std::sqrt(slots[kRnorm2]);
-      rho = slots[kRho];
+      rho = slots[kRhoNew];
+      if (slots[kDone] == kRunning) timing_add_bytes(ctx, KRS_K_BICG_P, bytes_p);
       hist(rnorm / nb);
       if (slots[kFlag] != 0.0) {
         status = KRS_BREAKDOWN;
@@ -1271,7 +1274,9 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
       const int done_now = (int)d[kDone];
       const bool half = done_now != kRunning && d[kEndHalf] != 0.0;
       const bool exited = done_now == kExited || done_now == kConvHalf;
-      timing_add_bytes(ctx, KRS_K_BICG_P, started * bytes_p + (exited ? 5 * NW : 0.0));
+      // p is formed at the end of every iteration that goes on
+      const int64_t p_updates = started - (done_now != kRunning ? 1 : 0);
+      timing_add_bytes(ctx, KRS_K_BICG_P, p_updates * bytes_p + (exited ? 5 * NW : 0.0));
       timing_add_bytes(ctx, KRS_K_BICG_SV, started * bytes_sv);
       timing_add_bytes(ctx, KRS_K_BICG_YR, (started - (half ? 1 : 0)) * bytes_yr);
       its = (int64_t)d[kIts];
@@ -1703,7 +1708,7 @@ int ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys, const krs
   auto inner_batch = [&](std::vector<IrSys*>& act) -> int {
     // setup of each inner solve, enqueued for all systems before one
     // synchronisation: the kernels rbicgstab_t runs (||b||, projection of b
-    // against C, r~, C^T r~, zero p v y) and the starting state it forms on
+    // against C, r~, C^T r~, p = r, zero y) and the starting state it forms on
     // the host, formed on the device (same values)
     std::vector<IrSys*> run;
     for (IrSys* x : act) {
@@ -1740,8 +1745,7 @@ int ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys, const krs
         KRS_LAUNCH(ctx, KRS_K_OTHER, 0,
                    finish_sum<float>(s, x->ipart, nblk, kc, x->isc + kBCtrt));
       }
-      KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<float>(s, x->p, x->n, 0.0));
-      KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<float>(s, x->v, x->n, 0.0));
+      KRS_LAUNCH(ctx, KRS_K_OTHER, 2 * NW, copy<float>(s, x->r, x->p, x->n));
       KRS_LAUNCH(ctx, KRS_K_OTHER, NW, fill<float>(s, x->y, x->n, 0.0));
       KRS_LAUNCH(ctx, KRS_K_OTHER, 0, bicg_setup(s, x->isc, kc, x->itol, io.div_factor));
     }
