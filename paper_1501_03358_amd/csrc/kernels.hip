@@ -1752,6 +1752,21 @@ __device__ __forceinline__ void p_rows(const T* __restrict__ r, T* __restrict__ 
   }
 }
 
+// the vector part of the half-step exit: y += alpha p, r = s
+template <class T, int W>
+__device__ __forceinline__ void exit_rows(const T* __restrict__ p, T* __restrict__ y,
+                                          const T* __restrict__ sv, T* __restrict__ r, T alpha,
+                                          int64_t i0, int64_t i1, int64_t step) {
+  for (int64_t iv = i0; iv < i1; iv += step) {
+    const Pk<T, W> pi = ldn<T, W>(p, iv), si = ldn<T, W>(sv, iv);
+    Pk<T, W> yi = ldn<T, W>(y, iv);
+#pragma unroll
+    for (int e = 0; e < W; ++e) yi.v[e] += alpha * pi.v[e];
+    stp<T, W>(y, iv, yi);
+    stp<T, W>(r, iv, si);
+  }
+}
+
 __device__ inline void hist_push(double* sc, double v) {
   const int h = (int)sc[kHlen];
   sc[kHistOff + h % kHistRing] = v;
@@ -1996,7 +2011,8 @@ __device__ __forceinline__ int half_step(const T* partials, int nblk, double* sc
 
 // eta2 = C^T t; omega = t^T s / (|t|^2 - |eta2|^2); xi += alpha eta1 + omega
 // eta2.  Every thread gets eta2 in sh[] and omega in *om; with `write` the
-// block stores them, the breakdown flag and xi.  Reads no scalar-area slot it
+// block stores them, the breakdown flag (kFlagT, which the half-step tests
+// running in the same launch do not read) and xi.  Reads no scalar-area slot it
 // writes except through `write`.
 template <class T>
 __device__ __forceinline__ void omega_step(const T* partials, int nblk, int kc, double* sums,
@@ -2013,7 +2029,7 @@ __device__ __forceinline__ void omega_step(const T* partials, int nblk, int kc, 
     const double tt = sh[kc + 1] - q;  // |t - C eta2|^2 with C^T C = I
     double omega = 0.0;  // t = 0 (breakdown): y += alpha p, r = s; the stop state is set next
     if (tt > 0.0 && isfinite(tt)) omega = ts / tt;
-    else if (write) sc[kFlag] = 2.0;
+    else if (write) sc[kFlagT] = 2.0;
     if (write) {
       sc[kTs] = ts;
       sc[kTt] = tt;
@@ -2038,7 +2054,8 @@ __device__ __forceinline__ void omega_step(const T* partials, int nblk, int kc, 
 // so every block reaches the same beta and decision); block 0 stores the
 // state.  No block reads a slot block 0 writes here: the old rho is kRho, the
 // new one goes to kRhoNew.  A block that starts after block 0 stored a stop
-// returns at once, as it would have decided the same.
+// returns at once, as it would have decided the same.  After a half-step
+// exit (kConvHalf) block 0 marks the exit applied and nothing else runs.
 template <class T, int W>
 __device__ __forceinline__ void bicg_finish_p_body(Blk k, const T* partials, int nblk,
                                                    double* sums, double* sc,
@@ -2047,8 +2064,14 @@ __device__ __forceinline__ void bicg_finish_p_body(Blk k, const T* partials, int
   __shared__ double sh[kFinishCols];
   __shared__ double beta_s;
   __shared__ int go;
-  if (sc[kDone] != 0.0) return;
   const bool write = k.b == 0;
+  const double d0 = sc[kDone];
+  if (d0 == (double)kConvHalf) {
+    // the half-step exit was applied by the yr pass of this iteration
+    if (write && threadIdx.x == 0) sc[kDone] = kExited;
+    return;
+  }
+  if (d0 != 0.0) return;
   if (nblk <= 2 * kThreads && nblk > kThreads)
     finish_cols_512<T, 2>(partials, nblk, 2, write ? sums : nullptr, sh);
   else
@@ -2059,7 +2082,7 @@ __device__ __forceinline__ void bicg_finish_p_body(Blk k, const T* partials, int
     const double beta = sc[kOmega] != 0.0 ? (rho / rho_old) * (sc[kAlpha] / sc[kOmega]) : 0.0;
     const double rn = sqrt(rn2);
     int d = 0;
-    if (sc[kFlag] != 0.0) d = kBreak;
+    if (sc[kFlag] != 0.0 || sc[kFlagT] != 0.0) d = kBreak;
     else if (!isfinite(rn) || rn > sc[kDivAbs]) d = kDiverge;
     else if (rn <= sc[kTolAbs]) d = kConvFull;
     else if (rho == 0.0) d = kBreak;
@@ -2113,25 +2136,47 @@ __global__ __launch_bounds__(kThreads) void k_bicg_sv_fused(Cols<T> C, const T* 
   bicg_sv_main<T, W, NC>(k, C, cf, (T)al, r, v, sv, n, partials, nblk);
 }
 
-// The omega step fused in front of the yr pass (as k_bicg_sv_fused); the
-// first pass after a half-step exit marks the exit applied and returns.
-template <class T, int W, int NC>
+// The omega step fused in front of the yr pass (as k_bicg_sv_fused).  With
+// HALF the half-step tests run first, from the sv pass's |s|^2 partials
+// `spart` (every block decides; block 0 stores the state): on convergence
+// the blocks apply the vector part of the exit (y += alpha p, r = s) instead
+// of the yr update, on a breakdown or divergence they return.  Block 0 may
+// store kConvHalf before another block starts: that block goes on and
+// reaches the same decision (the full step turns kConvHalf into kExited, so
+// a later iteration's pass never sees it).  Without HALF (the half-step
+// tests ran in their own launch) the first pass after a half-step exit marks
+// the exit applied and returns.
+template <class T, int W, int NC, bool HALF>
 __global__ __launch_bounds__(kThreads) void k_bicg_yr_fused(
     Cols<T> C, const T* __restrict__ t, const T* __restrict__ sv, const T* __restrict__ p,
     T* __restrict__ y, T* __restrict__ r, const T* __restrict__ rt, double* sc, int off_eta1,
-    int off_eta2, int off_xi, double* sums, int64_t n, const T* __restrict__ dot, T* partials,
-    int nblk) {
+    int off_eta2, int off_xi, double* sums, int64_t n, const T* __restrict__ dot,
+    const T* __restrict__ spart, T* partials, int nblk) {
   const Blk k = hw_blk();
   const double d0 = sc[kDone];
-  if (d0 == (double)kConvHalf) {
-    if (k.b == 0 && threadIdx.x == 0) sc[kDone] = kExited;
-    return;
+  const int kc = C.n1;
+  if constexpr (HALF) {
+    if (d0 != 0.0 && d0 != (double)kConvHalf) return;
+    const int hd = half_step<T>(spart, nblk, sc, off_eta1, off_xi, kc, k.b == 0);
+    if (hd == kConvHalf) {
+      const T alpha = (T)sc[kAlpha];
+      const int64_t npk = n / W;
+      exit_rows<T, W>(p, y, sv, r, alpha, first_row(k), npk, grid_step(k));
+      if (W > 1 && k.b == k.G - 1)
+        exit_rows<T, 1>(p, y, sv, r, alpha, npk * W + threadIdx.x, n, kThreads);
+      return;
+    }
+    if (hd != 0) return;
+  } else {
+    if (d0 == (double)kConvHalf) {
+      if (k.b == 0 && threadIdx.x == 0) sc[kDone] = kExited;
+      return;
+    }
+    if (d0 != 0.0) return;
   }
-  if (d0 != 0.0) return;
   __shared__ double sh[kFinishCols];
   __shared__ double om;
   __shared__ T cf[NC > 0 ? NC : 1];
-  const int kc = C.n1;
   omega_step<T>(dot, nblk, kc, sums, sc, off_eta1, off_eta2, off_xi, k.b == 0, sh, &om);
   for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (T)sh[c] : T(0);
   __syncthreads();
@@ -2270,7 +2315,8 @@ __global__ __launch_bounds__(kThreads) void kg_bicg_sv(const BatchTable* tb) {
   bicg_sv_main<float, 4, NC>(Blk{b, cnt}, q.C, cf, (float)al, q.r, q.v, q.sv, q.n, q.part2,
                              q.nblk);
 }
-// the omega step in front of the yr pass (as k_bicg_yr_fused)
+// the half-step tests and the omega step in front of the yr pass (as
+// k_bicg_yr_fused with HALF)
 template <int NC>
 __global__ __launch_bounds__(kThreads) void kg_bicg_yr(const BatchTable* tb) {
   const int s = batch_sys(tb->pass, tb->nsys);
@@ -2278,36 +2324,28 @@ __global__ __launch_bounds__(kThreads) void kg_bicg_yr(const BatchTable* tb) {
   const int b = (int)blockIdx.x - tb->pass[s], cnt = q.nblk;
   if (b >= cnt) return;
   const double d0 = q.sc[kDone];
-  if (d0 == (double)kConvHalf) {
-    if (b == 0 && threadIdx.x == 0) q.sc[kDone] = kExited;
+  if (d0 != 0.0 && d0 != (double)kConvHalf) return;
+  const int kc = q.C.n1;
+  const int hd = half_step<float>(q.part2, q.nblk, q.sc, kBEta1, kBXi, kc, b == 0);
+  if (hd == kConvHalf) {
+    const float alpha = (float)q.sc[kAlpha];
+    const int64_t npk = q.n / 4;
+    exit_rows<float, 4>(q.p, q.y, q.sv, q.r, alpha, first_row(Blk{b, cnt}), npk,
+                        grid_step(Blk{b, cnt}));
+    if (b == cnt - 1)
+      exit_rows<float, 1>(q.p, q.y, q.sv, q.r, alpha, npk * 4 + threadIdx.x, q.n, kThreads);
     return;
   }
-  if (d0 != 0.0) return;
+  if (hd != 0) return;
   __shared__ double sh[kFinishCols];
   __shared__ double om;
   __shared__ float cf[NC > 0 ? NC : 1];
-  const int kc = q.C.n1;
   omega_step<float>(q.part, q.nblk, kc, q.sc + kBSums, q.sc, kBEta1, kBEta2, kBXi, b == 0, sh,
                     &om);
   for (int c = threadIdx.x; c < NC; c += kThreads) cf[c] = c < kc ? (float)sh[c] : 0.f;
   __syncthreads();
   bicg_yr_main<float, 4, NC>(Blk{b, cnt}, q.C, cf, (float)q.sc[kAlpha], (float)om, q.t, q.sv,
-                             q.p, q.y, q.r, q.rt, q.n, q.part2, q.nblk);
-}
-// the half-step tests with the early-exit update (as k_bicg_half_exit)
-__global__ __launch_bounds__(kThreads) void kg_half_exit(const BatchTable* tb) {
-  const int s = batch_sys(tb->exitv, tb->nsys);
-  const BatchSys& q = tb->sys[s];
-  const int b = (int)blockIdx.x - tb->exitv[s], cnt = min(dev_grid_for(q.n), 512);
-  if (b >= cnt) return;
-  const double d0 = q.sc[kDone];
-  if (d0 != 0.0 && d0 != (double)kConvHalf) return;
-  if (half_step<float>(q.part2, q.nblk, q.sc, kBEta1, kBXi, q.C.n1, b == 0) != kConvHalf) return;
-  const float alpha = (float)q.sc[kAlpha];
-  for (int64_t i = (int64_t)b * kThreads + threadIdx.x; i < q.n; i += (int64_t)cnt * kThreads) {
-    q.y[i] += alpha * q.p[i];
-    q.r[i] = q.sv[i];
-  }
+                             q.p, q.y, q.r, q.rt, q.n, q.part3, q.nblk);
 }
 // the full step with the p update (as k_bicg_finish_p), nblk blocks per system
 __global__ __launch_bounds__(kThreads) void kg_finish_p(const BatchTable* tb) {
@@ -2315,7 +2353,7 @@ __global__ __launch_bounds__(kThreads) void kg_finish_p(const BatchTable* tb) {
   const BatchSys& q = tb->sys[s];
   const int b = (int)blockIdx.x - tb->pass[s], cnt = q.nblk;
   if (b >= cnt) return;
-  bicg_finish_p_body<float, 4>(Blk{b, cnt}, q.part2, q.nblk, q.sc + kBSums, q.sc, q.r, q.p, q.v,
+  bicg_finish_p_body<float, 4>(Blk{b, cnt}, q.part3, q.nblk, q.sc + kBSums, q.sc, q.r, q.p, q.v,
                                q.n);
 }
 
@@ -2708,29 +2746,35 @@ hipError_t bicg_sv_fused(hipStream_t s, const Cols<T>& C, const T* r, T* v, T* s
 template <class T>
 hipError_t bicg_yr_fused(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, const T* p,
                          T* y, T* r, const T* rt, double* sc, int off_eta1, int off_eta2,
-                         int off_xi, double* sums, int64_t n, const T* dot, T* partials,
-                         int nblk) {
+                         int off_xi, double* sums, int64_t n, const T* dot, const T* spart,
+                         T* partials, int nblk) {
   constexpr int VW = 16 / sizeof(T);
   const int kc = C.n1;
   if (kc + 2 > kFinishCols) return hipErrorInvalidValue;
   const bool vv = vec_ok(C) && vec_ok(t) && vec_ok(sv) && vec_ok(p) && vec_ok((const T*)y) &&
                   vec_ok((const T*)r) && vec_ok(rt);
-#define KRS_YRF(NCV)                                                                           \
+  const bool half = spart != nullptr;
+#define KRS_YRF(NCV, H)                                                                        \
   do {                                                                                         \
-    if (vv) k_bicg_yr_fused<T, VW, NCV><<<nblk, kThreads, 0, s>>>(C, t, sv, p, y, r, rt, sc,   \
-                                                                  off_eta1, off_eta2, off_xi,  \
-                                                                  sums, n, dot, partials,      \
-                                                                  nblk);                       \
-    else k_bicg_yr_fused<T, 1, NCV><<<nblk, kThreads, 0, s>>>(C, t, sv, p, y, r, rt, sc,       \
-                                                              off_eta1, off_eta2, off_xi,      \
-                                                              sums, n, dot, partials, nblk);   \
+    if (vv) k_bicg_yr_fused<T, VW, NCV, H><<<nblk, kThreads, 0, s>>>(                          \
+        C, t, sv, p, y, r, rt, sc, off_eta1, off_eta2, off_xi, sums, n, dot, spart, partials,  \
+        nblk);                                                                                 \
+    else k_bicg_yr_fused<T, 1, NCV, H><<<nblk, kThreads, 0, s>>>(                              \
+        C, t, sv, p, y, r, rt, sc, off_eta1, off_eta2, off_xi, sums, n, dot, spart, partials,  \
+        nblk);                                                                                 \
   } while (0)
-  if (kc == 0) KRS_YRF(0);
-  else if (kc <= 8) KRS_YRF(8);
-  else if (kc <= 16) KRS_YRF(16);
-  else if (kc <= 32) KRS_YRF(32);
-  else if (kc <= 64) KRS_YRF(64);
+#define KRS_YRF2(NCV)                \
+  do {                               \
+    if (half) KRS_YRF(NCV, true);    \
+    else KRS_YRF(NCV, false);        \
+  } while (0)
+  if (kc == 0) KRS_YRF2(0);
+  else if (kc <= 8) KRS_YRF2(8);
+  else if (kc <= 16) KRS_YRF2(16);
+  else if (kc <= 32) KRS_YRF2(32);
+  else if (kc <= 64) KRS_YRF2(64);
   else return hipErrorInvalidValue;
+#undef KRS_YRF2
 #undef KRS_YRF
   return hipGetLastError();
 }
@@ -2788,22 +2832,19 @@ hipError_t axpy_f32_into_f64(hipStream_t s, const float* d, double* x, int64_t n
 
 void batch_layout(BatchTable& tb) {
   auto up8 = [](int v) { return (v + kXcd - 1) / kXcd * kXcd; };
-  int pk = 0, ti = 0, pa = 0, ex = 0;
+  int pk = 0, ti = 0, pa = 0;
   for (int s = 0; s < tb.nsys; ++s) {
     const BatchSys& q = tb.sys[s];
     tb.pack[s] = pk;
     tb.tile[s] = ti;
     tb.pass[s] = pa;
-    tb.exitv[s] = ex;
     pk = up8(pk + grid_for(q.n / 4));
     ti = up8(ti + (q.g.nx / 8) * (q.g.ny / 8) * (q.g.nz / 8) / 2);   // tile pairs
     pa = up8(pa + q.nblk);
-    ex = up8(ex + std::min(grid_for(q.n), 512));
   }
   tb.pack[tb.nsys] = pk;
   tb.tile[tb.nsys] = ti;
   tb.pass[tb.nsys] = pa;
-  tb.exitv[tb.nsys] = ex;
 }
 
 #define KRS_BATCH_NC(ncount, ...)                                 \
@@ -2828,7 +2869,6 @@ hipError_t batch_bicg_first_half(hipStream_t s, const BatchTable* d_tb, const Ba
   // launchers do: [C, r~] has nc + 1 columns, the C-updates nc
   KRS_BATCH_NC(nc + 1, kg_block_dot<(NCB > 0 ? NCB : 8)><<<tb.pass[ns], kThreads, 0, s>>>(d_tb, 0));
   KRS_BATCH_NC(nc, kg_bicg_sv<NCB><<<tb.pass[ns], kThreads, 0, s>>>(d_tb));
-  kg_half_exit<<<tb.exitv[ns], kThreads, 0, s>>>(d_tb);
   return hipGetLastError();
 }
 
@@ -2877,7 +2917,7 @@ hipError_t batch_bicg_second_half(hipStream_t s, const BatchTable* d_tb, const B
                                        int, int, double*, int64_t, const T*, T*, int);           \
   template hipError_t bicg_yr_fused<T>(hipStream_t, const Cols<T>&, const T*, const T*,         \
                                        const T*, T*, T*, const T*, double*, int, int, int,       \
-                                       double*, int64_t, const T*, T*, int);                     \
+                                       double*, int64_t, const T*, const T*, T*, int);           \
   template hipError_t bicg_half_exit<T>(hipStream_t, const T*, T*, const T*, T*, double*, int,  \
                                         int, int, const T*, int, int64_t);                       \
   template hipError_t bicg_finish_p<T>(hipStream_t, const T*, int, double*, double*, const T*,    \

@@ -138,18 +138,23 @@ hipError_t cgs_decide(hipStream_t s, int ncols, const double* h1, double* hcol, 
 // kRho is the rho of the current iteration; the full step stores the next
 // one in kRhoNew and the next alpha step takes it over into kRho (so that no
 // block of the full-step launch reads a slot that its block 0 writes).
+// Breakdown flags: kFlag from the alpha step (1), kFlagT from the omega step
+// (2), whose launch may also run the half-step tests that read kFlag.
 enum BicgSlot {
-  kRho = 0, kRhoNew, kAlpha, kOmega, kBeta, kRtv, kSnorm2, kRnorm2, kTs, kTt, kFlag,
+  kRho = 0, kRhoNew, kAlpha, kOmega, kBeta, kRtv, kSnorm2, kRnorm2, kTs, kTt, kFlag, kFlagT,
   // device-driven iteration: state (kDone), iterations started, history
   // entries written, absolute stopping and divergence thresholds, and whether
   // the stop came at the half step
   kDone, kIts, kHlen, kTolAbs, kDivAbs, kEndHalf,
   kSlots
 };
-// kDone values: 0 running, 1 converged at the half step (early exit still to
-// apply), 2 converged at the full step, 3 breakdown, 4 diverged or non-finite,
-// 5 early exit applied.  Every BiCGStab pass returns at once when kDone != 0,
-// so iterations enqueued after the stop change nothing that the result reads.
+// kDone values: 0 running, 1 converged at the half step (the exit is applied
+// by the launch that sets it, except in the host-tested loop, where the next
+// yr pass marks it applied), 2 converged at the full step, 3 breakdown, 4
+// diverged or non-finite, 5 early exit applied (set by the pass after the
+// one that stored 1).  Every BiCGStab pass returns at once when kDone is
+// neither 0 nor, inside the launch that stored it, 1, so iterations enqueued
+// after the stop change nothing that the result reads.
 enum BicgDone { kRunning = 0, kConvHalf = 1, kConvFull = 2, kBreak = 3, kDiverge = 4, kExited = 5 };
 // history ring of the device-driven loop (absolute norms, 2 per iteration)
 constexpr int kHistOff = 512, kHistRing = 128;
@@ -164,12 +169,16 @@ template <class T>
 hipError_t bicg_sv_fused(hipStream_t s, const Cols<T>& C, const T* r, T* v, T* sv, double* sc,
                          int off_eta1, int off_ctrt, double* sums, int64_t n, const T* dot,
                          T* partials, int nblk);
+// With `spart` (the sv pass's |s|^2 partials) the yr pass first takes the
+// half-step tests and, on convergence there, applies the exit instead of its
+// update; without it (null) the tests ran in bicg_half_exit.
 template <class T>
 hipError_t bicg_yr_fused(hipStream_t s, const Cols<T>& C, const T* t, const T* sv, const T* p,
                          T* y, T* r, const T* rt, double* sc, int off_eta1, int off_eta2,
-                         int off_xi, double* sums, int64_t n, const T* dot, T* partials,
-                         int nblk);
-// The half-step tests fused with the vector part of the early exit.
+                         int off_xi, double* sums, int64_t n, const T* dot, const T* spart,
+                         T* partials, int nblk);
+// The half-step tests fused with the vector part of the early exit, in a
+// launch of their own (the host-tested loop reads the state after it).
 template <class T>
 hipError_t bicg_half_exit(hipStream_t s, const T* p, T* y, const T* sv, T* r, double* sc,
                           int off_eta1, int off_xi, int kc, const T* partials, int nblk,
@@ -238,7 +247,8 @@ struct BatchSys {
   const float* rt;        // shadow residual r~
   float *r, *p, *v, *sv, *t, *z, *y;
   float* part;            // per-block partial sums of the dot passes
-  float* part2;           // those of the update passes (not overlapping part's)
+  float* part2;           // |s|^2 partials of the sv pass (after part's)
+  float* part3;           // partials of the yr pass (after part2's)
   double* sc;             // scalar area (BicgSlot, BicgOff)
   int nblk;               // blocks of the streaming passes
   int64_t n;
@@ -249,14 +259,13 @@ struct BatchTable {
   int pack[kMaxBatch + 1];   // block ranges: four rows per thread (stencil packs)
   int tile[kMaxBatch + 1];   //   two Schwarz tiles (an x-pair) per block
   int pass[kMaxBatch + 1];   //   streaming passes (nblk blocks)
-  int exitv[kMaxBatch + 1];  //   the half-step exit update (at most 512 blocks)
   BatchSys sys[kMaxBatch];
 };
 // Fills the block ranges of `tb` from its systems (host side).
 void batch_layout(BatchTable& tb);
 // One rBiCGStab pass sequence for all systems of the table (device copy
-// d_tb, host copy tb): the first half (A~ p, C-projection, alpha,
-// s, half-step tests and exit) and the second half (A~ s, omega, y and r
+// d_tb, host copy tb): the first half (A~ p, C-projection, alpha, s) and
+// the second half (A~ s, the half-step tests and exit, omega, y and r
 // updates, full-step tests, next p).  The operator is Schwarz-Jacobi (packed Jacobi
 // local sweeps, one global sweep) followed by the matvec.  Systems whose stop
 // state is set skip every launch.  `nc` is the recycle dimension shared by

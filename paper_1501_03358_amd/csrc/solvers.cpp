@@ -1041,8 +1041,10 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     return std::isfinite(nb) ? KRS_OK : KRS_DIVERGED;
   }
   const int kc = rec ? rec->dim : 0;
-  // partials of the fused sv / yr passes, after the dot pass's kc + 2 columns
+  // partials of the fused sv pass (|s|^2) after the dot pass's kc + 2
+  // columns, then those of the yr pass (r~.r, |r|^2)
   T* const part2 = part + (size_t)nblk * (kc + 2);
+  T* const part3 = part2 + nblk;
   const T* U = rec ? (const T*)rec->U : nullptr;
   const T* C = rec ? (const T*)rec->C : nullptr;
   const int64_t ldr = rec ? rec->ld : 0;
@@ -1110,10 +1112,12 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     KRS_LAUNCH(ctx, KRS_K_BICG_SV, dev ? 0 : bytes_sv,
                bicg_sv_fused<T>(s, Cc, r, v, sv, sc, kEta1, kCtrt, sc + kSums, n, part, part2,
                                 nblk));
-    // half-step |s| tests; on convergence xi += alpha eta1 and, in the same
-    // launch, y += alpha p, r = s
-    KRS_LAUNCH(ctx, KRS_K_BICG_P, 0,
-               bicg_half_exit<T>(s, p, y, sv, r, sc, kEta1, kXi, kc, part2, nblk, n));
+    // host-tested loop: the half-step |s| tests in a launch of their own (on
+    // convergence xi += alpha eta1 and, in the same launch, y += alpha p,
+    // r = s), so that the host reads them before the second half
+    if (!dev)
+      KRS_LAUNCH(ctx, KRS_K_BICG_P, 0,
+                 bicg_half_exit<T>(s, p, y, sv, r, sc, kEta1, kXi, kc, part2, nblk, n));
     return 0;
   };
   auto second_half = [&](bool dev) -> int {
@@ -1123,13 +1127,16 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     KRS_LAUNCH(ctx, KRS_K_BLOCK_DOT, NW * (kc + 2),
                block_dot<T>(s, cols<T>(C, ldr, kc, sv, ld, 1), t, n, 1, part, nblk));
     // the omega step in front of the y and r updates (with the partials of
-    // the next rho = r~^T r), then the loop tests and the next p
+    // the next rho = r~^T r), then the loop tests and the next p.  In the
+    // device-driven loop the half-step tests run in front of the omega step
+    // (on convergence the pass applies the exit instead; A~ s and its dot
+    // pass have then run for nothing, once per solve)
     KRS_LAUNCH(ctx, KRS_K_BICG_YR, dev ? 0 : bytes_yr,
                bicg_yr_fused<T>(s, Cc, t, sv, p, y, r, rt, sc, kEta1, kEta2, kXi, sc + kSums, n,
-                                part, part2, nblk));
+                                part, dev ? part2 : nullptr, part3, nblk));
     // (its p update is charged once the state read back shows it ran)
     KRS_LAUNCH(ctx, KRS_K_BICG_P, 0,
-               bicg_finish_p<T>(s, part2, nblk, sc + kSums, sc, r, p, v, n));
+               bicg_finish_p<T>(s, part3, nblk, sc + kSums, sc, r, p, v, n));
     return 0;
   };
   if (o->flags & KRS_FLAG_HOST_LOOP) {
@@ -1170,7 +1177,7 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
       rho = slots[kRhoNew];
       if (slots[kDone] == kRunning) timing_add_bytes(ctx, KRS_K_BICG_P, bytes_p);
       hist(rnorm / nb);
-      if (slots[kFlag] != 0.0) {
+      if (slots[kFlag] != 0.0 || slots[kFlagT] != 0.0) {
         status = KRS_BREAKDOWN;
         break;
       }
@@ -1312,7 +1319,8 @@ int rbicgstab_t(krs_ctx* ctx, const krs_matrix* A, const krs_precond* M, const k
     // the flag the scalar steps left (1: alpha, 2: omega), else rho = 0
     int e = read_dev(ctx, sc, kSlots);
     if (e) return e;
-    site = ctx->pin[kFlag] != 0.0 ? (int64_t)ctx->pin[kFlag] : 3;
+    site = ctx->pin[kFlag] != 0.0 ? (int64_t)ctx->pin[kFlag]
+                                  : (ctx->pin[kFlagT] != 0.0 ? (int64_t)ctx->pin[kFlagT] : 3);
   }
   // postponed U-update: y -= U xi ; then x = M^-1 y
   if (kc > 0) {
@@ -1809,6 +1817,7 @@ int ir_solve_batched(krs_ctx* ctx, int nsys, const krs_ir_system* sys, const krs
         b.nblk = std::min(red_blocks(x->n), 512);
         // as in rbicgstab_t: after the dot passes' k_c + 2 columns
         b.part2 = b.part + (size_t)b.nblk * (b.C.n1 + 2);
+        b.part3 = b.part2 + b.nblk;
         b.n = x->n;
         b.ld = x->ld;
       }
