@@ -425,9 +425,11 @@ typedef enum krs_kernel_class {
   KRS_K_BLOCK_DOT = 4,      /* [C V]^T w and other block dot products */
   KRS_K_BLOCK_DOT2 = 5,     /* second Gram-Schmidt pass: [C V]^T (w - [C V] h) */
   KRS_K_BLOCK_UPDATE = 6,   /* w - [C V] h, solution and projection updates */
-  KRS_K_BICG_P = 7,         /* p = r + beta (p - omega v) and the half-step exit update */
+  KRS_K_BICG_P = 7,         /* full-step tests and p = r + beta (p - omega v); the separate
+                               half-step exit of the host-tested loop */
   KRS_K_BICG_SV = 8,        /* v -= C eta1, s = r - alpha v, |s|^2 */
-  KRS_K_BICG_YR = 9,        /* y += alpha p + omega s, r = s - omega (t - C eta2), dots */
+  KRS_K_BICG_YR = 9,        /* y += alpha p + omega s, r = s - omega (t - C eta2), dots; or the
+                               half-step exit update */
   KRS_K_GRAM = 10,          /* Gram blocks of the recycle update */
   KRS_K_ROW_TRANSFORM = 11, /* in-place (U, C) row-block updates */
   KRS_K_OTHER = 12,         /* finishing reductions, copies, casts, coefficient packing */
