@@ -1775,10 +1775,11 @@ __device__ inline void hist_push(double* sc, double v) {
 
 // ---------------------------------------------------------------------------
 // BiCGStab scalar steps: the columns of the per-block partials are summed
-// (FP64, fixed order), then one thread runs the scalar step.  The alpha and
-// omega steps run in front of the update passes that use them (every block),
-// the half-step tests with the early-exit update, the full-step tests in one
-// block.  Every kernel returns at once when the device-side stop state is set.
+// (FP64, fixed order), then one thread runs the scalar step.  Every block of
+// the pass that needs a step runs it in front of its own work: alpha before
+// the sv update, the half-step tests and omega before the yr update, the
+// full-step tests before the p update.  Every kernel returns at once when the
+// device-side stop state is set.
 // ---------------------------------------------------------------------------
 // Column sums go to `out` (device memory, for the host; may be null) and to
 // `sh` (LDS): the scalar step reads them from LDS, never back from memory it
@@ -2183,10 +2184,12 @@ __global__ __launch_bounds__(kThreads) void k_bicg_yr_fused(
   bicg_yr_main<T, W, NC>(k, C, cf, (T)sc[kAlpha], (T)om, t, sv, p, y, r, rt, n, partials, nblk);
 }
 
-// The half-step tests fused with the vector part of the early exit: every
-// block sums |s|^2 itself and takes the decision; block 0 stores the state.
-// A block that starts after block 0 stored kConvHalf goes on (it reaches the
-// same decision); kBreak or kDiverge from block 0 ends it, as intended.
+// The half-step tests fused with the vector part of the early exit, in a
+// launch of their own (the host-tested loop, which reads the state before
+// the second half): every block sums |s|^2 itself and takes the decision;
+// block 0 stores the state.  A block that starts after block 0 stored
+// kConvHalf goes on (it reaches the same decision); kBreak or kDiverge from
+// block 0 ends it, as intended.
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_bicg_half_exit(const T* __restrict__ p, T* y,
                                                              const T* __restrict__ sv, T* r,
