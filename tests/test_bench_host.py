@@ -59,3 +59,12 @@ def test_traffic_is_withheld_for_other_workloads(argv):
     val, why = bench.measured_traffic("block_dot", w)
     assert val is None and "another workload" in why
     assert bench.counter_workload(_args([])) == "porous256_ir"
+
+
+def test_shape_applies_to_the_default_workload_only():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "serve",
+                        "--shape", "64", "64", "32"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "--shape applies to the default workload" in p.stderr
+    assert p.stdout == ""
