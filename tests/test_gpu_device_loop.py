@@ -68,6 +68,46 @@ def test_device_loop_equals_host_loop(gpu_lib, pc, dtype):
         assert rc == krs.NOT_CONVERGED and st.matvecs == maxmv + (maxmv % 2)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", [(13, 11, 7), (5, 3, 1)])
+def test_device_loop_equals_host_loop_on_ragged_grids(gpu_lib, shape, dtype):
+    """Grids of 1001 and 15 cells, no multiple of a 16-byte pack: the last
+    rows of every pack-wide pass (the yr pass with the half-step exit in
+    front in the device loop, the separate exit launch in the host loop, the
+    full step with the p update) go to the last block.  Both loops agree
+    bitwise, with and without a recycle space, over tolerances that end at
+    the half and at the full step, and the true residual of the tightest
+    solve meets its tolerance."""
+    from oracle import stencil as S
+    krs = gpu_lib
+    prob = W.porous_problem(shape[0], extra=60, shape=shape)
+    d = Dev(krs, prob, "jacobi", dtype=dtype, m=10, k=4)
+    rec = krs.Recycle(d.ctx, prob.n, 4, dtype)
+    rec.U[:4, :prob.n] = torch.from_numpy(
+        np.random.default_rng(4).standard_normal((4, prob.n))).to(d.dev, dtype)
+    rec.set_dim(4)
+    krs.recycle_update(d.ctx, d.A, d.M, rec, d.ws)
+    b = W.random_vector(prob.n, 61)
+    f64 = dtype == torch.float64
+    tols = np.logspace(-2, -10 if f64 else -5, 9)
+    half_exits = 0
+    for use_rec in (None, rec):
+        for tol in tols:
+            rc, st = _compare(krs, d, use_rec, b, float(tol), 4000)
+            assert rc == krs.OK, (use_rec is not None, tol, rc)
+            half_exits += st.matvecs % 2 == 1
+        x = _solve(krs, d, use_rec, b, float(tols[-1]), 4000, 0)[3]
+        xh = x.double().cpu().numpy()
+        res = b - S.apply(prob.bands, prob.shape, prob.periodic, xh)
+        # the true residual (FP64 stencil on the FP64 bands) may exceed the
+        # updated one the loop stops on by about u * cond(A D^-1) (2.5e3 on
+        # the 1001-cell grid): FP64 2 tol; FP32, which also solved with
+        # bands rounded to FP32, 1e-3 (the bound u32 * cond is 1.5e-4)
+        bar = 2.0 * float(tols[-1]) if f64 else 1e-3
+        assert np.linalg.norm(res) <= bar * np.linalg.norm(b), np.linalg.norm(res) / np.linalg.norm(b)
+    assert half_exits > 0
+
+
 def test_device_loop_zero_rhs_and_converged_start(gpu_lib):
     krs = gpu_lib
     prob = W.grf_problem(8, extra=42)
