@@ -124,7 +124,8 @@ def host_info():
 
 def cpu_baseline(prob, U, C, counts):
     """The oracle (plain NumPy/SciPy FP64, as it stands) timed on the host
-    for a bounded sample of the 256^3 workload, scaled to a whole sequence:
+    for a bounded sample of the workload (the 256^3 line, the 128^3 channel
+    and porous sequences), scaled to a whole sequence:
 
       t_it   one rBiCGStab iteration with the k-dimensional recycle space
              (Alg. 4: two applications of A M^-1, the C-projections and the
@@ -569,8 +570,12 @@ def seq_main(args):
             rec.mark_stale()
         return True
 
+    counts, recs = {}, {}
+
     def run(name, solve):
         rec = krs.Recycle(ctx, prob.n, args.k, torch.float64)
+        recs[name] = rec
+        counts[name] = []
         krs.timing_reset(ctx)
         krs.timing_enable(ctx, True)
         mvs, its, byt, lat, bad, sp = [], 0, 0.0, [], 0, 0
@@ -583,6 +588,11 @@ def seq_main(args):
                 krs.recycle_update(ctx, A, Mp, rec, ws)   # re-form C = qr(A~ U) for the new matrix
             rc, st = solve(rec, i, bs[i])
             lat.append((time.perf_counter() - s0) * 1e3)
+            # per system: the solver that produced x (what the oracle sample is scaled by)
+            hyb = name.startswith("hybrid")
+            counts[name].append(("rgcrot" if (name == "rgcrot" or (hyb and st.solver ==
+                                                                    krs.SOLVER_RGCROT))
+                                 else "rbicgstab", int(st.iterations), int(st.cycles)))
             mvs.append(st.matvecs)
             its += st.iterations
             byt += st.bytes_model
@@ -647,6 +657,15 @@ def seq_main(args):
                    "GB_s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
                for c, v in kt.items() if v[0] > 0}
     r0 = res[main_name]
+    cpu = None
+    # the oracle sample of the 256^3 line, here for the main method's sequence
+    # (7-point Schwarz-Jacobi with Jacobi local sweeps, right preconditioning)
+    if (not args.no_cpu and args.local_solver == "jacobi" and not args.left and not gcrot
+            and args.workload in ("channel128", "porous128")):
+        log("[bench] timing the CPU oracle sample ...")
+        U64, C64 = recs[main_name].views()
+        cpu = cpu_baseline(prob, U64.cpu().numpy().copy(), C64.cpu().numpy().copy(),
+                           counts[main_name])
     out = {
         "metric": f"solves/s to 1e-8 relative residual (FP64, {main_name})",
         "value": r0["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": steps,
@@ -668,6 +687,7 @@ def seq_main(args):
                      "launches": n_l, "avg_launch_us": 1e3 * ms_l / max(n_l, 1),
                      "note": "128^3 FP64 working set (~1.6 GB) exceeds the 256 MB MALL"},
         "kernels": kernels,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
